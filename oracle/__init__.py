@@ -1,0 +1,208 @@
+"""CPU oracle for the principal-minor library -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct reference implementations of what the GPU path
+computes (Simkovic & Ferrero, arXiv:2104.07638).  Only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import this package.  It shares no code with the HIP library and never imports
+it; the two meet only through the seeded generators in ``workloads``.
+
+Functions (all fp64 / complex128, row-major inputs, outputs in bit-mask order,
+bit k <-> row/column k, out[0] = det of the empty matrix = 1):
+
+* ``minors(A)``            -- Sec. II: det(A[S]) for every subset S, one
+                              partial-pivoting LU per subset (C, ``apm_oracle.c``).
+* ``connected_sums(a, mode)`` -- Sec. V.A, Eq. (recursion), direct O(3^n) loop.
+* ``perm_minors(A)``       -- Sec. IV: Ryser's formula per subset, with the
+                              (-1)^|S| factor the printed Eq. (ryser) drops.
+* ``g0``-independent: the oracle consumes host matrices built by ``workloads``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "apm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True, path: str = _LIB, plant: int = 0) -> str:
+    """Compile ``apm_oracle.c`` (gcc -O2, OpenMP) into ``path``.
+
+    ``plant`` != 0 builds a deliberately broken variant; only the test that
+    checks the pins' power uses it."""
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-Wall", f"-DORACLE_PLANT={int(plant)}", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
+
+
+def load_library(path: str):
+    """Load an oracle shared library and declare its C signatures."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lp = ctypes.POINTER(ctypes.c_int64)
+    for name in ("apm_oracle_minors_r64", "apm_oracle_minors_c128", "apm_oracle_perm_minors"):
+        fn = getattr(lib, name)
+        fn.argtypes = [ctypes.c_int, dp, dp]
+        fn.restype = ctypes.c_int
+    lib.apm_oracle_connected_sums.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int]
+    lib.apm_oracle_connected_sums.restype = ctypes.c_int
+    for name in ("apm_oracle_minors_r64_batch", "apm_oracle_minors_c128_batch",
+                 "apm_oracle_perm_minors_batch"):
+        fn = getattr(lib, name)
+        fn.argtypes = [ctypes.c_int, ip, lp, lp, dp, dp, ctypes.c_int]
+        fn.restype = ctypes.c_int
+    lib.apm_oracle_connected_sums_batch.argtypes = [ctypes.c_int, ip, lp, dp, dp, ctypes.c_int,
+                                                    ctypes.c_int]
+    lib.apm_oracle_connected_sums_batch.restype = ctypes.c_int
+    lib.apm_oracle_max_threads.restype = ctypes.c_int
+    return lib
+
+
+def _load(lib=None):
+    global _lib
+    if lib is not None:
+        return lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        _lib = load_library(_LIB)
+    return _lib
+
+
+def _dp(x):
+    return x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def max_threads() -> int:
+    return int(_load().apm_oracle_max_threads())
+
+
+def _as_batch(A, complex_=False):
+    A = np.asarray(A)
+    single = A.ndim == 2
+    if single:
+        A = A[None]
+    if complex_:
+        A = np.ascontiguousarray(A, dtype=np.complex128)
+    else:
+        if np.iscomplexobj(A):
+            raise TypeError("real oracle called with complex input")
+        A = np.ascontiguousarray(A, dtype=np.float64)
+    return A, single
+
+
+def minors(A, nthreads: int = 0, lib=None) -> np.ndarray:
+    """All principal minors of a real (B, n, n) or (n, n) matrix batch (Sec. II).
+
+    Returns (B, 2**n) (or (2**n,) for a single matrix), fp64."""
+    A, single = _as_batch(A)
+    B, n, _ = A.shape
+    out = np.empty((B, 1 << n), dtype=np.float64)
+    nv = np.full(B, n, dtype=np.int32)
+    ioff = (np.arange(B, dtype=np.int64) * n * n)
+    ooff = (np.arange(B, dtype=np.int64) << n)
+    rc = _load(lib).apm_oracle_minors_r64_batch(B, nv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            ioff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                            ooff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                            _dp(A), _dp(out), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: bad matrix order")
+    return out[0] if single else out
+
+
+def minors_complex(A, nthreads: int = 0, lib=None) -> np.ndarray:
+    """All principal minors of a complex128 batch (Sec. V.C matrices are complex)."""
+    A, single = _as_batch(A, complex_=True)
+    B, n, _ = A.shape
+    out = np.empty((B, 1 << n), dtype=np.complex128)
+    nv = np.full(B, n, dtype=np.int32)
+    ioff = (np.arange(B, dtype=np.int64) * n * n)
+    ooff = (np.arange(B, dtype=np.int64) << n)
+    rc = _load(lib).apm_oracle_minors_c128_batch(B, nv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             ioff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                             ooff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                             _dp(A.view(np.float64)), _dp(out.view(np.float64)),
+                                             int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: bad matrix order")
+    return out[0] if single else out
+
+
+def minors_ragged(mats, nthreads: int = 0, lib=None):
+    """Principal minors of a list of real matrices of different orders."""
+    B = len(mats)
+    ns = np.array([m.shape[0] for m in mats], dtype=np.int32)
+    ioff = np.zeros(B, dtype=np.int64)
+    ooff = np.zeros(B, dtype=np.int64)
+    if B:
+        ioff[1:] = np.cumsum(ns[:-1].astype(np.int64) ** 2)
+        ooff[1:] = np.cumsum(np.left_shift(1, ns[:-1].astype(np.int64)))
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(m, dtype=np.float64).ravel() for m in mats])
+                                if B else np.zeros(0))
+    total = int(ooff[-1] + (1 << int(ns[-1]))) if B else 0
+    out = np.empty(total, dtype=np.float64)
+    rc = _load(lib).apm_oracle_minors_r64_batch(B, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            ioff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                            ooff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                            _dp(flat), _dp(out), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: bad matrix order")
+    return [out[int(o):int(o) + (1 << int(k))] for o, k in zip(ooff, ns)]
+
+
+def connected_sums(a, mode: int = 0, nthreads: int = 0, lib=None) -> np.ndarray:
+    """Connected sums c[S] from subset weights a[S] (Sec. V.A, Eq. (recursion)).
+
+    ``a`` is (B, 2**n) or (2**n,).  mode 0: rooted at vertex 0 (c = 0 on sets
+    without vertex 0); mode 1: every nonempty set, rooted at its lowest vertex."""
+    a = np.asarray(a, dtype=np.float64)
+    single = a.ndim == 1
+    if single:
+        a = a[None]
+    a = np.ascontiguousarray(a)
+    B, nm = a.shape
+    n = nm.bit_length() - 1
+    if (1 << n) != nm:
+        raise ValueError("length must be a power of two")
+    c = np.empty_like(a)
+    nv = np.full(B, n, dtype=np.int32)
+    off = np.arange(B, dtype=np.int64) * nm
+    rc = _load(lib).apm_oracle_connected_sums_batch(B, nv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                                _dp(a), _dp(c), int(mode), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: bad arguments")
+    return c[0] if single else c
+
+
+def perm_minors(A, nthreads: int = 0, lib=None) -> np.ndarray:
+    """All permanent principal minors (Sec. IV), Ryser per subset."""
+    A, single = _as_batch(A)
+    B, n, _ = A.shape
+    out = np.empty((B, 1 << n), dtype=np.float64)
+    nv = np.full(B, n, dtype=np.int32)
+    ioff = (np.arange(B, dtype=np.int64) * n * n)
+    ooff = (np.arange(B, dtype=np.int64) << n)
+    rc = _load(lib).apm_oracle_perm_minors_batch(B, nv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             ioff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                             ooff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                             _dp(A), _dp(out), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: bad matrix order")
+    return out[0] if single else out
+
+
+def cdet_weights(m_up, m_dn=None) -> np.ndarray:
+    """Sec. V.A: a[S] = det(M_up[S]) det(M_dn[S]) from two minors arrays
+    (a single array stands for both spins)."""
+    m_up = np.asarray(m_up, dtype=np.float64)
+    return m_up * (m_up if m_dn is None else np.asarray(m_dn, dtype=np.float64))

@@ -1,0 +1,297 @@
+/*
+ * apm_oracle.c -- CPU oracle for the principal-minor library (TEST INFRASTRUCTURE).
+ *
+ * This file is test infrastructure.  It is a plain, slow, obviously correct
+ * reference for the quantities computed in Simkovic & Ferrero, "Fast Principal
+ * Minor Algorithms for Quantum Many Body Systems" (arXiv:2104.07638).  Only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  The product path (the HIP library) shares no code with it and never
+ * calls it.
+ *
+ * Conventions (Sec. II, problem statement and bit-mask example S_13 = {1,3,4}):
+ *   - a subset of the rows/columns {0..n-1} is the integer mask m; bit k of m
+ *     set  <=>  row/column k is kept (0-based: the paper's 1-based row k+1).
+ *   - out[m] = det(A[S_m]); the empty minor out[0] = 1.
+ *   - matrices are dense row-major; complex values are interleaved (re, im).
+ *
+ * Every function computes the plain definition, with no reuse between subsets:
+ *   - principal minors: Gaussian elimination with partial pivoting on each
+ *     gathered submatrix (the "trivial way" of Sec. II, O(n^3 2^n));
+ *   - connected sums: the recursion of Sec. V.A, Eq. (recursion), summed
+ *     directly over subsets (O(3^n));
+ *   - permanent principal minors: Ryser's inclusion-exclusion formula of
+ *     Sec. IV applied separately to every subset, with the (-1)^|S| factor
+ *     that the printed Eq. (ryser) omits (see the note at apm_oracle_perm).
+ *
+ * Accuracy: fp64 / complex128 throughout.  Partial pivoting makes the minors
+ * backward stable; they are not exact for near-singular submatrices (tests use
+ * a high-precision reference there).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_MAX_N 24
+
+/* ORACLE_PLANT selects a deliberate mistake, used only by the test that checks
+ * that the pins catch plausible errors.  The shipped library is built with 0. */
+#ifndef ORACLE_PLANT
+#define ORACLE_PLANT 0
+#endif
+
+static int popcount32(uint32_t x) { return __builtin_popcount(x); }
+
+/* Determinant of a dense k x k real matrix (row-major, overwritten) by
+ * Gaussian elimination with partial pivoting.  det of the 0 x 0 matrix is 1. */
+static double det_real_inplace(int k, double *M)
+{
+    double det = 1.0;
+    for (int c = 0; c < k; ++c) {
+        int piv = c;
+        double best = fabs(M[c * k + c]);
+        for (int r = c + 1; r < k; ++r) {
+            double v = fabs(M[r * k + c]);
+            if (v > best) { best = v; piv = r; }
+        }
+        if (best == 0.0) return 0.0;
+        if (piv != c) {
+            for (int j = 0; j < k; ++j) {
+                double t = M[c * k + j]; M[c * k + j] = M[piv * k + j]; M[piv * k + j] = t;
+            }
+#if ORACLE_PLANT != 1
+            det = -det;
+#endif
+        }
+        double p = M[c * k + c];
+        det *= p;
+        for (int r = c + 1; r < k; ++r) {
+            double f = M[r * k + c] / p;
+            if (f == 0.0) continue;
+#if ORACLE_PLANT == 2
+            for (int j = c + 1; j < k; ++j) M[r * k + j] -= f * M[j * k + c];
+#else
+            for (int j = c + 1; j < k; ++j) M[r * k + j] -= f * M[c * k + j];
+#endif
+        }
+    }
+    return det;
+}
+
+/* Complex version; M holds k*k interleaved (re, im) pairs.  Result in d[0..1]. */
+static void det_cplx_inplace(int k, double *M, double *d)
+{
+    double dr = 1.0, di = 0.0;
+    for (int c = 0; c < k; ++c) {
+        int piv = c;
+        double best = hypot(M[2 * (c * k + c)], M[2 * (c * k + c) + 1]);
+        for (int r = c + 1; r < k; ++r) {
+            double v = hypot(M[2 * (r * k + c)], M[2 * (r * k + c) + 1]);
+            if (v > best) { best = v; piv = r; }
+        }
+        if (best == 0.0) { d[0] = 0.0; d[1] = 0.0; return; }
+        if (piv != c) {
+            for (int j = 0; j < 2 * k; ++j) {
+                double t = M[2 * c * k + j]; M[2 * c * k + j] = M[2 * piv * k + j]; M[2 * piv * k + j] = t;
+            }
+            dr = -dr; di = -di;
+        }
+        double pr = M[2 * (c * k + c)], pi = M[2 * (c * k + c) + 1];
+        double nr = dr * pr - di * pi, ni = dr * pi + di * pr;
+        dr = nr; di = ni;
+        double den = pr * pr + pi * pi;
+        for (int r = c + 1; r < k; ++r) {
+            double ar = M[2 * (r * k + c)], ai = M[2 * (r * k + c) + 1];
+            /* f = a / p */
+#if ORACLE_PLANT == 6
+            double fr = (ar * pr + ai * pi) / den, fi = (ar * pi - ai * pr) / den;
+#else
+            double fr = (ar * pr + ai * pi) / den, fi = (ai * pr - ar * pi) / den;
+#endif
+            for (int j = c + 1; j < k; ++j) {
+                double br = M[2 * (c * k + j)], bi = M[2 * (c * k + j) + 1];
+                M[2 * (r * k + j)]     -= fr * br - fi * bi;
+                M[2 * (r * k + j) + 1] -= fr * bi + fi * br;
+            }
+        }
+    }
+    d[0] = dr; d[1] = di;
+}
+
+/* All 2^n principal minors of a real n x n matrix, one LU per subset
+ * (Sec. II: det(A[S_m]) for every mask m, det(A[empty]) = 1). */
+int apm_oracle_minors_r64(int n, const double *A, double *out)
+{
+    if (n < 0 || n > ORACLE_MAX_N) return -1;
+    double sub[ORACLE_MAX_N * ORACLE_MAX_N];
+    int idx[ORACLE_MAX_N];
+    const uint32_t nm = 1u << n;
+    for (uint32_t m = 0; m < nm; ++m) {
+        int k = 0;
+        for (int i = 0; i < n; ++i) if (m >> i & 1u) idx[k++] = i;
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) sub[a * k + b] = A[idx[a] * n + idx[b]];
+        out[m] = det_real_inplace(k, sub);
+    }
+    return 0;
+}
+
+/* Complex128 version (Sec. V.C: Keldysh matrices have complex entries). */
+int apm_oracle_minors_c128(int n, const double *A, double *out)
+{
+    if (n < 0 || n > ORACLE_MAX_N) return -1;
+    double sub[2 * ORACLE_MAX_N * ORACLE_MAX_N];
+    int idx[ORACLE_MAX_N];
+    const uint32_t nm = 1u << n;
+    for (uint32_t m = 0; m < nm; ++m) {
+        int k = 0;
+        for (int i = 0; i < n; ++i) if (m >> i & 1u) idx[k++] = i;
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+                sub[2 * (a * k + b)]     = A[2 * (idx[a] * n + idx[b])];
+                sub[2 * (a * k + b) + 1] = A[2 * (idx[a] * n + idx[b]) + 1];
+            }
+        det_cplx_inplace(k, sub, &out[2 * m]);
+    }
+    return 0;
+}
+
+/* Connected sums, Sec. V.A, Eq. (recursion):
+ *     c[S] = a[S] - sum_{T subsetneq S, j in T} c[T] a[S \ T],
+ * with the distinguished vertex j fixed per S.
+ *   mode 0 (rooted): j = vertex 0; c[S] is produced for every S containing
+ *                    vertex 0 and c[S] = 0 is written for every other S;
+ *   mode 1 (all):    j = the lowest vertex of S; c[S] for every nonempty S.
+ * c[empty] = 0 and a[empty] is never read.  Subsets are visited in increasing
+ * numeric order, which visits every proper subset T of S before S. */
+int apm_oracle_connected_sums(int n, const double *a, double *c, int mode)
+{
+    if (n < 0 || n > ORACLE_MAX_N || (mode != 0 && mode != 1)) return -1;
+    const uint32_t nm = 1u << n;
+    c[0] = 0.0;
+    for (uint32_t S = 1; S < nm; ++S) {
+        uint32_t jbit = (mode == 0) ? 1u : (S & (0u - S));
+        if (!(S & jbit)) { c[S] = 0.0; continue; }
+        double acc = a[S];
+        /* proper subsets T of S that contain j: T = jbit | U, U a subset of S \ jbit, T != S */
+        uint32_t rest = S & ~jbit;
+        uint32_t U = rest;
+        for (;;) {
+            uint32_t T = jbit | U;
+#if ORACLE_PLANT == 3
+            if (T != S) acc -= c[T] * a[T];
+#elif ORACLE_PLANT == 4
+            if (T != S) acc -= c[T] * a[S & ~T];
+            else if (U != 0) acc -= c[jbit] * a[S & ~jbit];
+#else
+            if (T != S) acc -= c[T] * a[S & ~T];
+#endif
+            if (U == 0) break;
+            U = (U - 1) & rest;
+        }
+        c[S] = acc;
+    }
+    return 0;
+}
+
+/* Permanent principal minors by Ryser's formula applied to each subset S
+ * separately (Sec. IV, the "naive successive application", O(n 3^n)):
+ *     per(A[S]) = (-1)^|S| sum_{T subset of S} (-1)^|T| prod_{i in S} sum_{j in T} A_ij.
+ * Reading: the printed Eq. (ryser) lacks the overall (-1)^n; with it the
+ * formula gives per = 1 for the 1x1 matrix [1] and k! for the all-ones k x k
+ * matrix, as it must.  out[0] = 1 (empty product, T = S = empty). */
+int apm_oracle_perm_minors(int n, const double *A, double *out)
+{
+    if (n < 0 || n > ORACLE_MAX_N) return -1;
+    const uint32_t nm = 1u << n;
+    for (uint32_t S = 0; S < nm; ++S) {
+        double total = 0.0;
+        uint32_t T = S;
+        for (;;) {
+            double prod = 1.0;
+            for (int i = 0; i < n; ++i) {
+                if (!(S >> i & 1u)) continue;
+                double rs = 0.0;
+                for (int j = 0; j < n; ++j) if (T >> j & 1u) rs += A[i * n + j];
+                prod *= rs;
+            }
+#if ORACLE_PLANT == 5
+            int sgn = (popcount32(T) & 1) ? -1 : 1;
+#else
+            int sgn = ((popcount32(S) - popcount32(T)) & 1) ? -1 : 1;
+#endif
+            total += sgn * prod;
+            if (T == 0) break;
+            T = (T - 1) & S;
+        }
+        out[S] = total;
+    }
+    return 0;
+}
+
+/* ---- batched drivers (OpenMP over matrices; the per-matrix work is above) ---- */
+
+/* Matrix b has order n[b]; its input starts at element in_off[b] of A (for the
+ * complex kernels: complex element, i.e. 2 doubles each) and its 2^n[b]
+ * outputs start at element out_off[b] of out.  Returns 0, or -1 on a bad n. */
+typedef int (*oracle_fn)(int, const double *, double *);
+
+static int run_batch(oracle_fn fn, int width, int B, const int32_t *n, const int64_t *in_off,
+                     const int64_t *out_off, const double *A, double *out, int nthreads)
+{
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(| : bad)
+#endif
+    for (int b = 0; b < B; ++b) {
+        if (fn(n[b], A + (size_t)width * in_off[b], out + (size_t)width * out_off[b]) != 0) bad |= 1;
+    }
+    (void)nthreads;
+    return bad ? -1 : 0;
+}
+
+int apm_oracle_minors_r64_batch(int B, const int32_t *n, const int64_t *in_off, const int64_t *out_off,
+                                const double *A, double *out, int nthreads)
+{
+    return run_batch(apm_oracle_minors_r64, 1, B, n, in_off, out_off, A, out, nthreads);
+}
+
+int apm_oracle_minors_c128_batch(int B, const int32_t *n, const int64_t *in_off, const int64_t *out_off,
+                                 const double *A, double *out, int nthreads)
+{
+    return run_batch(apm_oracle_minors_c128, 2, B, n, in_off, out_off, A, out, nthreads);
+}
+
+int apm_oracle_perm_minors_batch(int B, const int32_t *n, const int64_t *in_off, const int64_t *out_off,
+                                 const double *A, double *out, int nthreads)
+{
+    return run_batch(apm_oracle_perm_minors, 1, B, n, in_off, out_off, A, out, nthreads);
+}
+
+int apm_oracle_connected_sums_batch(int B, const int32_t *n, const int64_t *off, const double *a,
+                                    double *c, int mode, int nthreads)
+{
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(| : bad)
+#endif
+    for (int b = 0; b < B; ++b) {
+        if (apm_oracle_connected_sums(n[b], a + off[b], c + off[b], mode) != 0) bad |= 1;
+    }
+    (void)nthreads;
+    return bad ? -1 : 0;
+}
+
+int apm_oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,423 @@
+"""Pins for the CPU oracle: facts fixed by the paper or by mathematics, not by the oracle.
+
+Each ``pin_*`` function takes the oracle functions to check (so that the same
+battery can run against deliberately broken builds) and raises AssertionError
+when the fact does not hold.  None of them re-types the oracle's formulas: they
+use closed forms, invariants, brute force over permutations or set partitions,
+independent library routines (numpy.linalg.det, numpy.poly) or mpmath at 40
+digits.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def submask_rows(m, n):
+    return [k for k in range(n) if m >> k & 1]
+
+
+def perm_sign(p):
+    p = list(p)
+    s = 1
+    seen = [False] * len(p)
+    for i in range(len(p)):
+        if seen[i]:
+            continue
+        j, L = i, 0
+        while not seen[j]:
+            seen[j] = True
+            j = p[j]
+            L += 1
+        if L % 2 == 0:
+            s = -s
+    return s
+
+
+def leibniz_det(M):
+    k = M.shape[0]
+    tot = 0.0
+    for p in itertools.permutations(range(k)):
+        prod = 1.0
+        for i in range(k):
+            prod = prod * M[i, p[i]]
+        tot = tot + perm_sign(p) * prod
+    return tot
+
+
+def brute_perm(M):
+    k = M.shape[0]
+    tot = 0.0
+    for p in itertools.permutations(range(k)):
+        prod = 1.0
+        for i in range(k):
+            prod *= M[i, p[i]]
+        tot += prod
+    return tot
+
+
+def set_partitions(items):
+    items = list(items)
+    if not items:
+        yield []
+        return
+    first, rest = items[0], items[1:]
+    for part in set_partitions(rest):
+        # put `first` in a new block or into an existing block
+        yield [[first]] + part
+        for i in range(len(part)):
+            yield part[:i] + [[first] + part[i]] + part[i + 1:]
+
+
+def close(a, b, rtol, atol=0.0):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.all(np.abs(a - b) <= atol + rtol * np.abs(b))
+
+
+# ----------------------------------------------------------------------------------
+# principal minors (Sec. II)
+# ----------------------------------------------------------------------------------
+def pin_minors_golden_mask(minors):
+    """Sec. II bit-mask example: mask 13 <-> rows {1,3,4} (1-based)."""
+    g = json.load(open(os.path.join(GOLDEN, "mask_convention.json")))
+    A = _rng(11).standard_normal((5, 5))
+    out = minors(A)
+    rows = g["rows_0based"]
+    assert [r + 1 for r in rows] == g["rows_1based"]
+    assert submask_rows(g["mask"], 5) == rows
+    ref = leibniz_det(A[np.ix_(rows, rows)])
+    assert abs(out[g["mask"]] - ref) <= 1e-13 * max(1.0, abs(ref)), (out[g["mask"]], ref)
+
+
+def pin_minors_empty_and_diag(minors):
+    A = _rng(1).standard_normal((6, 6))
+    out = minors(A)
+    assert out[0] == 1.0
+    for k in range(6):
+        assert out[1 << k] == A[k, k]
+
+
+def pin_minors_triangular(minors):
+    rng = _rng(2)
+    A = np.triu(rng.standard_normal((7, 7))) + 2.0 * np.eye(7)
+    for M in (A, A.T.copy()):
+        out = minors(M)
+        d = np.diag(M)
+        ref = np.array([np.prod(d[submask_rows(m, 7)]) for m in range(1 << 7)])
+        assert close(out, ref, 1e-13), np.max(np.abs(out - ref))
+
+
+def pin_minors_leibniz(minors):
+    rng = _rng(3)
+    for n in (1, 2, 3, 4, 5, 6):
+        A = rng.standard_normal((n, n))
+        out = minors(A)
+        for m in range(1 << n):
+            r = submask_rows(m, n)
+            ref = leibniz_det(A[np.ix_(r, r)]) if r else 1.0
+            assert abs(out[m] - ref) <= 1e-12 * max(1.0, abs(ref)), (n, m, out[m], ref)
+
+
+def pin_minors_det_I_plus_A(minors):
+    """sum_S det A[S] = det(I + A) (expansion of det(I+A) by multilinearity)."""
+    rng = _rng(4)
+    for n in (3, 8, 11):
+        A = rng.standard_normal((n, n)) / np.sqrt(n)
+        out = minors(A)
+        ref = np.linalg.det(np.eye(n) + A)
+        assert abs(out.sum() - ref) <= 1e-10 * max(1.0, np.abs(out).sum()), (n, out.sum(), ref)
+
+
+def pin_minors_charpoly(minors):
+    """Sum of the k x k principal minors = k-th coefficient of det(lambda I + A)."""
+    rng = _rng(5)
+    n = 9
+    A = rng.standard_normal((n, n))
+    out = minors(A)
+    pc = np.poly(A)            # det(lambda I - A) = sum_k pc[k] lambda^(n-k)
+    sizes = np.array([bin(m).count("1") for m in range(1 << n)])
+    for k in range(n + 1):
+        ek = out[sizes == k].sum()
+        ref = (-1) ** k * pc[k]
+        assert abs(ek - ref) <= 1e-9 * max(1.0, abs(ref)), (k, ek, ref)
+
+
+def pin_minors_invariances(minors):
+    rng = _rng(6)
+    n = 8
+    A = rng.standard_normal((n, n))
+    out = minors(A)
+    d = np.exp(rng.standard_normal(n))
+    assert close(minors(A.T.copy()), out, 1e-12, 1e-13)
+    assert close(minors((d[:, None] * A) / d[None, :]), out, 1e-11, 1e-13)
+    alpha = -1.7
+    sizes = np.array([bin(m).count("1") for m in range(1 << n)])
+    assert close(minors(alpha * A), out * alpha ** sizes, 1e-12, 1e-13)
+
+
+def pin_minors_block_diag(minors):
+    rng = _rng(7)
+    A1 = rng.standard_normal((3, 3))
+    A2 = rng.standard_normal((4, 4))
+    A = np.zeros((7, 7))
+    A[:3, :3] = A1
+    A[3:, 3:] = A2
+    out = minors(A)
+    o1 = minors(A1)
+    o2 = minors(A2)
+    ref = np.array([o1[m & 7] * o2[m >> 3] for m in range(1 << 7)])
+    assert close(out, ref, 1e-12, 1e-14)
+
+
+def pin_minors_mpmath_near_singular(minors):
+    """Near-singular submatrix: compare with 40-digit determinants (mpmath)."""
+    import mpmath
+    mpmath.mp.dps = 40
+    rng = _rng(8)
+    n = 7
+    A = rng.standard_normal((n, n))
+    # make A[{0,2,5}] nearly singular: third row = combination of the first two + 1e-11
+    A[5, [0, 2, 5]] = 0.3 * A[0, [0, 2, 5]] - 1.1 * A[2, [0, 2, 5]]
+    A[5, 5] += 1e-11
+    out = minors(A)
+    for m in range(1 << n):
+        r = submask_rows(m, n)
+        if not r:
+            continue
+        M = mpmath.matrix([[mpmath.mpf(float(A[i, j])) for j in r] for i in r])
+        ref = float(mpmath.det(M))
+        scale = float(np.prod([np.linalg.norm(A[i, r]) for i in r]))   # Hadamard bound
+        assert abs(out[m] - ref) <= 1e-13 * scale, (m, out[m], ref, scale)
+
+
+MINOR_PINS = [pin_minors_golden_mask, pin_minors_empty_and_diag, pin_minors_triangular,
+              pin_minors_leibniz, pin_minors_det_I_plus_A, pin_minors_charpoly,
+              pin_minors_invariances, pin_minors_block_diag, pin_minors_mpmath_near_singular]
+
+
+# ----------------------------------------------------------------------------------
+# complex minors (Sec. V.C)
+# ----------------------------------------------------------------------------------
+def pin_cminors_leibniz(cminors):
+    rng = _rng(21)
+    for n in (1, 2, 3, 4, 5):
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        out = cminors(A)
+        for m in range(1 << n):
+            r = submask_rows(m, n)
+            ref = leibniz_det(A[np.ix_(r, r)]) if r else 1.0
+            assert abs(out[m] - ref) <= 1e-12 * max(1.0, abs(ref)), (n, m, out[m], ref)
+
+
+def pin_cminors_hermitian_pd(cminors):
+    """Hermitian positive-definite => every principal minor is real and positive."""
+    rng = _rng(22)
+    n = 8
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    H = X @ X.conj().T + 0.5 * np.eye(n)
+    out = cminors(H)
+    assert np.all(out.real > 0)
+    assert np.all(np.abs(out.imag) <= 1e-12 * np.abs(out.real))
+
+
+def pin_cminors_det_I_plus_A(cminors):
+    rng = _rng(23)
+    n = 9
+    A = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    out = cminors(A)
+    ref = np.linalg.det(np.eye(n) + A)
+    assert abs(out.sum() - ref) <= 1e-10 * max(1.0, np.abs(out).sum())
+
+
+def pin_cminors_conjugate(cminors):
+    rng = _rng(24)
+    n = 6
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    assert close(cminors(A.conj()), np.conj(cminors(A)), 1e-12, 1e-13)
+
+
+CMINOR_PINS = [pin_cminors_leibniz, pin_cminors_hermitian_pd, pin_cminors_det_I_plus_A,
+               pin_cminors_conjugate]
+
+
+# ----------------------------------------------------------------------------------
+# connected sums (Sec. V.A, Eq. (recursion))
+# ----------------------------------------------------------------------------------
+def _sizes(n):
+    return np.array([bin(m).count("1") for m in range(1 << n)])
+
+
+def pin_cs_factorial(cs):
+    """a[S] = |S|!  =>  c[S] = (|S|-1)!  (number of permutations vs. number of cycles)."""
+    n = 7
+    sz = _sizes(n)
+    a = np.array([math.factorial(k) for k in sz], dtype=np.float64)
+    for mode in (0, 1):
+        c = cs(a, mode)
+        for m in range(1, 1 << n):
+            if mode == 0 and not (m & 1):
+                assert c[m] == 0.0
+                continue
+            assert c[m] == math.factorial(sz[m] - 1), (mode, m, c[m])
+
+
+def pin_cs_diagonal(cs):
+    """Multiplicative weights (diagonal M, a = prod d_i^2): c = 0 for |S| >= 2, c[{i}] = a[{i}]."""
+    n = 8
+    d = _rng(31).standard_normal(n)
+    a = np.array([np.prod(d[submask_rows(m, n)] ** 2) for m in range(1 << n)])
+    c = cs(a, 1)
+    sz = _sizes(n)
+    for m in range(1, 1 << n):
+        if sz[m] == 1:
+            assert c[m] == a[m]
+        else:
+            assert abs(c[m]) <= 1e-13 * max(1.0, np.abs(a).max()), (m, c[m])
+
+
+def pin_cs_block_diag(cs):
+    """Block-diagonal M: a factorises across blocks, so c vanishes on sets meeting both."""
+    rng = _rng(32)
+    n1, n2 = 3, 4
+    n = n1 + n2
+    A = np.zeros((n, n))
+    A[:n1, :n1] = rng.standard_normal((n1, n1))
+    A[n1:, n1:] = rng.standard_normal((n2, n2))
+    a = np.array([leibniz_det(A[np.ix_(r, r)]) ** 2 if r else 1.0
+                  for r in (submask_rows(m, n) for m in range(1 << n))])
+    for mode in (0, 1):
+        c = cs(a, mode)
+        for m in range(1, 1 << n):
+            if (m & ((1 << n1) - 1)) and (m >> n1):
+                assert abs(c[m]) <= 1e-12 * max(1.0, abs(a[m])), (mode, m, c[m])
+
+
+def pin_cs_exponential_formula(cs):
+    """a[S] = sum over set partitions of S of prod_B c[B] (c from mode 1)."""
+    n = 6
+    a = np.empty(1 << n)
+    rng = _rng(33)
+    a[1:] = rng.standard_normal((1 << n) - 1)
+    a[0] = 1.0
+    c = cs(a, 1)
+    for m in range(1, 1 << n):
+        tot = 0.0
+        for part in set_partitions(submask_rows(m, n)):
+            prod = 1.0
+            for blk in part:
+                prod *= c[sum(1 << i for i in blk)]
+            tot += prod
+        assert abs(tot - a[m]) <= 1e-12 * max(1.0, np.abs(a).max()), (m, tot, a[m])
+
+
+def pin_cs_root_independence(cs):
+    """Any choice of the distinguished vertex gives the same c (Sec. V.A): relabel
+    vertices in reverse so that 'lowest vertex' becomes 'highest vertex'."""
+    n = 8
+    rng = _rng(34)
+    a = rng.standard_normal(1 << n)
+    rev = np.array([int(format(m, f"0{n}b")[::-1], 2) for m in range(1 << n)])
+    c = cs(a, 1)
+    c_rev = cs(a[rev], 1)[rev]
+    assert close(c_rev, c, 1e-10, 1e-12)
+
+
+def pin_cs_single_det_cycles(cs):
+    """a = det M (one determinant): c[S] = (-1)^(|S|-1) * sum over cyclic permutations
+    of S of prod M_{i sigma(i)} (connected permutation diagrams are single cycles)."""
+    n = 6
+    M = _rng(35).standard_normal((n, n))
+    a = np.array([leibniz_det(M[np.ix_(r, r)]) if r else 1.0
+                  for r in (submask_rows(m, n) for m in range(1 << n))])
+    c = cs(a, 1)
+    for m in range(1, 1 << n):
+        r = submask_rows(m, n)
+        k = len(r)
+        tot = 0.0
+        for p in itertools.permutations(range(k)):
+            # single k-cycle?
+            j, L = 0, 0
+            while True:
+                j = p[j]
+                L += 1
+                if j == 0:
+                    break
+            if L != k:
+                continue
+            prod = 1.0
+            for i in range(k):
+                prod *= M[r[i], r[p[i]]]
+            tot += prod
+        ref = (-1) ** (k - 1) * tot
+        assert abs(c[m] - ref) <= 1e-12 * max(1.0, abs(ref)), (m, c[m], ref)
+
+
+CS_PINS = [pin_cs_factorial, pin_cs_diagonal, pin_cs_block_diag, pin_cs_exponential_formula,
+           pin_cs_root_independence, pin_cs_single_det_cycles]
+
+
+# ----------------------------------------------------------------------------------
+# permanent principal minors (Sec. IV)
+# ----------------------------------------------------------------------------------
+def pin_perm_all_ones(perm):
+    n = 7
+    out = perm(np.ones((n, n)))
+    for m in range(1 << n):
+        assert out[m] == math.factorial(bin(m).count("1")), (m, out[m])
+
+
+def pin_perm_diagonal(perm):
+    d = _rng(41).standard_normal(6)
+    out = perm(np.diag(d))
+    for m in range(1 << 6):
+        ref = np.prod(d[submask_rows(m, 6)])
+        assert abs(out[m] - ref) <= 1e-14 * max(1.0, abs(ref))
+
+
+def pin_perm_bruteforce(perm):
+    rng = _rng(42)
+    for n in (1, 2, 3, 5, 6):
+        A = rng.standard_normal((n, n))
+        out = perm(A)
+        for m in range(1 << n):
+            r = submask_rows(m, n)
+            ref = brute_perm(A[np.ix_(r, r)]) if r else 1.0
+            assert abs(out[m] - ref) <= 1e-12 * max(1.0, abs(ref)), (n, m, out[m], ref)
+
+
+def pin_perm_I_plus_A(perm):
+    """sum_S per A[S] = per(I + A)."""
+    n = 7
+    A = _rng(43).standard_normal((n, n)) / np.sqrt(n)
+    out = perm(A)
+    ref = brute_perm(np.eye(n) + A)
+    assert abs(out.sum() - ref) <= 1e-11 * max(1.0, np.abs(out).sum()), (out.sum(), ref)
+
+
+def pin_perm_invariances(perm):
+    n = 6
+    rng = _rng(44)
+    A = rng.standard_normal((n, n))
+    out = perm(A)
+    assert close(perm(A.T.copy()), out, 1e-12, 1e-13)
+    p = rng.permutation(n)
+    P = A[np.ix_(p, p)]
+    outp = perm(P)
+    # mask m of P <-> mask with bits p[k] of A
+    mp = np.array([sum(1 << int(p[k]) for k in submask_rows(m, n)) for m in range(1 << n)])
+    assert close(outp, out[mp], 1e-12, 1e-13)
+
+
+PERM_PINS = [pin_perm_all_ones, pin_perm_diagonal, pin_perm_bruteforce, pin_perm_I_plus_A,
+             pin_perm_invariances]

@@ -1,0 +1,42 @@
+"""The pins have power: each plausible mistake planted in the oracle (a wrong sign,
+index or operand; a dropped term) makes at least one pin fail.  Planted variants
+are built from the oracle's own source on the CPU with -DORACLE_PLANT=k."""
+import os
+import tempfile
+
+import pytest
+
+import oracle_pins as P
+
+PLANTS = {
+    1: ("minors", "row-swap sign dropped"),
+    2: ("minors", "transposed operand in the elimination update"),
+    3: ("cs", "a[T] used instead of a[S \\ T]"),
+    4: ("cs", "extra term: root singleton counted twice"),
+    5: ("perm", "Ryser sign without the (-1)^|S| factor"),
+    6: ("cminors", "conjugated quotient in the complex elimination"),
+}
+
+
+@pytest.mark.parametrize("plant", sorted(PLANTS))
+def test_planted_mistake_is_caught(oracle_mod, plant):
+    kind, what = PLANTS[plant]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, f"liboracle_plant{plant}.so")
+        oracle_mod.build(force=True, path=path, plant=plant)
+        lib = oracle_mod.load_library(path)
+        if kind == "minors":
+            fn, pins = (lambda A: oracle_mod.minors(A, lib=lib)), P.MINOR_PINS
+        elif kind == "cminors":
+            fn, pins = (lambda A: oracle_mod.minors_complex(A, lib=lib)), P.CMINOR_PINS
+        elif kind == "cs":
+            fn, pins = (lambda a, mode: oracle_mod.connected_sums(a, mode, lib=lib)), P.CS_PINS
+        else:
+            fn, pins = (lambda A: oracle_mod.perm_minors(A, lib=lib)), P.PERM_PINS
+        failed = []
+        for pin in pins:
+            try:
+                pin(fn)
+            except AssertionError:
+                failed.append(pin.__name__)
+        assert failed, f"no pin caught planted mistake {plant}: {what}"
