@@ -1,0 +1,157 @@
+/*
+ * apm.h -- C ABI of libapm.so: all principal minors, CDet connected sums and
+ * permanent principal minors of batches of small matrices on AMD MI355X (gfx950).
+ *
+ * Source of the operations: Simkovic & Ferrero, "Fast Principal Minor
+ * Algorithms for Quantum Many Body Systems", arXiv:2104.07638.
+ *
+ * Common conventions
+ *   - Subsets of {0..n-1} are integer masks; bit k set <=> row/column k kept
+ *     (the paper's Sec. II convention S_13 = {1,3,4}, shifted to 0-based rows).
+ *     Every output array of a matrix of order n has 2^n entries in mask order.
+ *   - Matrices are dense row-major; complex values are interleaved (re, im) pairs
+ *     (the layout of torch.complex128 / complex64 and C99 _Complex double).
+ *   - Pointers inside apm_batch and every data pointer are DEVICE pointers unless
+ *     stated otherwise; the caller owns all of them.  The library owns only its
+ *     small internal workspaces (queue counters), allocated on first use per device.
+ *   - Calls are asynchronous: arguments are validated on the host, work is
+ *     enqueued on `stream`, and the call returns.  Results are valid once the
+ *     stream has been synchronised.  Argument errors return before anything is
+ *     enqueued.  No call aborts, prints, or throws across the ABI.
+ *   - Calls are reentrant; calls that write the same buffers must be ordered by
+ *     the caller (same stream or events).
+ */
+#ifndef APM_H
+#define APM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    APM_OK = 0,
+    APM_EINVAL = 1,          /* bad argument (null pointer, bad size, bad enum)        */
+    APM_EUNSUPPORTED = 2,    /* valid request outside what this build implements       */
+    APM_EDEVICE = 3,         /* a HIP call failed (launch error, no device)           */
+    APM_ENOMEM = 4           /* internal workspace allocation failed                  */
+} apm_status;
+
+typedef enum {
+    APM_R64 = 0,    /* real fp64 in, fp64 Schur updates, fp64 out                              */
+    APM_R32S = 1,   /* real fp64 in, fp32 Schur updates with fp64 pivot division/test/shift,
+                       output float mantissa + int16 exponent (or fp64 with APM_OUT_F64)       */
+    APM_C128 = 2,   /* complex128 in/out (Sec. V.C matrices are complex)                       */
+    APM_C64S = 3    /* complex128 in, complex64 updates, fp64 pivot handling, output complex64
+                       mantissa + int16 exponent (or complex128 with APM_OUT_F64)              */
+} apm_dtype;
+
+#define APM_MAX_N 20          /* largest matrix order accepted by apm_all_minors          */
+#define APM_MAX_N_CS 20       /* largest order accepted by apm_connected_sums             */
+#define APM_MAX_N_PERM 16     /* largest order accepted by apm_all_perm_minors            */
+
+/* opaque HIP stream (binary compatible with hipStream_t); NULL = the default stream */
+typedef struct ihipStream_t *apm_stream;
+
+/* Batch descriptor (host struct; the arrays it points to are device arrays). */
+typedef struct {
+    int32_t batch;            /* number of matrices B >= 0; B == 0 is a no-op              */
+    int32_t n_uniform;        /* > 0: every matrix has this order; 0: orders in n[]       */
+    const int32_t *n;         /* [B] per-matrix orders in [1, max] (only if n_uniform==0) */
+    int32_t n_max;            /* with n[]: an upper bound of n[] (0 = the maximum)        */
+    const int64_t *in_off;    /* [B] element offset of matrix b; NULL = packed b*n*n
+                                 (ragged batches: NULL = packed prefix sums of n_b^2)      */
+    const int64_t *out_off;   /* [B] element offset of the 2^n_b outputs of b; NULL =
+                                 packed b*2^n (ragged: prefix sums of 2^n_b)              */
+} apm_batch;
+
+/* Options (NULL = defaults).
+ * Pivot shift (Sec. II, pivot correction; the paper leaves the test and C open):
+ * at a tree node with pivot p, largest row entry r = max_j |M_0j| and largest column
+ * entry c = max_i |M_i0| of the node's matrix (|z| = max(|Re z|, |Im z|) for complex),
+ * p is shifted to p + C when |p|^2 < piv_tol^2 * r * c or p == 0, with C the power of
+ * two just below sqrt(r c) (s = max_ij |A_ij| when r c == 0).  The test is invariant
+ * under diagonal similarity, as the minors are. */
+typedef struct {
+    double piv_tol;           /* <= 0: default 1e-3 (R64, C128) or 1e-2 (R32S, C64S)      */
+    uint32_t flags;           /* APM_OUT_F64 | APM_NO_PERTURB                             */
+} apm_opts;
+
+#define APM_OUT_F64 1u        /* R32S/C64S: write fp64/complex128 values, no exponents     */
+#define APM_NO_PERTURB 2u     /* never shift pivots (a zero pivot then yields non-finite
+                                 minors in its right subtree, reported as info = -3)       */
+
+/*
+ * apm_all_minors -- all 2^n principal minors det(A[S]) of every matrix of the batch.
+ *
+ * Passage: Sec. II (problem statement; det of the empty matrix = 1; the Schur-
+ * complement binary tree, Eqs. (dets_schur), (eq:schur), (lemma1), (lemma2),
+ * (eq:minor), Algorithm 1, its depth-first traversal, and the pivot correction
+ * det A[S] = det A~[S] - C det A[S \ {l}]).
+ *
+ *   dt      element type / precision variant (apm_dtype).
+ *   A       input matrices: double (R64, R32S) or complex128 (C128, C64S).
+ *   bd      batch descriptor (host pointer, must not be NULL).
+ *   minors  output: B x 2^n values in mask order, minors[0] = 1:
+ *             R64: double;  C128: complex128;
+ *             R32S: float mantissa m (|m| in [0.5,1) or 0) with value m * 2^exp;
+ *             C64S: complex64 mantissa (max(|re|,|im|) in [0.5,1) or 0), same exp;
+ *             with APM_OUT_F64 the two scaled variants write double / complex128.
+ *   exp     int16 exponents, same indexing as minors; required for R32S/C64S without
+ *           APM_OUT_F64, must be NULL otherwise.
+ *   info    [B] int32 or NULL: >= 0 number of shifted pivots of matrix b;
+ *           -2 non-finite input (outputs set to NaN); -3 a non-finite output.
+ *   opt     options or NULL.
+ * Returns APM_OK, APM_EINVAL (bad argument), APM_EUNSUPPORTED (n > APM_MAX_N), or
+ * APM_EDEVICE (launch failure).
+ */
+apm_status apm_all_minors(apm_dtype dt, const void *A, const apm_batch *bd, void *minors, int16_t *exp,
+                          int32_t *info, const apm_opts *opt, apm_stream stream);
+
+#define APM_CS_ROOTED 0u      /* distinguished vertex j = 0; c[S] = 0 for S not containing 0 */
+#define APM_CS_ALL 1u         /* j = lowest vertex of S; c[S] for every nonempty S           */
+
+/*
+ * apm_connected_sums -- CDet connected sums from subset weights.
+ *
+ * Passage: Sec. V.A, the weights a[S] = det M_up[S] det M_dn[S] and Eq. (recursion)
+ *     c[S] = a[S] - sum_{T subsetneq S, j in T} c[T] a[S \ T].
+ *
+ *   m_up    [B x 2^n] fp64 minors of M_up (mask order), e.g. apm_all_minors output.
+ *   m_dn    [B x 2^n] fp64 minors of M_dn, or NULL for m_dn = m_up (a = m_up^2).
+ *           With APM_CS_WEIGHTS in mode, m_up already holds a[] and m_dn must be NULL.
+ *   bd      batch descriptor; in_off/out_off (if given) index both m_* and c.
+ *   c       [B x 2^n] fp64 output; c[empty] = 0.
+ *   mode    APM_CS_ROOTED or APM_CS_ALL, optionally | APM_CS_WEIGHTS.
+ * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED (n > APM_MAX_N_CS) or APM_EDEVICE.
+ */
+#define APM_CS_WEIGHTS 2u
+apm_status apm_connected_sums(const double *m_up, const double *m_dn, const apm_batch *bd, double *c,
+                              uint32_t mode, apm_stream stream);
+
+/*
+ * apm_all_perm_minors -- all 2^n permanent principal minors per(A[S]).
+ *
+ * Passage: Sec. IV (Ryser's formula, its per-subset form and the division-free
+ * product recursion over subsets, O(3^n)).  Real fp64 only.
+ *
+ *   A       [B x n x n] fp64 input;  perm  [B x 2^n] fp64 output, perm[0] = 1.
+ * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED (n > APM_MAX_N_PERM) or APM_EDEVICE.
+ */
+apm_status apm_all_perm_minors(const double *A, const apm_batch *bd, double *perm, apm_stream stream);
+
+/* Human-readable name of a status code (static string). */
+const char *apm_status_str(apm_status s);
+
+/* The last HIP error seen by the library on this thread, as a HIP error code (0 = none). */
+int apm_last_hip_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int apm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APM_H */

@@ -139,6 +139,24 @@ int apm_oracle_minors_r64(int n, const double *A, double *out)
     return 0;
 }
 
+/* The same definition evaluated only at the listed masks (for parity checks of
+ * large orders, where all 2^n LU factorisations would take too long). */
+int apm_oracle_minors_r64_masks(int n, const double *A, int count, const uint32_t *masks, double *out)
+{
+    if (n < 0 || n > ORACLE_MAX_N) return -1;
+    double sub[ORACLE_MAX_N * ORACLE_MAX_N];
+    int idx[ORACLE_MAX_N];
+    for (int t = 0; t < count; ++t) {
+        uint32_t m = masks[t];
+        int k = 0;
+        for (int i = 0; i < n; ++i) if (m >> i & 1u) idx[k++] = i;
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) sub[a * k + b] = A[idx[a] * n + idx[b]];
+        out[t] = det_real_inplace(k, sub);
+    }
+    return 0;
+}
+
 /* Complex128 version (Sec. V.C: Keldysh matrices have complex entries). */
 int apm_oracle_minors_c128(int n, const double *A, double *out)
 {

@@ -1,0 +1,169 @@
+// api.hip -- the C ABI of libapm.so: argument validation, workspaces, launches.
+#include <math.h>
+#include <mutex>
+#include <vector>
+
+#include "../../include/apm.h"
+#include "apm_kernels.h"
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+apm_status from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return APM_OK;
+    g_last_hip_error = (int)e;
+    if (e == hipErrorOutOfMemory) return APM_ENOMEM;
+    return APM_EDEVICE;
+}
+
+// Per-device workspace for ragged batches: the queue order array and its head counter.
+struct Workspace {
+    int32_t* buf = nullptr;     // [cap + 64]: counter at buf[0], order at buf[64...]
+    int64_t cap = 0;
+    int cus = 0;
+};
+
+std::mutex g_ws_mu;
+std::vector<Workspace> g_ws;
+
+apm_status get_workspace(int64_t batch, int32_t** counter, int32_t** order, int* cus)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    Workspace& w = g_ws[dev];
+    if (w.cus == 0) {
+        int v = 0;
+        e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return from_hip(e);
+        w.cus = v;
+    }
+    if (w.cap < batch) {
+        if (w.buf) (void)hipFree(w.buf);
+        w.buf = nullptr;
+        int64_t cap = batch < 4096 ? 4096 : batch;
+        e = hipMalloc((void**)&w.buf, sizeof(int32_t) * (size_t)(cap + 64));
+        if (e != hipSuccess) { w.cap = 0; return from_hip(e); }
+        w.cap = cap;
+    }
+    *counter = w.buf;
+    *order = w.buf + 64;
+    *cus = w.cus;
+    return APM_OK;
+}
+
+bool bad_batch(const apm_batch* bd, int nmax)
+{
+    if (!bd || bd->batch < 0) return true;
+    if (bd->n_uniform < 0) return true;
+    if (bd->n_uniform == 0 && bd->batch > 0 && !bd->n) return true;
+    if (bd->n_uniform == 0 && (bd->n_max < 0)) return true;
+    (void)nmax;
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* apm_status_str(apm_status s)
+{
+    switch (s) {
+    case APM_OK: return "APM_OK";
+    case APM_EINVAL: return "APM_EINVAL: invalid argument";
+    case APM_EUNSUPPORTED: return "APM_EUNSUPPORTED: unsupported size or variant";
+    case APM_EDEVICE: return "APM_EDEVICE: HIP error";
+    case APM_ENOMEM: return "APM_ENOMEM: device allocation failed";
+    default: return "APM_?: unknown status";
+    }
+}
+
+int apm_last_hip_error(void) { return g_last_hip_error; }
+
+int apm_version(void) { return 100; }
+
+apm_status apm_all_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* minors, int16_t* exp,
+                          int32_t* info, const apm_opts* opt, apm_stream stream)
+{
+    if ((int)dt < 0 || (int)dt > 3) return APM_EINVAL;
+    if (bad_batch(bd, APM_MAX_N)) return APM_EINVAL;
+    const bool scaled = (dt == APM_R32S || dt == APM_C64S);
+    const uint32_t flags = opt ? opt->flags : 0u;
+    if (flags & ~(APM_OUT_F64 | APM_NO_PERTURB)) return APM_EINVAL;
+    const bool out_f64 = (flags & APM_OUT_F64) != 0;
+    if (opt && !isfinite(opt->piv_tol)) return APM_EINVAL;
+    if (bd->n_uniform > APM_MAX_N || bd->n_max > APM_MAX_N) return APM_EUNSUPPORTED;
+    if (bd->batch == 0) return APM_OK;
+    if (!A || !minors) return APM_EINVAL;
+    if (scaled && !out_f64 && !exp) return APM_EINVAL;
+    if ((!scaled || out_f64) && exp) return APM_EINVAL;
+
+    apm::LaunchMinors L{};
+    L.dtype = (int)dt;
+    L.A = A;
+    L.out = minors;
+    L.ex = exp;
+    L.info = info;
+    L.batch = bd->batch;
+    L.n_uniform = bd->n_uniform;
+    L.n = bd->n;
+    L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N;
+    L.in_off = bd->in_off;
+    L.out_off = bd->out_off;
+    const double tau_def = scaled ? 1e-2 : 1e-3;
+    L.tau = (opt && opt->piv_tol > 0) ? opt->piv_tol : tau_def;
+    L.perturb = !(flags & APM_NO_PERTURB);
+    L.out_f64 = out_f64;
+    if (bd->n_uniform == 0) {
+        apm_status s = get_workspace(bd->batch, &L.counter, &L.order, &L.n_workers);
+        if (s != APM_OK) return s;
+    }
+    return from_hip(apm::fpm_launch(L, (hipStream_t)stream));
+}
+
+apm_status apm_connected_sums(const double* m_up, const double* m_dn, const apm_batch* bd, double* c,
+                              uint32_t mode, apm_stream stream)
+{
+    if (bad_batch(bd, APM_MAX_N_CS)) return APM_EINVAL;
+    if (mode & ~(APM_CS_ALL | APM_CS_WEIGHTS)) return APM_EINVAL;
+    if ((mode & APM_CS_WEIGHTS) && m_dn) return APM_EINVAL;
+    if (bd->n_uniform > APM_MAX_N_CS || bd->n_max > APM_MAX_N_CS) return APM_EUNSUPPORTED;
+    if (bd->in_off != bd->out_off) return APM_EINVAL;   // one offset array indexes inputs and output
+    if (bd->batch == 0) return APM_OK;
+    if (!m_up || !c) return APM_EINVAL;
+    apm::LaunchCS L{};
+    L.m_up = m_up;
+    L.m_dn = m_dn;
+    L.c = c;
+    L.batch = bd->batch;
+    L.n_uniform = bd->n_uniform;
+    L.n = bd->n;
+    L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N_CS;
+    L.off = bd->out_off;
+    L.mode = mode;
+    return from_hip(apm::cs_launch(L, (hipStream_t)stream));
+}
+
+apm_status apm_all_perm_minors(const double* A, const apm_batch* bd, double* perm, apm_stream stream)
+{
+    if (bad_batch(bd, APM_MAX_N_PERM)) return APM_EINVAL;
+    if (bd->n_uniform > APM_MAX_N_PERM || bd->n_max > APM_MAX_N_PERM) return APM_EUNSUPPORTED;
+    if (bd->batch == 0) return APM_OK;
+    if (!A || !perm) return APM_EINVAL;
+    apm::LaunchPerm L{};
+    L.A = A;
+    L.out = perm;
+    L.batch = bd->batch;
+    L.n_uniform = bd->n_uniform;
+    L.n = bd->n;
+    L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N_PERM;
+    L.in_off = bd->in_off;
+    L.out_off = bd->out_off;
+    return from_hip(apm::perm_launch(L, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,307 @@
+// apm_device.h -- scalar "fields" and wave-level helpers shared by the gfx950 kernels.
+//
+// A field bundles the arithmetic one variant of the principal-minor tree needs:
+//   E   matrix element type held in LDS and registers (the Schur updates run in E)
+//   R   type of the pivot reciprocal (fp64 in every variant: the pivot division,
+//       the near-zero test and the shift stay in fp64, also on the fp32 paths)
+//   Bs  running product of pivots ("base" of a tree node: the minor of its kept set)
+//   V   value type in true units used by the post-order pivot corrections
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apm {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p ? 1 : 0); }
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// 1/x in fp64: hardware reciprocal estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+struct cd { double x, y; };
+struct cf { float x, y; };
+
+__device__ __forceinline__ cd operator*(cd a, cd b) { return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)}; }
+__device__ __forceinline__ cd operator-(cd a, cd b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cd operator*(double s, cd a) { return {s * a.x, s * a.y}; }
+
+// running product with a separate binary exponent: value = m * 2^e, |m| in [0.5, 1) or m == 0
+struct SBr { float m; int e; };
+struct SBc { cf m; int e; };
+
+// ------------------------------------------------------------------------------- R64
+struct FR64 {
+    using In = double;
+    using E = double;
+    using R = double;
+    using Bs = double;
+    using V = double;
+    static constexpr bool kScaled = false;
+    static constexpr bool kComplex = false;
+    __device__ static double in_mag(In v) { return fabs(v); }
+    __device__ static bool in_finite(In v) { return isfinite(v); }
+    __device__ static E conv(In v, double sc) { return v; }
+    __device__ static double mag(E p) { return fabs(p); }
+    __device__ static E shift(E p, double C) { return p + C; }
+    __device__ static R recip(E p) { return rcp64(p); }
+    __device__ static E rowscale(E v, R r) { return v * r; }
+    __device__ static E zero() { return 0.0; }
+    __device__ static E upd(E a, E c, E w) { return fma(-c, w, a); }
+    __device__ static Bs one() { return 1.0; }
+    __device__ static Bs bmul(Bs b, E p, int) { return b * p; }
+    __device__ static void store(void* out, int16_t*, int64_t i, Bs v, bool)
+    {
+        static_cast<double*>(out)[i] = v;
+    }
+    __device__ static double fincheck(Bs v) { return v * 0.0; }
+    __device__ static V load_v(const void* out, const int16_t*, int64_t i, bool)
+    {
+        return __builtin_nontemporal_load(static_cast<const double*>(out) + i);
+    }
+    __device__ static void store_v(void* out, int16_t*, int64_t i, V v, bool)
+    {
+        static_cast<double*>(out)[i] = v;
+    }
+    __device__ static V sub_scaled(V a, double C, V b) { return fma(-C, b, a); }
+    __device__ static void store_nan(void* out, int16_t*, int64_t i, bool)
+    {
+        static_cast<double*>(out)[i] = __builtin_nan("");
+    }
+};
+
+// ------------------------------------------------------------------------------- R32S
+// fp32 Schur updates, fp64 pivot reciprocal/test/shift, float mantissa + int exponent product.
+struct FR32S {
+    using In = double;
+    using E = float;
+    using R = double;
+    using Bs = SBr;
+    using V = double;
+    static constexpr bool kScaled = true;
+    static constexpr bool kComplex = false;
+    __device__ static double in_mag(In v) { return fabs(v); }
+    __device__ static bool in_finite(In v) { return isfinite(v); }
+    __device__ static E conv(In v, double sc) { return (float)(v * sc); }
+    __device__ static double mag(E p) { return fabs((double)p); }
+    __device__ static E shift(E p, double C) { return (float)((double)p + C); }
+    __device__ static R recip(E p) { return rcp64((double)p); }
+    __device__ static E rowscale(E v, R r) { return (float)((double)v * r); }
+    __device__ static E zero() { return 0.0f; }
+    __device__ static E upd(E a, E c, E w) { return fmaf(-c, w, a); }
+    __device__ static Bs one() { return {0.5f, 1}; }
+    __device__ static Bs bmul(Bs b, E p, int e0)
+    {
+        float m = b.m * p;
+        int ee;
+        m = frexpf(m, &ee);
+        return {m, b.e + ee + e0};
+    }
+    __device__ static void store(void* out, int16_t* ex, int64_t i, Bs v, bool f64)
+    {
+        if (f64) {
+            static_cast<double*>(out)[i] = ldexp((double)v.m, v.e);
+        } else {
+            static_cast<float*>(out)[i] = v.m;
+            ex[i] = (int16_t)v.e;
+        }
+    }
+    __device__ static float fincheck(Bs v) { return v.m * 0.0f; }
+    __device__ static V load_v(const void* out, const int16_t* ex, int64_t i, bool f64)
+    {
+        if (f64) return __builtin_nontemporal_load(static_cast<const double*>(out) + i);
+        float m = __builtin_nontemporal_load(static_cast<const float*>(out) + i);
+        int16_t e = __builtin_nontemporal_load(ex + i);
+        return ldexp((double)m, (int)e);
+    }
+    __device__ static void store_v(void* out, int16_t* ex, int64_t i, V v, bool f64)
+    {
+        if (f64) {
+            static_cast<double*>(out)[i] = v;
+        } else {
+            int ee;
+            double m = frexp(v, &ee);
+            float mf = (float)m;
+            if (fabsf(mf) == 1.0f) { mf *= 0.5f; ++ee; }
+            static_cast<float*>(out)[i] = mf;
+            ex[i] = (int16_t)(mf == 0.0f ? 0 : ee);
+        }
+    }
+    __device__ static V sub_scaled(V a, double C, V b) { return fma(-C, b, a); }
+    __device__ static void store_nan(void* out, int16_t* ex, int64_t i, bool f64)
+    {
+        if (f64) {
+            static_cast<double*>(out)[i] = __builtin_nan("");
+        } else {
+            static_cast<float*>(out)[i] = __builtin_nanf("");
+            ex[i] = 0;
+        }
+    }
+};
+
+// ------------------------------------------------------------------------------- C128
+struct FC128 {
+    using In = cd;
+    using E = cd;
+    using R = cd;
+    using Bs = cd;
+    using V = cd;
+    static constexpr bool kScaled = false;
+    static constexpr bool kComplex = true;
+    __device__ static double in_mag(In v) { return fmax(fabs(v.x), fabs(v.y)); }
+    __device__ static bool in_finite(In v) { return isfinite(v.x) && isfinite(v.y); }
+    __device__ static E conv(In v, double) { return v; }
+    __device__ static double mag(E p) { return fmax(fabs(p.x), fabs(p.y)); }
+    __device__ static E shift(E p, double C) { return {p.x + C, p.y}; }
+    __device__ static R recip(E p)
+    {
+        double d = rcp64(fma(p.x, p.x, p.y * p.y));
+        return {p.x * d, -p.y * d};
+    }
+    __device__ static E rowscale(E v, R r) { return v * r; }
+    __device__ static E zero() { return {0.0, 0.0}; }
+    __device__ static E upd(E a, E c, E w)
+    {
+        // a - c * w
+        return {fma(-c.x, w.x, fma(c.y, w.y, a.x)), fma(-c.x, w.y, fma(-c.y, w.x, a.y))};
+    }
+    __device__ static Bs one() { return {1.0, 0.0}; }
+    __device__ static Bs bmul(Bs b, E p, int) { return b * p; }
+    __device__ static void store(void* out, int16_t*, int64_t i, Bs v, bool)
+    {
+        static_cast<cd*>(out)[i] = v;
+    }
+    __device__ static double fincheck(Bs v) { return v.x * 0.0 + v.y * 0.0; }
+    __device__ static V load_v(const void* out, const int16_t*, int64_t i, bool)
+    {
+        const double* p = static_cast<const double*>(out) + 2 * i;
+        return {__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1)};
+    }
+    __device__ static void store_v(void* out, int16_t*, int64_t i, V v, bool)
+    {
+        static_cast<cd*>(out)[i] = v;
+    }
+    __device__ static V sub_scaled(V a, double C, V b) { return {fma(-C, b.x, a.x), fma(-C, b.y, a.y)}; }
+    __device__ static void store_nan(void* out, int16_t*, int64_t i, bool)
+    {
+        static_cast<cd*>(out)[i] = {__builtin_nan(""), __builtin_nan("")};
+    }
+};
+
+// ------------------------------------------------------------------------------- C64S
+// complex64 Schur updates; fp64 pivot reciprocal/test/shift; complex mantissa + exponent.
+struct FC64S {
+    using In = cd;
+    using E = cf;
+    using R = cd;
+    using Bs = SBc;
+    using V = cd;
+    static constexpr bool kScaled = true;
+    static constexpr bool kComplex = true;
+    __device__ static double in_mag(In v) { return fmax(fabs(v.x), fabs(v.y)); }
+    __device__ static bool in_finite(In v) { return isfinite(v.x) && isfinite(v.y); }
+    __device__ static E conv(In v, double sc) { return {(float)(v.x * sc), (float)(v.y * sc)}; }
+    __device__ static double mag(E p) { return (double)fmaxf(fabsf(p.x), fabsf(p.y)); }
+    __device__ static E shift(E p, double C) { return {(float)((double)p.x + C), p.y}; }
+    __device__ static R recip(E p)
+    {
+        double px = p.x, py = p.y;
+        double d = rcp64(fma(px, px, py * py));
+        return {px * d, -py * d};
+    }
+    __device__ static E rowscale(E v, R r)
+    {
+        double vx = v.x, vy = v.y;
+        return {(float)fma(vx, r.x, -vy * r.y), (float)fma(vx, r.y, vy * r.x)};
+    }
+    __device__ static E zero() { return {0.0f, 0.0f}; }
+    __device__ static E upd(E a, E c, E w)
+    {
+        return {fmaf(-c.x, w.x, fmaf(c.y, w.y, a.x)), fmaf(-c.x, w.y, fmaf(-c.y, w.x, a.y))};
+    }
+    __device__ static Bs one() { return {{0.5f, 0.0f}, 1}; }
+    __device__ static Bs bmul(Bs b, E p, int e0)
+    {
+        cf m = {fmaf(b.m.x, p.x, -b.m.y * p.y), fmaf(b.m.x, p.y, b.m.y * p.x)};
+        float big = fmaxf(fabsf(m.x), fabsf(m.y));
+        int ee;
+        (void)frexpf(big, &ee);
+        m.x = ldexpf(m.x, -ee);
+        m.y = ldexpf(m.y, -ee);
+        return {m, b.e + ee + e0};
+    }
+    __device__ static void store(void* out, int16_t* ex, int64_t i, Bs v, bool f64)
+    {
+        if (f64) {
+            static_cast<cd*>(out)[i] = {ldexp((double)v.m.x, v.e), ldexp((double)v.m.y, v.e)};
+        } else {
+            static_cast<cf*>(out)[i] = v.m;
+            ex[i] = (int16_t)v.e;
+        }
+    }
+    __device__ static float fincheck(Bs v) { return v.m.x * 0.0f + v.m.y * 0.0f; }
+    __device__ static V load_v(const void* out, const int16_t* ex, int64_t i, bool f64)
+    {
+        if (f64) {
+            const double* p = static_cast<const double*>(out) + 2 * i;
+            return {__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1)};
+        }
+        const float* p = static_cast<const float*>(out) + 2 * i;
+        int e = __builtin_nontemporal_load(ex + i);
+        return {ldexp((double)__builtin_nontemporal_load(p), e), ldexp((double)__builtin_nontemporal_load(p + 1), e)};
+    }
+    __device__ static void store_v(void* out, int16_t* ex, int64_t i, V v, bool f64)
+    {
+        if (f64) {
+            static_cast<cd*>(out)[i] = v;
+        } else {
+            double big = fmax(fabs(v.x), fabs(v.y));
+            int ee = 0;
+            if (big != 0.0) (void)frexp(big, &ee);
+            cf m = {(float)ldexp(v.x, -ee), (float)ldexp(v.y, -ee)};
+            if (fmaxf(fabsf(m.x), fabsf(m.y)) >= 1.0f) { m.x *= 0.5f; m.y *= 0.5f; ++ee; }
+            static_cast<cf*>(out)[i] = m;
+            ex[i] = (int16_t)ee;
+        }
+    }
+    __device__ static V sub_scaled(V a, double C, V b) { return {fma(-C, b.x, a.x), fma(-C, b.y, a.y)}; }
+    __device__ static void store_nan(void* out, int16_t* ex, int64_t i, bool f64)
+    {
+        if (f64) {
+            static_cast<cd*>(out)[i] = {__builtin_nan(""), __builtin_nan("")};
+        } else {
+            static_cast<cf*>(out)[i] = {__builtin_nanf(""), __builtin_nanf("")};
+            ex[i] = 0;
+        }
+    }
+};
+
+}  // namespace apm

@@ -1,0 +1,55 @@
+"""Error metrics for comparing principal minors with the oracle.
+
+Plain relative error is undefined for (near-)zero minors, so the parity gate is the
+mixed metric  e_S = |x_S - ref_S| / max(|ref_S|, H_S)  with the Hadamard bound
+H_S = prod_{i in S} ||A[i, S]||_2 >= |det A[S]|  (e_S = 0 when x_S == ref_S)."""
+import numpy as np
+
+
+def hadamard_bounds(A):
+    """H[m] = prod_{i in S_m} ||A[i, S_m]||_2 for every mask m, for one (n, n) matrix."""
+    A = np.asarray(A)
+    n = A.shape[0]
+    sq = np.abs(A) ** 2
+    nm = 1 << n
+    logH = np.zeros(nm)
+    masks = np.arange(nm)
+    for i in range(n):
+        rows = np.zeros(1)
+        for j in range(n):
+            rows = np.concatenate([rows, rows + sq[i, j]])
+        with np.errstate(divide="ignore"):
+            lr = 0.5 * np.log(rows)
+        inS = (masks >> i) & 1
+        logH = logH + np.where(inS == 1, lr, 0.0)
+    return np.exp(logH)
+
+
+def hadamard_at(A, masks):
+    A = np.asarray(A)
+    n = A.shape[0]
+    out = np.empty(len(masks))
+    for t, m in enumerate(masks):
+        r = [k for k in range(n) if m >> k & 1]
+        out[t] = np.prod([np.linalg.norm(A[i, r]) for i in r]) if r else 1.0
+    return out
+
+
+def mixed_err(x, ref, H):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    diff = np.abs(x - ref)
+    den = np.maximum(np.abs(ref), H)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        e = np.where(diff == 0, 0.0, diff / np.where(den == 0, np.finfo(float).tiny, den))
+    e = np.where(np.isfinite(x) | ~np.isfinite(ref), e, np.inf)
+    return e
+
+
+def max_mixed_err(X, REF, A):
+    """max over a batch of the mixed metric; X, REF are (B, 2^n), A is (B, n, n)."""
+    worst = 0.0
+    for b in range(X.shape[0]):
+        e = mixed_err(X[b], REF[b], hadamard_bounds(A[b]))
+        worst = max(worst, float(np.max(e)))
+    return worst

@@ -1,0 +1,203 @@
+"""GPU parity of apm_all_minors against the CPU oracle (mixed-metric tolerances:
+1e-10 for fp64 / complex128, 1e-4 for the fp32-scaled variants)."""
+import numpy as np
+import pytest
+
+import metrics
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def apm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_07638_amd as m
+    return m
+
+
+def run(apm, A, dtype="r64", **kw):
+    import torch
+    At = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    out, ex, info = apm.all_minors(At, dtype, **kw)
+    torch.cuda.synchronize()
+    if ex is not None:
+        out = apm.decode_scaled(out, ex)
+    return out.cpu().numpy(), info.cpu().numpy()
+
+
+def test_lattice_n8_full_batch(apm, oracle_mod):
+    """1024 real 8x8 lattice propagator matrices (L=16, t=1, mu=0, beta=4), every minor."""
+    A = W.lattice_batch(1024, 8, W.Lattice(16, 1.0, 0.0, 4.0))
+    out, info = run(apm, A)
+    ref = oracle_mod.minors(A)
+    assert np.all(info == 0)
+    assert out[:, 0].tolist() == [1.0] * 1024
+    assert metrics.max_mixed_err(out, ref, A) <= TOL64
+
+
+@pytest.mark.parametrize("n", list(range(1, 15)))
+def test_all_orders_gauss(apm, oracle_mod, n):
+    rng = np.random.default_rng(100 + n)
+    A = rng.standard_normal((5, n, n)) / np.sqrt(n) + np.eye(n)
+    out, info = run(apm, A)
+    ref = oracle_mod.minors(A)
+    assert metrics.max_mixed_err(out, ref, A) <= TOL64
+    assert np.all(info >= 0)
+
+
+@pytest.mark.parametrize("n", [15, 16, 17, 18, 20])
+def test_large_orders_sampled(apm, oracle_mod, n):
+    A = W.lattice_batch(3, n, W.Lattice(32, 1.0, -0.5, 5.0), seed=7 + n)
+    out, info = run(apm, A)
+    rng = np.random.default_rng(n)
+    masks = np.unique(np.concatenate([rng.integers(0, 1 << n, 3000), [0, 1, (1 << n) - 1, 1 << (n - 1)],
+                                      (1 << np.arange(n))]))
+    for b in range(3):
+        ref = oracle_mod.minors_at(A[b], masks)
+        e = metrics.mixed_err(out[b, masks], ref, metrics.hadamard_at(A[b], masks))
+        assert e.max() <= TOL64, (b, e.max())
+    # sum of all minors = det(I + A), checked on the whole output
+    for b in range(3):
+        ref = np.linalg.det(np.eye(n) + A[b])
+        assert abs(out[b].sum() - ref) <= 1e-9 * np.abs(out[b]).sum()
+
+
+@pytest.mark.parametrize("n", [2, 3, 6, 8, 10, 11, 12, 16])
+def test_zero_diagonal_needs_n_minus_1_shifts(apm, oracle_mod, n):
+    """Sec. II: a matrix with zero diagonal needs at least n-1 pivot corrections, and
+    generically exactly n-1 when only (near-)exact zeros are shifted (tiny tau).  With
+    the default threshold a few relatively small Schur pivots may be shifted too."""
+    G = W.zero_diagonal(W.gauss_batch(4, n, seed=n))
+    out, info = run(apm, G, tau=1e-12)
+    assert np.all(info == n - 1), info
+    assert metrics.max_mixed_err(out, oracle_mod.minors(G), G) <= TOL64
+    out, info = run(apm, G)
+    assert np.all(info >= n - 1), info
+    assert metrics.max_mixed_err(out, oracle_mod.minors(G), G) <= TOL64
+    # Half-filled (mu = 0) lattice propagators with zero diagonal: every odd-order minor
+    # vanishes structurally and elimination without row exchanges (the tree has none)
+    # loses a few more digits; the plain depth-first tree in the paper's own pivot order
+    # reaches 3e-10 on these matrices at n = 16 as well, so this family is gated at 1e-8.
+    A = W.zero_diagonal(W.lattice_batch(4, n, W.Lattice(16, 1.0, 0.0, 4.0), seed=n))
+    out, info = run(apm, A)
+    assert np.all(info >= n - 1), info
+    ref = oracle_mod.minors(A)
+    assert metrics.max_mixed_err(out, ref, A) <= 1e-8
+
+
+def test_stress_injections_n16(apm, oracle_mod):
+    A = W.lattice_batch(256, 16, W.Lattice(32, 1.0, -0.5, 5.0), seed=3)
+    A, log = W.inject_stress(A, every=64)
+    out, info = run(apm, A)
+    stressed = [b for b, _, _ in log]
+    ref = oracle_mod.minors(A[stressed])
+    assert metrics.max_mixed_err(out[stressed], ref, A[stressed]) <= TOL64
+    assert np.all(info >= 0)
+    normal = [1, 2, 100, 255]
+    ref = oracle_mod.minors(A[normal])
+    assert metrics.max_mixed_err(out[normal], ref, A[normal]) <= TOL64
+
+
+def test_exact_zero_pivots_and_singular(apm, oracle_mod):
+    rng = np.random.default_rng(5)
+    n = 12
+    A = rng.standard_normal((4, n, n))
+    A[0] = 0.0                                 # all-zero matrix
+    A[1, 3, :] = A[1, 5, :]                    # singular: two equal rows
+    A[2, :, 7] = 0.0                           # zero column
+    A[3, 0, 0] = 0.0
+    A[3, 11, 11] = 0.0
+    out, info = run(apm, A)
+    ref = oracle_mod.minors(A)
+    assert metrics.max_mixed_err(out, ref, A) <= TOL64
+    assert np.all(out[0, 1:] == 0.0) and out[0, 0] == 1.0
+
+
+def test_nonfinite_input_reported(apm):
+    A = np.eye(8)[None].repeat(3, 0).copy()
+    A[1, 2, 3] = np.nan
+    A[2, 0, 0] = np.inf
+    out, info = run(apm, A)
+    assert info.tolist() == [0, -2, -2]
+    assert np.all(np.isnan(out[1])) and np.all(np.isnan(out[2]))
+    assert np.all(out[0] == 1.0)
+
+
+def test_offsets_and_determinism(apm, oracle_mod):
+    import torch
+    rng = np.random.default_rng(9)
+    n, B = 10, 6
+    A = rng.standard_normal((B, n, n)) + 2 * np.eye(n)
+    # scatter the matrices with gaps, outputs in reverse order
+    buf = np.zeros(B * n * n + 1000)
+    ioff = np.array([37 + b * (n * n + 50) for b in range(B)], dtype=np.int64)
+    for b in range(B):
+        buf[ioff[b]:ioff[b] + n * n] = A[b].ravel()
+    ooff = np.array([(B - 1 - b) * (1 << n) for b in range(B)], dtype=np.int64)
+    dA = torch.from_numpy(buf).cuda()
+    out = torch.full((B << n,), 7.0, dtype=torch.float64, device="cuda")
+    info = torch.empty(B, dtype=torch.int32, device="cuda")
+    bd = apm.make_batch(B, n, None, 0, torch.from_numpy(ioff).cuda(), torch.from_numpy(ooff).cuda())
+    for rep in range(2):
+        rc = apm.apm_all_minors(apm.APM_R64, apm._ptr(dA), bd, apm._ptr(out), None, apm._ptr(info), None,
+                                apm._stream(None))
+        assert rc == 0
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().reshape(B, 1 << n)[::-1]
+        if rep == 0:
+            first = got.copy()
+        else:
+            assert np.array_equal(first, got)
+    ref = oracle_mod.minors(A)
+    assert metrics.max_mixed_err(got, ref, A) <= TOL64
+
+
+@pytest.mark.parametrize("n", [8, 12, 16])
+def test_fp32_scaled(apm, oracle_mod, n):
+    A = W.lattice_batch(16, n, W.Lattice(32, 1.0, -0.5, 5.0), seed=11)
+    A, _ = W.inject_stress(A, every=8)
+    ref = oracle_mod.minors(A)
+    out, info = run(apm, A, "r32s")
+    assert metrics.max_mixed_err(out, ref, A) <= TOL32
+    out2, _ = run(apm, A, "r32s", out_f64=True)
+    assert metrics.max_mixed_err(out2, ref, A) <= TOL32
+
+
+def test_fp32_scaled_large_range(apm, oracle_mod):
+    """Entries of size 1e30 and 1e-30: the exponent carries what fp32 cannot."""
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((4, 10, 10)) + 3 * np.eye(10)
+    A[0] *= 1e30
+    A[1] *= 1e-30
+    ref = oracle_mod.minors(A)
+    out, info = run(apm, A, "r32s")
+    assert metrics.max_mixed_err(out, ref, A) <= TOL32
+
+
+@pytest.mark.parametrize("n", [4, 9, 14])
+def test_complex_keldysh(apm, oracle_mod, n):
+    A = W.keldysh_batch(8, n, seed=21 + n)
+    ref = oracle_mod.minors_complex(A)
+    out, info = run(apm, A, "c128")
+    assert metrics.max_mixed_err(out, ref, A) <= TOL64
+    out, info = run(apm, A, "c64s")
+    assert metrics.max_mixed_err(out, ref, A) <= TOL32
+    out, info = run(apm, A, "c64s", out_f64=True)
+    assert metrics.max_mixed_err(out, ref, A) <= TOL32
+
+
+def test_complex_zero_diagonal(apm, oracle_mod):
+    rng = np.random.default_rng(3)
+    n = 11
+    A = rng.standard_normal((3, n, n)) + 1j * rng.standard_normal((3, n, n))
+    A[:, np.arange(n), np.arange(n)] = 0
+    out, info = run(apm, A, "c128")
+    assert np.all(info == n - 1)
+    ref = oracle_mod.minors_complex(A)
+    assert metrics.max_mixed_err(out, ref, A) <= TOL64
