@@ -82,6 +82,8 @@ struct FR64 {
     {
         static_cast<double*>(out)[i] = v;
     }
+    __device__ static void* optr(void* out, int64_t i, bool) { return static_cast<double*>(out) + i; }
+    __device__ static void store_rel(void* p, int16_t*, int r, Bs v, bool) { static_cast<double*>(p)[r] = v; }
     __device__ static double fincheck(Bs v) { return v * 0.0; }
     __device__ static V load_v(const void* out, const int16_t*, int64_t i, bool)
     {
@@ -134,7 +136,20 @@ struct FR32S {
             ex[i] = (int16_t)v.e;
         }
     }
-    __device__ static float fincheck(Bs v) { return v.m * 0.0f; }
+    __device__ static void* optr(void* out, int64_t i, bool f64)
+    {
+        return f64 ? (void*)(static_cast<double*>(out) + i) : (void*)(static_cast<float*>(out) + i);
+    }
+    __device__ static void store_rel(void* p, int16_t* e, int r, Bs v, bool f64)
+    {
+        if (f64) {
+            static_cast<double*>(p)[r] = ldexp((double)v.m, v.e);
+        } else {
+            static_cast<float*>(p)[r] = v.m;
+            e[r] = (int16_t)v.e;
+        }
+    }
+    __device__ static double fincheck(Bs v) { return (double)(v.m * 0.0f); }
     __device__ static V load_v(const void* out, const int16_t* ex, int64_t i, bool f64)
     {
         if (f64) return __builtin_nontemporal_load(static_cast<const double*>(out) + i);
@@ -199,6 +214,8 @@ struct FC128 {
     {
         static_cast<cd*>(out)[i] = v;
     }
+    __device__ static void* optr(void* out, int64_t i, bool) { return static_cast<cd*>(out) + i; }
+    __device__ static void store_rel(void* p, int16_t*, int r, Bs v, bool) { static_cast<cd*>(p)[r] = v; }
     __device__ static double fincheck(Bs v) { return v.x * 0.0 + v.y * 0.0; }
     __device__ static V load_v(const void* out, const int16_t*, int64_t i, bool)
     {
@@ -267,7 +284,20 @@ struct FC64S {
             ex[i] = (int16_t)v.e;
         }
     }
-    __device__ static float fincheck(Bs v) { return v.m.x * 0.0f + v.m.y * 0.0f; }
+    __device__ static void* optr(void* out, int64_t i, bool f64)
+    {
+        return f64 ? (void*)(static_cast<cd*>(out) + i) : (void*)(static_cast<cf*>(out) + i);
+    }
+    __device__ static void store_rel(void* p, int16_t* e, int r, Bs v, bool f64)
+    {
+        if (f64) {
+            static_cast<cd*>(p)[r] = {ldexp((double)v.m.x, v.e), ldexp((double)v.m.y, v.e)};
+        } else {
+            static_cast<cf*>(p)[r] = v.m;
+            e[r] = (int16_t)v.e;
+        }
+    }
+    __device__ static double fincheck(Bs v) { return (double)(v.m.x * 0.0f + v.m.y * 0.0f); }
     __device__ static V load_v(const void* out, const int16_t* ex, int64_t i, bool f64)
     {
         if (f64) {

@@ -1,625 +1,20 @@
-// fpm.hip -- all principal minors of a batch of small matrices on gfx950.
-//
-// Method: the Griffin-Tsatsomeros binary tree of Schur complements (Sec. II,
-// Eqs. (dets_schur)-(eq:minor) and Algorithm 1), traversed depth-first so that
-// only one matrix per level is kept (Sec. II, the paragraph after Algorithm 1),
-// with the near-zero-pivot shift C and its post-order back-propagation
-//     det A[S] = det A~[S] - C det A[S \ {l}]          (Sec. II, pivot correction).
-//
-// Mapping (one matrix per wavefront, 64 lanes):
-//   * the pivot order is a fixed permutation pi of the rows: first the T highest
-//     rows n-1, n-2, ..., n-T ("top" levels), then rows 0, 1, 2, ... .  Every
-//     level pivots on the first row of its (permuted) matrix, exactly as in the
-//     paper; the permutation only decides which mask bit each level owns.
-//   * top levels (bits n-1..n-T): cooperative depth-first walk in LDS; every
-//     leaf of this walk is a "chunk" node of order K = MID + K0 whose subtree
-//     owns the contiguous mask range [c 2^K, (c+1) 2^K).
-//   * mid levels (bits 0..MID-1, MID = 6): the chunk node is expanded
-//     breadth-first (first BF levels in LDS, the last two per lane in registers)
-//     into 64 nodes of order K0 -- one per lane, lane = the 6 low mask bits.
-//   * lane levels (bits MID..K-1): each lane walks its own subtree fully
-//     unrolled in registers.  Minor j of lane l is mask c 2^K + j 2^6 + l, so
-//     each store instruction of the wave writes 512 contiguous bytes (fp64).
-//   * every mask is written exactly once, by the lane whose subtree contains it;
-//     the node's recorded minor uses the true pivot (Algorithm 1 records before
-//     it shifts), its right subtree uses the shifted one.
-//   * shifted pivots (see analyse() for the test and the shift) are recorded with the
-//     exponent of their power-of-two shift (top: one byte per chunk transition; mid:
-//     one byte per node; lane: one byte per node packed in a 64-bit register) and
-//     corrected after the stores, deepest level first, by read-modify-write passes
-//     over the already written minors (rare path).
-#include "apm_device.h"
+// fpm.hip -- dispatch of apm_all_minors to the per-type kernel instantiations.
 #include "apm_kernels.h"
 
 namespace apm {
 
-constexpr int kMid = 6;
-constexpr int8_t kNoEv = -128;   // "no shifted pivot" marker in the int8 shift-exponent tables
-
-template <int N, int K0MAX>
-struct Plan {
-    static_assert(K0MAX >= 1 && K0MAX <= 4, "lane subtrees hold at most 7 shifted pivots per lane");
-    static constexpr int mid = N < kMid ? N : kMid;
-    static constexpr int k0 = (N - mid) < K0MAX ? (N - mid) : K0MAX;
-    static constexpr int K = mid + k0;
-    static constexpr int T = N - K;
-    static constexpr int inl = mid < 2 ? mid : 2;
-    static constexpr int bf = mid - inl;
-    static constexpr int active = 1 << mid;
-};
-
-constexpr int sq(int x) { return x * x; }
-constexpr int nz(int x) { return x > 0 ? x : 1; }
-
-// Per-wave LDS layout: matrices (units of E), then small typed arrays.
-template <class F, int N, int K0MAX>
-struct Lay {
-    using P = Plan<N, K0MAX>;
-    using E = typename F::E;
-    using R = typename F::R;
-    using Bs = typename F::Bs;
-    static constexpr int top_off(int d)
-    {
-        int s = 0;
-        for (int i = 0; i < d; ++i) s += sq(N - i);
-        return s;
-    }
-    static constexpr int lvl(int j) { return (1 << j) * sq(P::K - j); }
-    static constexpr int bufA()
-    {
-        int m = 0;
-        for (int j = 1; j <= P::bf; j += 2) m = lvl(j) > m ? lvl(j) : m;
-        return m;
-    }
-    static constexpr int bufB()
-    {
-        int m = 0;
-        for (int j = 2; j <= P::bf; j += 2) m = lvl(j) > m ? lvl(j) : m;
-        return m;
-    }
-    static constexpr int nE = top_off(P::T + 1) + bufA() + bufB();
-    static constexpr int nPiv = nz((1 << P::bf) - 1);   // mid nodes expanded breadth-first
-    static constexpr size_t al(size_t x) { return (x + 15) & ~size_t(15); }
-    static constexpr size_t oE = 0;
-    static constexpr size_t oPt = al(oE + sizeof(E) * nE);
-    static constexpr size_t oPu = al(oPt + sizeof(E) * nPiv);
-    static constexpr size_t oRi = al(oPu + sizeof(E) * nPiv);
-    static constexpr size_t oOff = al(oRi + sizeof(R) * nPiv);
-    static constexpr size_t oLd = al(oOff + sizeof(int) * (P::T + 1));
-    static constexpr size_t oBu = al(oLd + sizeof(int) * (P::T + 1));
-    static constexpr size_t oRec = al(oBu + sizeof(Bs) * (P::T + 1));
-    static constexpr size_t oTev = al(oRec + sizeof(Bs) * (P::T + 1));     // int8 [2^T]
-    static constexpr size_t oMid = al(oTev + (size_t(1) << P::T));        // int8 [64]
-    static constexpr size_t bytes = al(oMid + 64);
-    // element offset of the buffer of breadth-first level j (j >= 1); odd / even levels alternate
-    static constexpr int lvl_base(int j) { return top_off(P::T + 1) + ((j & 1) ? 0 : bufA()); }
-};
-
-struct Opts {
-    double tau;      // relative pivot threshold
-    bool perturb;
-    bool out_f64;
-};
-
-// Matrix-wide parameters of the pivot shift.
-struct PivCtl {
-    double tau2;     // tau^2
-    int es;          // binary exponent of s = max |A_ij| in stored units
-    int es_true;     // the same in true units (stored = true * 2^-e0)
-    bool perturb;
-};
-
-template <class F>
-struct PivInfo {
-    typename F::E pt, pu;
-    typename F::R ri;
-    bool pert;
-    int de;          // the shift is C = 2^(es + de) (stored units)
-};
-
-// Pivot analysis of a node (Sec. II, pivot correction).  A pivot p is shifted when
-// |p|^2 < tau^2 * rmax * cmax, rmax / cmax being the largest magnitudes in the pivot's
-// row / column of the node's matrix (a test invariant under diagonal similarity), or
-// when p == 0; the shift is the power of two nearest below sqrt(rmax * cmax) (s when the
-// row or column vanishes).
-template <class F>
-__device__ __forceinline__ PivInfo<F> analyse(typename F::E p, double rmax, double cmax, int size,
-                                              const PivCtl& pc)
-{
-    PivInfo<F> v;
-    v.pt = p;
-    v.de = 0;
-    const double prod = rmax * cmax;
-    const double pm = F::mag(p);
-    v.pert = pc.perturb && size >= 2 && (pm == 0.0 || pm * pm < pc.tau2 * prod);
-    v.pu = p;
-    if (v.pert) {
-        int de = 0;
-        if (prod > 0.0) {
-            int ep;
-            (void)frexp(prod, &ep);
-            de = (ep >> 1) - pc.es;
-            de = de < -127 ? -127 : (de > 127 ? 127 : de);
-        }
-        v.de = de;
-        v.pu = F::shift(p, ldexp(1.0, pc.es + de));
-    }
-    v.ri = F::recip(v.pu);
-    return v;
-}
-
-template <class F>
-struct Ctx {
-    void* out;
-    int16_t* ex;
-    int64_t base;   // output element index of this chunk's first mask
-    int lane;
-    bool active;
-    bool f64;
-    uint32_t ev;    // lane-level shifted pivots: bit = heap index of the node
-    uint64_t lc;    // their shift exponents, one byte per heap index
-    float chk;      // sum of v * 0 over stored minors: NaN iff one was not finite
-};
-
-template <class F>
-__device__ __forceinline__ void put(Ctx<F>& cx, int j, typename F::Bs v)
-{
-    if (cx.active) F::store(cx.out, cx.ex, cx.base + ((int64_t)j << kMid) + cx.lane, v, cx.f64);
-    cx.chk += (float)F::fincheck(v);
-}
-
-// Lane subtree: node of order KP - S0 held as the trailing view (S0.., S0..) of the
-// register matrix M (KP x KP); DEP = depth below the lane root, Q = bits decided so far.
-// Records the node's minor with the true pivot, then the left child (a view), then the
-// right child (Schur complement, possibly with a shifted pivot).
-template <class F, int KP, int S0, int DEP, int Q>
-__device__ __forceinline__ void lane_node(const typename F::E (&M)[KP * KP], typename F::Bs bu, Ctx<F>& cx,
-                                          const PivCtl& pc, int e0)
-{
-    using E = typename F::E;
-    constexpr int SZ = KP - S0;
-    const E p = M[S0 * KP + S0];
-    put<F>(cx, Q | (1 << DEP), F::bmul(bu, p, e0));
-    if constexpr (SZ > 1) {
-        lane_node<F, KP, S0 + 1, DEP + 1, Q>(M, bu, cx, pc, e0);
-        constexpr int m = SZ - 1;
-        double rmax = 0.0, cmax = 0.0;
-#pragma unroll
-        for (int b = 0; b < m; ++b) {
-            rmax = fmax(rmax, F::mag(M[S0 * KP + S0 + 1 + b]));
-            cmax = fmax(cmax, F::mag(M[(S0 + 1 + b) * KP + S0]));
-        }
-        const PivInfo<F> pv = analyse<F>(p, rmax, cmax, SZ, pc);
-        constexpr int id = (1 << DEP) - 1 + Q;
-        if (pv.pert) {
-            cx.ev |= 1u << id;
-            cx.lc = (cx.lc & ~(0xFFull << (8 * id))) | ((uint64_t)(uint8_t)(int8_t)pv.de << (8 * id));
-        }
-        E w[m];
-#pragma unroll
-        for (int b = 0; b < m; ++b) w[b] = F::rowscale(M[S0 * KP + S0 + 1 + b], pv.ri);
-        E S[m * m];
-#pragma unroll
-        for (int a = 0; a < m; ++a)
-#pragma unroll
-            for (int b = 0; b < m; ++b)
-                S[a * m + b] = F::upd(M[(S0 + 1 + a) * KP + S0 + 1 + b], M[(S0 + 1 + a) * KP + S0], w[b]);
-        lane_node<F, m, 0, DEP + 1, Q | (1 << DEP)>(S, F::bmul(bu, pv.pu, e0), cx, pc, e0);
-    }
-}
-
-// Row / column magnitude maxima of the pivot of a register matrix of order SZ.
-template <class F, int SZ>
-__device__ __forceinline__ void rc_max(const typename F::E (&M)[SZ * SZ], double& rmax, double& cmax)
-{
-    rmax = 0.0;
-    cmax = 0.0;
-#pragma unroll
-    for (int b = 1; b < SZ; ++b) {
-        rmax = fmax(rmax, F::mag(M[b]));
-        cmax = fmax(cmax, F::mag(M[b * SZ]));
-    }
-}
-
-// One in-lane mid level: node M (order SZ, registers) -> the lane's child (order SZ-1):
-// the Schur complement if the lane's bit of this level is set, else the trailing view.
-template <class F, int SZ>
-__device__ __forceinline__ void inlane_step(const typename F::E (&M)[SZ * SZ], typename F::E (&Q)[nz(sq(SZ - 1))],
-                                            bool right, typename F::R ri)
-{
-    using E = typename F::E;
-    constexpr int m = SZ - 1;
-    E w[nz(m)];
-#pragma unroll
-    for (int b = 0; b < m; ++b) w[b] = right ? F::rowscale(M[1 + b], ri) : F::zero();
-#pragma unroll
-    for (int a = 0; a < m; ++a)
-#pragma unroll
-        for (int b = 0; b < m; ++b) Q[a * m + b] = F::upd(M[(1 + a) * SZ + 1 + b], M[(1 + a) * SZ], w[b]);
-}
-
-// Breadth-first mid level J (and, recursively, the following ones) of a chunk.
-template <class F, int N, int K0MAX, int J>
-__device__ __forceinline__ void bf_levels(typename F::E* lds, typename F::E* pt_a, typename F::E* pu_a,
-                                          typename F::R* ri_a, int8_t* midc, int x0o, int x0l, int lane,
-                                          const PivCtl& pc, uint64_t& mid_ev)
-{
-    using P = Plan<N, K0MAX>;
-    using L = Lay<F, N, K0MAX>;
-    using E = typename F::E;
-    if constexpr (J < P::bf) {
-        constexpr int nodes = 1 << J;
-        constexpr int sz = P::K - J;
-        constexpr int m = sz - 1;
-        const E* par = (J == 0) ? lds + x0o : lds + L::lvl_base(J);
-        const int pld = (J == 0) ? x0l : sz;
-        constexpr int pstr = (J == 0) ? 0 : sz * sz;
-        bool pert = false;
-        if (lane < nodes) {
-            const E* Pm = par + lane * pstr;
-            double rmax = 0.0, cmax = 0.0;
-            for (int b = 1; b < sz; ++b) {
-                rmax = fmax(rmax, F::mag(Pm[b]));
-                cmax = fmax(cmax, F::mag(Pm[b * pld]));
-            }
-            const PivInfo<F> pv = analyse<F>(Pm[0], rmax, cmax, sz, pc);
-            pt_a[nodes - 1 + lane] = pv.pt;
-            pu_a[nodes - 1 + lane] = pv.pu;
-            ri_a[nodes - 1 + lane] = pv.ri;
-            midc[nodes - 1 + lane] = pv.pert ? (int8_t)pv.de : kNoEv;
-            pert = pv.pert;
-        }
-        mid_ev |= (ballot(pert) & ((1ull << nodes) - 1)) << (nodes - 1);
-        wave_sync();
-        E* ch = lds + L::lvl_base(J + 1);
-        for (int i = lane; i < 2 * nodes * m * m; i += kWave) {
-            const int q = i / (m * m);
-            const int e = i - q * (m * m);
-            const int a = e / m, b = e - (e / m) * m;
-            const int t = q & (nodes - 1);
-            const bool right = (q >> J) & 1;
-            const E* Pm = par + t * pstr;
-            const E w = right ? F::rowscale(Pm[b + 1], ri_a[nodes - 1 + t]) : F::zero();
-            ch[i] = F::upd(Pm[(a + 1) * pld + b + 1], Pm[(a + 1) * pld], w);
-        }
-        wave_sync();
-        bf_levels<F, N, K0MAX, J + 1>(lds, pt_a, pu_a, ri_a, midc, x0o, x0l, lane, pc, mid_ev);
-    }
-}
-
-// Correct the minors of one chunk for its lane- and mid-level shifted pivots, deepest
-// level first: det A[S] = det A~[S] - C det A[S \ {l}] over each shifted node's strict
-// right subtree (Sec. II, pivot correction).  Reads back what the chunk stored.
-template <class F, int N, int K0MAX>
-__device__ __noinline__ void chunk_fixup(void* out, int16_t* ex, int64_t base, int lane, bool f64, uint32_t ev,
-                                         uint64_t lc, uint64_t mid_ev, const int8_t* midc, int es_true)
-{
-    using P = Plan<N, K0MAX>;
-    constexpr int k0 = P::k0;
-    const bool active = lane < P::active;
-    __threadfence();
-    if constexpr (k0 >= 2) {
-        for (int dep = k0 - 2; dep >= 0; --dep) {
-            const uint32_t lvl_mask = ((1u << (1 << dep)) - 1) << ((1 << dep) - 1);
-            if (ballot(active && (ev & lvl_mask)) == 0) continue;
-            for (int q = 0; q < (1 << dep); ++q) {
-                const int id = (1 << dep) - 1 + q;
-                if (active && (ev >> id & 1u)) {
-                    const double Ct = ldexp(1.0, es_true + (int)(int8_t)(uint8_t)(lc >> (8 * id)));
-                    for (int u = 1; u < (1 << (k0 - 1 - dep)); ++u) {
-                        const int j = q | (1 << dep) | (u << (dep + 1));
-                        const int64_t i = base + ((int64_t)j << kMid) + lane;
-                        const int64_t pi = i - ((int64_t)(1 << dep) << kMid);
-                        auto v = F::sub_scaled(F::load_v(out, ex, i, f64), Ct, F::load_v(out, ex, pi, f64));
-                        F::store_v(out, ex, i, v, f64);
-                    }
-                }
-            }
-            __threadfence();
-        }
-    }
-    for (int b = P::mid - 1; b >= 0; --b) {
-        const uint64_t lv = (mid_ev >> ((1 << b) - 1)) & ((1ull << (1 << b)) - 1);
-        if (!lv) continue;
-        const int q = lane & ((1 << b) - 1);
-        const bool mine = active && ((lane >> b) & 1) && (lv >> q & 1ull);
-        if (mine) {
-            const double Ct = ldexp(1.0, es_true + (int)midc[(1 << b) - 1 + q]);
-            for (int j = 0; j < (1 << k0); ++j) {
-                if (j == 0 && (lane >> (b + 1)) == 0) continue;   // the node's own recorded minor
-                const int64_t i = base + ((int64_t)j << kMid) + lane;
-                auto v = F::sub_scaled(F::load_v(out, ex, i, f64), Ct, F::load_v(out, ex, i - (1 << b), f64));
-                F::store_v(out, ex, i, v, f64);
-            }
-        }
-        __threadfence();
-    }
-}
-
-// All principal minors of one N x N matrix by one wavefront.  Returns the info code.
-template <class F, int N, int K0MAX>
-__device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, void* out, int16_t* ex,
-                                        unsigned char* lds_raw, const Opts& o)
-{
-    using P = Plan<N, K0MAX>;
-    using L = Lay<F, N, K0MAX>;
-    using E = typename F::E;
-    using R = typename F::R;
-    using Bs = typename F::Bs;
-    constexpr int K = P::K, T = P::T, bf = P::bf, k0 = P::k0;
-    const int lane = lane_id();
-
-    E* lds = reinterpret_cast<E*>(lds_raw + L::oE);
-    E* pt_a = reinterpret_cast<E*>(lds_raw + L::oPt);
-    E* pu_a = reinterpret_cast<E*>(lds_raw + L::oPu);
-    R* ri_a = reinterpret_cast<R*>(lds_raw + L::oRi);
-    int* off_a = reinterpret_cast<int*>(lds_raw + L::oOff);
-    int* ld_a = reinterpret_cast<int*>(lds_raw + L::oLd);
-    Bs* bu_a = reinterpret_cast<Bs*>(lds_raw + L::oBu);
-    Bs* rec_a = reinterpret_cast<Bs*>(lds_raw + L::oRec);
-    int8_t* tevc = reinterpret_cast<int8_t*>(lds_raw + L::oTev);
-    int8_t* midc = reinterpret_cast<int8_t*>(lds_raw + L::oMid);
-
-    // ---- load, scale, finiteness ------------------------------------------------------
-    double smax = 0.0;
-    bool bad = false;
-    for (int i = lane; i < N * N; i += kWave) {
-        const typename F::In v = A[i];
-        bad |= !F::in_finite(v);
-        smax = fmax(smax, F::in_mag(v));
-    }
-    if (ballot(bad)) {
-        for (int64_t i = lane; i < (int64_t(1) << N); i += kWave) F::store_nan(out, ex, i, o.out_f64);
-        return -2;
-    }
-    double s = wave_max(smax);
-    if (s == 0.0) s = 1.0;
-    int e0 = 0;
-    if constexpr (F::kScaled) (void)frexp(s, &e0);
-    const double sc = ldexp(1.0, -e0);
-    PivCtl pc;
-    pc.tau2 = o.tau * o.tau;
-    pc.perturb = o.perturb;
-    (void)frexp(s * sc, &pc.es);
-    pc.es_true = pc.es + e0;
-    for (int i = lane; i < N * N; i += kWave) {
-        const int a = i / N, b = i - (i / N) * N;
-        const int pa = a < T ? N - 1 - a : a - T;
-        const int pb = b < T ? N - 1 - b : b - T;
-        lds[i] = F::conv(A[pa * N + pb], sc);
-    }
-    for (int c = lane; c < (1 << T); c += kWave) tevc[c] = kNoEv;
-    if (lane <= T) {
-        off_a[lane] = lane * (N + 1);
-        ld_a[lane] = N;
-        bu_a[lane] = F::one();
-        rec_a[lane] = F::one();
-    }
-    wave_sync();
-
-    int nev = 0;
-    bool any_top = false;
-    float chkf = 0.0f;
-
-    for (int c = 0; c < (1 << T); ++c) {
-        // ---- top: take the right branch at the deepest level that changes -----------
-        if (c > 0) {
-            const int d = T - 1 - __builtin_ctz((unsigned)c);
-            const int xo = off_a[d], xl = ld_a[d];
-            const E* X = lds + xo;
-            const int m = N - d - 1;
-            double rmax = 0.0, cmax = 0.0;
-            for (int b = lane; b < m; b += kWave) {
-                rmax = fmax(rmax, F::mag(X[b + 1]));
-                cmax = fmax(cmax, F::mag(X[(b + 1) * xl]));
-            }
-            const PivInfo<F> pv = analyse<F>(X[0], wave_max(rmax), wave_max(cmax), m + 1, pc);
-            const Bs bud = bu_a[d];
-            E* S = lds + L::top_off(d + 1);
-            for (int i = lane; i < m * m; i += kWave) {
-                const int a = i / m, b = i - (i / m) * m;
-                S[i] = F::upd(X[(a + 1) * xl + b + 1], X[(a + 1) * xl], F::rowscale(X[b + 1], pv.ri));
-            }
-            if (pv.pert) {
-                nev += 1;
-                any_top = true;
-                if (lane == 0) tevc[c] = (int8_t)pv.de;
-            }
-            const Bs bnew = F::bmul(bud, pv.pu, e0);
-            const Bs rnew = F::bmul(bud, pv.pt, e0);
-            for (int dd = d + 1 + lane; dd <= T; dd += kWave) {
-                off_a[dd] = L::top_off(d + 1) + (dd - d - 1) * (m + 1);
-                ld_a[dd] = m;
-                bu_a[dd] = bnew;
-                rec_a[dd] = rnew;
-            }
-            wave_sync();
-        }
-        const int x0o = off_a[T], x0l = ld_a[T];
-        const Bs bu0 = bu_a[T], rec0 = rec_a[T];
-
-        // ---- mid levels 0..bf-1: breadth-first in LDS --------------------------------
-        uint64_t mid_ev = 0;
-        bf_levels<F, N, K0MAX, 0>(lds, pt_a, pu_a, ri_a, midc, x0o, x0l, lane, pc, mid_ev);
-
-        // ---- mid levels bf.., per lane, in registers ---------------------------------
-        constexpr int szb = K - bf;               // order of the level-bf node
-        const int tb = lane & ((1 << bf) - 1);
-        const E* Pb = (bf == 0) ? lds + x0o : lds + L::lvl_base(bf) + tb * szb * szb;
-        const int pbl = (bf == 0) ? x0l : szb;
-        E M0[szb * szb];
-#pragma unroll
-        for (int a = 0; a < szb; ++a)
-#pragma unroll
-            for (int b = 0; b < szb; ++b) M0[a * szb + b] = Pb[a * pbl + b];
-        double rm, cm;
-        rc_max<F, szb>(M0, rm, cm);
-        const PivInfo<F> v0 = analyse<F>(M0[0], rm, cm, szb, pc);
-        mid_ev |= (ballot(lane < (1 << bf) && v0.pert) & ((1ull << (1 << bf)) - 1)) << ((1 << bf) - 1);
-        if (lane < (1 << bf)) midc[(1 << bf) - 1 + lane] = v0.pert ? (int8_t)v0.de : kNoEv;
-        E M1[nz(sq(szb - 1))];
-        inlane_step<F, szb>(M0, M1, (lane >> bf) & 1, v0.ri);
-        // lane base: product of the used pivots on the lane's right branches; the recorded
-        // value of the lane's own mask uses the true pivot at its highest bit.
-        Bs acc = bu0, rec = rec0;
-        const int h = lane ? 31 - __builtin_clz((unsigned)lane) : -1;
-#pragma unroll
-        for (int j = 0; j < bf; ++j) {
-            if ((lane >> j) & 1) {
-                const int id = (1 << j) - 1 + (lane & ((1 << j) - 1));
-                if (j == h) rec = F::bmul(acc, pt_a[id], e0);
-                acc = F::bmul(acc, pu_a[id], e0);
-            }
-        }
-        if ((lane >> bf) & 1) {
-            if (bf == h) rec = F::bmul(acc, v0.pt, e0);
-            acc = F::bmul(acc, v0.pu, e0);
-        }
-
-        Ctx<F> cx;
-        cx.out = out;
-        cx.ex = ex;
-        cx.base = (int64_t)c << K;
-        cx.lane = lane;
-        cx.active = lane < P::active;
-        cx.f64 = o.out_f64;
-        cx.ev = 0;
-        cx.lc = 0x8080808080808080ull;
-        cx.chk = 0.0f;
-
-        if constexpr (P::inl == 2) {
-            constexpr int sz1 = szb - 1;
-            double rm1, cm1;
-            rc_max<F, sz1>(M1, rm1, cm1);
-            const PivInfo<F> v1 = analyse<F>(M1[0], rm1, cm1, sz1, pc);
-            mid_ev |= (ballot(lane < (2 << bf) && v1.pert) & ((1ull << (2 << bf)) - 1)) << ((2 << bf) - 1);
-            if (lane < (2 << bf)) midc[(2 << bf) - 1 + lane] = v1.pert ? (int8_t)v1.de : kNoEv;
-            if ((lane >> (bf + 1)) & 1) {
-                if (bf + 1 == h) rec = F::bmul(acc, v1.pt, e0);
-                acc = F::bmul(acc, v1.pu, e0);
-            }
-            put<F>(cx, 0, rec);
-            if constexpr (k0 > 0) {
-                E M2[k0 * k0];
-                inlane_step<F, sz1>(M1, M2, (lane >> (bf + 1)) & 1, v1.ri);
-                lane_node<F, k0, 0, 0, 0>(M2, acc, cx, pc, e0);
-            }
-        } else {
-            put<F>(cx, 0, rec);
-        }
-
-        // ---- rare path: shifted pivots inside this chunk --------------------------------
-        const bool lane_ev = ballot(cx.active && cx.ev != 0) != 0;
-        if (lane_ev || mid_ev) {
-            wave_sync();
-            nev += __builtin_popcountll(mid_ev) + wave_sum(cx.active ? __builtin_popcount(cx.ev) : 0);
-            chunk_fixup<F, N, K0MAX>(out, ex, cx.base, lane, o.out_f64, cx.ev, cx.lc, mid_ev, midc, pc.es_true);
-        }
-        chkf += cx.chk;
-    }
-
-    // ---- top-level corrections, deepest first ---------------------------------------
-    if constexpr (T > 0) {
-        if (any_top) {
-            __threadfence();
-            for (int d = T - 1; d >= 0; --d) {
-                const int step = 1 << (T - 1 - d);
-                const int64_t half = int64_t(1) << (N - 1 - d);
-                bool did = false;
-                for (int c = step; c < (1 << T); c += 2 * step) {
-                    const int de = tevc[c];
-                    if (de == kNoEv) continue;
-                    did = true;
-                    const double Ct = ldexp(1.0, pc.es_true + de);
-                    const int64_t start = (int64_t)c << K;
-                    for (int64_t i = start + 1 + lane; i < start + half; i += kWave) {
-                        auto v = F::sub_scaled(F::load_v(out, ex, i, o.out_f64), Ct,
-                                               F::load_v(out, ex, i - half, o.out_f64));
-                        F::store_v(out, ex, i, v, o.out_f64);
-                    }
-                }
-                if (did) __threadfence();
-            }
-        }
-    }
-    const bool nonfinite = ballot(!(chkf == chkf)) != 0;
-    return nonfinite ? -3 : nev;
-}
-
-// ------------------------------------------------------------------------------ kernels
-template <class F, int N, int K0MAX>
-__global__ __launch_bounds__(64) void fpm_uniform_kernel(const typename F::In* __restrict__ A, void* out,
-                                                         int16_t* ex, int32_t* info, int32_t batch,
-                                                         const int64_t* __restrict__ in_off,
-                                                         const int64_t* __restrict__ out_off, Opts o)
-{
-    extern __shared__ __align__(16) unsigned char lds_dyn[];
-    const int b = blockIdx.x;
-    if (b >= batch) return;
-    const int64_t io = in_off ? in_off[b] : (int64_t)b * N * N;
-    const int64_t oo = out_off ? out_off[b] : ((int64_t)b << N);
-    void* ob;
-    if constexpr (F::kComplex) {
-        ob = (o.out_f64 || !F::kScaled) ? (void*)(static_cast<cd*>(out) + oo) : (void*)(static_cast<cf*>(out) + oo);
-    } else {
-        ob = (o.out_f64 || !F::kScaled) ? (void*)(static_cast<double*>(out) + oo)
-                                        : (void*)(static_cast<float*>(out) + oo);
-    }
-    int16_t* eb = ex ? ex + oo : nullptr;
-    const int r = fpm_wave<F, N, K0MAX>(A + io, ob, eb, lds_dyn, o);
-    if (info && lane_id() == 0) info[b] = r;
-}
-
-}  // namespace apm
-
-// ------------------------------------------------------------------------- host side
-namespace apm {
-namespace {
-
-template <class F>
-constexpr int k0max()
-{
-    return (sizeof(typename F::E) >= 16) ? 3 : 4;
-}
-
-template <class F, int N>
-hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
-{
-    constexpr int K0 = k0max<F>();
-    using Ly = Lay<F, N, K0>;
-    auto kern = fpm_uniform_kernel<F, N, K0>;
-    if (Ly::bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)Ly::bytes);
-        if (e != hipSuccess) return e;
-    }
-    Opts o{L.tau, L.perturb, L.out_f64};
-    hipLaunchKernelGGL(kern, dim3((unsigned)L.batch), dim3(64), Ly::bytes, st,
-                       static_cast<const typename F::In*>(L.A), L.out, L.ex, L.info, L.batch, L.in_off, L.out_off, o);
-    return hipGetLastError();
-}
-
-template <class F, int N>
-hipError_t dispatch_n(const LaunchMinors& L, hipStream_t st)
-{
-    if constexpr (N > 20) {
-        return hipErrorInvalidValue;
-    } else {
-        if (L.n_uniform == N) return launch_uniform<F, N>(L, st);
-        return dispatch_n<F, N + 1>(L, st);
-    }
-}
-
-}  // namespace
+hipError_t fpm_launch_r64(const LaunchMinors& L, hipStream_t st);
+hipError_t fpm_launch_r32s(const LaunchMinors& L, hipStream_t st);
+hipError_t fpm_launch_c128(const LaunchMinors& L, hipStream_t st);
+hipError_t fpm_launch_c64s(const LaunchMinors& L, hipStream_t st);
 
 hipError_t fpm_launch(const LaunchMinors& L, hipStream_t st)
 {
-    if (L.n_uniform <= 0) return hipErrorInvalidValue;   // ragged batches: see fpm_ragged.hip
     switch (L.dtype) {
-    case 0: return dispatch_n<FR64, 1>(L, st);
-    case 1: return dispatch_n<FR32S, 1>(L, st);
-    case 2: return dispatch_n<FC128, 1>(L, st);
-    case 3: return dispatch_n<FC64S, 1>(L, st);
+    case 0: return fpm_launch_r64(L, st);
+    case 1: return fpm_launch_r32s(L, st);
+    case 2: return fpm_launch_c128(L, st);
+    case 3: return fpm_launch_c64s(L, st);
     default: return hipErrorInvalidValue;
     }
 }

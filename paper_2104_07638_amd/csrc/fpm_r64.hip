@@ -1,0 +1,14 @@
+// fpm_r64.hip -- instantiation of the principal-minor kernels for one element type.
+#include "fpm_impl.h"
+
+namespace apm {
+
+template <>
+int default_k0<FR64>(int n)
+{
+    return 5;
+}
+
+hipError_t fpm_launch_r64(const LaunchMinors& L, hipStream_t st) { return fpm_launch_field<FR64>(L, st); }
+
+}  // namespace apm
