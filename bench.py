@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark of the principal-minor library on one MI355X.
+
+Headline workload: all 65,536 principal minors of each of 8192 synthetic propagator
+matrices of order n = 16 (2D square-lattice G0 with L=32, t=1, mu=-0.5, beta=5; vertices
+uniform on sites and imaginary time; one matrix in 64 made near-singular), fp64 path.
+One step = one apm_all_minors launch over the whole batch, inputs resident in HBM.
+
+Printed on stdout: ONE JSON line (metric, value = matrices/s, roofline of the minors
+kernel, the CPU oracle baseline, the fp32-scaled variant and the other workloads in
+"extra").  Everything else goes to stderr.
+
+Flags: --steps K --warmup W (timed / untimed steps), --gpus N (only N = 1 is supported),
+--no-cpu (skip the oracle baseline leg), --no-extra (skip the secondary workloads),
+--copy-calibration (run only a plain 1 GiB device copy; used to calibrate the HBM
+traffic counters).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "matrices/s all-principal-minors at n=16 (FP64 vs FP32-scaled); MC ESS/s"
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2104_07638_amd/csrc/fpm_impl.h", "paper_2104_07638_amd/csrc/apm_device.h",
+                  "paper_2104_07638_amd/csrc/fpm_r64.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fpm_r64_n16_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def ensure_built():
+    if not os.path.exists(os.path.join(ROOT, "paper_2104_07638_amd", "libapm.so")):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+class Timer:
+    """HIP events on the current stream (the stream the library launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = []
+
+    def __enter__(self):
+        t = self.torch
+        self.e0 = t.cuda.Event(enable_timing=True)
+        self.e1 = t.cuda.Event(enable_timing=True)
+        self.e0.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.e1.record()
+        self.pairs.append((self.e0, self.e1))
+
+    def avg_ms(self):
+        self.torch.cuda.synchronize()
+        v = [a.elapsed_time(b) for a, b in self.pairs]
+        return sum(v) / len(v)
+
+
+def time_fn(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t = Timer(torch)
+    for _ in range(reps):
+        with t:
+            fn()
+    return t.avg_ms()
+
+
+def copy_calibration():
+    import torch
+    n = (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copied 3 x {n * 8} bytes")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (matrices are independent; the batch would be "
+              "sharded with no exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    ensure_built()
+    import numpy as np
+    import torch
+
+    import paper_2104_07638_amd as apm
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    n, B = 16, 8192
+    lat = W.Lattice(32, 1.0, -0.5, 5.0)
+    log("generating inputs ...")
+    A = W.lattice_batch(B, n, lat, seed=W.BASE_SEED)
+    A, stress_log = W.inject_stress(A, every=64)
+    dA = torch.from_numpy(A).cuda()
+    out = torch.empty((B, 1 << n), dtype=torch.float64, device="cuda")
+    info = torch.empty(B, dtype=torch.int32, device="cuda")
+
+    def step():
+        apm.all_minors(dA, "r64", out=out, info=info)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kt = Timer(torch)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        with kt:
+            step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms = kt.avg_ms()
+    value = B * args.steps / elapsed
+    ms_per_step = elapsed * 1e3 / args.steps
+    infos = info.cpu().numpy()
+    log(f"r64 n={n} B={B}: {ms_per_step:.3f} ms/step, kernel {kern_ms:.3f} ms, {value / 1e6:.2f} M matrices/s; "
+        f"shifted pivots: {int((infos > 0).sum())} matrices (max {int(infos.max())}, total {int(infos[infos > 0].sum())}), errors: {int((infos < 0).sum())}")
+
+    bytes_per_matrix = 8 * n * n + 8 * (1 << n) + 4
+    achieved = bytes_per_matrix * B / (kern_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_hash") == kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": f"fpm_uniform_kernel<FR64,{n},5>", "bytes_per_launch": bytes_per_matrix * B,
+                "kernel_ms": round(kern_ms, 4)}
+
+    # ---- fp32-scaled variant on the same batch (mantissa + int16 exponent output)
+    out32 = torch.empty((B, 1 << n), dtype=torch.float32, device="cuda")
+    ex32 = torch.empty((B, 1 << n), dtype=torch.int16, device="cuda")
+    ms32 = time_fn(torch, lambda: apm.all_minors(dA, "r32s", out=out32, exp=ex32, info=info), args.steps)
+    fp32s = {"value": round(B / (ms32 * 1e-3), 1), "unit": "matrices/s", "ms_per_step": round(ms32, 4),
+             "ratio_vs_fp64": round(kern_ms / ms32, 3),
+             "achieved_GBs": round((8 * n * n + 6 * (1 << n) + 4) * B / (ms32 * 1e-3) / 1e9, 1)}
+    log(f"r32s: {ms32:.3f} ms, {fp32s['value'] / 1e6:.2f} M matrices/s")
+
+    extra = {}
+    if not args.no_extra:
+        extra = run_extra(torch, apm, W, np, args.steps)
+
+    cpu = None
+    accuracy = None
+    if not args.no_cpu:
+        cpu, accuracy = cpu_leg(np, A, stress_log, out, out32, ex32, apm)
+
+    res = {"metric": METRIC, "value": round(value, 1), "unit": "matrices/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "all principal minors, 8192 2D-lattice propagator matrices of order 16 "
+                                  "(L=32, t=1, mu=-0.5, beta=5), 1 in 64 near-singular",
+                      "n": n, "batch": B, "output": "fp64, 2^16 minors per matrix"},
+           "roofline": roofline, "cpu_baseline": cpu, "fp32s": fp32s, "accuracy": accuracy, "extra": extra}
+    print(json.dumps(res), flush=True)
+
+
+def run_extra(torch, apm, W, np, steps):
+    """Secondary workloads: each timed with HIP events on the current stream."""
+    ex = {}
+    # 1024 real 8 x 8 lattice matrices (L=16, mu=0, beta=4): launch-latency bound
+    A1 = torch.from_numpy(W.lattice_batch(1024, 8, W.Lattice(16, 1.0, 0.0, 4.0))).cuda()
+    o1 = torch.empty((1024, 256), dtype=torch.float64, device="cuda")
+    ms = time_fn(torch, lambda: apm.all_minors(A1, "r64", out=o1), steps)
+    ex["lattice_n8_1024_r64"] = {"us_per_launch": round(ms * 1e3, 2), "matrices_per_s": round(1024 / (ms * 1e-3), 1)}
+    # 4096 complex n = 14 Keldysh matrices, complex128 and complex64-scaled
+    K = torch.from_numpy(W.keldysh_batch(4096, 14)).cuda()
+    oc = torch.empty((4096, 1 << 14), dtype=torch.complex128, device="cuda")
+    ms = time_fn(torch, lambda: apm.all_minors(K, "c128", out=oc), steps)
+    ex["keldysh_n14_4096_c128"] = {"ms": round(ms, 4), "matrices_per_s": round(4096 / (ms * 1e-3), 1),
+                                   "GBs": round((16 * 196 + 16 * (1 << 14)) * 4096 / (ms * 1e-3) / 1e9, 1)}
+    del oc
+    oc = torch.empty((4096, 1 << 14), dtype=torch.complex64, device="cuda")
+    ec = torch.empty((4096, 1 << 14), dtype=torch.int16, device="cuda")
+    ms = time_fn(torch, lambda: apm.all_minors(K, "c64s", out=oc, exp=ec), steps)
+    ex["keldysh_n14_4096_c64s"] = {"ms": round(ms, 4), "matrices_per_s": round(4096 / (ms * 1e-3), 1),
+                                   "GBs": round((16 * 196 + 10 * (1 << 14)) * 4096 / (ms * 1e-3) / 1e9, 1)}
+    del oc, ec
+    for k, v in ex.items():
+        log(f"{k}: {v}")
+    return ex
+
+
+def cpu_leg(np, A, stress_log, out, out32, ex32, apm):
+    """The CPU oracle (LU per subset, fp64, all host threads) on a bounded sample of the
+    same batch; also the per-result error of both GPU paths on that sample."""
+    import oracle
+    from oracle import metrics
+    oracle._load()
+    stressed = [b for b, _, _ in stress_log]
+    order = stressed[:8] + [b for b in range(A.shape[0]) if b not in set(stressed[:8])]
+    done = []
+    t0 = time.perf_counter()
+    refs = []
+    chunk = 64
+    count = 0
+    while time.perf_counter() - t0 < 10.0 and count < 4 * len(order):
+        pos = count % len(order)
+        idx = order[pos:pos + chunk]
+        r = oracle.minors(A[idx])
+        if len(done) < 256:
+            refs.append(r[:256 - len(done)])
+            done.extend(idx[:256 - len(done)])
+        count += len(idx)
+    el = time.perf_counter() - t0
+    cores = oracle.max_threads()
+    cpu = {"value": round(count / el, 2), "unit": "matrices/s", "cores": cores, "kind": "oracle",
+           "sample": f"{count} matrices of the 8192-matrix order-16 batch (the first 8 near-singular ones "
+                     f"included), LU with partial pivoting per subset, fp64, {el:.1f} s"}
+    log(f"cpu oracle: {cpu}")
+    ref = np.concatenate(refs)
+    g64 = out[done].cpu().numpy()
+    g32 = apm.decode_scaled(out32[done], ex32[done]).cpu().numpy()
+    e64 = e32 = 0.0
+    r32 = 0.0
+    for k, b in enumerate(done[:256]):
+        H = metrics.hadamard_bounds(A[b])
+        e64 = max(e64, float(metrics.mixed_err(g64[k], ref[k], H).max()))
+        e32 = max(e32, float(metrics.mixed_err(g32[k], ref[k], H).max()))
+        nz = np.abs(ref[k]) > 1e-3 * H
+        r32 = max(r32, float(np.max(np.abs(g32[k][nz] - ref[k][nz]) / np.abs(ref[k][nz]))))
+    acc = {"matrices_checked": min(len(done), 256), "r64_max_mixed_err": e64, "r32s_max_mixed_err": e32,
+           "r32s_max_rel_err_well_conditioned": r32,
+           "metric": "|x - ref| / max(|ref|, Hadamard bound of A[S]) over every minor"}
+    log(f"accuracy: {acc}")
+    return cpu, acc
+
+
+if __name__ == "__main__":
+    main()

@@ -74,7 +74,7 @@ typedef struct {
  * two just below sqrt(r c) (s = max_ij |A_ij| when r c == 0).  The test is invariant
  * under diagonal similarity, as the minors are. */
 typedef struct {
-    double piv_tol;           /* <= 0: default 1e-3 (R64, C128) or 1e-2 (R32S, C64S)      */
+    double piv_tol;           /* <= 0: default 1e-4 (R64, C128) or 1e-3 (R32S, C64S)      */
     uint32_t flags;           /* APM_OUT_F64 | APM_NO_PERTURB                             */
 } apm_opts;
 

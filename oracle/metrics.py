@@ -1,4 +1,4 @@
-"""Error metrics for comparing principal minors with the oracle.
+"""Error metrics (test and benchmark infrastructure) for comparing principal minors with the oracle.
 
 Plain relative error is undefined for (near-)zero minors, so the parity gate is the
 mixed metric  e_S = |x_S - ref_S| / max(|ref_S|, H_S)  with the Hadamard bound

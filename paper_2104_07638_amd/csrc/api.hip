@@ -114,7 +114,7 @@ apm_status apm_all_minors(apm_dtype dt, const void* A, const apm_batch* bd, void
     L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N;
     L.in_off = bd->in_off;
     L.out_off = bd->out_off;
-    const double tau_def = scaled ? 1e-2 : 1e-3;
+    const double tau_def = scaled ? 1e-3 : 1e-4;
     L.tau = (opt && opt->piv_tol > 0) ? opt->piv_tol : tau_def;
     L.perturb = !(flags & APM_NO_PERTURB);
     L.out_f64 = out_f64;

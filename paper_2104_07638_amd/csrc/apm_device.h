@@ -21,6 +21,11 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Order this wavefront's own global stores before its later loads of the same addresses.
+// Each block is a single wavefront, so workgroup scope suffices: it waits for the
+// outstanding memory operations without the L2 write-back that an agent-scope fence costs.
+__device__ __forceinline__ void wave_mem_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p ? 1 : 0); }
@@ -87,7 +92,7 @@ struct FR64 {
     __device__ static double fincheck(Bs v) { return v * 0.0; }
     __device__ static V load_v(const void* out, const int16_t*, int64_t i, bool)
     {
-        return __builtin_nontemporal_load(static_cast<const double*>(out) + i);
+        return static_cast<const double*>(out)[i];
     }
     __device__ static void store_v(void* out, int16_t*, int64_t i, V v, bool)
     {
@@ -152,9 +157,9 @@ struct FR32S {
     __device__ static double fincheck(Bs v) { return (double)(v.m * 0.0f); }
     __device__ static V load_v(const void* out, const int16_t* ex, int64_t i, bool f64)
     {
-        if (f64) return __builtin_nontemporal_load(static_cast<const double*>(out) + i);
-        float m = __builtin_nontemporal_load(static_cast<const float*>(out) + i);
-        int16_t e = __builtin_nontemporal_load(ex + i);
+        if (f64) return static_cast<const double*>(out)[i];
+        float m = static_cast<const float*>(out)[i];
+        int16_t e = ex[i];
         return ldexp((double)m, (int)e);
     }
     __device__ static void store_v(void* out, int16_t* ex, int64_t i, V v, bool f64)
@@ -220,7 +225,7 @@ struct FC128 {
     __device__ static V load_v(const void* out, const int16_t*, int64_t i, bool)
     {
         const double* p = static_cast<const double*>(out) + 2 * i;
-        return {__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1)};
+        return {p[0], p[1]};
     }
     __device__ static void store_v(void* out, int16_t*, int64_t i, V v, bool)
     {
@@ -302,11 +307,11 @@ struct FC64S {
     {
         if (f64) {
             const double* p = static_cast<const double*>(out) + 2 * i;
-            return {__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1)};
+            return {p[0], p[1]};
         }
         const float* p = static_cast<const float*>(out) + 2 * i;
-        int e = __builtin_nontemporal_load(ex + i);
-        return {ldexp((double)__builtin_nontemporal_load(p), e), ldexp((double)__builtin_nontemporal_load(p + 1), e)};
+        int e = ex[i];
+        return {ldexp((double)p[0], e), ldexp((double)p[1], e)};
     }
     __device__ static void store_v(void* out, int16_t* ex, int64_t i, V v, bool f64)
     {

@@ -354,7 +354,7 @@ __device__ __noinline__ void chunk_fixup(void* out, int16_t* ex, int64_t base, i
     using P = Plan<N, K0MAX>;
     constexpr int k0 = P::k0;
     const bool active = lane < P::active;
-    __threadfence();
+    wave_mem_fence();
     if constexpr (k0 >= 2) {
         for (int dep = k0 - 2; dep >= 0; --dep) {
             const uint32_t lvl_mask = ((1u << (1 << dep)) - 1) << ((1 << dep) - 1);
@@ -364,16 +364,31 @@ __device__ __noinline__ void chunk_fixup(void* out, int16_t* ex, int64_t base, i
                 if (active && (ev >> id & 1u)) {
                     const uint64_t lw = id < 8 ? lc0 : lc1;
                     const double Ct = ldexp(1.0, es_true + (int)(int8_t)(uint8_t)(lw >> (8 * (id & 7))));
-                    for (int u = 1; u < (1 << (k0 - 1 - dep)); ++u) {
-                        const int j = q | (1 << dep) | (u << (dep + 1));
-                        const int64_t i = base + ((int64_t)j << kMid) + lane;
-                        const int64_t pi = i - ((int64_t)(1 << dep) << kMid);
-                        auto v = F::sub_scaled(F::load_v(out, ex, i, f64), Ct, F::load_v(out, ex, pi, f64));
-                        F::store_v(out, ex, i, v, f64);
+                    const int nu = 1 << (k0 - 1 - dep);
+                    const int64_t pstep = (int64_t)(1 << dep) << kMid;
+                    for (int u0 = 1; u0 < nu; u0 += 4) {
+                        typename F::V va[4], vb[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int u = u0 + k;
+                            if (u < nu) {
+                                const int64_t i = base + ((int64_t)(q | (1 << dep) | (u << (dep + 1))) << kMid) + lane;
+                                va[k] = F::load_v(out, ex, i, f64);
+                                vb[k] = F::load_v(out, ex, i - pstep, f64);
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int u = u0 + k;
+                            if (u < nu) {
+                                const int64_t i = base + ((int64_t)(q | (1 << dep) | (u << (dep + 1))) << kMid) + lane;
+                                F::store_v(out, ex, i, F::sub_scaled(va[k], Ct, vb[k]), f64);
+                            }
+                        }
                     }
                 }
             }
-            __threadfence();
+            wave_mem_fence();
         }
     }
     for (int b = P::mid - 1; b >= 0; --b) {
@@ -383,14 +398,25 @@ __device__ __noinline__ void chunk_fixup(void* out, int16_t* ex, int64_t base, i
         if (ballot(mine) == 0) continue;
         if (mine) {
             const double Ct = ldexp(1.0, es_true + de);
-            for (int j = 0; j < (1 << k0); ++j) {
-                if (j == 0 && (lane >> (b + 1)) == 0) continue;   // the node's own recorded minor
-                const int64_t i = base + ((int64_t)j << kMid) + lane;
-                auto v = F::sub_scaled(F::load_v(out, ex, i, f64), Ct, F::load_v(out, ex, i - (1 << b), f64));
-                F::store_v(out, ex, i, v, f64);
+            const int j0 = ((lane >> (b + 1)) == 0) ? 1 : 0;   // skip the node's own recorded minor
+            for (int jb = j0; jb < (1 << k0); jb += 4) {
+                typename F::V va[4], vb[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t i = base + ((int64_t)(jb + k) << kMid) + lane;
+                    if (jb + k < (1 << k0)) {
+                        va[k] = F::load_v(out, ex, i, f64);
+                        vb[k] = F::load_v(out, ex, i - (1 << b), f64);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t i = base + ((int64_t)(jb + k) << kMid) + lane;
+                    if (jb + k < (1 << k0)) F::store_v(out, ex, i, F::sub_scaled(va[k], Ct, vb[k]), f64);
+                }
             }
         }
-        __threadfence();
+        wave_mem_fence();
     }
 }
 
@@ -582,7 +608,7 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
     // ---- top-level corrections, deepest first ---------------------------------------
     if constexpr (T > 0) {
         if (any_top) {
-            __threadfence();
+            wave_mem_fence();
             for (int d = T - 1; d >= 0; --d) {
                 const int step = 1 << (T - 1 - d);
                 const int64_t half = int64_t(1) << (N - 1 - d);
@@ -592,14 +618,26 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
                     if (de == kNoEv) continue;
                     did = true;
                     const double Ct = ldexp(1.0, pc.es_true + de);
-                    const int64_t start = (int64_t)c << K;
-                    for (int64_t i = start + 1 + lane; i < start + half; i += kWave) {
-                        auto v = F::sub_scaled(F::load_v(out, ex, i, o.out_f64), Ct,
-                                               F::load_v(out, ex, i - half, o.out_f64));
-                        F::store_v(out, ex, i, v, o.out_f64);
+                    const int64_t start = (int64_t)c << K, end = start + half;
+                    constexpr int kU = 8;
+                    for (int64_t i0 = start + 1; i0 < end; i0 += kWave * kU) {
+                        typename F::V va[kU], vb[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int64_t i = i0 + lane + kWave * u;
+                            if (i < end) {
+                                va[u] = F::load_v(out, ex, i, o.out_f64);
+                                vb[u] = F::load_v(out, ex, i - half, o.out_f64);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int64_t i = i0 + lane + kWave * u;
+                            if (i < end) F::store_v(out, ex, i, F::sub_scaled(va[u], Ct, vb[u]), o.out_f64);
+                        }
                     }
                 }
-                if (did) __threadfence();
+                if (did) wave_mem_fence();
             }
         }
     }

@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-import metrics
+from oracle import metrics
 import workloads as W
 
 pytestmark = pytest.mark.gpu
