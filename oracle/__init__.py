@@ -67,6 +67,8 @@ def load_library(path: str):
     lib.apm_oracle_minors_r64_masks.argtypes = [ctypes.c_int, dp, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_uint32), dp]
     lib.apm_oracle_minors_r64_masks.restype = ctypes.c_int
+    lib.apm_oracle_cs_scale.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int]
+    lib.apm_oracle_cs_scale.restype = ctypes.c_int
     return lib
 
 
@@ -199,6 +201,21 @@ def connected_sums(a, mode: int = 0, nthreads: int = 0, lib=None) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle: bad arguments")
     return c[0] if single else c
+
+
+def cs_scale(a, c, mode: int = 0, lib=None) -> np.ndarray:
+    """Error scale of the recursion at every S (metric helper for parity tests):
+    d[S] = |a[S]| + sum_T |c[T]| |a[S \\ T]| over the recursion's terms."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    n = a.shape[-1].bit_length() - 1
+    d = np.empty_like(a)
+    for idx in np.ndindex(a.shape[:-1]):
+        rc = _load(lib).apm_oracle_cs_scale(n, _dp(np.ascontiguousarray(a[idx])), _dp(np.ascontiguousarray(c[idx])),
+                                            _dp(d[idx]), int(mode))
+        if rc != 0:
+            raise ValueError("oracle: bad arguments")
+    return d
 
 
 def perm_minors(A, nthreads: int = 0, lib=None) -> np.ndarray:

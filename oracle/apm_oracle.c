@@ -215,6 +215,32 @@ int apm_oracle_connected_sums(int n, const double *a, double *c, int mode)
     return 0;
 }
 
+/* Error scale of the recursion (test metric, not part of the method):
+ *     d[S] = |a[S]| + sum_{T subsetneq S, j in T} |c[T]| |a[S \ T]|
+ * with the same choice of j as apm_oracle_connected_sums; every rounding error of the
+ * recursion at S is a small multiple of eps * d[S]. */
+int apm_oracle_cs_scale(int n, const double *a, const double *c, double *d, int mode)
+{
+    if (n < 0 || n > ORACLE_MAX_N || (mode != 0 && mode != 1)) return -1;
+    const uint32_t nm = 1u << n;
+    d[0] = 0.0;
+    for (uint32_t S = 1; S < nm; ++S) {
+        uint32_t jbit = (mode == 0) ? 1u : (S & (0u - S));
+        if (!(S & jbit)) { d[S] = 0.0; continue; }
+        double acc = fabs(a[S]);
+        uint32_t rest = S & ~jbit;
+        uint32_t U = rest;
+        for (;;) {
+            uint32_t T = jbit | U;
+            if (T != S) acc += fabs(c[T]) * fabs(a[S & ~T]);
+            if (U == 0) break;
+            U = (U - 1) & rest;
+        }
+        d[S] = acc;
+    }
+    return 0;
+}
+
 /* Permanent principal minors by Ryser's formula applied to each subset S
  * separately (Sec. IV, the "naive successive application", O(n 3^n)):
  *     per(A[S]) = (-1)^|S| sum_{T subset of S} (-1)^|T| prod_{i in S} sum_{j in T} A_ij.

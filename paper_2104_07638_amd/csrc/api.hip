@@ -135,6 +135,7 @@ apm_status apm_connected_sums(const double* m_up, const double* m_dn, const apm_
     if (bd->in_off != bd->out_off) return APM_EINVAL;   // one offset array indexes inputs and output
     if (bd->batch == 0) return APM_OK;
     if (!m_up || !c) return APM_EINVAL;
+    if (c == m_up || c == m_dn) return APM_EINVAL;      // the output must not alias the inputs
     apm::LaunchCS L{};
     L.m_up = m_up;
     L.m_dn = m_dn;

@@ -1,0 +1,330 @@
+// csum.hip -- CDet connected sums (Sec. V.A, Eq. (recursion)) on gfx950.
+//
+//   c[S] = a[S] - sum_{T subsetneq S, j in T} c[T] a[S \ T],   a[S] = m_up[S] m_dn[S].
+//
+// For a distinguished vertex j write S = {j} + X and T = {j} + Y with X, Y subsets of the
+// vertices above j (m = n-1-j bits).  Then, with c'[X] = c[{j}+X], a0[X] = a[{j}+X] and
+// b[U] = a[U] (U above j, nonempty),
+//
+//   c'[X] = a0[X] - sum_{Y subsetneq X} c'[Y] b[X \ Y]                          (*)
+//
+// a triangular subset convolution of 3^m multiply-adds.  Rooted mode solves (*) for j = 0;
+// "all" mode solves it for every j (independent problems, one workgroup each).
+//
+// Blocking (one 256-thread workgroup per problem):
+//   * X = (X2, X1): X1 = the low P = min(m, 12) bits, X2 = the rest.  Blocks of 2^P values
+//     are staged in LDS (c' block and b block, 32 KiB each).  Block X2 needs every block
+//     Y2 subsetneq X2 (a full subset convolution of two blocks, "conv") and then the
+//     triangular solve (*) restricted to the block ("tri") with the b block of X2 = 0.
+//     The running right-hand side a0 - sum(conv) lives in the output array.
+//   * inside a block, X1 = (Xh, Xl) with Xl the low LB = min(P, 5) bits held in registers:
+//     one (Xh, Yh) pair is a 5-bit subset convolution of two 32-value rows, 243 FMAs for
+//     64 LDS loads.  Rows Xh are processed rank by rank (|Xh|); the 2^|Xh| pairs of a row
+//     are split over G lanes of one wavefront and summed with shuffles.
+//   * LDS rows are swizzled per 16-byte pair so that lanes reading different rows at the
+//     same column spread over the banks.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "apm_device.h"
+#include "apm_kernels.h"
+
+namespace apm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPmax = 12;
+
+__device__ __forceinline__ uint32_t pdep_u32(uint32_t k, uint32_t mask)
+{
+    uint32_t r = 0;
+    for (uint32_t bit = 1; mask; bit <<= 1) {
+        const uint32_t low = mask & (0u - mask);
+        if (k & bit) r |= low;
+        mask ^= low;
+    }
+    return r;
+}
+
+// Element X1 of an LDS block with rows of 2^LB values, pairs swizzled by row.
+template <int LB>
+__device__ __forceinline__ int sw(int x1)
+{
+    if constexpr (LB <= 1) {
+        return x1;
+    } else {
+        constexpr int W = 1 << LB;
+        constexpr int pm = (W >> 1) - 1;
+        const int row = x1 >> LB, col = x1 & (W - 1);
+        return row * W + ((((col >> 1) ^ (row & pm)) << 1) | (col & 1));
+    }
+}
+
+template <int LB>
+__device__ __forceinline__ void load_row(const double* buf, int row, double (&v)[1 << LB])
+{
+    constexpr int W = 1 << LB;
+    if constexpr (LB <= 1) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) v[i] = buf[row * W + i];
+    } else {
+        constexpr int pm = (W >> 1) - 1;
+        const double* r = buf + row * W;
+#pragma unroll
+        for (int p = 0; p < W / 2; ++p) {
+            const double2 t = *reinterpret_cast<const double2*>(r + 2 * (p ^ (row & pm)));
+            v[2 * p] = t.x;
+            v[2 * p + 1] = t.y;
+        }
+    }
+}
+
+// acc[x] -= sum_{y subset of x} f[y] g[x \ y]   (LB-bit subset convolution, unrolled)
+template <int LB>
+__device__ __forceinline__ void conv_tile(const double (&f)[1 << LB], const double (&g)[1 << LB],
+                                          double (&acc)[1 << LB])
+{
+    constexpr int W = 1 << LB;
+#pragma unroll
+    for (int x = 0; x < W; ++x)
+#pragma unroll
+        for (int y = 0; y < W; ++y)
+            if ((y & ~x) == 0) acc[x] = fma(-f[y], g[x ^ y], acc[x]);
+}
+
+// c[x] = r[x] - sum_{y subsetneq x} c[y] g0[x \ y], x in increasing order (in place on r).
+template <int LB>
+__device__ __forceinline__ void tri_tile(double (&r)[1 << LB], const double (&g0)[1 << LB])
+{
+    constexpr int W = 1 << LB;
+#pragma unroll
+    for (int x = 1; x < W; ++x)
+#pragma unroll
+        for (int y = 0; y < W; ++y)
+            if ((y & ~x) == 0 && y != x) r[x] = fma(-r[y], g0[x ^ y], r[x]);
+}
+
+struct CsArgs {
+    const double* up;
+    const double* dn;
+    double* c;
+    int weights;       // m_up already holds a[]
+};
+
+// a[S] from the inputs
+__device__ __forceinline__ double weight(const CsArgs& g, int64_t base, int64_t S)
+{
+    const double u = g.up[base + S];
+    if (g.weights) return u;
+    return u * (g.dn ? g.dn[base + S] : u);
+}
+
+template <int M>
+struct CsPlan {
+    static constexpr int P = M < kPmax ? M : kPmax;     // block bits
+    static constexpr int TB = M - P;                    // block-index bits
+    static constexpr int LB = P < 5 ? P : 5;            // register tile bits
+    static constexpr int H = P - LB;                    // row bits inside a block
+    static constexpr int ROWS = 1 << H;
+};
+
+// One rank pass over the rows of a block: TRI (rows of rank r of block X2, pairs
+// Yh subsetneq Xh, then the in-row triangular solve) or CONV (pairs Yh subset of Xh,
+// result subtracted from the right-hand side in the output).
+template <int M, bool TRI>
+__device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const int* rk_off, const double* cb,
+                                          const double* bb, double* cdst, const CsArgs& g, int64_t base,
+                                          int64_t sroot, int jsh, int x2, double* cb_out)
+{
+    using CP = CsPlan<M>;
+    constexpr int LB = CP::LB, W = 1 << LB, H = CP::H;
+    const int tid = threadIdx.x;
+    const int nout = rk_off[r + 1] - rk_off[r];
+    const int items = TRI ? (1 << r) - 1 : (1 << r);
+    int G = 1;
+    while (G * 2 <= kWave && nout * G * 2 <= kThreads && G * 2 <= (items > 0 ? items : 1)) G *= 2;
+    const int per_pass = kThreads / G;
+    for (int ob = 0; ob < nout; ob += per_pass) {
+        const int o = ob + tid / G;
+        const int s = tid % G;
+        const bool valid = o < nout;
+        const uint32_t xh = valid ? rk_tab[rk_off[r] + o] : 0u;
+        double acc[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) acc[i] = 0.0;
+        if (valid) {
+            for (int k = s; k < items; k += G) {
+                const uint32_t yh = pdep_u32((uint32_t)k, xh);
+                double f[W], gg[W];
+                load_row<LB>(cb, (int)yh, f);
+                load_row<LB>(bb, (int)(xh ^ yh), gg);
+                conv_tile<LB>(f, gg, acc);
+            }
+        }
+        // sum the G partial rows (consecutive lanes of one wavefront)
+        for (int off = 1; off < G; off <<= 1)
+#pragma unroll
+            for (int i = 0; i < W; ++i) acc[i] += __shfl_xor(acc[i], off);
+        if (valid && s == 0) {
+            // right-hand side row (Xh, .) of block x2, in the output array
+            const int64_t xrow = ((int64_t)x2 << CP::P) | ((int64_t)xh << LB);
+            double rr[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) rr[i] = cdst[sroot + ((xrow | i) << jsh)] + acc[i];
+            if constexpr (TRI) {
+                double g0[W];
+                load_row<LB>(bb, 0, g0);
+                tri_tile<LB>(rr, g0);
+                double* out = cb_out + (int)xh * W;
+                if constexpr (LB <= 1) {
+#pragma unroll
+                    for (int i = 0; i < W; ++i) out[i] = rr[i];
+                } else {
+                    constexpr int pm = (W >> 1) - 1;
+#pragma unroll
+                    for (int p = 0; p < W / 2; ++p)
+                        *reinterpret_cast<double2*>(out + 2 * (p ^ ((int)xh & pm))) = make_double2(rr[2 * p], rr[2 * p + 1]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i) cdst[sroot + ((xrow | i) << jsh)] = rr[i];
+        }
+    }
+    (void)base;
+    (void)g;
+    (void)H;
+}
+
+// Problem (matrix b, root j): solve (*) for the m = n-1-j vertices above j.
+template <int M>
+__device__ void cs_problem(const CsArgs& g, int64_t base, int n, int j, double* lds_c, double* lds_b,
+                           uint16_t* rk_tab, int* rk_off)
+{
+    using CP = CsPlan<M>;
+    constexpr int P = CP::P, LB = CP::LB, H = CP::H;
+    const int tid = threadIdx.x;
+    const int jsh = j + 1;                          // X -> S = (1 << j) | (X << (j+1))
+    const int64_t sroot = base + (int64_t(1) << j);  // element index of S = {j}
+    double* c = g.c;
+    (void)n;
+
+    // rows of a block sorted by rank
+    if (tid == 0) {
+        int pos = 0;
+        for (int r = 0; r <= H; ++r) {
+            rk_off[r] = pos;
+            for (int x = 0; x < (1 << H); ++x)
+                if (__builtin_popcount(x) == r) rk_tab[pos++] = (uint16_t)x;
+        }
+        rk_off[H + 1] = pos;
+    }
+    // right-hand side a0 into the output positions
+    for (int64_t x = tid; x < (int64_t(1) << M); x += kThreads) c[sroot + (x << jsh)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
+    __syncthreads();
+
+    for (int x2 = 0; x2 < (1 << CP::TB); ++x2) {
+        // cross-block contributions: every Y2 subsetneq X2
+        for (uint32_t y2 = 0; y2 < (uint32_t)x2; ++y2) {
+            if (y2 & ~(uint32_t)x2) continue;   // proper subsets of X2 only
+            const uint32_t d2 = (uint32_t)x2 ^ y2;
+            for (int x1 = tid; x1 < (1 << P); x1 += kThreads) {
+                const int64_t xy = ((int64_t)y2 << P) | x1;
+                lds_c[sw<LB>(x1)] = c[sroot + (xy << jsh)];
+                const int64_t xd = ((int64_t)d2 << P) | x1;
+                lds_b[sw<LB>(x1)] = weight(g, base, xd << jsh);
+            }
+            __syncthreads();
+            for (int r = 0; r <= H; ++r) {
+                rank_pass<M, false>(r, rk_tab, rk_off, lds_c, lds_b, c, g, base, sroot, jsh, x2, nullptr);
+            }
+            __syncthreads();
+        }
+        // the block's own triangular solve, with b of block 0
+        for (int x1 = tid; x1 < (1 << P); x1 += kThreads)
+            lds_b[sw<LB>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
+        __syncthreads();
+        for (int r = 0; r <= H; ++r) {
+            rank_pass<M, true>(r, rk_tab, rk_off, lds_c, lds_b, c, g, base, sroot, jsh, x2, lds_c);
+            __syncthreads();
+        }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void cs_kernel(CsArgs g, int32_t batch, int n_uniform, const int32_t* nv,
+                                                      const int64_t* off, uint32_t mode, int roots)
+{
+    __shared__ __align__(16) double lds_c[1 << CsPlan<M>::P];
+    __shared__ __align__(16) double lds_b[1 << CsPlan<M>::P];
+    __shared__ uint16_t rk_tab[1 << CsPlan<M>::H];
+    __shared__ int rk_off[CsPlan<M>::H + 2];
+    const int b = blockIdx.x / roots;
+    const int j = blockIdx.x % roots;
+    if (b >= batch) return;
+    const int n = n_uniform > 0 ? n_uniform : nv[b];
+    if (n - 1 - j != M) return;   // launched for problems with exactly M bits
+    const int64_t base = off ? off[b] : ((int64_t)b << n);
+    cs_problem<M>(g, base, n, j, lds_c, lds_b, rk_tab, rk_off);
+    (void)mode;
+}
+
+// c[S] = 0 outside the rooted problem (S without vertex 0) and c[empty] = 0 in all modes.
+__global__ void cs_zero_kernel(double* c, int32_t batch, int n_uniform, const int32_t* nv, const int64_t* off,
+                               uint32_t mode)
+{
+    const int b = blockIdx.y;
+    if (b >= batch) return;
+    const int n = n_uniform > 0 ? n_uniform : nv[b];
+    const int64_t base = off ? off[b] : ((int64_t)b << n);
+    const int64_t nm = int64_t(1) << n;
+    if (mode & 1u) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) c[base] = 0.0;
+        return;
+    }
+    for (int64_t s = (int64_t)(blockIdx.x * blockDim.x + threadIdx.x) * 2; s < nm; s += (int64_t)gridDim.x * blockDim.x * 2)
+        c[base + s] = 0.0;
+}
+
+template <int M>
+hipError_t launch_m(const LaunchCS& L, CsArgs g, int roots, hipStream_t st)
+{
+    hipLaunchKernelGGL(cs_kernel<M>, dim3((unsigned)(L.batch * roots)), dim3(kThreads), 0, st, g, L.batch,
+                       L.n_uniform, L.n, L.off, L.mode, roots);
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_all_m(int mlo, int mhi, const LaunchCS& L, CsArgs g, int roots, hipStream_t st)
+{
+    if constexpr (M < 0) {
+        return hipSuccess;
+    } else {
+        if (M >= mlo && M <= mhi) {
+            hipError_t e = launch_m<M>(L, g, roots, st);
+            if (e != hipSuccess) return e;
+        }
+        return launch_all_m<M - 1>(mlo, mhi, L, g, roots, st);
+    }
+}
+
+}  // namespace
+
+hipError_t cs_launch(const LaunchCS& L, hipStream_t st)
+{
+    CsArgs g{L.m_up, L.m_dn, L.c, (L.mode & 2u) ? 1 : 0};
+    const bool all = (L.mode & 1u) != 0;
+    const int nmax = L.n_uniform > 0 ? L.n_uniform : L.n_max;
+    const int nmin = L.n_uniform > 0 ? L.n_uniform : 1;
+    const int roots = all ? nmax : 1;
+    // one launch per problem size m = n-1-j (largest first); each block exits unless its
+    // problem has exactly that size
+    const int mhi = nmax - 1;
+    const int mlo = all ? 0 : nmin - 1;
+    hipError_t e = launch_all_m<19>(mlo, mhi, L, g, roots, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cs_zero_kernel, dim3(64, (unsigned)L.batch), dim3(256), 0, st, L.c, L.batch, L.n_uniform,
+                       L.n, L.off, L.mode);
+    return hipGetLastError();
+}
+
+}  // namespace apm
