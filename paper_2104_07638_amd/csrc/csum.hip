@@ -12,15 +12,15 @@
 // "all" mode solves it for every j (independent problems, one workgroup each).
 //
 // Blocking (one 256-thread workgroup per problem):
-//   * X = (X2, X1): X1 = the low P = min(m, 12) bits, X2 = the rest.  Blocks of 2^P values
-//     are staged in LDS (c' block and b block, 32 KiB each).  Block X2 needs every block
+//   * X = (X2, X1): X1 = the low P = min(m, 11) bits, X2 = the rest.  Blocks of 2^P values
+//     are staged in LDS (c' block, b block and the right-hand side, 16 KiB each).  Block X2 needs every block
 //     Y2 subsetneq X2 (a full subset convolution of two blocks, "conv") and then the
 //     triangular solve (*) restricted to the block ("tri") with the b block of X2 = 0.
 //     The running right-hand side a0 - sum(conv) lives in the output array.
 //   * inside a block, X1 = (Xh, Xl) with Xl the low LB = min(P, 5) bits held in registers:
 //     one (Xh, Yh) pair is a 5-bit subset convolution of two 32-value rows, 243 FMAs for
 //     64 LDS loads.  Rows Xh are processed rank by rank (|Xh|); the 2^|Xh| pairs of a row
-//     are split over G lanes of one wavefront and summed with shuffles.
+//     are split over G lanes of one wavefront and summed with DPP row shifts.
 //   * LDS rows are swizzled per 16-byte pair so that lanes reading different rows at the
 //     same column spread over the banks.
 #include <hip/hip_runtime.h>
@@ -32,8 +32,11 @@
 namespace apm {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kPmax = 12;
+constexpr int kPmax = 11;
+
+// threads per problem: one wavefront for small problems, four for large ones
+template <int M>
+constexpr int cs_threads() { return M <= 10 ? 64 : 256; }
 
 __device__ __forceinline__ uint32_t pdep_u32(uint32_t k, uint32_t mask)
 {
@@ -104,6 +107,92 @@ __device__ __forceinline__ void tri_tile(double (&r)[1 << LB], const double (&g0
             if ((y & ~x) == 0 && y != x) r[x] = fma(-r[y], g0[x ^ y], r[x]);
 }
 
+// The same product for 5-bit tiles with the operands loaded in halves (split on the top
+// tile bit), so that only 48 operand values are live at a time:
+//   acc_lo -= f_lo * g_lo;  acc_hi -= f_lo * g_hi + f_hi * g_lo.
+template <int LB>
+__device__ __forceinline__ void load_half(const double* buf, int row, int half, double (&v)[1 << (LB - 1)])
+{
+    constexpr int W = 1 << LB;
+    constexpr int pm = (W >> 1) - 1;
+    const double* r = buf + row * W;
+#pragma unroll
+    for (int p = 0; p < W / 4; ++p) {
+        const int pp = p + half * (W / 4);
+        const double2 t = *reinterpret_cast<const double2*>(r + 2 * (pp ^ (row & pm)));
+        v[2 * p] = t.x;
+        v[2 * p + 1] = t.y;
+    }
+}
+
+template <int HB>
+__device__ __forceinline__ void conv_half(const double (&f)[1 << HB], const double (&g)[1 << HB], double* acc)
+{
+    constexpr int W = 1 << HB;
+#pragma unroll
+    for (int x = 0; x < W; ++x)
+#pragma unroll
+        for (int y = 0; y < W; ++y)
+            if ((y & ~x) == 0) acc[x] = fma(-f[y], g[x ^ y], acc[x]);
+}
+
+template <int LB>
+__device__ __forceinline__ void conv_rows_split(const double* cb, int yrow, const double* bb, int drow,
+                                                double (&acc)[1 << LB])
+{
+    constexpr int HW = 1 << (LB - 1);
+    double f[HW], g0[HW], g1[HW];
+    load_half<LB>(cb, yrow, 0, f);
+    load_half<LB>(bb, drow, 0, g0);
+    load_half<LB>(bb, drow, 1, g1);
+    conv_half<LB - 1>(f, g0, acc);
+    conv_half<LB - 1>(f, g1, acc + HW);
+    load_half<LB>(cb, yrow, 1, f);
+    conv_half<LB - 1>(f, g0, acc + HW);
+}
+
+// v += v of the lane DELTA below (0 if outside the row of 16 / the group), for doubles.
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_add(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int slo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xF, true);
+    const int shi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xF, true);
+    return v + __hiloint2double(shi, slo);
+}
+
+// Sum over aligned groups of G consecutive lanes; the total lands in the LAST lane of
+// each group.  row_shr:k (0x110 + k) shifts within rows of 16 lanes; row_bcast:15 (0x142)
+// and row_bcast:31 (0x143) carry row ends across rows.
+template <int W>
+__device__ __forceinline__ void group_sum(double (&acc)[W], int G)
+{
+    if (G >= 2) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) acc[i] = dpp_add<0x111>(acc[i]);
+    }
+    if (G >= 4) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) acc[i] = dpp_add<0x112>(acc[i]);
+    }
+    if (G >= 8) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) acc[i] = dpp_add<0x114>(acc[i]);
+    }
+    if (G >= 16) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) acc[i] = dpp_add<0x118>(acc[i]);
+    }
+    if (G >= 32) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) acc[i] = dpp_add<0x142, 0xA>(acc[i]);
+    }
+    if (G >= 64) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) acc[i] = dpp_add<0x143, 0xC>(acc[i]);
+    }
+}
+
 struct CsArgs {
     const double* up;
     const double* dn;
@@ -131,19 +220,38 @@ struct CsPlan {
 // One rank pass over the rows of a block: TRI (rows of rank r of block X2, pairs
 // Yh subsetneq Xh, then the in-row triangular solve) or CONV (pairs Yh subset of Xh,
 // result subtracted from the right-hand side in the output).
+template <int LB>
+__device__ __forceinline__ void store_row(double* buf, int row, const double (&v)[1 << LB])
+{
+    constexpr int W = 1 << LB;
+    if constexpr (LB <= 1) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) buf[row * W + i] = v[i];
+    } else {
+        constexpr int pm = (W >> 1) - 1;
+        double* r = buf + row * W;
+#pragma unroll
+        for (int p = 0; p < W / 2; ++p)
+            *reinterpret_cast<double2*>(r + 2 * (p ^ (row & pm))) = make_double2(v[2 * p], v[2 * p + 1]);
+    }
+}
+
+// One rank pass over the rows Xh of rank r of a block: TRI (pairs Yh subsetneq Xh, then
+// the in-row triangular solve; the finished row goes to cb_out) or CONV (pairs Yh subset
+// of Xh).  Either way the result updates the right-hand-side row in rb.
 template <int M, bool TRI>
 __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const int* rk_off, const double* cb,
-                                          const double* bb, double* cdst, const CsArgs& g, int64_t base,
-                                          int64_t sroot, int jsh, int x2, double* cb_out)
+                                          const double* bb, double* rb, double* cb_out)
 {
     using CP = CsPlan<M>;
-    constexpr int LB = CP::LB, W = 1 << LB, H = CP::H;
+    constexpr int LB = CP::LB, W = 1 << LB;
+    constexpr int NT = cs_threads<M>();
     const int tid = threadIdx.x;
     const int nout = rk_off[r + 1] - rk_off[r];
     const int items = TRI ? (1 << r) - 1 : (1 << r);
     int G = 1;
-    while (G * 2 <= kWave && nout * G * 2 <= kThreads && G * 2 <= (items > 0 ? items : 1)) G *= 2;
-    const int per_pass = kThreads / G;
+    while (G * 2 <= kWave && nout * G * 2 <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
+    const int per_pass = NT / G;
     for (int ob = 0; ob < nout; ob += per_pass) {
         const int o = ob + tid / G;
         const int s = tid % G;
@@ -155,61 +263,49 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
         if (valid) {
             for (int k = s; k < items; k += G) {
                 const uint32_t yh = pdep_u32((uint32_t)k, xh);
-                double f[W], gg[W];
-                load_row<LB>(cb, (int)yh, f);
-                load_row<LB>(bb, (int)(xh ^ yh), gg);
-                conv_tile<LB>(f, gg, acc);
+                if constexpr (LB >= 3) {
+                    conv_rows_split<LB>(cb, (int)yh, bb, (int)(xh ^ yh), acc);
+                } else {
+                    double f[W], gg[W];
+                    load_row<LB>(cb, (int)yh, f);
+                    load_row<LB>(bb, (int)(xh ^ yh), gg);
+                    conv_tile<LB>(f, gg, acc);
+                }
             }
         }
-        // sum the G partial rows (consecutive lanes of one wavefront)
-        for (int off = 1; off < G; off <<= 1)
-#pragma unroll
-            for (int i = 0; i < W; ++i) acc[i] += __shfl_xor(acc[i], off);
-        if (valid && s == 0) {
-            // right-hand side row (Xh, .) of block x2, in the output array
-            const int64_t xrow = ((int64_t)x2 << CP::P) | ((int64_t)xh << LB);
+        // sum the G partial rows (consecutive lanes of one wavefront) into the last lane
+        group_sum<W>(acc, G);
+        if (valid && s == G - 1) {
             double rr[W];
+            load_row<LB>(rb, (int)xh, rr);
 #pragma unroll
-            for (int i = 0; i < W; ++i) rr[i] = cdst[sroot + ((xrow | i) << jsh)] + acc[i];
+            for (int i = 0; i < W; ++i) rr[i] += acc[i];
             if constexpr (TRI) {
                 double g0[W];
                 load_row<LB>(bb, 0, g0);
                 tri_tile<LB>(rr, g0);
-                double* out = cb_out + (int)xh * W;
-                if constexpr (LB <= 1) {
-#pragma unroll
-                    for (int i = 0; i < W; ++i) out[i] = rr[i];
-                } else {
-                    constexpr int pm = (W >> 1) - 1;
-#pragma unroll
-                    for (int p = 0; p < W / 2; ++p)
-                        *reinterpret_cast<double2*>(out + 2 * (p ^ ((int)xh & pm))) = make_double2(rr[2 * p], rr[2 * p + 1]);
-                }
+                store_row<LB>(cb_out, (int)xh, rr);
+            } else {
+                store_row<LB>(rb, (int)xh, rr);
             }
-#pragma unroll
-            for (int i = 0; i < W; ++i) cdst[sroot + ((xrow | i) << jsh)] = rr[i];
         }
     }
-    (void)base;
-    (void)g;
-    (void)H;
 }
 
 // Problem (matrix b, root j): solve (*) for the m = n-1-j vertices above j.
 template <int M>
-__device__ void cs_problem(const CsArgs& g, int64_t base, int n, int j, double* lds_c, double* lds_b,
+__device__ void cs_problem(const CsArgs& g, int64_t base, int j, double* lds_c, double* lds_b, double* lds_r,
                            uint16_t* rk_tab, int* rk_off)
 {
     using CP = CsPlan<M>;
     constexpr int P = CP::P, LB = CP::LB, H = CP::H;
+    constexpr int NT = cs_threads<M>();
     const int tid = threadIdx.x;
     const int jsh = j + 1;                          // X -> S = (1 << j) | (X << (j+1))
     const int64_t sroot = base + (int64_t(1) << j);  // element index of S = {j}
     double* c = g.c;
-    (void)n;
 
-    // rows of a block sorted by rank
-    if (tid == 0) {
+    if (tid == 0) {                                 // rows of a block sorted by rank
         int pos = 0;
         for (int r = 0; r <= H; ++r) {
             rk_off[r] = pos;
@@ -218,44 +314,44 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int n, int j, double* 
         }
         rk_off[H + 1] = pos;
     }
-    // right-hand side a0 into the output positions
-    for (int64_t x = tid; x < (int64_t(1) << M); x += kThreads) c[sroot + (x << jsh)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
-    __syncthreads();
-
     for (int x2 = 0; x2 < (1 << CP::TB); ++x2) {
+        // right-hand side a0 of the block
+        for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+            const int64_t x = ((int64_t)x2 << P) | x1;
+            lds_r[sw<LB>(x1)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
+        }
         // cross-block contributions: every Y2 subsetneq X2
         for (uint32_t y2 = 0; y2 < (uint32_t)x2; ++y2) {
-            if (y2 & ~(uint32_t)x2) continue;   // proper subsets of X2 only
+            if (y2 & ~(uint32_t)x2) continue;
             const uint32_t d2 = (uint32_t)x2 ^ y2;
-            for (int x1 = tid; x1 < (1 << P); x1 += kThreads) {
-                const int64_t xy = ((int64_t)y2 << P) | x1;
-                lds_c[sw<LB>(x1)] = c[sroot + (xy << jsh)];
-                const int64_t xd = ((int64_t)d2 << P) | x1;
-                lds_b[sw<LB>(x1)] = weight(g, base, xd << jsh);
+            __syncthreads();
+            for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+                lds_c[sw<LB>(x1)] = c[sroot + ((((int64_t)y2 << P) | x1) << jsh)];
+                lds_b[sw<LB>(x1)] = weight(g, base, (((int64_t)d2 << P) | x1) << jsh);
             }
             __syncthreads();
-            for (int r = 0; r <= H; ++r) {
-                rank_pass<M, false>(r, rk_tab, rk_off, lds_c, lds_b, c, g, base, sroot, jsh, x2, nullptr);
-            }
-            __syncthreads();
+            for (int r = 0; r <= H; ++r) rank_pass<M, false>(r, rk_tab, rk_off, lds_c, lds_b, lds_r, nullptr);
         }
         // the block's own triangular solve, with b of block 0
-        for (int x1 = tid; x1 < (1 << P); x1 += kThreads)
-            lds_b[sw<LB>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
+        __syncthreads();
+        for (int x1 = tid; x1 < (1 << P); x1 += NT) lds_b[sw<LB>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
         __syncthreads();
         for (int r = 0; r <= H; ++r) {
-            rank_pass<M, true>(r, rk_tab, rk_off, lds_c, lds_b, c, g, base, sroot, jsh, x2, lds_c);
+            rank_pass<M, true>(r, rk_tab, rk_off, lds_c, lds_b, lds_r, lds_c);
             __syncthreads();
         }
+        for (int x1 = tid; x1 < (1 << P); x1 += NT)
+            c[sroot + ((((int64_t)x2 << P) | x1) << jsh)] = lds_c[sw<LB>(x1)];
     }
 }
 
 template <int M>
-__global__ __launch_bounds__(kThreads) void cs_kernel(CsArgs g, int32_t batch, int n_uniform, const int32_t* nv,
-                                                      const int64_t* off, uint32_t mode, int roots)
+__global__ __launch_bounds__(cs_threads<M>()) void cs_kernel(CsArgs g, int32_t batch, int n_uniform,
+                                                             const int32_t* nv, const int64_t* off, int roots)
 {
     __shared__ __align__(16) double lds_c[1 << CsPlan<M>::P];
     __shared__ __align__(16) double lds_b[1 << CsPlan<M>::P];
+    __shared__ __align__(16) double lds_r[1 << CsPlan<M>::P];
     __shared__ uint16_t rk_tab[1 << CsPlan<M>::H];
     __shared__ int rk_off[CsPlan<M>::H + 2];
     const int b = blockIdx.x / roots;
@@ -264,8 +360,7 @@ __global__ __launch_bounds__(kThreads) void cs_kernel(CsArgs g, int32_t batch, i
     const int n = n_uniform > 0 ? n_uniform : nv[b];
     if (n - 1 - j != M) return;   // launched for problems with exactly M bits
     const int64_t base = off ? off[b] : ((int64_t)b << n);
-    cs_problem<M>(g, base, n, j, lds_c, lds_b, rk_tab, rk_off);
-    (void)mode;
+    cs_problem<M>(g, base, j, lds_c, lds_b, lds_r, rk_tab, rk_off);
 }
 
 // c[S] = 0 outside the rooted problem (S without vertex 0) and c[empty] = 0 in all modes.
@@ -288,8 +383,8 @@ __global__ void cs_zero_kernel(double* c, int32_t batch, int n_uniform, const in
 template <int M>
 hipError_t launch_m(const LaunchCS& L, CsArgs g, int roots, hipStream_t st)
 {
-    hipLaunchKernelGGL(cs_kernel<M>, dim3((unsigned)(L.batch * roots)), dim3(kThreads), 0, st, g, L.batch,
-                       L.n_uniform, L.n, L.off, L.mode, roots);
+    hipLaunchKernelGGL(cs_kernel<M>, dim3((unsigned)(L.batch * roots)), dim3(cs_threads<M>()), 0, st, g, L.batch,
+                       L.n_uniform, L.n, L.off, roots);
     return hipGetLastError();
 }
 
