@@ -18,9 +18,9 @@ apm_status from_hip(hipError_t e)
     return APM_EDEVICE;
 }
 
-// Per-device workspace for ragged batches: the queue order array and its head counter.
+// Per-device workspace for ragged batches: queue head, queue order, packed offsets.
 struct Workspace {
-    int32_t* buf = nullptr;     // [cap + 64]: counter at buf[0], order at buf[64...]
+    void* buf = nullptr;        // counter (256 B) | order [cap] int32 | ioff [cap] int64 | ooff [cap] int64
     int64_t cap = 0;
     int cus = 0;
 };
@@ -28,7 +28,8 @@ struct Workspace {
 std::mutex g_ws_mu;
 std::vector<Workspace> g_ws;
 
-apm_status get_workspace(int64_t batch, int32_t** counter, int32_t** order, int* cus)
+apm_status get_workspace(int64_t batch, int32_t** counter, int32_t** order, int64_t** ioff, int64_t** ooff,
+                         int* cus)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -46,12 +47,15 @@ apm_status get_workspace(int64_t batch, int32_t** counter, int32_t** order, int*
         if (w.buf) (void)hipFree(w.buf);
         w.buf = nullptr;
         int64_t cap = batch < 4096 ? 4096 : batch;
-        e = hipMalloc((void**)&w.buf, sizeof(int32_t) * (size_t)(cap + 64));
+        e = hipMalloc(&w.buf, 256 + (size_t)cap * (4 + 8 + 8));
         if (e != hipSuccess) { w.cap = 0; return from_hip(e); }
         w.cap = cap;
     }
-    *counter = w.buf;
-    *order = w.buf + 64;
+    char* p = static_cast<char*>(w.buf);
+    *counter = reinterpret_cast<int32_t*>(p);
+    *order = reinterpret_cast<int32_t*>(p + 256);
+    *ioff = reinterpret_cast<int64_t*>(p + 256 + (size_t)w.cap * 4);
+    *ooff = reinterpret_cast<int64_t*>(p + 256 + (size_t)w.cap * 12);
     *cus = w.cus;
     return APM_OK;
 }
@@ -119,7 +123,7 @@ apm_status apm_all_minors(apm_dtype dt, const void* A, const apm_batch* bd, void
     L.perturb = !(flags & APM_NO_PERTURB);
     L.out_f64 = out_f64;
     if (bd->n_uniform == 0) {
-        apm_status s = get_workspace(bd->batch, &L.counter, &L.order, &L.n_workers);
+        apm_status s = get_workspace(bd->batch, &L.counter, &L.order, &L.ioff_ws, &L.ooff_ws, &L.n_workers);
         if (s != APM_OK) return s;
     }
     return from_hip(apm::fpm_launch(L, (hipStream_t)stream));

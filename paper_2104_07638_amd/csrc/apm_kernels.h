@@ -20,11 +20,14 @@ struct LaunchMinors {
     double tau;
     bool perturb, out_f64;
     int32_t* order;            // ragged: workspace [batch] (matrix indices, descending n)
-    int32_t* counter;          // ragged: workspace, 1 int queue head
-    int n_workers;             // ragged: persistent waves to launch
+    int32_t* counter;          // ragged: workspace, queue head
+    int64_t* ioff_ws;          // ragged: workspace [batch] packed input offsets (if in_off == NULL)
+    int64_t* ooff_ws;          // ragged: workspace [batch] packed output offsets (if out_off == NULL)
+    int n_workers;             // ragged: number of compute units (persistent grid sizing)
 };
 
 hipError_t fpm_launch(const LaunchMinors& L, hipStream_t st);
+hipError_t fpm_prep_launch(const LaunchMinors& L, hipStream_t st);   // ragged-batch queue preparation
 
 struct LaunchCS {
     const double* m_up;

@@ -3,6 +3,69 @@
 
 namespace apm {
 
+// Queue preparation (one workgroup): bucket the matrices by order, largest first, so the
+// persistent waves start with the longest work; packed default offsets; queue head = 0.
+__global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int32_t* __restrict__ nv, int32_t* order,
+                                                        int32_t* counter, int64_t* ioff, int64_t* ooff)
+{
+    __shared__ int cnt[22];
+    __shared__ int pos[22];
+    __shared__ int64_t carry[2];
+    __shared__ int64_t part[2][1024];
+    const int t = threadIdx.x;
+    if (t < 22) cnt[t] = 0;
+    if (t < 2) carry[t] = 0;
+    __syncthreads();
+    // bucket 21 - n for valid orders (so that larger n come first), 21 for invalid ones
+    for (int b = t; b < batch; b += 1024) {
+        const int n = nv[b];
+        atomicAdd(&cnt[(n >= 1 && n <= 20) ? 20 - n : 21], 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int s = 0;
+        for (int k = 0; k < 22; ++k) { pos[k] = s; s += cnt[k]; }
+        counter[0] = 0;
+    }
+    __syncthreads();
+    for (int b = t; b < batch; b += 1024) {
+        const int n = nv[b];
+        const int k = (n >= 1 && n <= 20) ? 20 - n : 21;
+        order[atomicAdd(&pos[k], 1)] = b;
+    }
+    // exclusive prefix sums of n^2 and 2^n in matrix order (chunks of 1024)
+    for (int b0 = 0; b0 < batch; b0 += 1024) {
+        const int b = b0 + t;
+        const int n = (b < batch) ? nv[b] : 0;
+        const bool ok = n >= 1 && n <= 20;
+        part[0][t] = ok ? (int64_t)n * n : 0;
+        part[1][t] = ok ? (int64_t(1) << n) : 0;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            int64_t a0 = 0, a1 = 0;
+            if (t >= d) { a0 = part[0][t - d]; a1 = part[1][t - d]; }
+            __syncthreads();
+            part[0][t] += a0;
+            part[1][t] += a1;
+            __syncthreads();
+        }
+        if (b < batch) {
+            ioff[b] = carry[0] + part[0][t] - (ok ? (int64_t)n * n : 0);
+            ooff[b] = carry[1] + part[1][t] - (ok ? (int64_t(1) << n) : 0);
+        }
+        __syncthreads();
+        if (t == 1023) { carry[0] += part[0][1023]; carry[1] += part[1][1023]; }
+        __syncthreads();
+    }
+}
+
+hipError_t fpm_prep_launch(const LaunchMinors& L, hipStream_t st)
+{
+    hipLaunchKernelGGL(fpm_prep_kernel, dim3(1), dim3(1024), 0, st, L.batch, L.n, L.order, L.counter, L.ioff_ws,
+                       L.ooff_ws);
+    return hipGetLastError();
+}
+
 hipError_t fpm_launch_r64(const LaunchMinors& L, hipStream_t st);
 hipError_t fpm_launch_r32s(const LaunchMinors& L, hipStream_t st);
 hipError_t fpm_launch_c128(const LaunchMinors& L, hipStream_t st);

@@ -734,10 +734,123 @@ hipError_t dispatch_n(const LaunchMinors& L, hipStream_t st)
     }
 }
 
+// ----------------------------------------------------------------- ragged batches
+// Lane-subtree order used by the persistent mixed-order kernel: one below the largest,
+// which keeps the merged kernel at two wavefronts per SIMD.
+template <class F>
+constexpr int ragged_k0()
+{
+    return K0Set<F>::hi > K0Set<F>::lo ? K0Set<F>::hi - 1 : K0Set<F>::hi;
+}
+
+// One order per (non-inlined) function, so that each keeps its own register allocation.
+template <class F, int N>
+__device__ __noinline__ int fpm_wave_n(const typename F::In* A, void* ob, int16_t* eb, unsigned char* lds, Opts o)
+{
+    return fpm_wave<F, N, ragged_k0<F>()>(A, ob, eb, lds, o);
+}
+
+template <class F, int N>
+__device__ __forceinline__ int fpm_dispatch(int n, const typename F::In* A, void* ob, int16_t* eb, unsigned char* lds,
+                                            const Opts& o)
+{
+    if constexpr (N > 20) {
+        return -1;
+    } else {
+        if (n == N) return fpm_wave_n<F, N>(A, ob, eb, lds, o);
+        return fpm_dispatch<F, N + 1>(n, A, ob, eb, lds, o);
+    }
+}
+
+// Persistent waves over the prepared queue; each matrix is handled by the code for its order.
+template <class F>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fpm_ragged_kernel(const typename F::In* __restrict__ A, void* out, int16_t* ex,
+                                                        int32_t* info, int32_t batch, const int32_t* __restrict__ nv,
+                                                        const int64_t* __restrict__ in_off,
+                                                        const int64_t* __restrict__ out_off,
+                                                        const int32_t* __restrict__ order, int32_t* counter, Opts o)
+{
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    for (;;) {
+        int i = 0;
+        if (lane_id() == 0) i = atomicAdd(counter, 1);
+        i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
+        if (i >= batch) break;
+        const int b = order[i];
+        const int n = nv[b];
+        int r = -1;
+        if (n >= 1 && n <= 20) {
+            const int64_t io = in_off[b];
+            const int64_t oo = out_off[b];
+            void* ob;
+            if constexpr (F::kComplex) {
+                ob = (o.out_f64 || !F::kScaled) ? (void*)(static_cast<cd*>(out) + oo)
+                                                : (void*)(static_cast<cf*>(out) + oo);
+            } else {
+                ob = (o.out_f64 || !F::kScaled) ? (void*)(static_cast<double*>(out) + oo)
+                                                : (void*)(static_cast<float*>(out) + oo);
+            }
+            int16_t* eb = ex ? ex + oo : nullptr;
+            r = fpm_dispatch<F, 1>(n, A + io, ob, eb, lds_dyn, o);
+        }
+        if (info && lane_id() == 0) info[b] = r;
+        wave_sync();
+    }
+}
+
+template <class F, int N>
+constexpr size_t max_lay_bytes()
+{
+    if constexpr (N > 20) {
+        return 0;
+    } else {
+        constexpr size_t a = Lay<F, N, ragged_k0<F>()>::bytes;
+        constexpr size_t b = max_lay_bytes<F, N + 1>();
+        return a > b ? a : b;
+    }
+}
+
+template <class F, int N>
+size_t lay_bytes_upto(int nmax)
+{
+    if constexpr (N > 20) {
+        return 0;
+    } else {
+        const size_t a = N <= nmax ? Lay<F, N, ragged_k0<F>()>::bytes : 0;
+        const size_t b = lay_bytes_upto<F, N + 1>(nmax);
+        return a > b ? a : b;
+    }
+}
+
+template <class F>
+hipError_t fpm_launch_ragged(const LaunchMinors& L, hipStream_t st)
+{
+    const int64_t* ioff = L.in_off ? L.in_off : L.ioff_ws;
+    const int64_t* ooff = L.out_off ? L.out_off : L.ooff_ws;
+    hipError_t e = fpm_prep_launch(L, st);
+    if (e != hipSuccess) return e;
+    const size_t bytes = lay_bytes_upto<F, 1>(L.n_max);
+    auto kern = fpm_ragged_kernel<F>;
+    if (bytes > 65536) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64, bytes);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)per_cu * (L.n_workers > 0 ? L.n_workers : 256);
+    if (grid > L.batch) grid = L.batch;
+    Opts o{L.tau, L.perturb, L.out_f64};
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), bytes, st, static_cast<const typename F::In*>(L.A),
+                       L.out, L.ex, L.info, L.batch, L.n, ioff, ooff, L.order, L.counter, o);
+    return hipGetLastError();
+}
+
 template <class F>
 hipError_t fpm_launch_field(const LaunchMinors& L, hipStream_t st)
 {
-    if (L.n_uniform <= 0) return hipErrorInvalidValue;
+    if (L.n_uniform <= 0) return fpm_launch_ragged<F>(L, st);
     return dispatch_n<F, 1>(L, st);
 }
 

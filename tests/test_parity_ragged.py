@@ -1,0 +1,121 @@
+"""Mixed-order batches: one persistent launch over matrices of different orders
+(apm_all_minors with per-matrix n[]), and the CDet pipeline on such a batch."""
+import numpy as np
+import pytest
+
+from oracle import metrics
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_07638_amd as m
+    return m
+
+
+def pack(mats):
+    ns = np.array([m.shape[0] for m in mats], dtype=np.int32)
+    flat = np.concatenate([m.ravel() for m in mats])
+    ooff = np.concatenate([[0], np.cumsum(np.left_shift(1, ns.astype(np.int64)))[:-1]]).astype(np.int64)
+    return ns, flat, ooff, int(np.sum(np.left_shift(1, ns.astype(np.int64))))
+
+
+def test_ragged_all_orders(apm, oracle_mod):
+    import torch
+    rng = np.random.default_rng(3)
+    orders = [5, 1, 20, 9, 14, 2, 16, 11, 6, 18, 3, 12, 8, 17, 10, 13, 4, 7, 15, 19] * 2
+    mats = [W.lattice_batch(1, k, W.Lattice(32, 1.0, -0.5, 5.0), seed=300 + i)[0] for i, k in enumerate(orders)]
+    ns, flat, ooff, tot = pack(mats)
+    out = torch.full((tot,), 3.0, dtype=torch.float64, device="cuda")
+    n_t = torch.from_numpy(ns).cuda()
+    A_t = torch.from_numpy(flat).cuda()
+    _, _, info = apm.all_minors_ragged(A_t, n_t, 20, "r64", out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    info = info.cpu().numpy()
+    assert np.all(info >= 0), info
+    for k, M in enumerate(mats):
+        n = M.shape[0]
+        seg = got[ooff[k]:ooff[k] + (1 << n)]
+        if n <= 14:
+            ref = oracle_mod.minors(M)
+            assert metrics.mixed_err(seg, ref, metrics.hadamard_bounds(M)).max() <= 1e-10, n
+        else:
+            masks = np.unique(np.concatenate([rng.integers(0, 1 << n, 800), [0, (1 << n) - 1]]))
+            ref = oracle_mod.minors_at(M, masks)
+            assert metrics.mixed_err(seg[masks], ref, metrics.hadamard_at(M, masks)).max() <= 1e-10, n
+
+
+def test_ragged_bad_order_reported(apm):
+    import torch
+    ns = np.array([3, 25, 0, 4], dtype=np.int32)
+    flat = np.concatenate([np.eye(3).ravel(), np.zeros(0), np.zeros(0), 2 * np.eye(4).ravel()])
+    ioff = np.array([0, 9, 9, 9], dtype=np.int64)
+    ooff = np.array([0, 8, 8, 8], dtype=np.int64)
+    out = torch.zeros(8 + 16, dtype=torch.float64, device="cuda")
+    _, _, info = apm.all_minors_ragged(torch.from_numpy(flat).cuda(), torch.from_numpy(ns).cuda(), 20, "r64",
+                                       in_off=torch.from_numpy(ioff).cuda(), out_off=torch.from_numpy(ooff).cuda(),
+                                       out=out)
+    torch.cuda.synchronize()
+    assert info.cpu().numpy().tolist() == [0, -1, -1, 0]
+    o = out.cpu().numpy()
+    assert np.all(o[:8] == 1.0)
+    assert np.allclose(o[8:], [2.0 ** bin(m).count("1") for m in range(16)])
+
+
+@pytest.mark.parametrize("dtype", ["r32s", "c128"])
+def test_ragged_other_types(apm, oracle_mod, dtype):
+    import torch
+    orders = [6, 12, 3, 10, 14, 8]
+    if dtype == "c128":
+        mats = [W.keldysh_batch(1, k, seed=50 + k)[0] for k in orders]
+        ref = [oracle_mod.minors_complex(M) for M in mats]
+    else:
+        mats = [W.lattice_batch(1, k, W.Lattice(32, 1.0, -0.5, 5.0), seed=50 + k)[0] for k in orders]
+        ref = [oracle_mod.minors(M) for M in mats]
+    ns, flat, ooff, tot = pack(mats)
+    if dtype == "c128":
+        out = torch.empty(tot, dtype=torch.complex128, device="cuda")
+        _, _, info = apm.all_minors_ragged(torch.from_numpy(flat).cuda(), torch.from_numpy(ns).cuda(), 14, dtype,
+                                           out=out)
+        got = out.cpu().numpy()
+        tol = 1e-10
+    else:
+        out = torch.empty(tot, dtype=torch.float32, device="cuda")
+        ex = torch.empty(tot, dtype=torch.int16, device="cuda")
+        _, _, info = apm.all_minors_ragged(torch.from_numpy(flat).cuda(), torch.from_numpy(ns).cuda(), 14, dtype,
+                                           out=out, exp=ex)
+        got = apm.decode_scaled(out, ex).cpu().numpy()
+        tol = 1e-4
+    torch.cuda.synchronize()
+    for k, M in enumerate(mats):
+        seg = got[ooff[k]:ooff[k] + (1 << M.shape[0])]
+        assert metrics.mixed_err(seg, ref[k], metrics.hadamard_bounds(M)).max() <= tol
+
+
+def test_cdet_pipeline_ragged(apm, oracle_mod):
+    """Minors -> weights a = det^2 -> rooted connected sums, mixed orders, vs the oracle."""
+    import torch
+    orders = [10, 13, 11, 12, 10, 14]
+    mats = [W.lattice_batch(1, k, W.Lattice(32, 1.0, -0.5, 5.0), seed=70 + i)[0] for i, k in enumerate(orders)]
+    ns, flat, ooff, tot = pack(mats)
+    m = torch.empty(tot, dtype=torch.float64, device="cuda")
+    n_t = torch.from_numpy(ns).cuda()
+    apm.all_minors_ragged(torch.from_numpy(flat).cuda(), n_t, 14, "r64", out=m)
+    c = torch.empty_like(m)
+    off = torch.from_numpy(ooff).cuda()
+    bd = apm.make_batch(len(ns), 0, n_t, 14, off, off)
+    assert apm.apm_connected_sums(apm._ptr(m), None, bd, apm._ptr(c), apm.APM_CS_ROOTED, apm._stream(None)) == 0
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()
+    for k, M in enumerate(mats):
+        a = oracle_mod.minors(M) ** 2
+        ref = oracle_mod.connected_sums(a, 0)
+        d = oracle_mod.cs_scale(a, ref, 0)
+        seg = got[ooff[k]:ooff[k] + (1 << M.shape[0])]
+        assert np.all(np.abs(seg - ref) <= 1e-10 * d + 1e-300)
