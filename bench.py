@@ -173,9 +173,18 @@ def main():
              "achieved_GBs": round((8 * n * n + 6 * (1 << n) + 4) * B / (ms32 * 1e-3) / 1e9, 1)}
     log(f"r32s: {ms32:.3f} ms, {fp32s['value'] / 1e6:.2f} M matrices/s")
 
-    extra = {}
+    # CDet connected sums of the same batch (a = det^2, rooted at vertex 0)
+    cs_out = torch.empty_like(out)
+    ms_cs = time_fn(torch, lambda: apm.connected_sums(out, out=cs_out), max(2, args.steps // 10))
+    csum = {"ms": round(ms_cs, 3), "matrices_per_s": round(B / (ms_cs * 1e-3), 1),
+            "TFLOPs": round(2 * B * 3 ** (n - 1) / (ms_cs * 1e-3) / 1e12, 2),
+            "frac_fp64_peak": round(2 * B * 3 ** (n - 1) / (ms_cs * 1e-3) / 78.6e12, 4)}
+    log(f"connected sums n={n}: {csum}")
+    del cs_out
+
+    extra = {"csum_n16_8192": csum}
     if not args.no_extra:
-        extra = run_extra(torch, apm, W, np, args.steps)
+        extra.update(run_extra(torch, apm, W, np, args.steps))
 
     cpu = None
     accuracy = None
@@ -214,6 +223,38 @@ def run_extra(torch, apm, W, np, steps):
     ex["keldysh_n14_4096_c64s"] = {"ms": round(ms, 4), "matrices_per_s": round(4096 / (ms * 1e-3), 1),
                                    "GBs": round((16 * 196 + 10 * (1 << 14)) * 4096 / (ms * 1e-3) / 1e9, 1)}
     del oc, ec
+    # mixed orders: 8192 lattice matrices with n uniform in {10..16} (L=32, beta=5, mu=-0.5):
+    # all minors in one persistent launch, then the rooted CDet connected sums (a = det^2)
+    mats, ns = W.lattice_ragged(8192, 10, 16, W.Lattice(32, 1.0, -0.5, 5.0), seed=W.BASE_SEED + 1)
+    flat = torch.from_numpy(np.concatenate([m.ravel() for m in mats])).cuda()
+    n_t = torch.from_numpy(ns).cuda()
+    sizes = np.left_shift(1, ns.astype(np.int64))
+    ooff = torch.from_numpy(np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)).cuda()
+    tot = int(sizes.sum())
+    mm = torch.empty(tot, dtype=torch.float64, device="cuda")
+    cc = torch.empty_like(mm)
+    ms_m = time_fn(torch, lambda: apm.all_minors_ragged(flat, n_t, 16, "r64", out=mm, out_off=ooff), steps)
+    bd = apm.make_batch(8192, 0, n_t, 16, ooff, ooff)
+
+    def csum():
+        rc = apm.apm_connected_sums(apm._ptr(mm), None, bd, apm._ptr(cc), apm.APM_CS_ROOTED, apm._stream(None))
+        assert rc == 0
+
+    ms_c = time_fn(torch, csum, max(2, steps // 4))
+    fma = float(np.sum(3.0 ** (ns.astype(np.float64) - 1)))
+    ex["mixed_n10_16_8192_cdet"] = {
+        "minors_ms": round(ms_m, 4), "minors_GBs": round((8 * float(np.sum(ns.astype(np.float64) ** 2)) + 8 * tot)
+                                                          / (ms_m * 1e-3) / 1e9, 1),
+        "csum_ms": round(ms_c, 4), "csum_fma": fma, "csum_TFLOPs": round(2 * fma / (ms_c * 1e-3) / 1e12, 2),
+        "csum_frac_fp64_peak": round(2 * fma / (ms_c * 1e-3) / 78.6e12, 4),
+        "matrices_per_s": round(8192 / ((ms_m + ms_c) * 1e-3), 1)}
+    del mm, cc, flat
+    # permanent principal minors: 2048 real n = 12, entries N(0,1)/sqrt(12)
+    P = torch.from_numpy(W.gauss_batch(2048, 12)).cuda()
+    po = torch.empty((2048, 1 << 12), dtype=torch.float64, device="cuda")
+    ms = time_fn(torch, lambda: apm.all_perm_minors(P, out=po), steps)
+    ex["perm_n12_2048"] = {"ms": round(ms, 4), "matrices_per_s": round(2048 / (ms * 1e-3), 1),
+                           "products_per_s": round(2048 * 3 ** 12 / (ms * 1e-3), 1)}
     for k, v in ex.items():
         log(f"{k}: {v}")
     return ex

@@ -294,8 +294,8 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
 
 // Problem (matrix b, root j): solve (*) for the m = n-1-j vertices above j.
 template <int M>
-__device__ void cs_problem(const CsArgs& g, int64_t base, int j, double* lds_c, double* lds_b, double* lds_r,
-                           uint16_t* rk_tab, int* rk_off)
+__device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even, double* lds_c, double* lds_b,
+                           double* lds_r, uint16_t* rk_tab, int* rk_off)
 {
     using CP = CsPlan<M>;
     constexpr int P = CP::P, LB = CP::LB, H = CP::H;
@@ -340,9 +340,22 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, double* lds_c, 
             rank_pass<M, true>(r, rk_tab, rk_off, lds_c, lds_b, lds_r, lds_c);
             __syncthreads();
         }
-        for (int x1 = tid; x1 < (1 << P); x1 += NT)
-            c[sroot + ((((int64_t)x2 << P) | x1) << jsh)] = lds_c[sw<LB>(x1)];
+        if (zero_even && !(base & 1)) {
+            // rooted problem: write (c[2x] = 0, c[2x+1] = c'[x]) as one 16-byte store
+            for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+                const int64_t x = ((int64_t)x2 << P) | x1;
+                *reinterpret_cast<double2*>(c + base + 2 * x) = make_double2(0.0,
+                                                                             lds_c[sw<LB>(x1)]);
+            }
+        } else {
+            for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+                const int64_t x = ((int64_t)x2 << P) | x1;
+                c[sroot + (x << jsh)] = lds_c[sw<LB>(x1)];
+                if (zero_even) c[base + 2 * x] = 0.0;
+            }
+        }
     }
+    if (j == 0 && tid == 0) c[base] = 0.0;   // c[empty] = 0
 }
 
 template <int M>
@@ -360,24 +373,8 @@ __global__ __launch_bounds__(cs_threads<M>()) void cs_kernel(CsArgs g, int32_t b
     const int n = n_uniform > 0 ? n_uniform : nv[b];
     if (n - 1 - j != M) return;   // launched for problems with exactly M bits
     const int64_t base = off ? off[b] : ((int64_t)b << n);
-    cs_problem<M>(g, base, j, lds_c, lds_b, lds_r, rk_tab, rk_off);
-}
-
-// c[S] = 0 outside the rooted problem (S without vertex 0) and c[empty] = 0 in all modes.
-__global__ void cs_zero_kernel(double* c, int32_t batch, int n_uniform, const int32_t* nv, const int64_t* off,
-                               uint32_t mode)
-{
-    const int b = blockIdx.y;
-    if (b >= batch) return;
-    const int n = n_uniform > 0 ? n_uniform : nv[b];
-    const int64_t base = off ? off[b] : ((int64_t)b << n);
-    const int64_t nm = int64_t(1) << n;
-    if (mode & 1u) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) c[base] = 0.0;
-        return;
-    }
-    for (int64_t s = (int64_t)(blockIdx.x * blockDim.x + threadIdx.x) * 2; s < nm; s += (int64_t)gridDim.x * blockDim.x * 2)
-        c[base + s] = 0.0;
+    // the rooted problem also writes c[S] = 0 for the sets without vertex 0
+    cs_problem<M>(g, base, j, roots == 1, lds_c, lds_b, lds_r, rk_tab, rk_off);
 }
 
 template <int M>
@@ -415,11 +412,7 @@ hipError_t cs_launch(const LaunchCS& L, hipStream_t st)
     // problem has exactly that size
     const int mhi = nmax - 1;
     const int mlo = all ? 0 : nmin - 1;
-    hipError_t e = launch_all_m<19>(mlo, mhi, L, g, roots, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cs_zero_kernel, dim3(64, (unsigned)L.batch), dim3(256), 0, st, L.c, L.batch, L.n_uniform,
-                       L.n, L.off, L.mode);
-    return hipGetLastError();
+    return launch_all_m<19>(mlo, mhi, L, g, roots, st);
 }
 
 }  // namespace apm
