@@ -216,3 +216,96 @@ def zero_diagonal(A):
     idx = np.arange(A.shape[-1])
     A[..., idx, idx] = 0.0
     return A
+
+
+# --------------------------------------------------------------------------------------
+# Monte Carlo over vertex configurations with a learned proposal (inputs only)
+# --------------------------------------------------------------------------------------
+@dataclass(frozen=True)
+class McModel:
+    """Vertex configurations of the imaginary-time lattice expansion.
+
+    A configuration is n vertices; vertex i sits on lattice site s_i = y_i L + x_i and
+    at imaginary time tau_i = (j_i + 1/2) beta / n_tau on a grid of n_tau points.  A
+    vertex is packed as ``s | (j << 16)``.  The learned proposal groups the n_tau time
+    points into n_bin equal bins and mixes in a fraction ``eps`` of the uniform proposal.
+    """
+    n: int = 10
+    L: int = 16
+    t: float = 1.0
+    mu: float = 0.0
+    beta: float = 4.0
+    n_tau: int = 128
+    n_bin: int = 16
+    eps: float = 0.1
+
+    @property
+    def lattice(self) -> Lattice:
+        return Lattice(L=self.L, t=self.t, mu=self.mu, beta=self.beta)
+
+    @property
+    def d_in(self) -> int:
+        return 3 * (self.n - 1)
+
+    @property
+    def d_out(self) -> int:
+        return self.L * self.L + self.n_bin
+
+
+def mc_g0_table(m: McModel) -> np.ndarray:
+    """G0 on the vertex grid: row d + n_tau - 1 holds tau difference d beta / n_tau
+    (d in [-(n_tau-1), n_tau-1]; d = 0 is 0^-), column dy*L + dx holds the site
+    difference (dx, dy) taken mod L.  Shape (2 n_tau - 1, L^2), fp64."""
+    d = np.arange(-(m.n_tau - 1), m.n_tau)
+    s = np.arange(m.L * m.L)
+    tau = d[:, None] * (m.beta / m.n_tau)
+    return np.ascontiguousarray(g0_lattice((s % m.L)[None, :], (s // m.L)[None, :], tau, m.lattice))
+
+
+def pack_vertex(site, tidx):
+    return (np.asarray(site, dtype=np.uint32) | (np.asarray(tidx, dtype=np.uint32) << np.uint32(16)))
+
+
+def mc_initial_states(W, m: McModel, seed=BASE_SEED) -> np.ndarray:
+    """W configurations of n vertices, sites and time points uniform; uint32 (W, n)."""
+    rng = _rng(seed + 31337)
+    site = rng.integers(0, m.L * m.L, size=(W, m.n))
+    tidx = rng.integers(0, m.n_tau, size=(W, m.n))
+    return np.ascontiguousarray(pack_vertex(site, tidx))
+
+
+MLP_HIDDEN = 128
+
+
+def mlp_dims(d_in: int, d_out: int):
+    """Padded sizes of the proposal network: inputs to a multiple of 16 (at least 16),
+    outputs to a multiple of 16."""
+    dp = max(16, -(-d_in // 16) * 16)
+    op = -(-d_out // 16) * 16
+    return dp, op
+
+
+def mlp_param_count(d_in: int, d_out: int) -> int:
+    """fp32 parameters in the packed order W1 (H x Dp) | W2 (H x H) | W3 (Op x H) |
+    b1 (H) | b2 (H) | b3 (Op), matrices row-major [out][in]."""
+    dp, op = mlp_dims(d_in, d_out)
+    H = MLP_HIDDEN
+    return H * dp + H * H + op * H + H + H + op
+
+
+def mlp_init(d_in: int, d_out: int, seed=BASE_SEED, gain: float = 1.0) -> np.ndarray:
+    """Packed fp32 parameters: Glorot-uniform weights on the logical block (scaled by
+    ``gain``), zero padding rows/columns and zero biases."""
+    rng = _rng(seed + 271828)
+    dp, op = mlp_dims(d_in, d_out)
+    H = MLP_HIDDEN
+    p = np.zeros(mlp_param_count(d_in, d_out), dtype=np.float32)
+    off = 0
+    # (stored rows, stored cols, logical rows, logical cols)
+    for rows, cols, lr, lc in ((H, dp, H, d_in), (H, H, H, H), (op, H, d_out, H)):
+        lim = gain * np.sqrt(6.0 / (lr + lc))
+        w = np.zeros((rows, cols), dtype=np.float32)
+        w[:lr, :lc] = rng.uniform(-lim, lim, size=(lr, lc))
+        p[off:off + rows * cols] = w.ravel()
+        off += rows * cols
+    return p
