@@ -7,6 +7,9 @@ Operations (Simkovic & Ferrero, arXiv:2104.07638):
   by the Schur-complement binary tree with pivot shifts and their back-propagation.
 * ``apm_connected_sums`` / ``connected_sums`` -- Sec. V.A, Eq. (recursion).
 * ``apm_all_perm_minors`` / ``all_perm_minors`` -- Sec. IV, O(3^n) permanent minors.
+* ``apm_mc_*`` / ``apm_mlp_*`` (``include/apm_mc.h``) -- Metropolis-Hastings steps over
+  vertex configurations weighted by |c[V]| (Sec. V.A), with a learned proposal network
+  trained by the library's own forward/backward/Adam kernels (``Mlp``, ``mc_step``).
 
 The ``apm_*`` functions mirror the C ABI of ``include/apm.h`` one to one and take raw
 device pointers; the lower-case wrappers marshal torch tensors (device memory and the
@@ -33,7 +36,12 @@ DTYPES = {"r64": APM_R64, "r32s": APM_R32S, "c128": APM_C128, "c64s": APM_C64S}
 
 #: names exported by include/apm.h (checked by the tests)
 EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_status_str",
-           "apm_last_hip_error", "apm_version")
+           "apm_last_hip_error", "apm_version",
+           "apm_mlp_param_count", "apm_mlp_weight_count", "apm_mlp_work_bytes", "apm_mlp_sync",
+           "apm_mlp_forward", "apm_mlp_backward", "apm_mlp_adam", "apm_mc_work_bytes", "apm_mc_evaluate",
+           "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept")
+
+APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
 
 class apm_batch(ctypes.Structure):
@@ -43,6 +51,33 @@ class apm_batch(ctypes.Structure):
 
 class apm_opts(ctypes.Structure):
     _fields_ = [("piv_tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class apm_mlp(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_int32), ("d_out", ctypes.c_int32), ("param", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("wt", ctypes.c_void_p)]
+
+
+class apm_adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("t", ctypes.c_int32)]
+
+
+class apm_mc_model(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("L", ctypes.c_int32), ("n_tau", ctypes.c_int32), ("n_bin", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("g0", ctypes.c_void_p)]
+
+
+class apm_mc_chain(ctypes.Structure):
+    _fields_ = [("walkers", ctypes.c_int32), ("state", ctypes.c_void_p), ("logw", ctypes.c_void_p),
+                ("sign", ctypes.c_void_p)]
+
+
+class apm_mc_record(ctypes.Structure):
+    _fields_ = [("moved", ctypes.c_void_p), ("proposed", ctypes.c_void_p), ("logq", ctypes.c_void_p),
+                ("logc_prop", ctypes.c_void_p), ("accepted", ctypes.c_void_p), ("obs_logw", ctypes.c_void_p),
+                ("obs_sign", ctypes.c_void_p), ("loss", ctypes.c_void_p)]
 
 
 class ApmError(RuntimeError):
@@ -68,6 +103,29 @@ def _load():
     lib.apm_status_str.restype = ctypes.c_char_p
     lib.apm_last_hip_error.restype = ctypes.c_int
     lib.apm_version.restype = ctypes.c_int
+    i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    P = ctypes.POINTER
+    for name in ("apm_mlp_param_count", "apm_mlp_weight_count"):
+        getattr(lib, name).argtypes = [i32, i32]
+        getattr(lib, name).restype = i64
+    lib.apm_mlp_work_bytes.argtypes = [i32, i32, i32]
+    lib.apm_mlp_work_bytes.restype = i64
+    lib.apm_mlp_sync.argtypes = [P(apm_mlp), vp]
+    lib.apm_mlp_forward.argtypes = [P(apm_mlp), vp, i32, vp, vp, vp]
+    lib.apm_mlp_backward.argtypes = [P(apm_mlp), vp, i32, vp, vp]
+    lib.apm_mlp_adam.argtypes = [P(apm_mlp), P(apm_adam), vp]
+    lib.apm_mc_work_bytes.argtypes = [P(apm_mc_model), i32, i32]
+    lib.apm_mc_work_bytes.restype = i64
+    lib.apm_mc_evaluate.argtypes = [P(apm_mc_model), P(apm_mc_chain), vp, vp]
+    lib.apm_mc_step.argtypes = [P(apm_mc_model), P(apm_mc_chain), P(apm_mlp), P(apm_adam), u64, i32,
+                                P(apm_mc_record), vp, vp]
+    lib.apm_mc_context.argtypes = [P(apm_mc_model), P(apm_mc_chain), u64, i32, vp, vp, vp]
+    lib.apm_mc_propose.argtypes = [P(apm_mc_model), P(apm_mc_chain), u64, i32, vp, vp, i32, vp, vp, vp, vp]
+    lib.apm_mc_accept.argtypes = [P(apm_mc_model), P(apm_mc_chain), u64, i32, vp, vp, vp, vp, P(apm_mc_record),
+                                  vp, vp]
+    for name in ("apm_mlp_sync", "apm_mlp_forward", "apm_mlp_backward", "apm_mlp_adam", "apm_mc_evaluate",
+                 "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept"):
+        getattr(lib, name).restype = ctypes.c_int
     return lib
 
 
@@ -212,3 +270,194 @@ def decode_scaled(m, e):
         s = torch.ldexp(torch.ones_like(e, dtype=torch.float64), e.to(torch.float64))
         return m.to(torch.complex128) * s
     return torch.ldexp(m.to(torch.float64), e.to(torch.float64))
+
+
+# ----------------------------------------------------------------- Monte Carlo + proposal network
+def _ref(x):
+    return None if x is None else ctypes.byref(x)
+
+
+def apm_mlp_param_count(d_in, d_out):
+    return _lib.apm_mlp_param_count(int(d_in), int(d_out))
+
+
+def apm_mlp_weight_count(d_in, d_out):
+    return _lib.apm_mlp_weight_count(int(d_in), int(d_out))
+
+
+def apm_mlp_work_bytes(d_in, d_out, batch):
+    return _lib.apm_mlp_work_bytes(int(d_in), int(d_out), int(batch))
+
+
+def apm_mlp_sync(net, stream):
+    return _lib.apm_mlp_sync(_ref(net), stream)
+
+
+def apm_mlp_forward(net, x, batch, out, work, stream):
+    return _lib.apm_mlp_forward(_ref(net), x, int(batch), out, work, stream)
+
+
+def apm_mlp_backward(net, dout, batch, work, stream):
+    return _lib.apm_mlp_backward(_ref(net), dout, int(batch), work, stream)
+
+
+def apm_mlp_adam(net, h, stream):
+    return _lib.apm_mlp_adam(_ref(net), _ref(h), stream)
+
+
+def apm_mc_work_bytes(m, walkers, with_net):
+    return _lib.apm_mc_work_bytes(_ref(m), int(walkers), int(with_net))
+
+
+def apm_mc_evaluate(m, ch, work, stream):
+    return _lib.apm_mc_evaluate(_ref(m), _ref(ch), work, stream)
+
+
+def apm_mc_step(m, ch, net, train, seed, step, rec, work, stream):
+    return _lib.apm_mc_step(_ref(m), _ref(ch), _ref(net), _ref(train), int(seed), int(step), _ref(rec), work, stream)
+
+
+def apm_mc_context(m, ch, seed, step, moved, feat, stream):
+    return _lib.apm_mc_context(_ref(m), _ref(ch), int(seed), int(step), moved, feat, stream)
+
+
+def apm_mc_propose(m, ch, seed, step, moved, logits, stride, proposed, logq, mats, stream):
+    return _lib.apm_mc_propose(_ref(m), _ref(ch), int(seed), int(step), moved, logits, int(stride), proposed, logq,
+                               mats, stream)
+
+
+def apm_mc_accept(m, ch, seed, step, moved, proposed, logq, mats, rec, work, stream):
+    return _lib.apm_mc_accept(_ref(m), _ref(ch), int(seed), int(step), moved, proposed, logq, mats, _ref(rec), work,
+                              stream)
+
+
+def mlp_dims(d_in, d_out):
+    """Padded (Dp, Op) of the proposal network."""
+    return max(16, -(-d_in // 16) * 16), -(-d_out // 16) * 16
+
+
+class Mlp:
+    """Device buffers of one proposal network (fp32 master parameters, gradient, Adam
+    moments, BF16 weight copies) and its C descriptor."""
+
+    def __init__(self, d_in, d_out, params=None, device="cuda"):
+        P = apm_mlp_param_count(d_in, d_out)
+        NW = apm_mlp_weight_count(d_in, d_out)
+        if P < 0:
+            raise ValueError("network sizes out of range")
+        self.d_in, self.d_out = int(d_in), int(d_out)
+        self.dp, self.op = mlp_dims(d_in, d_out)
+        f32 = dict(dtype=torch.float32, device=device)
+        self.param = torch.zeros(P, **f32)
+        if params is not None:
+            self.param.copy_(torch.as_tensor(params, dtype=torch.float32))
+        self.grad = torch.zeros(P, **f32)
+        self.adam_m = torch.zeros(P, **f32)
+        self.adam_v = torch.zeros(P, **f32)
+        self.w = torch.zeros(NW, dtype=torch.bfloat16, device=device)
+        self.wt = torch.zeros(NW, dtype=torch.bfloat16, device=device)
+        self.c = apm_mlp(self.d_in, self.d_out, self.param.data_ptr(), self.grad.data_ptr(),
+                         self.adam_m.data_ptr(), self.adam_v.data_ptr(), self.w.data_ptr(), self.wt.data_ptr())
+        self.t = 0
+        self.sync()
+
+    def sync(self, stream=None):
+        _check(apm_mlp_sync(self.c, _stream(stream)), "apm_mlp_sync")
+
+    def work(self, batch):
+        return torch.empty(apm_mlp_work_bytes(self.d_in, self.d_out, batch), dtype=torch.uint8,
+                           device=self.param.device)
+
+    def forward(self, x, out=None, work=None, stream=None):
+        """x: (B, Dp) bfloat16 device tensor -> (B, Op) float32 logits."""
+        B = x.shape[0]
+        if x.dtype != torch.bfloat16 or x.shape[1] != self.dp or not x.is_contiguous():
+            raise TypeError("x must be a contiguous (B, Dp) bfloat16 tensor")
+        if out is None:
+            out = torch.empty((B, self.op), dtype=torch.float32, device=x.device)
+        _check(apm_mlp_forward(self.c, _ptr(x), B, _ptr(out), _ptr(work), _stream(stream)), "apm_mlp_forward")
+        return out
+
+    def backward(self, dout, work, stream=None):
+        _check(apm_mlp_backward(self.c, _ptr(dout), dout.shape[0], _ptr(work), _stream(stream)),
+               "apm_mlp_backward")
+        return self.grad
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, t=None, stream=None):
+        self.t = self.t + 1 if t is None else int(t)
+        h = apm_adam(lr, beta1, beta2, eps, self.t)
+        _check(apm_mlp_adam(self.c, h, _stream(stream)), "apm_mlp_adam")
+
+
+class McChain:
+    """Walker state on the device: packed vertices (int32 storage of the uint32 words),
+    log|c[V]| and the sign of c[V]."""
+
+    def __init__(self, states, device="cuda"):
+        if isinstance(states, torch.Tensor):
+            if states.dtype != torch.int32:
+                raise TypeError("device states must be int32 storage of the packed uint32 vertices")
+            st = states
+        else:
+            import numpy as np
+            st = torch.from_numpy(np.ascontiguousarray(np.asarray(states, dtype=np.uint32)).view(np.int32))
+        self.state = st.to(device).contiguous()
+        W = self.state.shape[0]
+        self.logw = torch.full((W,), float("-inf"), dtype=torch.float64, device=device)
+        self.sign = torch.zeros(W, dtype=torch.int8, device=device)
+        self.c = apm_mc_chain(W, self.state.data_ptr(), self.logw.data_ptr(), self.sign.data_ptr())
+
+    @property
+    def walkers(self):
+        return self.state.shape[0]
+
+
+def mc_model(n, L, n_tau, n_bin, eps, g0):
+    """C descriptor of the model; ``g0`` is the device fp64 table (kept alive by the caller)."""
+    return apm_mc_model(int(n), int(L), int(n_tau), int(n_bin), float(eps), g0.data_ptr())
+
+
+def mc_work(model, walkers, with_net, device="cuda"):
+    nb = apm_mc_work_bytes(model, walkers, 1 if with_net else 0)
+    if nb < 0:
+        raise ValueError("bad model or walker count")
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+
+
+class McRecord:
+    """Per-step outputs of ``mc_step`` (device tensors)."""
+
+    def __init__(self, walkers, device="cuda", loss=True):
+        W = walkers
+        self.moved = torch.empty(W, dtype=torch.int32, device=device)
+        self.proposed = torch.empty(W, dtype=torch.int32, device=device)
+        self.logq = torch.empty(W, dtype=torch.float64, device=device)
+        self.logc_prop = torch.empty(W, dtype=torch.float64, device=device)
+        self.accepted = torch.empty(W, dtype=torch.uint8, device=device)
+        self.obs_logw = torch.empty(W, dtype=torch.float32, device=device)
+        self.obs_sign = torch.empty(W, dtype=torch.int8, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device) if loss else None
+        self.c = self._c()
+
+    def _c(self, obs_logw=None, obs_sign=None):
+        return apm_mc_record(self.moved.data_ptr(), self.proposed.data_ptr(), self.logq.data_ptr(),
+                             self.logc_prop.data_ptr(), self.accepted.data_ptr(),
+                             (self.obs_logw if obs_logw is None else obs_logw).data_ptr(),
+                             (self.obs_sign if obs_sign is None else obs_sign).data_ptr(),
+                             self.loss.data_ptr() if self.loss is not None else None)
+
+
+def mc_evaluate(model, chain, work, stream=None):
+    _check(apm_mc_evaluate(model, chain.c, _ptr(work), _stream(stream)), "apm_mc_evaluate")
+
+
+def mc_step(model, chain, work, seed, step, net=None, train=None, record=None, stream=None):
+    """One Metropolis-Hastings step of every walker; ``train`` = dict(lr, beta1, beta2,
+    eps, t) trains ``net`` on the step's proposals."""
+    h = None
+    if train is not None:
+        h = apm_adam(train.get("lr", 1e-3), train.get("beta1", 0.9), train.get("beta2", 0.999),
+                     train.get("eps", 1e-8), int(train["t"]))
+    rec = record.c if isinstance(record, McRecord) else record
+    _check(apm_mc_step(model, chain.c, net.c if net is not None else None, h, seed, step, rec, _ptr(work),
+                       _stream(stream)), "apm_mc_step")

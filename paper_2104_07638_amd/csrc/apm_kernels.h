@@ -56,4 +56,56 @@ struct LaunchPerm {
 
 hipError_t perm_launch(const LaunchPerm& L, hipStream_t st);
 
+// ---------------------------------------------------------------- proposal network
+struct MlpNet {
+    int dp, op;                // padded input / output sizes
+    float* param;
+    float* grad;
+    float* m;
+    float* v;
+    uint16_t* w;
+    uint16_t* wt;
+};
+
+struct MlpWork {
+    float* h1;                 // [B][128] fp32 activations
+    float* h2;
+    uint16_t* actT;            // [Dp + 256][B] bf16: x^T | h1^T | h2^T
+    uint16_t* gT;              // [Op + 256][B] bf16: dout^T | dz2^T | dz1^T
+};
+
+int64_t mlp_param_count(int dp, int op);
+int64_t mlp_weight_count(int dp, int op);
+int64_t mlp_work_bytes(int dp, int op, int B);
+MlpWork mlp_work_carve(void* work, int dp, int op, int B);
+hipError_t mlp_forward_launch(const MlpNet& net, const uint16_t* x, int B, float* out, const MlpWork* wk,
+                              hipStream_t st);
+hipError_t mlp_backward_launch(const MlpNet& net, const float* dout, int B, const MlpWork& wk, hipStream_t st);
+hipError_t mlp_adam_launch(const MlpNet& net, bool update, float lr, float b1, float b2, float eps, int t,
+                           hipStream_t st);
+
+// ---------------------------------------------------------------- Monte Carlo step
+struct McArgs {
+    int n, L, n_tau, n_bin;
+    double eps;
+    const double* g0;
+    int W;
+    uint32_t* state;
+    double* logw;
+    int8_t* sign;
+    uint64_t seed;
+    int step;
+};
+
+hipError_t mc_context_launch(const McArgs& a, int32_t* moved, uint16_t* feat, int dp, hipStream_t st);
+hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, const float* logits, int stride, uint32_t* prop,
+                             double* logq, double* mats, hipStream_t st);
+hipError_t mc_gather_launch(const McArgs& a, double* mats, hipStream_t st);
+hipError_t mc_accept_launch(const McArgs& a, const int32_t* moved, const uint32_t* prop, const double* logq,
+                            const double* c, double* logc_out, uint8_t* acc_out, float* obs_logw, int8_t* obs_sign,
+                            hipStream_t st);
+hipError_t mc_set_launch(const McArgs& a, const double* c, hipStream_t st);
+hipError_t mc_loss_launch(const McArgs& a, const float* logits, int Op, const uint32_t* prop, const double* logc,
+                          float* gbuf, float* dout, float* loss, double clip, hipStream_t st);
+
 }  // namespace apm

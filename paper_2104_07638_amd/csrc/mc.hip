@@ -1,0 +1,393 @@
+// mc.hip -- Metropolis-Hastings step over vertex configurations on gfx950.
+//
+// The weight of a configuration is |c[V]|, the connected sum over all its vertices
+// (Sec. V.A, Eq. (recursion)) of a[S] = det(M[S])^2 with M_ij = G0(X_i - X_j), computed by
+// the minors and connected-sum kernels of this library.  The kernels here do the rest
+// of a step: the moved vertex and its context features, the proposal (uniform, or drawn
+// from the network's site and time-bin logits) with its log proposal ratio, the
+// gather of the proposal's propagator matrix from the G0 table, the acceptance test
+// and the regression loss that trains the network.
+//
+// Random numbers: Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11) keyed by
+// (seed, 0) at counter (walker, step, call, 0).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "apm_device.h"
+#include "apm_kernels.h"
+
+namespace apm {
+namespace {
+
+struct U4 {
+    uint64_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1)
+{
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 draws(const McArgs& a, int w, int call)
+{
+    return philox((uint64_t)w, (uint64_t)(uint32_t)a.step, (uint64_t)call, 0ull, a.seed, 0ull);
+}
+
+__device__ __forceinline__ int below(uint64_t r, int m) { return (int)__umul64hi(r, (uint64_t)m); }
+
+__device__ __forceinline__ double unif(uint64_t r) { return ((double)(r >> 12) + 0.5) * 0x1p-52; }
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ double wave_min_d(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// inclusive prefix sum over the 64 lanes
+__device__ __forceinline__ double wave_scan(double v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Propagator matrix of walker w with vertex k replaced by vnew (k < 0: no replacement).
+// Vertices outside the grid give NaN entries (no table read).
+__device__ void gather(const McArgs& a, int w, int k, uint32_t vnew, double* __restrict__ mats)
+{
+    const int lane = lane_id();
+    const int n = a.n, L = a.L, L2 = L * L, nn = n * n;
+    uint32_t v = 0;
+    if (lane < n) v = (lane == k) ? vnew : a.state[(size_t)w * n + lane];
+    double* M = mats + (size_t)w * nn;
+    for (int base = 0; base < nn; base += kWave) {
+        const int e = base + lane;
+        const int i = e < nn ? e / n : 0, j = e < nn ? e % n : 0;
+        const uint32_t vi = __shfl(v, i), vj = __shfl(v, j);
+        if (e < nn) {
+            const int si = (int)(vi & 0xFFFFu), ti = (int)(vi >> 16);
+            const int sj = (int)(vj & 0xFFFFu), tj = (int)(vj >> 16);
+            double val = __builtin_nan("");
+            if (si < L2 && sj < L2 && ti < a.n_tau && tj < a.n_tau) {
+                const int dx = (si % L - sj % L + L) % L;
+                const int dy = (si / L - sj / L + L) % L;
+                const int d = ti - tj + a.n_tau - 1;
+                val = a.g0[(size_t)d * L2 + dy * L + dx];
+            }
+            M[e] = val;
+        }
+    }
+}
+
+// moved vertex and (optionally) BF16 context features; one wavefront per walker
+__global__ __launch_bounds__(256) void mc_context_kernel(McArgs a, int32_t* __restrict__ moved,
+                                                         uint16_t* __restrict__ feat, int dp)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.W) return;
+    const int n = a.n;
+    const U4 d0 = draws(a, w, 0);
+    const int k = below(d0.x, n);
+    if (lane == 0) moved[w] = k;
+    if (!feat) return;
+    const uint32_t v = lane < n ? a.state[(size_t)w * n + lane] : 0xFFFFFFFFu;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+        const uint32_t vj = __shfl(v, j);
+        if (j != k && j != lane && (vj < v || (vj == v && j < lane))) ++rank;
+    }
+    uint16_t* f = feat + (size_t)w * dp;
+    if (lane < n && lane != k) {
+        const int s = (int)(v & 0xFFFFu), t = (int)(v >> 16);
+        f[3 * rank + 0] = f2bf((float)(s % a.L) / (float)a.L);
+        f[3 * rank + 1] = f2bf((float)(s / a.L) / (float)a.L);
+        f[3 * rank + 2] = f2bf(((float)t + 0.5f) / (float)a.n_tau);
+    }
+    for (int q = 3 * (n - 1) + lane; q < dp; q += kWave) f[q] = 0;
+}
+
+struct Dist {
+    double mx, tot;   // max logit, sum of exp(logit - mx)
+};
+
+// log q~(v) of the mixed learned proposal given the site and bin normalisers
+__device__ __forceinline__ double log_qt(const McArgs& a, const float* lg, Dist ds, Dist db, int per_bin, int s, int t)
+{
+    const int L2 = a.L * a.L;
+    const double ps = exp((double)lg[s] - ds.mx) / ds.tot;
+    const double pb = exp((double)lg[L2 + t / per_bin] - db.mx) / db.tot;
+    return log((1.0 - a.eps) * ps * pb / per_bin + a.eps / ((double)L2 * a.n_tau));
+}
+
+__global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t* __restrict__ moved,
+                                                         const float* __restrict__ logits, int stride,
+                                                         uint32_t* __restrict__ prop, double* __restrict__ logq,
+                                                         double* __restrict__ mats)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.W) return;
+    const int n = a.n, L2 = a.L * a.L;
+    int k = moved[w];
+    if (k < 0 || k >= n) k = 0;
+    const U4 d0 = draws(a, w, 0);
+    int site = below(d0.z, L2), t = below(d0.w, a.n_tau);
+    double lq = 0.0;
+    if (logits) {
+        const U4 d1 = draws(a, w, 1);
+        const float* lg = logits + (size_t)w * stride;
+        const int per_bin = a.n_tau / a.n_bin;
+        // site distribution: lane owns the contiguous block [j0, j1)
+        const int P = (L2 + kWave - 1) / kWave;
+        const int j0 = min(L2, lane * P), j1 = min(L2, j0 + P);
+        double mx = -INFINITY;
+        for (int j = j0; j < j1; ++j) mx = fmax(mx, (double)lg[j]);
+        mx = wave_max(mx);
+        double part = 0.0;
+        for (int j = j0; j < j1; ++j) part += exp((double)lg[j] - mx);
+        const double incl = wave_scan(part);
+        double excl = __shfl_up(incl, 1);
+        if (lane == 0) excl = 0.0;
+        const Dist ds{mx, __shfl(incl, 63)};
+        // bin distribution: one bin per lane
+        const double bl = lane < a.n_bin ? (double)lg[L2 + lane] : -INFINITY;
+        const double mxb = wave_max(bl);
+        const double pbl = lane < a.n_bin ? exp(bl - mxb) : 0.0;
+        const double inclb = wave_scan(pbl);
+        const Dist db{mxb, __shfl(inclb, 63)};
+        if (!(unif(d0.y) < a.eps)) {
+            const double tg = unif(d1.x) * ds.tot;
+            int cand = 0x7FFFFFFF, lastpos = -1;
+            double run = excl;
+            for (int j = j0; j < j1; ++j) {
+                const double p = exp((double)lg[j] - mx);
+                run += p;
+                if (p > 0.0) {
+                    lastpos = j;
+                    if (run > tg && cand == 0x7FFFFFFF) cand = j;
+                }
+            }
+            site = wave_min_i(cand);
+            if (site == 0x7FFFFFFF) site = wave_max_i(lastpos);
+            const double tgb = unif(d1.y) * db.tot;
+            const int cb = (lane < a.n_bin && pbl > 0.0 && inclb > tgb) ? lane : 0x7FFFFFFF;
+            int b = wave_min_i(cb);
+            if (b == 0x7FFFFFFF) b = wave_max_i((lane < a.n_bin && pbl > 0.0) ? lane : -1);
+            t = b * per_bin + below(d1.z, per_bin);
+        }
+        const uint32_t vk = a.state[(size_t)w * n + k];
+        lq = log_qt(a, lg, ds, db, per_bin, (int)(vk & 0xFFFFu) < L2 ? (int)(vk & 0xFFFFu) : 0,
+                    (int)(vk >> 16) < a.n_tau ? (int)(vk >> 16) : 0) -
+             log_qt(a, lg, ds, db, per_bin, site, t);
+    }
+    const uint32_t vnew = (uint32_t)site | ((uint32_t)t << 16);
+    if (lane == 0) {
+        prop[w] = vnew;
+        logq[w] = lq;
+    }
+    gather(a, w, k, vnew, mats);
+}
+
+__global__ __launch_bounds__(256) void mc_gather_kernel(McArgs a, double* __restrict__ mats)
+{
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.W) return;
+    gather(a, w, -1, 0u, mats);
+}
+
+__device__ __forceinline__ double log_abs(double c) { return (isfinite(c) && c != 0.0) ? log(fabs(c)) : -INFINITY; }
+
+__global__ __launch_bounds__(256) void mc_accept_kernel(McArgs a, const int32_t* __restrict__ moved,
+                                                        const uint32_t* __restrict__ prop,
+                                                        const double* __restrict__ logq,
+                                                        const double* __restrict__ c, double* logc_out,
+                                                        uint8_t* acc_out, float* obs_logw, int8_t* obs_sign)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    const size_t nm = (size_t)1 << a.n;
+    const double cv = c[(size_t)w * nm + nm - 1];
+    const double lc = log_abs(cv);
+    double lw = a.logw[w];
+    int8_t sg = a.sign[w];
+    const int k = moved[w];
+    const U4 d1 = draws(a, w, 1);
+    const double logR = lc - lw + logq[w];
+    const bool acc = (k >= 0 && k < a.n) && lc > -INFINITY && (!(lw > -INFINITY) || log(unif(d1.w)) < logR);
+    if (acc) {
+        a.state[(size_t)w * a.n + k] = prop[w];
+        lw = lc;
+        sg = cv > 0.0 ? (int8_t)1 : (int8_t)-1;
+        a.logw[w] = lw;
+        a.sign[w] = sg;
+    }
+    if (logc_out) logc_out[w] = lc;
+    if (acc_out) acc_out[w] = acc ? 1 : 0;
+    if (obs_logw) obs_logw[w] = (float)lw;
+    if (obs_sign) obs_sign[w] = sg;
+}
+
+__global__ __launch_bounds__(256) void mc_set_kernel(McArgs a, const double* __restrict__ c)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    const size_t nm = (size_t)1 << a.n;
+    const double cv = c[(size_t)w * nm + nm - 1];
+    const double lc = log_abs(cv);
+    a.logw[w] = lc;
+    a.sign[w] = lc > -INFINITY ? (cv > 0.0 ? (int8_t)1 : (int8_t)-1) : (int8_t)0;
+}
+
+// Regression targets: y = log|c'| clipped below at (max - clip); g[r] = 2 (pred - y) / W.
+__global__ __launch_bounds__(1024) void mc_loss_kernel(McArgs a, const float* __restrict__ logits, int Op,
+                                                       const uint32_t* __restrict__ prop,
+                                                       const double* __restrict__ logc, float* __restrict__ gbuf,
+                                                       float* loss, double clip)
+{
+    __shared__ double red[1024 / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int L2 = a.L * a.L, per_bin = a.n_tau / a.n_bin;
+    double mx = -INFINITY;
+    for (int r = tid; r < a.W; r += 1024) {
+        const double y = logc[r];
+        if (isfinite(y)) mx = fmax(mx, y);
+    }
+    mx = wave_max(mx);
+    if (lane == 0) red[wv] = mx;
+    __syncthreads();
+    mx = -INFINITY;
+    for (int i = 0; i < 16; ++i) mx = fmax(mx, red[i]);
+    __syncthreads();
+    const bool any = mx > -INFINITY;
+    const double floor_y = mx - clip;
+    double sum = 0.0;
+    for (int r = tid; r < a.W; r += 1024) {
+        float gr = 0.0f;
+        if (any) {
+            double y = logc[r];
+            y = isfinite(y) ? fmax(y, floor_y) : floor_y;
+            const uint32_t v = prop[r];
+            const int s = (int)(v & 0xFFFFu), b = (int)(v >> 16) / per_bin;
+            const double pred = (double)logits[(size_t)r * Op + s] + (double)logits[(size_t)r * Op + L2 + b];
+            const double diff = pred - y;
+            gr = (float)(2.0 * diff / a.W);
+            sum += diff * diff;
+        }
+        gbuf[r] = gr;
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if (lane == 0) red[wv] = sum;
+    __syncthreads();
+    if (tid == 0 && loss) {
+        double s = 0.0;
+        for (int i = 0; i < 16; ++i) s += red[i];
+        loss[0] = (float)(s / (a.W > 0 ? a.W : 1));
+    }
+}
+
+__global__ __launch_bounds__(256) void mc_dout_kernel(McArgs a, int Op, const uint32_t* __restrict__ prop,
+                                                      const float* __restrict__ gbuf, float* __restrict__ dout)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)a.W * Op) return;
+    const int r = (int)(i / Op), f = (int)(i % Op);
+    const uint32_t v = prop[r];
+    const int L2 = a.L * a.L;
+    const int s = (int)(v & 0xFFFFu), b = (int)(v >> 16) / (a.n_tau / a.n_bin);
+    dout[i] = (f == s || f == L2 + b) ? gbuf[r] : 0.0f;
+}
+
+unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t mc_context_launch(const McArgs& a, int32_t* moved, uint16_t* feat, int dp, hipStream_t st)
+{
+    if (a.W == 0) return hipSuccess;
+    hipLaunchKernelGGL(mc_context_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, moved, feat, dp);
+    return hipGetLastError();
+}
+
+hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, const float* logits, int stride, uint32_t* prop,
+                             double* logq, double* mats, hipStream_t st)
+{
+    if (a.W == 0) return hipSuccess;
+    hipLaunchKernelGGL(mc_propose_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, moved, logits, stride, prop,
+                       logq, mats);
+    return hipGetLastError();
+}
+
+hipError_t mc_gather_launch(const McArgs& a, double* mats, hipStream_t st)
+{
+    if (a.W == 0) return hipSuccess;
+    hipLaunchKernelGGL(mc_gather_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, mats);
+    return hipGetLastError();
+}
+
+hipError_t mc_accept_launch(const McArgs& a, const int32_t* moved, const uint32_t* prop, const double* logq,
+                            const double* c, double* logc_out, uint8_t* acc_out, float* obs_logw, int8_t* obs_sign,
+                            hipStream_t st)
+{
+    if (a.W == 0) return hipSuccess;
+    hipLaunchKernelGGL(mc_accept_kernel, dim3(blocks_for(a.W, 256)), dim3(256), 0, st, a, moved, prop, logq, c,
+                       logc_out, acc_out, obs_logw, obs_sign);
+    return hipGetLastError();
+}
+
+hipError_t mc_set_launch(const McArgs& a, const double* c, hipStream_t st)
+{
+    if (a.W == 0) return hipSuccess;
+    hipLaunchKernelGGL(mc_set_kernel, dim3(blocks_for(a.W, 256)), dim3(256), 0, st, a, c);
+    return hipGetLastError();
+}
+
+hipError_t mc_loss_launch(const McArgs& a, const float* logits, int Op, const uint32_t* prop, const double* logc,
+                          float* gbuf, float* dout, float* loss, double clip, hipStream_t st)
+{
+    if (a.W == 0) return hipSuccess;
+    hipLaunchKernelGGL(mc_loss_kernel, dim3(1), dim3(1024), 0, st, a, logits, Op, prop, logc, gbuf, loss, clip);
+    hipLaunchKernelGGL(mc_dout_kernel, dim3(blocks_for((int64_t)a.W * Op, 256)), dim3(256), 0, st, a, Op, prop, gbuf,
+                       dout);
+    return hipGetLastError();
+}
+
+}  // namespace apm

@@ -1,4 +1,4 @@
-"""The C ABI library loads, exports every symbol include/apm.h declares, and rejects bad
+"""The C ABI library loads, exports every symbol include/*.h declares, and rejects bad
 arguments on the host before any device work (no GPU needed)."""
 import ctypes
 import os
@@ -16,8 +16,13 @@ def apm():
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "apm.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:apm_status|const char|int)\s*\*?\s*(apm_\w+)\s*\(", src, re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"^\s*(?:apm_status|const char|int|int64_t)\s*\*?\s*(apm_\w+)\s*\(", src,
+                                    re.M))
+    return sorted(names)
 
 
 def test_header_declarations_are_exported(apm):
@@ -70,3 +75,54 @@ def test_cs_and_perm_validation(apm):
     assert apm.apm_all_perm_minors(P, _bd(apm, n=17), P, None) == apm.APM_EUNSUPPORTED
     assert apm.apm_all_perm_minors(None, _bd(apm), P, None) == apm.APM_EINVAL
     assert apm.apm_all_perm_minors(P, _bd(apm, batch=0), P, None) == apm.APM_OK
+
+
+def _model(apm, n=10, L=16, n_tau=128, n_bin=16, eps=0.1, g0=16):
+    return apm.apm_mc_model(n, L, n_tau, n_bin, eps, g0)
+
+
+def test_mlp_sizes_and_validation(apm):
+    assert apm.apm_mlp_param_count(27, 272) == 128 * 32 + 128 * 128 + 272 * 128 + 128 + 128 + 272
+    assert apm.apm_mlp_weight_count(6, 8) == 128 * 16 + 128 * 128 + 16 * 128
+    assert apm.apm_mlp_param_count(0, 8) == -1 and apm.apm_mlp_param_count(65, 8) == -1
+    assert apm.apm_mlp_param_count(8, 4097) == -1
+    assert apm.apm_mlp_work_bytes(27, 272, 33) == -1 and apm.apm_mlp_work_bytes(27, 272, 64) > 0
+    net = apm.apm_mlp(27, 272, 16, 16, 16, 16, 16, 16)
+    assert apm.apm_mlp_forward(net, P, 48, P, None, None) == apm.APM_EINVAL        # batch % 32
+    assert apm.apm_mlp_forward(net, None, 32, P, None, None) == apm.APM_EINVAL
+    assert apm.apm_mlp_forward(net, P, 0, P, None, None) == apm.APM_OK
+    assert apm.apm_mlp_forward(None, P, 32, P, None, None) == apm.APM_EINVAL
+    assert apm.apm_mlp_backward(net, P, 32, None, None) == apm.APM_EINVAL          # needs the forward work
+    bad = apm.apm_mlp(0, 272, 16, 16, 16, 16, 16, 16)
+    assert apm.apm_mlp_sync(bad, None) == apm.APM_EINVAL
+    assert apm.apm_mlp_adam(net, apm.apm_adam(1e-3, 0.9, 0.999, 1e-8, 0), None) == apm.APM_EINVAL
+    assert apm.apm_mlp_adam(net, apm.apm_adam(1e-3, 1.0, 0.999, 1e-8, 1), None) == apm.APM_EINVAL
+    assert apm.apm_mlp_adam(net, None, None) == apm.APM_EINVAL
+
+
+def test_mc_validation(apm):
+    ch = apm.apm_mc_chain(64, 16, 16, 16)
+    assert apm.apm_mc_work_bytes(_model(apm, g0=0), 64, 1) > 0                      # sizing needs no table
+    assert apm.apm_mc_work_bytes(_model(apm), 33, 1) == -1
+    assert apm.apm_mc_work_bytes(_model(apm, n=1), 64, 0) == -1
+    f = apm.apm_mc_step
+    assert f(_model(apm, n=17), ch, None, None, 1, 0, None, P, None) == apm.APM_EUNSUPPORTED
+    assert f(_model(apm, n=1), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    assert f(_model(apm, n_tau=100, n_bin=16), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    assert f(_model(apm, n_bin=65, n_tau=130), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    assert f(_model(apm, eps=1.5), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    assert f(_model(apm, L=257), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    assert f(_model(apm, g0=0), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    assert f(_model(apm), ch, None, None, 1, 0, None, None, None) == apm.APM_EINVAL    # no work buffer
+    assert f(_model(apm), apm.apm_mc_chain(64, None, 16, 16), None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    net = apm.apm_mlp(27, 272, 16, 16, 16, 16, 16, 16)
+    wrong = apm.apm_mlp(26, 272, 16, 16, 16, 16, 16, 16)
+    assert f(_model(apm), ch, wrong, None, 1, 0, None, P, None) == apm.APM_EINVAL     # sizes do not match n, L
+    assert f(_model(apm), apm.apm_mc_chain(48, 16, 16, 16), net, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    adam = apm.apm_adam(1e-3, 0.9, 0.999, 1e-8, 1)
+    assert f(_model(apm), ch, None, adam, 1, 0, None, P, None) == apm.APM_EINVAL      # training needs a net
+    assert f(_model(apm), apm.apm_mc_chain(0, None, None, None), None, None, 1, 0, None, None, None) == apm.APM_OK
+    assert apm.apm_mc_propose(_model(apm), ch, 1, 0, P, P, 100, P, P, P, None) == apm.APM_EINVAL  # short stride
+    assert apm.apm_mc_context(_model(apm), ch, 1, 0, None, None, None) == apm.APM_EINVAL
+    assert apm.apm_mc_accept(_model(apm), ch, 1, 0, P, P, P, P, None, None, None) == apm.APM_EINVAL
+    assert apm.apm_mc_evaluate(_model(apm), ch, None, None) == apm.APM_EINVAL
