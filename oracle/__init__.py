@@ -54,6 +54,8 @@ def load_library(path: str):
         fn.argtypes = [ctypes.c_int, dp, dp]
         fn.restype = ctypes.c_int
     lib.apm_oracle_connected_sums.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int]
+    lib.apm_oracle_cs_input_bound.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_int]
+    lib.apm_oracle_cs_input_bound.restype = ctypes.c_int
     lib.apm_oracle_connected_sums.restype = ctypes.c_int
     for name in ("apm_oracle_minors_r64_batch", "apm_oracle_minors_c128_batch",
                  "apm_oracle_perm_minors_batch"):
@@ -216,6 +218,23 @@ def cs_scale(a, c, mode: int = 0, lib=None) -> np.ndarray:
         if rc != 0:
             raise ValueError("oracle: bad arguments")
     return d
+
+
+def cs_input_bound(a, c, da, mode: int = 0, lib=None) -> np.ndarray:
+    """First-order bound on |c' - c| when the weights carry errors of at most ``da``
+    (metric helper for parity tests; Eq. (recursion) differentiated term by term)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    da = np.ascontiguousarray(da, dtype=np.float64)
+    n = a.shape[-1].bit_length() - 1
+    e = np.empty_like(a)
+    for idx in np.ndindex(a.shape[:-1]):
+        rc = _load(lib).apm_oracle_cs_input_bound(n, _dp(np.ascontiguousarray(a[idx])),
+                                                  _dp(np.ascontiguousarray(c[idx])),
+                                                  _dp(np.ascontiguousarray(da[idx])), _dp(e[idx]), int(mode))
+        if rc != 0:
+            raise ValueError("oracle: bad arguments")
+    return e
 
 
 def perm_minors(A, nthreads: int = 0, lib=None) -> np.ndarray:

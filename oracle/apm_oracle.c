@@ -241,6 +241,32 @@ int apm_oracle_cs_scale(int n, const double *a, const double *c, double *d, int 
     return 0;
 }
 
+/* First-order bound on the change of the connected sums when the weights a[] carry
+ * errors of at most da[] (metric helper for parity tests whose weights come from
+ * independently rounded minors): from Eq. (recursion),
+ *     e[S] = da[S] + sum_{T: j in T, T != S} ( e[T] |a[S \ T]| + |c[T]| da[S \ T] ). */
+int apm_oracle_cs_input_bound(int n, const double *a, const double *c, const double *da, double *e, int mode)
+{
+    if (n < 0 || n > ORACLE_MAX_N || (mode != 0 && mode != 1)) return -1;
+    const uint32_t nm = 1u << n;
+    e[0] = 0.0;
+    for (uint32_t S = 1; S < nm; ++S) {
+        uint32_t jbit = (mode == 0) ? 1u : (S & (0u - S));
+        if (!(S & jbit)) { e[S] = 0.0; continue; }
+        double acc = da[S];
+        uint32_t rest = S & ~jbit;
+        uint32_t U = rest;
+        for (;;) {
+            uint32_t T = jbit | U;
+            if (T != S) acc += e[T] * fabs(a[S & ~T]) + fabs(c[T]) * da[S & ~T];
+            if (U == 0) break;
+            U = (U - 1) & rest;
+        }
+        e[S] = acc;
+    }
+    return 0;
+}
+
 /* Permanent principal minors by Ryser's formula applied to each subset S
  * separately (Sec. IV, the "naive successive application", O(n 3^n)):
  *     per(A[S]) = (-1)^|S| sum_{T subset of S} (-1)^|T| prod_{i in S} sum_{j in T} A_ij.

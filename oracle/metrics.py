@@ -53,3 +53,35 @@ def max_mixed_err(X, REF, A):
         e = mixed_err(X[b], REF[b], hadamard_bounds(A[b]))
         worst = max(worst, float(np.max(e)))
     return worst
+
+
+def hadamard_bounds_batch(A):
+    """hadamard_bounds for a (B, n, n) batch."""
+    A = np.asarray(A)
+    B, n, _ = A.shape
+    sq = np.abs(A) ** 2
+    nm = 1 << n
+    masks = np.arange(nm)
+    logH = np.zeros((B, nm))
+    for i in range(n):
+        rows = np.zeros((B, 1))
+        for j in range(n):
+            rows = np.concatenate([rows, rows + sq[:, i, j:j + 1]], axis=1)
+        with np.errstate(divide="ignore"):
+            lr = 0.5 * np.log(rows)
+        logH = logH + np.where(((masks >> i) & 1) == 1, lr, 0.0)
+    return np.exp(logH)
+
+
+def cdet_tolerance(A, m, c, eps_minor=1e-10, eps_cs=1e-10, mode=0):
+    """Tolerance for connected sums computed from independently rounded minors of A:
+    each minor may be off by eps_minor * max(|m|, H_S) (the minors' own gate), which
+    gives weight errors da = 2|m| dm + dm^2 for a = m^2, propagated through the
+    recursion to first order; plus eps_cs times the recursion's own rounding scale."""
+    from . import cs_input_bound, cs_scale
+    A = np.asarray(A)
+    H = hadamard_bounds_batch(A)
+    dm = eps_minor * np.maximum(np.abs(m), H)
+    a = m * m
+    da = 2.0 * np.abs(m) * dm + dm * dm
+    return eps_cs * cs_scale(a, c, mode) + cs_input_bound(a, c, da, mode)

@@ -42,3 +42,33 @@ def test_rooted_mode_zero_outside_root(oracle_mod):
             assert c0[m] == c1[m]       # the lowest vertex of a set containing 0 is 0
         else:
             assert c0[m] == 0.0
+
+
+def test_cs_input_bound_bounds_perturbations(oracle_mod):
+    """The first-order error bound of the recursion covers actual perturbations of a."""
+    rng = np.random.default_rng(17)
+    n = 7
+    for mode in (0, 1):
+        a = rng.standard_normal(1 << n)
+        c = oracle_mod.connected_sums(a, mode)
+        da = np.abs(a) * 1e-9 + 1e-12
+        e = oracle_mod.cs_input_bound(a, c, da, mode)
+        worst = 0.0
+        for _ in range(20):
+            pert = a + da * rng.uniform(-1, 1, a.shape)
+            diff = np.abs(oracle_mod.connected_sums(pert, mode) - c)
+            worst = max(worst, float(np.max(diff / (e + 1e-300))))
+        assert worst <= 1.0 + 1e-6
+        # and a single-entry perturbation at the full bound is reached exactly at first order
+        S = (1 << n) - 1
+        p2 = a.copy()
+        p2[S] += da[S]
+        assert abs(oracle_mod.connected_sums(p2, mode)[S] - c[S]) <= e[S] * (1 + 1e-6)
+
+
+def test_hadamard_batch_matches_single():
+    from oracle import metrics
+    A = np.random.default_rng(3).standard_normal((4, 6, 6))
+    Hb = metrics.hadamard_bounds_batch(A)
+    for b in range(4):
+        np.testing.assert_allclose(Hb[b], metrics.hadamard_bounds(A[b]), rtol=1e-14)

@@ -139,12 +139,13 @@ def test_mlp_adam(apm):
 
 # ------------------------------------------------------------------ Monte Carlo pieces
 class _Setup:
-    def __init__(self, apm, model, W, seed=5):
+    def __init__(self, apm, model, W, seed=5, cluster=True):
         self.model = model
         self.g0 = wl.mc_g0_table(model)
         self.g0_d = torch.from_numpy(self.g0).cuda()
         self.m = apm.mc_model(model.n, model.L, model.n_tau, model.n_bin, model.eps, self.g0_d)
-        self.states = wl.mc_initial_states(W, model, seed=seed)
+        self.states = (wl.mc_cluster_states(W, model, seed=seed) if cluster
+                       else wl.mc_initial_states(W, model, seed=seed))
         self.chain = apm.McChain(self.states)
         self.W = W
 
@@ -234,50 +235,60 @@ def test_mc_propose_learned(apm, gain):
     np.testing.assert_array_equal(mats.cpu().numpy(), omc.matrices(s.model, s.g0, new))
 
 
-def _accept_check(s, seed, step, k, prop_u32, logq, logw, acc_gpu, lc_gpu):
-    """Compare a GPU acceptance with the oracle; returns the walkers whose decision was a
-    near-tie (excluded from later comparisons)."""
+def _accept_check(s, seed, step, k, prop_u32, logq, logw, logw_tol, acc_gpu, lc_gpu):
+    """Compare a GPU acceptance with the oracle; returns (near-tie walkers, oracle
+    decisions, log-space tolerance of the proposals' weights)."""
     new = s.states_cur.copy()
     new[np.arange(s.W), k] = prop_u32
-    m = omc.minors(omc.matrices(s.model, s.g0, new))
-    from oracle import connected_sums, cs_scale
-    a = m * m
-    c = connected_sums(a, mode=0)
-    d = cs_scale(a, c, mode=0)[:, -1]
+    M = omc.matrices(s.model, s.g0, new)
+    m = omc.minors(M)
+    from oracle import connected_sums, metrics
+    c = connected_sums(m * m, mode=0)
     cv = c[:, -1]
+    tabs = metrics.cdet_tolerance(M, m, c)[:, -1]
+    # ||c_gpu| - |c_ref|| within the propagated tolerance; exp(-inf) = 0
+    assert np.all(np.abs(np.exp(lc_gpu) - np.abs(cv)) <= tabs + 1e-300)
     lc = omc.log_abs(cv)
     fin = np.isfinite(lc)
-    tol = 1e-10 * d[fin] / np.abs(cv[fin]) + 1e-14
-    assert np.all(np.abs(lc_gpu[fin] - lc[fin]) <= tol)
-    assert np.all(~np.isfinite(lc_gpu[~fin]))
+    tol = np.full(s.W, np.inf)
+    tol[fin] = tabs[fin] / np.abs(cv[fin])
     _, d1 = omc.draws(seed, s.W, step)
     u = philox.uniform(d1[:, 3])
     acc = omc.accept(logw, lc, logq, u)
-    with np.errstate(invalid="ignore"):
-        margin = np.abs(np.log(u) - (lc - logw + logq))
-    tie = fin & np.isfinite(logw) & (margin <= 1e-9 * np.maximum(1.0, np.abs(lc - logw)))
+    # the decision is fixed unless log u falls inside the bracket of log R that the
+    # tolerance on |c'| allows (a zero current weight accepts any nonzero proposal)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        hi = np.log(np.abs(cv) + tabs) - logw + logq + logw_tol
+        lo = np.log(np.maximum(np.abs(cv) - tabs, 0.0)) - logw + logq - logw_tol
+        lu = np.log(u)
+        tie = np.isfinite(logw) & (lu < hi + 1e-9) & (lu >= lo - 1e-9)
     assert np.all((acc == acc_gpu) | tie)
-    return tie, acc
+    return tie, acc, tol
 
 
 def test_mc_evaluate(apm):
     s = _Setup(apm, CFG5, 512, seed=3)
-    bad = s.states.copy()
-    bad[5, 2] = omc.pack(300, 0)           # site outside the lattice
-    bad[6, 0] = omc.pack(0, 500)           # time point outside the grid
-    ch = apm.McChain(bad)
+    mix = s.states.copy()
+    mix[256:] = wl.mc_initial_states(256, s.model, seed=3)      # half spread out (weights at rounding level)
+    mix[5, 2] = omc.pack(300, 0)           # site outside the lattice
+    mix[6, 0] = omc.pack(0, 500)           # time point outside the grid
+    ch = apm.McChain(mix)
     work = apm.mc_work(s.m, s.W, False)
     apm.mc_evaluate(s.m, ch, work)
     lw = ch.logw.cpu().numpy()
     sg = ch.sign.cpu().numpy()
-    c = omc.full_connected_sum(s.model, s.g0, s.states)
     ok = np.ones(s.W, dtype=bool)
     ok[[5, 6]] = False
-    from oracle import connected_sums, cs_scale
-    m = omc.minors(omc.matrices(s.model, s.g0, s.states))
-    d = cs_scale(m * m, connected_sums(m * m, 0), 0)[:, -1]
-    assert np.all(np.abs(lw[ok] - omc.log_abs(c)[ok]) <= 1e-10 * d[ok] / np.abs(c[ok]) + 1e-14)
-    assert np.all(sg[ok] == np.sign(c[ok]))
+    from oracle import connected_sums, metrics
+    M = omc.matrices(s.model, s.g0, mix[ok])
+    m = omc.minors(M)
+    c = connected_sums(m * m, 0)
+    tabs = metrics.cdet_tolerance(M, m, c)[:, -1]
+    cv = c[:, -1]
+    resolved = np.abs(cv) > 2.0 * tabs                 # the sign is fixed by the bound
+    assert resolved[:200].sum() >= 180                 # most of the clustered half
+    assert np.all(np.abs(np.exp(lw[ok]) - np.abs(cv)) <= tabs)
+    assert np.all(sg[ok][resolved] == np.sign(cv[resolved]))
     assert np.all(np.isneginf(lw[~ok])) and np.all(sg[~ok] == 0)
 
 
@@ -288,8 +299,12 @@ def test_mc_uniform_chain(apm):
     apm.mc_evaluate(s.m, s.chain, work)
     rec = apm.McRecord(s.W, loss=False)
     states = s.states.copy()
-    c0 = omc.full_connected_sum(s.model, s.g0, states)
-    logw = omc.log_abs(c0)
+    from oracle import connected_sums, metrics
+    M0 = omc.matrices(s.model, s.g0, states)
+    m0 = omc.minors(M0)
+    c0 = connected_sums(m0 * m0, 0)
+    logw = omc.log_abs(c0[:, -1])
+    logw_tol = metrics.cdet_tolerance(M0, m0, c0)[:, -1] / np.abs(c0[:, -1])
     live = np.ones(s.W, dtype=bool)
     n_acc = 0
     for step in range(12):
@@ -300,15 +315,17 @@ def test_mc_uniform_chain(apm):
         pr, lq = omc.propose(s.model, states, k, d0, d1, None)
         np.testing.assert_array_equal(rec.proposed.cpu().numpy().view(np.uint32)[live], pr[live])
         s.states_cur = states
-        tie, acc = _accept_check(s, 2024, step, k, pr, lq, logw, rec.accepted.cpu().numpy().astype(bool),
-                                 rec.logc_prop.cpu().numpy())
-        live &= ~tie
+        acc_gpu = rec.accepted.cpu().numpy().astype(bool)
+        tie, acc, tol = _accept_check(s, 2024, step, k, pr, lq, logw, logw_tol, acc_gpu,
+                                      rec.logc_prop.cpu().numpy())
+        live &= acc == acc_gpu          # a differing decision (a tie) ends that walker's comparison
         n_acc += int(acc[live].sum())
         new = states.copy()
         new[np.arange(s.W), k] = pr
         cnew = omc.full_connected_sum(s.model, s.g0, new)
         states = np.where(acc[:, None], new, states)
         logw = np.where(acc, omc.log_abs(cnew), logw)
+        logw_tol = np.where(acc, tol, logw_tol)
         got = s.state_np()
         np.testing.assert_array_equal(got[live], states[live])
     assert n_acc > 0

@@ -274,6 +274,22 @@ def mc_initial_states(W, m: McModel, seed=BASE_SEED) -> np.ndarray:
     return np.ascontiguousarray(pack_vertex(site, tidx))
 
 
+def mc_cluster_states(W, m: McModel, seed=BASE_SEED, width: int = 2, t_width: int = 8) -> np.ndarray:
+    """W configurations whose n vertices sit in a width x width block of sites and
+    t_width consecutive time points around a random corner (the compact region where
+    |c[V]| is large and resolved in fp64; uniformly spread vertices give |c[V]| at the
+    rounding level of the recursion's terms).  uint32 (W, n)."""
+    rng = _rng(seed + 4242)
+    x0 = rng.integers(0, m.L, size=(W, 1))
+    y0 = rng.integers(0, m.L, size=(W, 1))
+    tw = min(t_width, m.n_tau)
+    t0 = rng.integers(0, m.n_tau - tw + 1, size=(W, 1))
+    x = (x0 + rng.integers(0, width, size=(W, m.n))) % m.L
+    y = (y0 + rng.integers(0, width, size=(W, m.n))) % m.L
+    t = t0 + rng.integers(0, tw, size=(W, m.n))
+    return np.ascontiguousarray(pack_vertex(y * m.L + x, t))
+
+
 MLP_HIDDEN = 128
 
 
