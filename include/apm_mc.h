@@ -4,7 +4,10 @@
  *
  * The weight of a configuration X of n vertices is |c[V](X)|, the connected sum over
  * the full vertex set (Simkovic & Ferrero, arXiv:2104.07638, Sec. V.A, Eq. (recursion))
- * of the CDet weights a[S] = det(M[S])^2 with M_ij = G0(X_i - X_j) (both spins share M).
+ * of the CDet weights a[S] = det(M[S])^2 with M_ij = G0(X_i - X_j) (both spins share M),
+ * set to zero where it is not resolved above the recursion's rounding level (see
+ * apm_mc_model.resolve): c[V] cancels the disconnected products, and for spread-out
+ * vertices what remains is below fp64 resolution.
  * A step evaluates it with the same kernels as apm_all_minors and apm_connected_sums.
  * The paper defines the weight and the series, not the sampler: proposal, acceptance
  * and network below are this library's design.
@@ -105,6 +108,10 @@ typedef struct {
     int32_t n_tau;            /* time points, 1..32768                                    */
     int32_t n_bin;            /* time bins of the learned proposal, 1..64, divides n_tau  */
     double eps;               /* uniform fraction of the learned proposal, in [0, 1]      */
+    double resolve;           /* >= 0: a configuration whose |c[V]| is below resolve * d[V]
+                                 has weight 0, with d[V] = |a[V]| + sum over T containing
+                                 vertex 0, T != V, of |c[T]| |a[V \ T]| (the rounding
+                                 scale of the recursion at V); 0 keeps every nonzero c[V] */
     const double *g0;         /* [(2 n_tau - 1) x L^2] fp64: row d + n_tau - 1 holds the
                                  time difference d beta / n_tau (d = 0 is 0^-), column
                                  dy*L + dx the site difference mod L                     */
@@ -134,7 +141,8 @@ typedef struct {
 int64_t apm_mc_work_bytes(const apm_mc_model *m, int32_t walkers, int32_t with_net);
 
 /* logw and sign of the current configurations (initialisation).  Invalid vertices
- * (site >= L^2 or time point >= n_tau) give logw = -inf, sign = 0. */
+ * (site >= L^2 or time point >= n_tau) and unresolved weights give logw = -inf,
+ * sign = 0. */
 apm_status apm_mc_evaluate(const apm_mc_model *m, const apm_mc_chain *ch, void *work, apm_stream stream);
 
 /*
@@ -148,8 +156,9 @@ apm_status apm_mc_evaluate(const apm_mc_model *m, const apm_mc_chain *ch, void *
  *      q~(v) = (1-eps) p_site p_bin / (n_tau/n_bin) + eps / (L^2 n_tau).
  *      Categorical draws take the first index whose running sum exceeds u * total.
  *   3. c[V](X') via the minors and the rooted connected-sum recursion.
- *   4. accept iff log u < log|c'| - log|c| + log q~(v_k) - log q~(v'); a zero or
- *      non-finite c' is rejected; a walker at weight 0 moves to any nonzero proposal.
+ *   4. accept iff log u < log|c'| - log|c| + log q~(v_k) - log q~(v'); a zero,
+ *      unresolved or non-finite c' is rejected; a walker at weight 0 moves to any
+ *      proposal of nonzero weight.
  *   5. train != NULL (requires net): regression of site logit + bin logit of v' on
  *      log|c'| clipped below at (batch maximum - 30), mean squared error over the
  *      walkers, then apm_mlp_backward and one Adam step with *train.

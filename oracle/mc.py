@@ -3,7 +3,9 @@
 Target distribution: pi(X) proportional to |c[V](X)|, the connected sum over the full
 vertex set V of a configuration X (Sec. V.A, Eq. (recursion)) with the CDet weights
 a[S] = det(M[S])^2 (both spins share M) and M_ij = G0(X_i - X_j) (Sec. V.A), taken from
-the tabulated propagator of ``workloads.mc_g0_table``.
+the tabulated propagator of ``workloads.mc_g0_table``.  With model.resolve > 0 the weight
+is zero where |c[V]| < resolve * d[V], d[V] = |a[V]| + sum_T |c[T]| |a[V - T]| the
+recursion's rounding scale (``oracle.cs_scale``): there c[V] is not resolved in fp64.
 
 One step per walker (the paper defines the weight, not the sampler; this is the
 project's design):
@@ -25,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import connected_sums, minors
+from . import connected_sums, cs_scale, minors
 from . import mlp as _mlp
 from . import philox
 
@@ -55,6 +57,22 @@ def full_connected_sum(model, g0, states):
     m = minors(matrices(model, g0, states))
     c = connected_sums(m * m, mode=0)
     return c[:, -1]
+
+
+def weight(model, g0, states):
+    """(log of the weight, sign) per configuration: log|c[V]| and sign(c[V]), or
+    (-inf, 0) for a zero, non-finite or unresolved c[V]."""
+    m = minors(matrices(model, g0, states))
+    a = m * m
+    c = connected_sums(a, mode=0)
+    cv = c[:, -1]
+    ok = np.isfinite(cv) & (cv != 0.0)
+    if model.resolve > 0.0:
+        d = cs_scale(a, c, mode=0)[:, -1]
+        ok &= np.abs(cv) >= model.resolve * d
+    lw = np.full(cv.shape, -np.inf)
+    lw[ok] = np.log(np.abs(cv[ok]))
+    return lw, np.where(ok, np.sign(cv), 0.0).astype(np.int8)
 
 
 def log_abs(c):
@@ -180,13 +198,12 @@ def step(model, g0, states, logw, sign, seed, step_no, params=None, logits=None)
     prop, logq = propose(model, states, k, d0, d1, logits)
     new = states.copy()
     new[np.arange(W), k] = prop
-    c_prop = full_connected_sum(model, g0, new)
-    lc = log_abs(c_prop)
+    lc, sg = weight(model, g0, new)
     acc = accept(logw, lc, logq, philox.uniform(d1[:, 3]))
     out_states = np.where(acc[:, None], new, states)
     out_logw = np.where(acc, lc, logw)
-    out_sign = np.where(acc, np.sign(c_prop), sign).astype(np.int8)
-    return dict(k=k, feat=feat, logits=logits, prop=prop, logq=logq, c_prop=c_prop, logc_prop=lc,
+    out_sign = np.where(acc, sg, sign).astype(np.int8)
+    return dict(k=k, feat=feat, logits=logits, prop=prop, logq=logq, logc_prop=lc,
                 accept=acc, states=out_states, logw=out_logw, sign=out_sign)
 
 

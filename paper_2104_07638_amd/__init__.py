@@ -66,7 +66,7 @@ class apm_adam(ctypes.Structure):
 
 class apm_mc_model(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("L", ctypes.c_int32), ("n_tau", ctypes.c_int32), ("n_bin", ctypes.c_int32),
-                ("eps", ctypes.c_double), ("g0", ctypes.c_void_p)]
+                ("eps", ctypes.c_double), ("resolve", ctypes.c_double), ("g0", ctypes.c_void_p)]
 
 
 class apm_mc_chain(ctypes.Structure):
@@ -412,9 +412,9 @@ class McChain:
         return self.state.shape[0]
 
 
-def mc_model(n, L, n_tau, n_bin, eps, g0):
+def mc_model(n, L, n_tau, n_bin, eps, g0, resolve=0.0):
     """C descriptor of the model; ``g0`` is the device fp64 table (kept alive by the caller)."""
-    return apm_mc_model(int(n), int(L), int(n_tau), int(n_bin), float(eps), g0.data_ptr())
+    return apm_mc_model(int(n), int(L), int(n_tau), int(n_bin), float(eps), float(resolve), g0.data_ptr())
 
 
 def mc_work(model, walkers, with_net, device="cuda"):

@@ -40,6 +40,7 @@ apm_status check_model(const apm_mc_model* m, bool need_table = true)
     if (m->L < 1 || m->L > 256 || m->n_tau < 1 || m->n_tau > 32768) return APM_EINVAL;
     if (m->n_bin < 1 || m->n_bin > 64 || m->n_tau % m->n_bin != 0) return APM_EINVAL;
     if (!(m->eps >= 0.0 && m->eps <= 1.0)) return APM_EINVAL;
+    if (!(m->resolve >= 0.0) || !isfinite(m->resolve)) return APM_EINVAL;
     return APM_OK;
 }
 
@@ -113,6 +114,7 @@ apm::McArgs args_of(const apm_mc_model* m, const apm_mc_chain* ch, uint64_t seed
     a.n_tau = m->n_tau;
     a.n_bin = m->n_bin;
     a.eps = m->eps;
+    a.resolve = m->resolve;
     a.g0 = m->g0;
     a.W = ch->walkers;
     a.state = ch->state;
@@ -226,7 +228,7 @@ apm_status apm_mc_evaluate(const apm_mc_model* m, const apm_mc_chain* ch, void* 
     const hipStream_t st = (hipStream_t)stream;
     hipError_t e = apm::mc_gather_launch(a, wk.mats, st);
     if (e == hipSuccess) e = weights(a, wk, st);
-    if (e == hipSuccess) e = apm::mc_set_launch(a, wk.csum, st);
+    if (e == hipSuccess) e = apm::mc_set_launch(a, wk.csum, wk.minors, st);
     return from_hip(e);
 }
 
@@ -272,7 +274,7 @@ apm_status apm_mc_accept(const apm_mc_model* m, const apm_mc_chain* ch, uint64_t
     const hipStream_t st = (hipStream_t)stream;
     hipError_t e = weights(a, wk, st);
     if (e == hipSuccess)
-        e = apm::mc_accept_launch(a, moved, proposed, logq, wk.csum, rec ? rec->logc_prop : nullptr,
+        e = apm::mc_accept_launch(a, moved, proposed, logq, wk.csum, wk.minors, rec ? rec->logc_prop : nullptr,
                                   rec ? rec->accepted : nullptr, rec ? rec->obs_logw : nullptr,
                                   rec ? rec->obs_sign : nullptr, st);
     return from_hip(e);
@@ -310,7 +312,7 @@ apm_status apm_mc_step(const apm_mc_model* m, const apm_mc_chain* ch, const apm_
     if (e == hipSuccess) e = apm::mc_propose_launch(a, moved, net ? wk.logits : nullptr, op, prop, logq, wk.mats, st);
     if (e == hipSuccess) e = weights(a, wk, st);
     if (e == hipSuccess)
-        e = apm::mc_accept_launch(a, moved, prop, logq, wk.csum, logc, rec ? rec->accepted : nullptr,
+        e = apm::mc_accept_launch(a, moved, prop, logq, wk.csum, wk.minors, logc, rec ? rec->accepted : nullptr,
                                   rec ? rec->obs_logw : nullptr, rec ? rec->obs_sign : nullptr, st);
     if (train) {
         if (e == hipSuccess)

@@ -88,6 +88,7 @@ hipError_t mlp_adam_launch(const MlpNet& net, bool update, float lr, float b1, f
 struct McArgs {
     int n, L, n_tau, n_bin;
     double eps;
+    double resolve;
     const double* g0;
     int W;
     uint32_t* state;
@@ -102,9 +103,9 @@ hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, const float*
                              double* logq, double* mats, hipStream_t st);
 hipError_t mc_gather_launch(const McArgs& a, double* mats, hipStream_t st);
 hipError_t mc_accept_launch(const McArgs& a, const int32_t* moved, const uint32_t* prop, const double* logq,
-                            const double* c, double* logc_out, uint8_t* acc_out, float* obs_logw, int8_t* obs_sign,
-                            hipStream_t st);
-hipError_t mc_set_launch(const McArgs& a, const double* c, hipStream_t st);
+                            const double* c, const double* minors, double* logc_out, uint8_t* acc_out,
+                            float* obs_logw, int8_t* obs_sign, hipStream_t st);
+hipError_t mc_set_launch(const McArgs& a, const double* c, const double* minors, hipStream_t st);
 hipError_t mc_loss_launch(const McArgs& a, const float* logits, int Op, const uint32_t* prop, const double* logc,
                           float* gbuf, float* dout, float* loss, double clip, hipStream_t st);
 

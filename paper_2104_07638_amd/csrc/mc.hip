@@ -59,12 +59,6 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ double wave_min_d(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
-}
-
 __device__ __forceinline__ int wave_min_i(int v)
 {
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
@@ -234,47 +228,81 @@ __global__ __launch_bounds__(256) void mc_gather_kernel(McArgs a, double* __rest
     gather(a, w, -1, 0u, mats);
 }
 
-__device__ __forceinline__ double log_abs(double c) { return (isfinite(c) && c != 0.0) ? log(fabs(c)) : -INFINITY; }
+// log|c[V]| and the sign of c[V] for walker w, or (-inf, 0) when c[V] is zero, not
+// finite, or (resolve > 0) below resolve * d[V] with
+//     d[V] = |a[V]| + sum_{T containing vertex 0, T != V} |c[T]| |a[V \ T]|,  a = m^2,
+// the rounding scale of the recursion at V.  Called by a whole wavefront.
+struct Wt {
+    double lc;
+    int8_t sg;
+};
 
+__device__ Wt full_weight(const McArgs& a, int w, const double* __restrict__ c, const double* __restrict__ m)
+{
+    const int lane = lane_id();
+    const uint32_t nm = 1u << a.n, V = nm - 1u;
+    const double* cw = c + (size_t)w * nm;
+    const double* mw = m + (size_t)w * nm;
+    const double cv = cw[V];
+    bool ok = isfinite(cv) && cv != 0.0;
+    if (ok && a.resolve > 0.0) {
+        double part = 0.0;
+        for (uint32_t i = lane; i < nm / 2; i += kWave) {
+            const uint32_t T = 2u * i + 1u;                 // sets containing vertex 0
+            if (T == V) {
+                part += mw[V] * mw[V];                     // |a[V]|
+            } else {
+                const double mr = mw[V & ~T];
+                part += fabs(cw[T]) * (mr * mr);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+        ok = fabs(cv) >= a.resolve * part;
+    }
+    return ok ? Wt{log(fabs(cv)), cv > 0.0 ? (int8_t)1 : (int8_t)-1} : Wt{-INFINITY, (int8_t)0};
+}
+
+// acceptance test and state update; one wavefront per walker
 __global__ __launch_bounds__(256) void mc_accept_kernel(McArgs a, const int32_t* __restrict__ moved,
                                                         const uint32_t* __restrict__ prop,
                                                         const double* __restrict__ logq,
-                                                        const double* __restrict__ c, double* logc_out,
+                                                        const double* __restrict__ c,
+                                                        const double* __restrict__ minors, double* logc_out,
                                                         uint8_t* acc_out, float* obs_logw, int8_t* obs_sign)
 {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= a.W) return;
-    const size_t nm = (size_t)1 << a.n;
-    const double cv = c[(size_t)w * nm + nm - 1];
-    const double lc = log_abs(cv);
+    const Wt wt = full_weight(a, w, c, minors);
+    if (lane_id() != 0) return;
     double lw = a.logw[w];
     int8_t sg = a.sign[w];
     const int k = moved[w];
     const U4 d1 = draws(a, w, 1);
-    const double logR = lc - lw + logq[w];
-    const bool acc = (k >= 0 && k < a.n) && lc > -INFINITY && (!(lw > -INFINITY) || log(unif(d1.w)) < logR);
+    const double logR = wt.lc - lw + logq[w];
+    const bool acc = (k >= 0 && k < a.n) && wt.lc > -INFINITY && (!(lw > -INFINITY) || log(unif(d1.w)) < logR);
     if (acc) {
         a.state[(size_t)w * a.n + k] = prop[w];
-        lw = lc;
-        sg = cv > 0.0 ? (int8_t)1 : (int8_t)-1;
+        lw = wt.lc;
+        sg = wt.sg;
         a.logw[w] = lw;
         a.sign[w] = sg;
     }
-    if (logc_out) logc_out[w] = lc;
+    if (logc_out) logc_out[w] = wt.lc;
     if (acc_out) acc_out[w] = acc ? 1 : 0;
     if (obs_logw) obs_logw[w] = (float)lw;
     if (obs_sign) obs_sign[w] = sg;
 }
 
-__global__ __launch_bounds__(256) void mc_set_kernel(McArgs a, const double* __restrict__ c)
+__global__ __launch_bounds__(256) void mc_set_kernel(McArgs a, const double* __restrict__ c,
+                                                     const double* __restrict__ minors)
 {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= a.W) return;
-    const size_t nm = (size_t)1 << a.n;
-    const double cv = c[(size_t)w * nm + nm - 1];
-    const double lc = log_abs(cv);
-    a.logw[w] = lc;
-    a.sign[w] = lc > -INFINITY ? (cv > 0.0 ? (int8_t)1 : (int8_t)-1) : (int8_t)0;
+    const Wt wt = full_weight(a, w, c, minors);
+    if (lane_id() == 0) {
+        a.logw[w] = wt.lc;
+        a.sign[w] = wt.sg;
+    }
 }
 
 // Regression targets: y = log|c'| clipped below at (max - clip); g[r] = 2 (pred - y) / W.
@@ -364,19 +392,19 @@ hipError_t mc_gather_launch(const McArgs& a, double* mats, hipStream_t st)
 }
 
 hipError_t mc_accept_launch(const McArgs& a, const int32_t* moved, const uint32_t* prop, const double* logq,
-                            const double* c, double* logc_out, uint8_t* acc_out, float* obs_logw, int8_t* obs_sign,
-                            hipStream_t st)
+                            const double* c, const double* minors, double* logc_out, uint8_t* acc_out,
+                            float* obs_logw, int8_t* obs_sign, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_accept_kernel, dim3(blocks_for(a.W, 256)), dim3(256), 0, st, a, moved, prop, logq, c,
+    hipLaunchKernelGGL(mc_accept_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, moved, prop, logq, c, minors,
                        logc_out, acc_out, obs_logw, obs_sign);
     return hipGetLastError();
 }
 
-hipError_t mc_set_launch(const McArgs& a, const double* c, hipStream_t st)
+hipError_t mc_set_launch(const McArgs& a, const double* c, const double* minors, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_set_kernel, dim3(blocks_for(a.W, 256)), dim3(256), 0, st, a, c);
+    hipLaunchKernelGGL(mc_set_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, c, minors);
     return hipGetLastError();
 }
 

@@ -77,8 +77,8 @@ def test_cs_and_perm_validation(apm):
     assert apm.apm_all_perm_minors(P, _bd(apm, batch=0), P, None) == apm.APM_OK
 
 
-def _model(apm, n=10, L=16, n_tau=128, n_bin=16, eps=0.1, g0=16):
-    return apm.apm_mc_model(n, L, n_tau, n_bin, eps, g0)
+def _model(apm, n=10, L=16, n_tau=128, n_bin=16, eps=0.1, g0=16, resolve=0.0):
+    return apm.apm_mc_model(n, L, n_tau, n_bin, eps, resolve, g0)
 
 
 def test_mlp_sizes_and_validation(apm):
@@ -113,6 +113,8 @@ def test_mc_validation(apm):
     assert f(_model(apm, eps=1.5), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
     assert f(_model(apm, L=257), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
     assert f(_model(apm, g0=0), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    assert f(_model(apm, resolve=-1.0), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
+    assert f(_model(apm, resolve=float("nan")), ch, None, None, 1, 0, None, P, None) == apm.APM_EINVAL
     assert f(_model(apm), ch, None, None, 1, 0, None, None, None) == apm.APM_EINVAL    # no work buffer
     assert f(_model(apm), apm.apm_mc_chain(64, None, 16, 16), None, None, 1, 0, None, P, None) == apm.APM_EINVAL
     net = apm.apm_mlp(27, 272, 16, 16, 16, 16, 16, 16)

@@ -328,3 +328,19 @@ def test_loss_gradient_finite_differences():
         lm[r, f] -= 1e-6
         fd = (mc.loss_grad(m, lp, prop, y)[0] - mc.loss_grad(m, lm, prop, y)[0]) / 2e-6
         assert abs(fd - dout[r, f]) < 1e-7
+
+
+def test_resolution_cutoff_two_vertices():
+    # n = 2: d[V] = |a[V]| + |c[{0}]| |a[{1}]| = det^2 + (M00 M11)^2 and c[V] = det^2 - (M00 M11)^2
+    m = wl.McModel(n=2, L=4, n_tau=8, n_bin=2, beta=3.0, mu=0.2, resolve=0.5)
+    g0 = wl.mc_g0_table(m)
+    st = wl.mc_initial_states(256, m, seed=10)
+    M = mc.matrices(m, g0, st)
+    det2 = (M[:, 0, 0] * M[:, 1, 1] - M[:, 0, 1] * M[:, 1, 0]) ** 2
+    dd = (M[:, 0, 0] * M[:, 1, 1]) ** 2
+    keep = np.abs(det2 - dd) >= 0.5 * (det2 + dd)
+    lw, sg = mc.weight(m, g0, st)
+    assert 0 < keep.sum() < 256
+    np.testing.assert_array_equal(np.isfinite(lw), keep)
+    np.testing.assert_allclose(lw[keep], np.log(np.abs(det2 - dd))[keep], rtol=1e-12)
+    assert np.all(sg[~keep] == 0)

@@ -143,7 +143,7 @@ class _Setup:
         self.model = model
         self.g0 = wl.mc_g0_table(model)
         self.g0_d = torch.from_numpy(self.g0).cuda()
-        self.m = apm.mc_model(model.n, model.L, model.n_tau, model.n_bin, model.eps, self.g0_d)
+        self.m = apm.mc_model(model.n, model.L, model.n_tau, model.n_bin, model.eps, self.g0_d, model.resolve)
         self.states = (wl.mc_cluster_states(W, model, seed=seed) if cluster
                        else wl.mc_initial_states(W, model, seed=seed))
         self.chain = apm.McChain(self.states)
@@ -242,13 +242,21 @@ def _accept_check(s, seed, step, k, prop_u32, logq, logw, logw_tol, acc_gpu, lc_
     new[np.arange(s.W), k] = prop_u32
     M = omc.matrices(s.model, s.g0, new)
     m = omc.minors(M)
-    from oracle import connected_sums, metrics
+    from oracle import connected_sums, cs_scale, metrics
     c = connected_sums(m * m, mode=0)
     cv = c[:, -1]
     tabs = metrics.cdet_tolerance(M, m, c)[:, -1]
-    # ||c_gpu| - |c_ref|| within the propagated tolerance; exp(-inf) = 0
-    assert np.all(np.abs(np.exp(lc_gpu) - np.abs(cv)) <= tabs + 1e-300)
-    lc = omc.log_abs(cv)
+    kappa = s.model.resolve
+    dV = cs_scale(m * m, c, mode=0)[:, -1]
+    # near the resolution threshold either verdict is correct
+    thresh = (kappa > 0) & (np.abs(np.abs(cv) - kappa * dV) <= tabs * (1 + kappa) + 1e-300)
+    resolved = np.isfinite(cv) & (cv != 0) & ((kappa == 0) | (np.abs(cv) >= kappa * dV))
+    gpu_res = np.isfinite(lc_gpu)
+    assert np.all((gpu_res == resolved) | thresh)
+    ok = gpu_res & resolved
+    # ||c_gpu| - |c_ref|| within the propagated tolerance
+    assert np.all(np.abs(np.exp(lc_gpu[ok]) - np.abs(cv[ok])) <= tabs[ok] + 1e-300)
+    lc = np.where(resolved, omc.log_abs(cv), -np.inf)
     fin = np.isfinite(lc)
     tol = np.full(s.W, np.inf)
     tol[fin] = tabs[fin] / np.abs(cv[fin])
@@ -261,9 +269,35 @@ def _accept_check(s, seed, step, k, prop_u32, logq, logw, logw_tol, acc_gpu, lc_
         hi = np.log(np.abs(cv) + tabs) - logw + logq + logw_tol
         lo = np.log(np.maximum(np.abs(cv) - tabs, 0.0)) - logw + logq - logw_tol
         lu = np.log(u)
-        tie = np.isfinite(logw) & (lu < hi + 1e-9) & (lu >= lo - 1e-9)
+        tie = (np.isfinite(logw) & (lu < hi + 1e-9) & (lu >= lo - 1e-9)) | thresh
     assert np.all((acc == acc_gpu) | tie)
     return tie, acc, tol
+
+
+def test_mc_evaluate_resolve(apm):
+    """With resolve = 1e-10 the spread-out configurations (|c[V]| at the rounding level of
+    the recursion) get weight 0 and the compact ones keep theirs."""
+    model = wl.McModel(n=10, L=16, mu=0.0, beta=4.0, n_tau=128, n_bin=16, resolve=1e-10)
+    s = _Setup(apm, model, 512, seed=3)
+    mix = s.states.copy()
+    mix[256:] = wl.mc_initial_states(256, model, seed=3)
+    ch = apm.McChain(mix)
+    work = apm.mc_work(s.m, s.W, False)
+    apm.mc_evaluate(s.m, ch, work)
+    lw = ch.logw.cpu().numpy()
+    ref, sg_ref = omc.weight(model, s.g0, mix)
+    from oracle import connected_sums, cs_scale, metrics
+    M = omc.matrices(model, s.g0, mix)
+    m = omc.minors(M)
+    c = connected_sums(m * m, 0)
+    d = cs_scale(m * m, c, 0)[:, -1]
+    tabs = metrics.cdet_tolerance(M, m, c)[:, -1]
+    near = np.abs(np.abs(c[:, -1]) - 1e-10 * d) <= tabs * 2
+    agree = np.isfinite(lw) == np.isfinite(ref)
+    assert np.all(agree | near)
+    assert np.isfinite(ref[:256]).sum() >= 250 and np.isfinite(ref[256:]).sum() <= 5
+    both = np.isfinite(lw) & np.isfinite(ref)
+    assert np.all(ch.sign.cpu().numpy()[both] == sg_ref[both])
 
 
 def test_mc_evaluate(apm):
@@ -292,9 +326,11 @@ def test_mc_evaluate(apm):
     assert np.all(np.isneginf(lw[~ok])) and np.all(sg[~ok] == 0)
 
 
-def test_mc_uniform_chain(apm):
+@pytest.mark.parametrize("resolve", [0.0, 1e-10])
+def test_mc_uniform_chain(apm, resolve):
     """Twelve full steps of apm_mc_step with the uniform proposal against the oracle."""
-    s = _Setup(apm, CFG5, 1024, seed=4)
+    model = wl.McModel(n=10, L=16, t=1.0, mu=0.0, beta=4.0, n_tau=128, n_bin=16, eps=0.1, resolve=resolve)
+    s = _Setup(apm, model, 1024, seed=4)
     work = apm.mc_work(s.m, s.W, False)
     apm.mc_evaluate(s.m, s.chain, work)
     rec = apm.McRecord(s.W, loss=False)
@@ -303,9 +339,9 @@ def test_mc_uniform_chain(apm):
     M0 = omc.matrices(s.model, s.g0, states)
     m0 = omc.minors(M0)
     c0 = connected_sums(m0 * m0, 0)
-    logw = omc.log_abs(c0[:, -1])
+    logw, _ = omc.weight(s.model, s.g0, states)
     logw_tol = metrics.cdet_tolerance(M0, m0, c0)[:, -1] / np.abs(c0[:, -1])
-    live = np.ones(s.W, dtype=bool)
+    live = np.isfinite(logw) == np.isfinite(s.chain.logw.cpu().numpy())
     n_acc = 0
     for step in range(12):
         apm.mc_step(s.m, s.chain, work, seed=2024, step=step, record=rec)
@@ -322,9 +358,9 @@ def test_mc_uniform_chain(apm):
         n_acc += int(acc[live].sum())
         new = states.copy()
         new[np.arange(s.W), k] = pr
-        cnew = omc.full_connected_sum(s.model, s.g0, new)
+        lnew, _ = omc.weight(s.model, s.g0, new)
         states = np.where(acc[:, None], new, states)
-        logw = np.where(acc, omc.log_abs(cnew), logw)
+        logw = np.where(acc, lnew, logw)
         logw_tol = np.where(acc, tol, logw_tol)
         got = s.state_np()
         np.testing.assert_array_equal(got[live], states[live])
@@ -351,7 +387,7 @@ def test_mc_training_step_gradient(apm):
     np.testing.assert_array_equal(rec.proposed.cpu().numpy().view(np.uint32), pr)
     new = s.states.copy()
     new[np.arange(s.W), k] = pr
-    y = omc.log_abs(omc.full_connected_sum(model, s.g0, new))
+    y, _ = omc.weight(model, s.g0, new)
     loss, dout = omc.loss_grad(model, out, pr, y)
     assert abs(rec.loss.cpu().item() - loss) <= 1e-2 * loss
     g_ref = omlp.backward(cache, dout)

@@ -229,6 +229,8 @@ class McModel:
     at imaginary time tau_i = (j_i + 1/2) beta / n_tau on a grid of n_tau points.  A
     vertex is packed as ``s | (j << 16)``.  The learned proposal groups the n_tau time
     points into n_bin equal bins and mixes in a fraction ``eps`` of the uniform proposal.
+    ``resolve`` > 0 gives weight zero to configurations whose connected sum is below
+    resolve times the rounding scale of the recursion.
     """
     n: int = 10
     L: int = 16
@@ -238,6 +240,7 @@ class McModel:
     n_tau: int = 128
     n_bin: int = 16
     eps: float = 0.1
+    resolve: float = 0.0
 
     @property
     def lattice(self) -> Lattice:
