@@ -10,10 +10,16 @@ Printed on stdout: ONE JSON line (metric, value = matrices/s, roofline of the mi
 kernel, the CPU oracle baseline, the fp32-scaled variant and the other workloads in
 "extra").  Everything else goes to stderr.
 
+Second part of the metric ("mc"): Monte Carlo over vertex configurations weighted by
+|c[V]| (8192 walkers, n = 10, 16 x 16 lattice, mu = 0, beta = 4), effective samples per
+second of sign(c) and log|c| with the learned proposal (trained online for
+--mc-train-steps steps, then frozen) against the uniform proposal (same number of
+burn-in steps), over --mc-steps measured steps each.
+
 Flags: --steps K --warmup W (timed / untimed steps), --gpus N (only N = 1 is supported),
 --no-cpu (skip the oracle baseline leg), --no-extra (skip the secondary workloads),
---copy-calibration (run only a plain 1 GiB device copy; used to calibrate the HBM
-traffic counters).
+--no-mc, --mc-train-steps, --mc-steps, --copy-calibration (run only a plain 1 GiB device
+copy; used to calibrate the HBM traffic counters).
 """
 from __future__ import annotations
 
@@ -106,6 +112,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-mc", action="store_true")
+    ap.add_argument("--mc-train-steps", type=int, default=20000)
+    ap.add_argument("--mc-steps", type=int, default=5000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (matrices are independent; the batch would be "
@@ -186,6 +195,10 @@ def main():
     if not args.no_extra:
         extra.update(run_extra(torch, apm, W, np, args.steps))
 
+    mc = None
+    if not args.no_mc:
+        mc = run_mc(torch, apm, W, np, args.mc_train_steps, args.mc_steps)
+
     cpu = None
     accuracy = None
     if not args.no_cpu:
@@ -198,7 +211,8 @@ def main():
            "config": {"workload": "all principal minors, 8192 2D-lattice propagator matrices of order 16 "
                                   "(L=32, t=1, mu=-0.5, beta=5), 1 in 64 near-singular",
                       "n": n, "batch": B, "output": "fp64, 2^16 minors per matrix"},
-           "roofline": roofline, "cpu_baseline": cpu, "fp32s": fp32s, "accuracy": accuracy, "extra": extra}
+           "roofline": roofline, "cpu_baseline": cpu, "fp32s": fp32s, "accuracy": accuracy, "mc": mc,
+           "extra": extra}
     print(json.dumps(res), flush=True)
 
 
@@ -258,6 +272,82 @@ def run_extra(torch, apm, W, np, steps):
     for k, v in ex.items():
         log(f"{k}: {v}")
     return ex
+
+
+def tau_int(np, x, c=5.0):
+    """Integrated autocorrelation time of the (steps, walkers) series x: the walker-averaged
+    autocorrelation function summed with Sokal's automatic window (smallest M >= c tau)."""
+    x = x - x.mean(axis=0, keepdims=True)
+    N = x.shape[0]
+    f = np.fft.rfft(x, n=2 * N, axis=0)
+    acf = np.fft.irfft(f * np.conj(f), axis=0)[:N].mean(axis=1)
+    if acf[0] <= 0:
+        return float("nan")
+    rho = acf / acf[0]
+    tau = 1.0
+    for M in range(1, N):
+        tau += 2.0 * rho[M]
+        if M >= c * tau:
+            break
+    return float(tau)
+
+
+def run_mc(torch, apm, W, np, n_train, n_meas, walkers=8192, n_series=1024):
+    """ESS/s of the learned proposal against the uniform one on the same target."""
+    model = W.McModel(n=10, L=16, t=1.0, mu=0.0, beta=4.0, n_tau=128, n_bin=16, eps=0.1, resolve=1e-10)
+    g0 = torch.from_numpy(W.mc_g0_table(model)).cuda()
+    m = apm.mc_model(model.n, model.L, model.n_tau, model.n_bin, model.eps, g0, model.resolve)
+    out = {"workload": f"{walkers} walkers, n={model.n}, L={model.L}, t=1, mu=0, beta=4, {model.n_tau} time points, "
+                       f"weight |c[V]| (a = det^2, rooted recursion) resolved above 1e-10 of its rounding scale",
+           "train_steps": n_train, "measured_steps": n_meas}
+    for kind in ("uniform", "learned"):
+        learned = kind == "learned"
+        chain = apm.McChain(W.mc_cluster_states(walkers, model, seed=W.BASE_SEED))
+        net = apm.Mlp(model.d_in, model.d_out, W.mlp_init(model.d_in, model.d_out)) if learned else None
+        work = apm.mc_work(m, walkers, learned)
+        apm.mc_evaluate(m, chain, work)
+        rec = apm.McRecord(walkers)
+        t0 = time.perf_counter()
+        for i in range(n_train):
+            apm.mc_step(m, chain, work, seed=2021, step=i, net=net,
+                        train=dict(lr=1e-3, t=i + 1) if learned else None, record=rec)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        loss = rec.loss.item() if learned else None
+        hs = torch.empty((n_meas, walkers), dtype=torch.int8, device="cuda")
+        hl = torch.empty((n_meas, walkers), dtype=torch.float32, device="cuda")
+        ha = torch.empty((n_meas, walkers), dtype=torch.uint8, device="cuda")
+        recs = []
+        for i in range(n_meas):
+            r = rec._c(hl[i], hs[i])
+            r.accepted = ha[i].data_ptr()
+            recs.append(r)
+        tm = Timer(torch)
+        with tm:
+            for i in range(n_meas):
+                apm.mc_step(m, chain, work, seed=2021, step=n_train + i, net=net, record=recs[i])
+        ms = tm.avg_ms()
+        sg = hs[:, :n_series].cpu().numpy().astype(np.float64)
+        lw = hl[:, :n_series].cpu().numpy().astype(np.float64)
+        ts, tl = tau_int(np, sg), tau_int(np, lw)
+        sec = ms * 1e-3
+        out[kind] = {"ms_per_step": round(ms / n_meas, 4), "acceptance": round(float(ha.float().mean().item()), 4),
+                     "mean_sign": round(float(hs.float().mean().item()), 5),
+                     "mean_log_c": round(float(hl.mean().item()), 3),
+                     "tau_int_sign": round(ts, 2), "tau_int_log_c": round(tl, 2),
+                     "ess_per_s_sign": round(walkers * n_meas / ts / sec, 1),
+                     "ess_per_s_log_c": round(walkers * n_meas / tl / sec, 1),
+                     "burn_in_s": round(t_train, 2)}
+        if learned:
+            out[kind]["final_train_loss"] = round(loss, 3)
+        log(f"mc {kind}: {out[kind]}")
+        del hs, hl, ha, work
+    u, l = out["uniform"], out["learned"]
+    out["gain_ess_per_s_sign"] = round(l["ess_per_s_sign"] / u["ess_per_s_sign"], 3)
+    out["gain_ess_per_s_log_c"] = round(l["ess_per_s_log_c"] / u["ess_per_s_log_c"], 3)
+    out["note"] = ("equal-error comparison: the wall time to reach a given standard error of the mean scales as "
+                   "1 / (ESS/s), so the gain is the ratio of the learned to the uniform ESS/s")
+    return out
 
 
 def cpu_leg(np, A, stress_log, out, out32, ex32, apm):
