@@ -79,6 +79,7 @@ struct FR64 {
     __device__ static E shift(E p, double C) { return p + C; }
     __device__ static R recip(E p) { return rcp64(p); }
     __device__ static E rowscale(E v, R r) { return v * r; }
+    __device__ static E det2(E p, E r, E c, E d) { return fma(p, d, -c * r); }   // p d - c r
     __device__ static E zero() { return 0.0; }
     __device__ static E upd(E a, E c, E w) { return fma(-c, w, a); }
     __device__ static Bs one() { return 1.0; }
@@ -122,6 +123,8 @@ struct FR32S {
     __device__ static E shift(E p, double C) { return (float)((double)p + C); }
     __device__ static R recip(E p) { return rcp64((double)p); }
     __device__ static E rowscale(E v, R r) { return (float)((double)v * r); }
+    // p d - c r with exact fp64 products of the fp32 operands, one rounding to fp32
+    __device__ static E det2(E p, E r, E c, E d) { return (float)fma((double)p, (double)d, -((double)c * (double)r)); }
     __device__ static E zero() { return 0.0f; }
     __device__ static E upd(E a, E c, E w) { return fmaf(-c, w, a); }
     __device__ static Bs one() { return {0.5f, 1}; }
@@ -207,6 +210,11 @@ struct FC128 {
         return {p.x * d, -p.y * d};
     }
     __device__ static E rowscale(E v, R r) { return v * r; }
+    __device__ static E det2(E p, E r, E c, E d)
+    {
+        return {fma(p.x, d.x, fma(-p.y, d.y, fma(-c.x, r.x, c.y * r.y))),
+                fma(p.x, d.y, fma(p.y, d.x, fma(-c.x, r.y, -c.y * r.x)))};
+    }
     __device__ static E zero() { return {0.0, 0.0}; }
     __device__ static E upd(E a, E c, E w)
     {
@@ -263,6 +271,12 @@ struct FC64S {
     {
         double vx = v.x, vy = v.y;
         return {(float)fma(vx, r.x, -vy * r.y), (float)fma(vx, r.y, vy * r.x)};
+    }
+    __device__ static E det2(E p, E r, E c, E d)
+    {
+        const double px = p.x, py = p.y, dx = d.x, dy = d.y, cx = c.x, cy = c.y, rx = r.x, ry = r.y;
+        return {(float)fma(px, dx, fma(-py, dy, fma(-cx, rx, cy * ry))),
+                (float)fma(px, dy, fma(py, dx, fma(-cx, ry, -cy * rx)))};
     }
     __device__ static E zero() { return {0.0f, 0.0f}; }
     __device__ static E upd(E a, E c, E w)

@@ -32,7 +32,10 @@
 namespace apm {
 namespace {
 
-constexpr int kPmax = 11;
+#ifndef APM_CS_PMAX
+#define APM_CS_PMAX 11
+#endif
+constexpr int kPmax = APM_CS_PMAX;
 
 // threads per problem: one wavefront for small problems, four for large ones
 template <int M>
@@ -208,11 +211,22 @@ __device__ __forceinline__ double weight(const CsArgs& g, int64_t base, int64_t 
     return u * (g.dn ? g.dn[base + S] : u);
 }
 
+#ifndef APM_CS_LB_SMALL
+#define APM_CS_LB_SMALL 4
+#endif
+#ifndef APM_CS_LB_LARGE
+#define APM_CS_LB_LARGE 4
+#endif
+#ifndef APM_CS_GMUL
+#define APM_CS_GMUL 2
+#endif
+
 template <int M>
 struct CsPlan {
     static constexpr int P = M < kPmax ? M : kPmax;     // block bits
     static constexpr int TB = M - P;                    // block-index bits
-    static constexpr int LB = P < 5 ? P : 5;            // register tile bits
+    static constexpr int LBW = M <= 10 ? APM_CS_LB_SMALL : APM_CS_LB_LARGE;
+    static constexpr int LB = P < LBW ? P : LBW;        // register tile bits
     static constexpr int H = P - LB;                    // row bits inside a block
     static constexpr int ROWS = 1 << H;
 };
@@ -250,7 +264,7 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
     const int nout = rk_off[r + 1] - rk_off[r];
     const int items = TRI ? (1 << r) - 1 : (1 << r);
     int G = 1;
-    while (G * 2 <= kWave && nout * G * 2 <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
+    while (G * 2 <= kWave && nout * G * APM_CS_GMUL <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
     const int per_pass = NT / G;
     for (int ob = 0; ob < nout; ob += per_pass) {
         const int o = ob + tid / G;

@@ -118,6 +118,17 @@ struct PivCtl {
     bool perturb;
 };
 
+// Largest value of v[0..M) by a pairwise tree (depth log2 M instead of a chain of M).
+template <int M>
+__device__ __forceinline__ double tree_max(double (&v)[M])
+{
+#pragma unroll
+    for (int w = 1; w < M; w *= 2)
+#pragma unroll
+        for (int i = 0; i + w < M; i += 2 * w) v[i] = fmax(v[i], v[i + w]);
+    return M > 0 ? v[0] : 0.0;
+}
+
 template <class F>
 struct PivInfo {
     typename F::E pt, pu;
@@ -189,16 +200,23 @@ __device__ __forceinline__ void lane_node(const typename F::E (&M)[KP * KP], typ
     constexpr int SZ = KP - S0;
     const E p = M[S0 * KP + S0];
     put<F, AL>(cx, Q | (1 << DEP), F::bmul(bu, p, e0));
-    if constexpr (SZ > 1) {
+    if constexpr (SZ == 2) {
+        // a 2 x 2 node is finished without division: the left child's minor is bu d and
+        // the right child's is bu (p d - c r), exact whatever the pivot, so no shift
+        const E r = M[S0 * KP + S0 + 1], c = M[(S0 + 1) * KP + S0], d = M[(S0 + 1) * KP + S0 + 1];
+        put<F, AL>(cx, Q | (1 << (DEP + 1)), F::bmul(bu, d, e0));
+        // (the scaled variants store values times 2^-e0, so the product of two carries 2^-2 e0)
+        put<F, AL>(cx, Q | (1 << DEP) | (1 << (DEP + 1)), F::bmul(bu, F::det2(p, r, c, d), 2 * e0));
+    } else if constexpr (SZ > 2) {
         lane_node<F, AL, KP, S0 + 1, DEP + 1, Q>(M, bu, cx, pc, e0);
         constexpr int m = SZ - 1;
-        double rmax = 0.0, cmax = 0.0;
+        double rv[m], cv[m];
 #pragma unroll
         for (int b = 0; b < m; ++b) {
-            rmax = fmax(rmax, F::mag(M[S0 * KP + S0 + 1 + b]));
-            cmax = fmax(cmax, F::mag(M[(S0 + 1 + b) * KP + S0]));
+            rv[b] = F::mag(M[S0 * KP + S0 + 1 + b]);
+            cv[b] = F::mag(M[(S0 + 1 + b) * KP + S0]);
         }
-        const PivInfo<F> pv = analyse<F>(p, rmax, cmax, SZ, pc);
+        const PivInfo<F> pv = analyse<F>(p, tree_max<m>(rv), tree_max<m>(cv), SZ, pc);
         constexpr int id = (1 << DEP) - 1 + Q;
         if (pv.pert) {
             cx.ev |= 1u << id;
@@ -226,13 +244,14 @@ __device__ __forceinline__ void lane_node(const typename F::E (&M)[KP * KP], typ
 template <class F, int SZ>
 __device__ __forceinline__ void rc_max(const typename F::E (&M)[SZ * SZ], double& rmax, double& cmax)
 {
-    rmax = 0.0;
-    cmax = 0.0;
+    double rv[SZ - 1 > 0 ? SZ - 1 : 1], cv[SZ - 1 > 0 ? SZ - 1 : 1];
 #pragma unroll
     for (int b = 1; b < SZ; ++b) {
-        rmax = fmax(rmax, F::mag(M[b]));
-        cmax = fmax(cmax, F::mag(M[b * SZ]));
+        rv[b - 1] = F::mag(M[b]);
+        cv[b - 1] = F::mag(M[b * SZ]);
     }
+    rmax = SZ > 1 ? tree_max(rv) : 0.0;
+    cmax = SZ > 1 ? tree_max(cv) : 0.0;
 }
 
 // One in-lane mid level: node M (order SZ, registers) -> the lane's child (order SZ-1):
@@ -275,16 +294,16 @@ __device__ __forceinline__ void bf_levels(typename F::E* lds, typename F::E* pt_
             const E* Pm = (J == 0) ? lds + x0o : lds + L::lvl_base(J) + t * sz * sz;
             const int pl = (J == 0) ? x0l : sz;
             E row[m], mine[m];
-            double rmax = 0.0, cmax = 0.0;
+            double rv[m], cv[m];
 #pragma unroll
             for (int b = 0; b < m; ++b) {
                 row[b] = Pm[b + 1];
                 mine[b] = Pm[(a + 1) * pl + b + 1];
-                rmax = fmax(rmax, F::mag(row[b]));
-                cmax = fmax(cmax, F::mag(Pm[(b + 1) * pl]));
+                rv[b] = F::mag(row[b]);
+                cv[b] = F::mag(Pm[(b + 1) * pl]);
             }
             const E c = Pm[(a + 1) * pl];
-            const PivInfo<F> pv = analyse<F>(Pm[0], rmax, cmax, sz, pc);
+            const PivInfo<F> pv = analyse<F>(Pm[0], tree_max(rv), tree_max(cv), sz, pc);
             E* Lr = lds + L::lvl_base(J + 1) + t * m * m + a * m;
             E* Rr = Lr + nodes * m * m;
 #pragma unroll
@@ -315,21 +334,23 @@ __device__ __forceinline__ PivInfo<F> top_right(typename F::E* lds, int xo, int 
     using E = typename F::E;
     constexpr int m = N - D - 1;
     const E* X = lds + xo;
-    E row[m];
-    double rmax = 0.0, cmax = 0.0;
+    double rv[m], cv[m];
 #pragma unroll
     for (int b = 0; b < m; ++b) {      // every lane reads the same entries (broadcast)
-        row[b] = X[b + 1];
-        rmax = fmax(rmax, F::mag(row[b]));
-        cmax = fmax(cmax, F::mag(X[(b + 1) * xl]));
+        rv[b] = F::mag(X[b + 1]);
+        cv[b] = F::mag(X[(b + 1) * xl]);
     }
-    const PivInfo<F> pv = analyse<F>(X[0], rmax, cmax, m + 1, pc);
+    const PivInfo<F> pv = analyse<F>(X[0], tree_max(rv), tree_max(cv), m + 1, pc);
     E* S = lds + L::top_off(D + 1);
-    for (int a = lane; a < m; a += kWave) {
-        const E* xr = X + (a + 1) * xl;
-        const E c = xr[0];
-#pragma unroll
-        for (int b = 0; b < m; ++b) S[a * m + b] = F::upd(xr[b + 1], c, F::rowscale(row[b], pv.ri));
+    // lane (a0, b): column b of rows a0, a0 + g, ... (g = 64 / m row groups)
+    constexpr int g = kWave / m;
+    if (lane < g * m) {
+        const int b = lane % m, a0 = lane / m;
+        const E wb = F::rowscale(X[b + 1], pv.ri);
+        for (int a = a0; a < m; a += g) {
+            const E* xr = X + (a + 1) * xl;
+            S[a * m + b] = F::upd(xr[b + 1], xr[0], wb);
+        }
     }
     return pv;
 }
@@ -526,12 +547,13 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
             r0[b] = Pb[b + 1];
             c0[b] = Pb[(b + 1) * pbl];
         }
-        double rm = 0.0, cm = 0.0;
+        double rvm[nz(szb - 1)], cvm[nz(szb - 1)];
 #pragma unroll
         for (int b = 0; b < szb - 1; ++b) {
-            rm = fmax(rm, F::mag(r0[b]));
-            cm = fmax(cm, F::mag(c0[b]));
+            rvm[b] = F::mag(r0[b]);
+            cvm[b] = F::mag(c0[b]);
         }
+        const double rm = szb > 1 ? tree_max(rvm) : 0.0, cm = szb > 1 ? tree_max(cvm) : 0.0;
         const PivInfo<F> v0 = analyse<F>(Pb[0], rm, cm, szb, pc);
         mid_any |= ballot(lane < (1 << bf) && v0.pert) != 0;
         if (lane < (1 << bf)) midc[(1 << bf) - 1 + lane] = v0.pert ? (int8_t)v0.de : kNoEv;
