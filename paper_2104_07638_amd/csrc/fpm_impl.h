@@ -73,7 +73,11 @@ struct Lay {
     }
     // Mid levels 0..bf-1 are expanded breadth-first into compact matrices: BF level j
     // (1..bf) holds all 2^j nodes of order K-j; odd and even levels alternate buffers.
-    static constexpr int lvl(int j) { return (1 << j) * sq(P::K - j); }
+    // Rows are padded to an odd number of elements, so that lanes reading the same column
+    // of consecutive rows (of one node or of consecutive nodes) hit distinct LDS banks.
+    static constexpr int rs(int sz) { return sz | 1; }
+    static constexpr int ns(int sz) { return sz * rs(sz); }
+    static constexpr int lvl(int j) { return (1 << j) * ns(P::K - j); }
     static constexpr int bufA()
     {
         int m = 0;
@@ -100,7 +104,7 @@ struct Lay {
     static constexpr size_t oTev = al(oRec + sizeof(Bs) * (P::T + 1));     // int8 [2^T]
     static constexpr size_t oMid = al(oTev + (size_t(1) << P::T));        // int8 [64]
     static constexpr size_t bytes = al(oMid + 64);
-    // element offset of BF level j (j >= 1); node q of that level starts at q (K-j)^2
+    // element offset of BF level j (j >= 1); node q of that level starts at q ns(K-j)
     static constexpr int lvl_base(int j) { return top_off(P::T + 1) + ((j & 1) ? 0 : bufA()); }
 };
 
@@ -291,8 +295,8 @@ __device__ __forceinline__ void bf_levels(typename F::E* lds, typename F::E* pt_
         bool pert = false;
         if (lane < nodes * m) {
             const int t = lane / m, a = lane - (lane / m) * m;
-            const E* Pm = (J == 0) ? lds + x0o : lds + L::lvl_base(J) + t * sz * sz;
-            const int pl = (J == 0) ? x0l : sz;
+            const E* Pm = (J == 0) ? lds + x0o : lds + L::lvl_base(J) + t * L::ns(sz);
+            const int pl = (J == 0) ? x0l : L::rs(sz);
             E row[m], mine[m];
             double rv[m], cv[m];
 #pragma unroll
@@ -304,8 +308,8 @@ __device__ __forceinline__ void bf_levels(typename F::E* lds, typename F::E* pt_
             }
             const E c = Pm[(a + 1) * pl];
             const PivInfo<F> pv = analyse<F>(Pm[0], tree_max(rv), tree_max(cv), sz, pc);
-            E* Lr = lds + L::lvl_base(J + 1) + t * m * m + a * m;
-            E* Rr = Lr + nodes * m * m;
+            E* Lr = lds + L::lvl_base(J + 1) + t * L::ns(m) + a * L::rs(m);
+            E* Rr = Lr + nodes * L::ns(m);
 #pragma unroll
             for (int b = 0; b < m; ++b) {
                 Lr[b] = mine[b];
@@ -539,8 +543,8 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
         constexpr bool AL = (P::active == kWave);
         constexpr int szb = K - bf;               // order of the lane's level-bf node
         const int tb = lane & ((1 << bf) - 1);
-        const E* Pb = (bf == 0) ? lds + x0o : lds + L::lvl_base(bf) + tb * szb * szb;
-        const int pbl = (bf == 0) ? x0l : szb;
+        const E* Pb = (bf == 0) ? lds + x0o : lds + L::lvl_base(bf) + tb * L::ns(szb);
+        const int pbl = (bf == 0) ? x0l : L::rs(szb);
         E r0[nz(szb - 1)], c0[nz(szb - 1)];
 #pragma unroll
         for (int b = 0; b < szb - 1; ++b) {
