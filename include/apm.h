@@ -13,7 +13,11 @@
  *     (the layout of torch.complex128 / complex64 and C99 _Complex double).
  *   - Pointers inside apm_batch and every data pointer are DEVICE pointers unless
  *     stated otherwise; the caller owns all of them.  The library owns only its
- *     small internal workspaces (queue counters), allocated on first use per device.
+ *     small internal workspace (queue counters and packed offsets of mixed-order
+ *     batches), allocated on first use per device and grown when a larger mixed-order
+ *     batch arrives.  Mixed-order calls (n_uniform == 0) share that workspace: they
+ *     must not overlap in time on one device (order them on one stream).  A call that
+ *     would grow it must not be the first such call inside a graph capture.
  *   - Calls are asynchronous: arguments are validated on the host, work is
  *     enqueued on `stream`, and the call returns.  Results are valid once the
  *     stream has been synchronised.  Argument errors return before anything is

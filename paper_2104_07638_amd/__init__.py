@@ -220,15 +220,10 @@ def all_minors(A, dtype="r64", *, out=None, exp=None, info=None, out_f64=False, 
 def all_minors_ragged(A_flat, n, n_max=0, dtype="r64", *, in_off=None, out_off=None, out=None, exp=None,
                       info=None, out_f64=False, tau=0.0, perturb=True, stream=None):
     """Ragged batch: matrices of orders n[b] (device int32) packed in ``A_flat``
-    (default offsets: prefix sums of n_b^2 and 2^n_b, computed on the device)."""
+    (offsets None: packed prefix sums of n_b^2 and 2^n_b, formed by the library's own
+    queue-preparation kernel on the device)."""
     dt = DTYPES[dtype]
     B = n.numel()
-    if in_off is None:
-        sz = n.to(torch.int64) ** 2
-        in_off = torch.cumsum(sz, 0) - sz
-    if out_off is None:
-        sz = torch.ones_like(n, dtype=torch.int64) << n.to(torch.int64)
-        out_off = torch.cumsum(sz, 0) - sz
     if out is None:
         raise ValueError("ragged batches need a preallocated output")
     if info is None:

@@ -70,6 +70,22 @@ bool bad_batch(const apm_batch* bd, int nmax)
     return false;
 }
 
+// Packed default offsets of a ragged batch given without offset arrays: the queue
+// preparation kernel writes the prefix sums of n_b^2 and 2^n_b into the workspace.
+apm_status packed_offsets(const apm_batch* bd, hipStream_t st, const int64_t** ioff, const int64_t** ooff)
+{
+    apm::LaunchMinors L{};
+    L.batch = bd->batch;
+    L.n = bd->n;
+    apm_status s = get_workspace(bd->batch, &L.counter, &L.order, &L.ioff_ws, &L.ooff_ws, &L.n_workers);
+    if (s != APM_OK) return s;
+    hipError_t e = apm::fpm_prep_launch(L, st);
+    if (e != hipSuccess) return from_hip(e);
+    *ioff = L.ioff_ws;
+    *ooff = L.ooff_ws;
+    return APM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -150,6 +166,11 @@ apm_status apm_connected_sums(const double* m_up, const double* m_dn, const apm_
     L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N_CS;
     L.off = bd->out_off;
     L.mode = mode;
+    if (bd->n_uniform == 0 && !L.off) {
+        const int64_t* ioff = nullptr;
+        apm_status s = packed_offsets(bd, (hipStream_t)stream, &ioff, &L.off);
+        if (s != APM_OK) return s;
+    }
     return from_hip(apm::cs_launch(L, (hipStream_t)stream));
 }
 
@@ -168,6 +189,13 @@ apm_status apm_all_perm_minors(const double* A, const apm_batch* bd, double* per
     L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N_PERM;
     L.in_off = bd->in_off;
     L.out_off = bd->out_off;
+    if (bd->n_uniform == 0 && (!L.in_off || !L.out_off)) {
+        const int64_t *ioff = nullptr, *ooff = nullptr;
+        apm_status s = packed_offsets(bd, (hipStream_t)stream, &ioff, &ooff);
+        if (s != APM_OK) return s;
+        if (!L.in_off) L.in_off = ioff;
+        if (!L.out_off) L.out_off = ooff;
+    }
     return from_hip(apm::perm_launch(L, (hipStream_t)stream));
 }
 

@@ -119,3 +119,86 @@ def test_cdet_pipeline_ragged(apm, oracle_mod):
         d = oracle_mod.cs_scale(a, ref, 0)
         seg = got[ooff[k]:ooff[k] + (1 << M.shape[0])]
         assert np.all(np.abs(seg - ref) <= 1e-10 * d + 1e-300)
+
+
+def test_mixed_pipeline_graph_replay(apm, oracle_mod):
+    """The mixed-order pipeline (queue preparation, persistent minors launch, connected
+    sums) captured in a HIP graph and replayed several times, with eager work between the
+    replays (clearing the outputs and an unrelated ragged launch that reuses the library's
+    queue workspace): every replay reproduces the eager result bit for bit."""
+    import torch
+    mats, ns = W.lattice_ragged(600, 8, 14, W.Lattice(32, 1.0, -0.5, 5.0), seed=91)
+    nsz, flat, ooff, tot = pack(mats)
+    A = torch.from_numpy(flat).cuda()
+    n_t = torch.from_numpy(nsz).cuda()
+    m = torch.empty(tot, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(m)
+    bd = apm.make_batch(len(nsz), 0, n_t, 14, None, None)
+
+    def pipeline():
+        apm.all_minors_ragged(A, n_t, 14, "r64", out=m)
+        rc = apm.apm_connected_sums(apm._ptr(m), None, bd, apm._ptr(c), apm.APM_CS_ROOTED, apm._stream(None))
+        assert rc == 0
+
+    pipeline()
+    torch.cuda.synchronize()
+    m_ref, c_ref = m.clone(), c.clone()
+    # the eager result is right
+    got = m_ref.cpu().numpy()
+    for k in range(0, len(mats), 37):
+        M = mats[k]
+        seg = got[ooff[k]:ooff[k] + (1 << M.shape[0])]
+        assert metrics.mixed_err(seg, oracle_mod.minors(M), metrics.hadamard_bounds(M)).max() <= 1e-10
+    other_mats, other_ns = W.lattice_ragged(100, 10, 12, W.Lattice(32, 1.0, -0.5, 5.0), seed=92)
+    o_ns, o_flat, _, o_tot = pack(other_mats)
+    oA = torch.from_numpy(o_flat).cuda()
+    on_t = torch.from_numpy(o_ns).cuda()
+    om = torch.empty(o_tot, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pipeline()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pipeline()
+    for i in range(4):
+        m.zero_()
+        c.zero_()
+        apm.all_minors_ragged(oA, on_t, 12, "r64", out=om)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(m, m_ref), i
+        assert torch.equal(c, c_ref), i
+
+
+def test_ragged_default_offsets_csum_perm(apm, oracle_mod):
+    """Mixed-order batches given without offset arrays use the packed prefix sums of
+    n_b^2 and 2^n_b, for the connected sums and the permanents as for the minors."""
+    import torch
+    mats, ns = W.lattice_ragged(64, 3, 12, W.Lattice(16, 1.0, 0.0, 4.0), seed=93)
+    nsz, flat, ooff, tot = pack(mats)
+    n_t = torch.from_numpy(nsz).cuda()
+    A = torch.from_numpy(flat).cuda()
+    m = torch.empty(tot, dtype=torch.float64, device="cuda")
+    apm.all_minors_ragged(A, n_t, 12, "r64", out=m)
+    c_def = torch.empty_like(m)
+    c_exp = torch.empty_like(m)
+    st = apm._stream(None)
+    assert apm.apm_connected_sums(apm._ptr(m), None, apm.make_batch(len(nsz), 0, n_t, 12, None, None),
+                                  apm._ptr(c_def), apm.APM_CS_ROOTED, st) == 0
+    oo = torch.from_numpy(ooff).cuda()
+    assert apm.apm_connected_sums(apm._ptr(m), None, apm.make_batch(len(nsz), 0, n_t, 12, oo, oo),
+                                  apm._ptr(c_exp), apm.APM_CS_ROOTED, st) == 0
+    p_def = torch.empty_like(m)
+    assert apm.apm_all_perm_minors(apm._ptr(A), apm.make_batch(len(nsz), 0, n_t, 12, None, None),
+                                   apm._ptr(p_def), st) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(c_def, c_exp)
+    got = p_def.cpu().numpy()
+    for k in range(0, len(mats), 5):
+        M = mats[k]
+        seg = got[ooff[k]:ooff[k] + (1 << M.shape[0])]
+        ref = oracle_mod.perm_minors(M)
+        assert np.allclose(seg, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
