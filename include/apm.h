@@ -145,6 +145,26 @@ apm_status apm_connected_sums(const double *m_up, const double *m_dn, const apm_
  */
 apm_status apm_all_perm_minors(const double *A, const apm_batch *bd, double *perm, apm_stream stream);
 
+/*
+ * apm_autotune_minors -- pick the per-order layout of apm_all_minors by measurement.
+ *
+ * The layout parameter is the order K0 of the per-lane register subtrees (the mid
+ * levels are expanded breadth-first down to nodes of order K0, one per lane).  Every
+ * instantiated K0 for (dt, n) is timed on a synthetic batch of `batch` diagonally
+ * dominant matrices on `stream`; the fastest is installed for all later uniform-order
+ * calls with that dtype and order in this process (an APM_K0 environment value still
+ * takes precedence).  Allocates and frees device memory and synchronises `stream`: call
+ * it outside timed regions and graph captures.
+ *   k0      if not NULL, receives the chosen value (host pointer).
+ * Returns APM_OK, APM_EINVAL (bad dt, n outside [1, APM_MAX_N], batch < 1),
+ * APM_ENOMEM or APM_EDEVICE.
+ */
+apm_status apm_autotune_minors(apm_dtype dt, int32_t n, int32_t batch, int32_t *k0, apm_stream stream);
+
+/* The lane-subtree order apm_all_minors uses for (dt, n) now (APM_K0, tuned or default);
+ * -1 for bad arguments.  Host-only. */
+int32_t apm_minors_k0(apm_dtype dt, int32_t n);
+
 /* Human-readable name of a status code (static string). */
 const char *apm_status_str(apm_status s);
 

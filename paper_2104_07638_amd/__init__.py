@@ -39,7 +39,8 @@ EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_s
            "apm_last_hip_error", "apm_version",
            "apm_mlp_param_count", "apm_mlp_weight_count", "apm_mlp_work_bytes", "apm_mlp_sync",
            "apm_mlp_forward", "apm_mlp_backward", "apm_mlp_adam", "apm_mc_work_bytes", "apm_mc_evaluate",
-           "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept")
+           "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
+           "apm_minors_k0")
 
 APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
@@ -104,6 +105,10 @@ def _load():
     lib.apm_last_hip_error.restype = ctypes.c_int
     lib.apm_version.restype = ctypes.c_int
     i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    lib.apm_autotune_minors.argtypes = [ctypes.c_int, i32, i32, ctypes.POINTER(i32), vp]
+    lib.apm_autotune_minors.restype = ctypes.c_int
+    lib.apm_minors_k0.argtypes = [ctypes.c_int, i32]
+    lib.apm_minors_k0.restype = i32
     P = ctypes.POINTER
     for name in ("apm_mlp_param_count", "apm_mlp_weight_count"):
         getattr(lib, name).argtypes = [i32, i32]
@@ -124,7 +129,8 @@ def _load():
     lib.apm_mc_accept.argtypes = [P(apm_mc_model), P(apm_mc_chain), u64, i32, vp, vp, vp, vp, P(apm_mc_record),
                                   vp, vp]
     for name in ("apm_mlp_sync", "apm_mlp_forward", "apm_mlp_backward", "apm_mlp_adam", "apm_mc_evaluate",
-                 "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept"):
+                 "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
+           "apm_minors_k0"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -157,6 +163,22 @@ def apm_last_hip_error():
 
 def apm_version():
     return _lib.apm_version()
+
+
+def apm_autotune_minors(dt, n, batch, k0, stream):
+    return _lib.apm_autotune_minors(int(dt), int(n), int(batch), k0, stream)
+
+
+def apm_minors_k0(dt, n):
+    return _lib.apm_minors_k0(int(dt), int(n))
+
+
+def autotune_minors(dtype, n, batch=4096, stream=None):
+    """Time every instantiated lane-subtree order for (dtype, n) and install the fastest;
+    returns it."""
+    k = ctypes.c_int32(0)
+    _check(apm_autotune_minors(DTYPES[dtype], n, batch, ctypes.byref(k), _stream(stream)), "apm_autotune_minors")
+    return k.value
 
 
 # ----------------------------------------------------------------- torch wrappers

@@ -1,5 +1,6 @@
 // api.hip -- the C ABI of libapm.so: argument validation, workspaces, launches.
 #include <math.h>
+#include <stdlib.h>
 #include <mutex>
 #include <vector>
 
@@ -143,6 +144,83 @@ apm_status apm_all_minors(apm_dtype dt, const void* A, const apm_batch* bd, void
         if (s != APM_OK) return s;
     }
     return from_hip(apm::fpm_launch(L, (hipStream_t)stream));
+}
+
+int32_t apm_minors_k0(apm_dtype dt, int32_t n)
+{
+    if ((int)dt < 0 || (int)dt > 3 || n < 1 || n > APM_MAX_N) return -1;
+    const char* e = getenv("APM_K0");
+    int k = e ? atoi(e) : 0;
+    if (k <= 0) k = apm::tuned_k0((int)dt, n);
+    if (k <= 0) {
+        static const int def[4] = {5, 5, 3, 4};   // the per-type defaults of the kernels
+        k = def[(int)dt];
+    }
+    int lo, hi;
+    apm::k0_range((int)dt, &lo, &hi);
+    return k < lo ? lo : (k > hi ? hi : k);
+}
+
+apm_status apm_autotune_minors(apm_dtype dt, int32_t n, int32_t batch, int32_t* k0_out, apm_stream stream)
+{
+    if ((int)dt < 0 || (int)dt > 3 || n < 1 || n > APM_MAX_N || batch < 1) return APM_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    const bool cplx = (dt == APM_C128 || dt == APM_C64S), scaled = (dt == APM_R32S || dt == APM_C64S);
+    const size_t in_b = (size_t)batch * n * n * (cplx ? 16 : 8);
+    const size_t out_b = ((size_t)batch << n) * (scaled ? (cplx ? 8 : 4) : (cplx ? 16 : 8));
+    const size_t ex_b = scaled ? ((size_t)batch << n) * 2 : 0;
+    void *A = nullptr, *out = nullptr, *ex = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int lo, hi;
+    apm::k0_range((int)dt, &lo, &hi);
+    int best = apm_minors_k0(dt, n);
+    hipError_t e = hipMalloc(&A, in_b);
+    if (e == hipSuccess) e = hipMalloc(&out, out_b);
+    if (e == hipSuccess && ex_b) e = hipMalloc(&ex, ex_b);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = apm::fill_tune_input(A, (int)dt, n, batch, st);
+    if (e == hipSuccess && n > 6) {
+        float best_ms = 3.4e38f;
+        int prev_eff = -1;
+        for (int k = lo; k <= hi && e == hipSuccess; ++k) {
+            const int eff = (n - 6) < k ? (n - 6) : k;     // the order actually used
+            if (eff == prev_eff) continue;
+            prev_eff = eff;
+            apm::LaunchMinors L{};
+            L.dtype = (int)dt;
+            L.A = A;
+            L.out = out;
+            L.ex = static_cast<int16_t*>(ex);
+            L.batch = batch;
+            L.n_uniform = n;
+            L.n_max = n;
+            L.tau = scaled ? 1e-3 : 1e-4;
+            L.perturb = true;
+            L.force_k0 = k;
+            e = apm::fpm_launch(L, st);                       // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = apm::fpm_launch(L, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = k;
+            }
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (ex) (void)hipFree(ex);
+    if (out) (void)hipFree(out);
+    if (A) (void)hipFree(A);
+    if (e != hipSuccess) return from_hip(e);
+    apm::set_tuned_k0((int)dt, n, best);
+    if (k0_out) *k0_out = best;
+    return APM_OK;
 }
 
 apm_status apm_connected_sums(const double* m_up, const double* m_dn, const apm_batch* bd, double* c,

@@ -65,6 +65,7 @@ struct SBc { cf m; int e; };
 
 // ------------------------------------------------------------------------------- R64
 struct FR64 {
+    static constexpr int kId = 0;   // apm_dtype
     using In = double;
     using E = double;
     using R = double;
@@ -109,6 +110,7 @@ struct FR64 {
 // ------------------------------------------------------------------------------- R32S
 // fp32 Schur updates, fp64 pivot reciprocal/test/shift, float mantissa + int exponent product.
 struct FR32S {
+    static constexpr int kId = 1;   // apm_dtype
     using In = double;
     using E = float;
     using R = double;
@@ -192,6 +194,7 @@ struct FR32S {
 
 // ------------------------------------------------------------------------------- C128
 struct FC128 {
+    static constexpr int kId = 2;   // apm_dtype
     using In = cd;
     using E = cd;
     using R = cd;
@@ -249,6 +252,7 @@ struct FC128 {
 // ------------------------------------------------------------------------------- C64S
 // complex64 Schur updates; fp64 pivot reciprocal/test/shift; complex mantissa + exponent.
 struct FC64S {
+    static constexpr int kId = 3;   // apm_dtype
     using In = cd;
     using E = cf;
     using R = cd;

@@ -24,9 +24,17 @@ struct LaunchMinors {
     int64_t* ioff_ws;          // ragged: workspace [batch] packed input offsets (if in_off == NULL)
     int64_t* ooff_ws;          // ragged: workspace [batch] packed output offsets (if out_off == NULL)
     int n_workers;             // ragged: number of compute units (persistent grid sizing)
+    int force_k0;              // > 0: lane-subtree order to use (autotuning); 0: the table
 };
 
 hipError_t fpm_launch(const LaunchMinors& L, hipStream_t st);
+
+// Lane-subtree order per (dtype, order): tuned values installed by the autotuner
+// (0 = none), the instantiated range of a dtype, and the synthetic tuning input.
+int tuned_k0(int dtype, int n);
+void set_tuned_k0(int dtype, int n, int k0);
+void k0_range(int dtype, int* lo, int* hi);
+hipError_t fill_tune_input(void* A, int dtype, int n, int batch, hipStream_t st);
 hipError_t fpm_prep_launch(const LaunchMinors& L, hipStream_t st);   // ragged-batch queue preparation
 
 struct LaunchCS {

@@ -1,7 +1,60 @@
-// fpm.hip -- dispatch of apm_all_minors to the per-type kernel instantiations.
+// fpm.hip -- dispatch of apm_all_minors to the per-type kernel instantiations, the queue
+// preparation of mixed-order batches, and the table of autotuned lane-subtree orders.
+#include <atomic>
+
 #include "apm_kernels.h"
 
 namespace apm {
+
+namespace {
+std::atomic<int> g_tuned[4][21];   // zero-initialised: nothing tuned
+}
+
+int tuned_k0(int dtype, int n)
+{
+    if (dtype < 0 || dtype > 3 || n < 0 || n > 20) return 0;
+    return g_tuned[dtype][n].load(std::memory_order_relaxed);
+}
+
+void set_tuned_k0(int dtype, int n, int k0)
+{
+    if (dtype < 0 || dtype > 3 || n < 0 || n > 20) return;
+    g_tuned[dtype][n].store(k0, std::memory_order_relaxed);
+}
+
+// the instantiated lane-subtree orders of each type (the K0Set of the kernels)
+void k0_range(int dtype, int* lo, int* hi)
+{
+    static const int r[4][2] = {{3, 5}, {3, 5}, {2, 3}, {3, 4}};
+    *lo = r[dtype & 3][0];
+    *hi = r[dtype & 3][1];
+}
+
+// Synthetic tuning input: diagonally dominant matrices with entries from a hash of
+// (matrix, row, column) in [-0.5, 0.5) plus n on the diagonal (no pivot shifts).
+__global__ __launch_bounds__(256) void fill_tune_kernel(double* A, int comps, int n, int64_t total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 29;
+    double v = (double)(h >> 11) * 0x1p-53 - 0.5;
+    const int64_t e = i / comps;               // element index within the batch
+    const int64_t ij = e % ((int64_t)n * n);
+    if (ij / n == ij % n && (i % comps) == 0) v += n;
+    A[i] = v;
+}
+
+hipError_t fill_tune_input(void* A, int dtype, int n, int batch, hipStream_t st)
+{
+    const int comps = (dtype == 2 || dtype == 3) ? 2 : 1;
+    const int64_t total = (int64_t)batch * n * n * comps;
+    hipLaunchKernelGGL(fill_tune_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       static_cast<double*>(A), comps, n, total);
+    return hipGetLastError();
+}
 
 // Queue preparation (one workgroup): bucket the matrices by order, largest first, so the
 // persistent waves start with the longest work; packed default offsets; queue head = 0.

@@ -701,8 +701,9 @@ __global__ __launch_bounds__(64) APM_FPM_OCC void fpm_uniform_kernel(const typen
 // ------------------------------------------------------------------------- host side
 namespace apm {
 
-// Lane-subtree order K0 per field and matrix order: the default table, measured on MI355X;
-// APM_K0=<k> overrides it (tuning runs).  Values outside the instantiated set fall back.
+// Lane-subtree order K0 per field and matrix order: an explicit request (autotuning), then
+// APM_K0=<k>, then the value the autotuner installed for this (dtype, order), then the
+// default table measured on MI355X.  Values outside the instantiated set fall back.
 template <class F>
 struct K0Set;
 template <> struct K0Set<FR64> { static constexpr int lo = 3, hi = 5; };
@@ -753,8 +754,11 @@ hipError_t dispatch_n(const LaunchMinors& L, hipStream_t st)
         return hipErrorInvalidValue;
     } else {
         if (L.n_uniform == N) {
-            const int e = env_k0();
-            return dispatch_k0<F, N, K0Set<F>::lo>(e > 0 ? e : default_k0<F>(N), L, st);
+            int k = L.force_k0;
+            if (k <= 0) k = env_k0();
+            if (k <= 0) k = tuned_k0(F::kId, N);
+            if (k <= 0) k = default_k0<F>(N);
+            return dispatch_k0<F, N, K0Set<F>::lo>(k, L, st);
         }
         return dispatch_n<F, N + 1>(L, st);
     }

@@ -20,7 +20,7 @@ def _declared():
     for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
         if h.endswith(".h"):
             src = open(os.path.join(ROOT, "include", h)).read()
-            names |= set(re.findall(r"^\s*(?:apm_status|const char|int|int64_t)\s*\*?\s*(apm_\w+)\s*\(", src,
+            names |= set(re.findall(r"^\s*(?:apm_status|const char|int|int32_t|int64_t)\s*\*?\s*(apm_\w+)\s*\(", src,
                                     re.M))
     return sorted(names)
 
@@ -128,3 +128,12 @@ def test_mc_validation(apm):
     assert apm.apm_mc_context(_model(apm), ch, 1, 0, None, None, None) == apm.APM_EINVAL
     assert apm.apm_mc_accept(_model(apm), ch, 1, 0, P, P, P, P, None, None, None) == apm.APM_EINVAL
     assert apm.apm_mc_evaluate(_model(apm), ch, None, None) == apm.APM_EINVAL
+
+
+def test_autotune_validation(apm):
+    assert apm.apm_autotune_minors(0, 0, 16, None, None) == apm.APM_EINVAL
+    assert apm.apm_autotune_minors(0, 21, 16, None, None) == apm.APM_EINVAL
+    assert apm.apm_autotune_minors(4, 10, 16, None, None) == apm.APM_EINVAL
+    assert apm.apm_autotune_minors(0, 10, 0, None, None) == apm.APM_EINVAL
+    assert apm.apm_minors_k0(0, 16) in (3, 4, 5) and apm.apm_minors_k0(2, 14) in (2, 3)
+    assert apm.apm_minors_k0(0, 0) == -1 and apm.apm_minors_k0(5, 8) == -1

@@ -211,3 +211,24 @@ def test_complex_zero_diagonal(apm, oracle_mod):
     assert np.all(info == spine_shifts(n))
     ref = oracle_mod.minors_complex(A)
     assert metrics.max_mixed_err(out, ref, A) <= TOL64
+
+
+@pytest.mark.parametrize("dtype,n", [("r64", 12), ("c128", 11), ("r32s", 9)])
+def test_autotuned_layout(apm, oracle_mod, dtype, n):
+    """apm_autotune_minors installs one of the instantiated lane-subtree orders for
+    (dtype, n); results stay correct with it."""
+    k = apm.autotune_minors(dtype, n, batch=512)
+    dt = apm.DTYPES[dtype]
+    assert apm.apm_minors_k0(dt, n) == k
+    lo, hi = {"r64": (3, 5), "r32s": (3, 5), "c128": (2, 3)}[dtype]
+    assert lo <= k <= hi
+    if dtype == "c128":
+        A = W.keldysh_batch(64, n, seed=n)
+        out, info = run(apm, A, "c128")
+        ref = oracle_mod.minors_complex(A)
+        assert metrics.max_mixed_err(out, ref, A) <= TOL64
+    else:
+        A = W.lattice_batch(64, n, W.Lattice(32, 1.0, -0.5, 5.0), seed=n)
+        out, info = run(apm, A, dtype)
+        ref = oracle_mod.minors(A)
+        assert metrics.max_mixed_err(out, ref, A) <= (TOL64 if dtype == "r64" else 1e-4)
