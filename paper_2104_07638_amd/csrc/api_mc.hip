@@ -68,6 +68,7 @@ struct McWork {
     uint32_t* prop;
     double* logq;
     double* logc;
+    double* summ;      // (c[V], d[V]) per walker, orders <= 12
     uint16_t* feat;
     float* logits;
     float* dout;
@@ -95,6 +96,7 @@ int64_t mc_layout(const apm_mc_model* m, int64_t W, bool with_net, char* base, M
     w.prop = reinterpret_cast<uint32_t*>(take(W * 4));
     w.logq = reinterpret_cast<double*>(take(W * 8));
     w.logc = reinterpret_cast<double*>(take(W * 8));
+    w.summ = reinterpret_cast<double*>(take(W * 16));
     if (with_net) {
         w.feat = reinterpret_cast<uint16_t*>(take(W * dp * 2));
         w.logits = reinterpret_cast<float*>(take(W * op * 4));
@@ -125,6 +127,8 @@ apm::McArgs args_of(const apm_mc_model* m, const apm_mc_chain* ch, uint64_t seed
     return a;
 }
 
+double* summ_of(const apm::McArgs& a, const McWork& wk) { return a.n <= 12 ? wk.summ : nullptr; }
+
 // c[V] of the configurations whose matrices are in wk.mats: minors, then the rooted recursion.
 hipError_t weights(const apm::McArgs& a, const McWork& wk, hipStream_t st)
 {
@@ -147,6 +151,9 @@ hipError_t weights(const apm::McArgs& a, const McWork& wk, hipStream_t st)
     C.n_uniform = a.n;
     C.n_max = a.n;
     C.mode = APM_CS_ROOTED;
+    // up to 12 vertices the rooted recursion fits one LDS block: the kernel then writes only
+    // c[V] and its rounding scale d[V] per walker instead of the whole c[] array
+    C.summ = summ_of(a, wk);
     return apm::cs_launch(C, st);
 }
 
@@ -228,7 +235,7 @@ apm_status apm_mc_evaluate(const apm_mc_model* m, const apm_mc_chain* ch, void* 
     const hipStream_t st = (hipStream_t)stream;
     hipError_t e = apm::mc_gather_launch(a, wk.mats, st);
     if (e == hipSuccess) e = weights(a, wk, st);
-    if (e == hipSuccess) e = apm::mc_set_launch(a, wk.csum, wk.minors, st);
+    if (e == hipSuccess) e = apm::mc_set_launch(a, wk.csum, wk.minors, summ_of(a, wk), st);
     return from_hip(e);
 }
 
@@ -274,7 +281,8 @@ apm_status apm_mc_accept(const apm_mc_model* m, const apm_mc_chain* ch, uint64_t
     const hipStream_t st = (hipStream_t)stream;
     hipError_t e = weights(a, wk, st);
     if (e == hipSuccess)
-        e = apm::mc_accept_launch(a, moved, proposed, logq, wk.csum, wk.minors, rec ? rec->logc_prop : nullptr,
+        e = apm::mc_accept_launch(a, moved, proposed, logq, wk.csum, wk.minors, summ_of(a, wk),
+                                  rec ? rec->logc_prop : nullptr,
                                   rec ? rec->accepted : nullptr, rec ? rec->obs_logw : nullptr,
                                   rec ? rec->obs_sign : nullptr, st);
     return from_hip(e);
@@ -312,7 +320,8 @@ apm_status apm_mc_step(const apm_mc_model* m, const apm_mc_chain* ch, const apm_
     if (e == hipSuccess) e = apm::mc_propose_launch(a, moved, net ? wk.logits : nullptr, op, prop, logq, wk.mats, st);
     if (e == hipSuccess) e = weights(a, wk, st);
     if (e == hipSuccess)
-        e = apm::mc_accept_launch(a, moved, prop, logq, wk.csum, wk.minors, logc, rec ? rec->accepted : nullptr,
+        e = apm::mc_accept_launch(a, moved, prop, logq, wk.csum, wk.minors, summ_of(a, wk), logc,
+                                  rec ? rec->accepted : nullptr,
                                   rec ? rec->obs_logw : nullptr, rec ? rec->obs_sign : nullptr, st);
     if (train) {
         if (e == hipSuccess)

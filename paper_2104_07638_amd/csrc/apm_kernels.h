@@ -47,6 +47,7 @@ struct LaunchCS {
     int32_t n_max;
     const int64_t* off;        // element offsets (shared by inputs and output), may be NULL
     uint32_t mode;
+    double* summ;              // rooted, orders <= 12 only: (c[V], d[V]) per matrix instead of c[]
 };
 
 hipError_t cs_launch(const LaunchCS& L, hipStream_t st);
@@ -110,10 +111,13 @@ hipError_t mc_context_launch(const McArgs& a, int32_t* moved, uint16_t* feat, in
 hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, const float* logits, int stride, uint32_t* prop,
                              double* logq, double* mats, hipStream_t st);
 hipError_t mc_gather_launch(const McArgs& a, double* mats, hipStream_t st);
+// summ (if not NULL): per-walker (c[V], d[V]) written by the connected-sum kernel; else
+// c[V] and d[V] are formed from the full c[] and minors arrays.
 hipError_t mc_accept_launch(const McArgs& a, const int32_t* moved, const uint32_t* prop, const double* logq,
-                            const double* c, const double* minors, double* logc_out, uint8_t* acc_out,
-                            float* obs_logw, int8_t* obs_sign, hipStream_t st);
-hipError_t mc_set_launch(const McArgs& a, const double* c, const double* minors, hipStream_t st);
+                            const double* c, const double* minors, const double* summ, double* logc_out,
+                            uint8_t* acc_out, float* obs_logw, int8_t* obs_sign, hipStream_t st);
+hipError_t mc_set_launch(const McArgs& a, const double* c, const double* minors, const double* summ,
+                         hipStream_t st);
 hipError_t mc_loss_launch(const McArgs& a, const float* logits, int Op, const uint32_t* prop, const double* logc,
                           float* gbuf, float* dout, float* loss, double clip, hipStream_t st);
 

@@ -38,8 +38,11 @@ namespace {
 constexpr int kPmax = APM_CS_PMAX;
 
 // threads per problem: one wavefront for small problems, four for large ones
+#ifndef APM_CS_NT_LARGE
+#define APM_CS_NT_LARGE 256
+#endif
 template <int M>
-constexpr int cs_threads() { return M <= 10 ? 64 : 256; }
+constexpr int cs_threads() { return M <= 10 ? 64 : APM_CS_NT_LARGE; }
 
 __device__ __forceinline__ uint32_t pdep_u32(uint32_t k, uint32_t mask)
 {
@@ -201,6 +204,7 @@ struct CsArgs {
     const double* dn;
     double* c;
     int weights;       // m_up already holds a[]
+    double* summ;      // rooted problems of at most one block: (c[V], d[V]) per matrix instead of c[]
 };
 
 // a[S] from the inputs
@@ -354,6 +358,28 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
             rank_pass<M, true>(r, rk_tab, rk_off, lds_c, lds_b, lds_r, lds_c);
             __syncthreads();
         }
+        if constexpr (CP::TB == 0) {
+            if (g.summ) {
+                // only the full-set value and the recursion's rounding scale at it:
+                // d[V] = |a[V]| + sum_{X full-exclusive} |c'[X]| |b[full \ X]|, with a[V] = a0[full]
+                constexpr int full = (1 << P) - 1;
+                double part = 0.0;
+                for (int x1 = tid; x1 < full; x1 += NT) part += fabs(lds_c[sw<LB>(x1)]) * fabs(lds_b[sw<LB>(full ^ x1)]);
+                for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+                if constexpr (NT > kWave) {
+                    __syncthreads();
+                    if ((tid & (kWave - 1)) == 0) lds_b[tid / kWave] = part;   // b block no longer needed
+                    __syncthreads();
+                    part = 0.0;
+                    for (int w = 0; w < NT / kWave; ++w) part += lds_b[w];
+                }
+                if (tid == 0) {
+                    g.summ[0] = lds_c[sw<LB>(full)];
+                    g.summ[1] = fabs(lds_r[sw<LB>(full)]) + part;
+                }
+                return;
+            }
+        }
         if (zero_even && !(base & 1)) {
             // rooted problem: write (c[2x] = 0, c[2x+1] = c'[x]) as one 16-byte store
             for (int x1 = tid; x1 < (1 << P); x1 += NT) {
@@ -388,7 +414,9 @@ __global__ __launch_bounds__(cs_threads<M>()) void cs_kernel(CsArgs g, int32_t b
     if (n - 1 - j != M) return;   // launched for problems with exactly M bits
     const int64_t base = off ? off[b] : ((int64_t)b << n);
     // the rooted problem also writes c[S] = 0 for the sets without vertex 0
-    cs_problem<M>(g, base, j, roots == 1, lds_c, lds_b, lds_r, rk_tab, rk_off);
+    CsArgs gb = g;
+    if (gb.summ) gb.summ += 2 * (int64_t)b;
+    cs_problem<M>(gb, base, j, roots == 1, lds_c, lds_b, lds_r, rk_tab, rk_off);
 }
 
 template <int M>
@@ -417,7 +445,7 @@ hipError_t launch_all_m(int mlo, int mhi, const LaunchCS& L, CsArgs g, int roots
 
 hipError_t cs_launch(const LaunchCS& L, hipStream_t st)
 {
-    CsArgs g{L.m_up, L.m_dn, L.c, (L.mode & 2u) ? 1 : 0};
+    CsArgs g{L.m_up, L.m_dn, L.c, (L.mode & 2u) ? 1 : 0, L.summ};
     const bool all = (L.mode & 1u) != 0;
     const int nmax = L.n_uniform > 0 ? L.n_uniform : L.n_max;
     const int nmin = L.n_uniform > 0 ? L.n_uniform : 1;

@@ -237,9 +237,15 @@ struct Wt {
     int8_t sg;
 };
 
-__device__ Wt full_weight(const McArgs& a, int w, const double* __restrict__ c, const double* __restrict__ m)
+__device__ Wt full_weight(const McArgs& a, int w, const double* __restrict__ c, const double* __restrict__ m,
+                         const double* __restrict__ summ)
 {
     const int lane = lane_id();
+    if (summ) {
+        const double cv = summ[2 * w], dv = summ[2 * w + 1];
+        const bool ok = isfinite(cv) && cv != 0.0 && !(a.resolve > 0.0 && !(fabs(cv) >= a.resolve * dv));
+        return ok ? Wt{log(fabs(cv)), cv > 0.0 ? (int8_t)1 : (int8_t)-1} : Wt{-INFINITY, (int8_t)0};
+    }
     const uint32_t nm = 1u << a.n, V = nm - 1u;
     const double* cw = c + (size_t)w * nm;
     const double* mw = m + (size_t)w * nm;
@@ -267,12 +273,13 @@ __global__ __launch_bounds__(256) void mc_accept_kernel(McArgs a, const int32_t*
                                                         const uint32_t* __restrict__ prop,
                                                         const double* __restrict__ logq,
                                                         const double* __restrict__ c,
-                                                        const double* __restrict__ minors, double* logc_out,
+                                                        const double* __restrict__ minors,
+                                                        const double* __restrict__ summ, double* logc_out,
                                                         uint8_t* acc_out, float* obs_logw, int8_t* obs_sign)
 {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= a.W) return;
-    const Wt wt = full_weight(a, w, c, minors);
+    const Wt wt = full_weight(a, w, c, minors, summ);
     if (lane_id() != 0) return;
     double lw = a.logw[w];
     int8_t sg = a.sign[w];
@@ -294,11 +301,12 @@ __global__ __launch_bounds__(256) void mc_accept_kernel(McArgs a, const int32_t*
 }
 
 __global__ __launch_bounds__(256) void mc_set_kernel(McArgs a, const double* __restrict__ c,
-                                                     const double* __restrict__ minors)
+                                                     const double* __restrict__ minors,
+                                                     const double* __restrict__ summ)
 {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= a.W) return;
-    const Wt wt = full_weight(a, w, c, minors);
+    const Wt wt = full_weight(a, w, c, minors, summ);
     if (lane_id() == 0) {
         a.logw[w] = wt.lc;
         a.sign[w] = wt.sg;
@@ -392,19 +400,19 @@ hipError_t mc_gather_launch(const McArgs& a, double* mats, hipStream_t st)
 }
 
 hipError_t mc_accept_launch(const McArgs& a, const int32_t* moved, const uint32_t* prop, const double* logq,
-                            const double* c, const double* minors, double* logc_out, uint8_t* acc_out,
-                            float* obs_logw, int8_t* obs_sign, hipStream_t st)
+                            const double* c, const double* minors, const double* summ, double* logc_out,
+                            uint8_t* acc_out, float* obs_logw, int8_t* obs_sign, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
     hipLaunchKernelGGL(mc_accept_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, moved, prop, logq, c, minors,
-                       logc_out, acc_out, obs_logw, obs_sign);
+                       summ, logc_out, acc_out, obs_logw, obs_sign);
     return hipGetLastError();
 }
 
-hipError_t mc_set_launch(const McArgs& a, const double* c, const double* minors, hipStream_t st)
+hipError_t mc_set_launch(const McArgs& a, const double* c, const double* minors, const double* summ, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_set_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, c, minors);
+    hipLaunchKernelGGL(mc_set_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, c, minors, summ);
     return hipGetLastError();
 }
 
