@@ -69,6 +69,9 @@ def load_library(path: str):
     lib.apm_oracle_minors_r64_masks.argtypes = [ctypes.c_int, dp, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_uint32), dp]
     lib.apm_oracle_minors_r64_masks.restype = ctypes.c_int
+    lib.apm_oracle_perm_minors_masks.argtypes = [ctypes.c_int, dp, ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_uint32), dp]
+    lib.apm_oracle_perm_minors_masks.restype = ctypes.c_int
     lib.apm_oracle_cs_scale.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int]
     lib.apm_oracle_cs_scale.restype = ctypes.c_int
     return lib
@@ -252,6 +255,20 @@ def perm_minors(A, nthreads: int = 0, lib=None) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle: bad matrix order")
     return out[0] if single else out
+
+
+def perm_minors_at(A, masks, lib=None) -> np.ndarray:
+    """per(A[S_m]) for the listed masks only (same definition as ``perm_minors``)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    masks = np.ascontiguousarray(masks, dtype=np.uint32)
+    out = np.empty(masks.shape[0], dtype=np.float64)
+    rc = _load(lib).apm_oracle_perm_minors_masks(n, _dp(A), int(masks.shape[0]),
+                                                 masks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                                 _dp(out))
+    if rc != 0:
+        raise ValueError("oracle: bad matrix order or mask")
+    return out
 
 
 def cdet_weights(m_up, m_dn=None) -> np.ndarray:

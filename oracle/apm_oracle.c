@@ -273,31 +273,45 @@ int apm_oracle_cs_input_bound(int n, const double *a, const double *c, const dou
  * Reading: the printed Eq. (ryser) lacks the overall (-1)^n; with it the
  * formula gives per = 1 for the 1x1 matrix [1] and k! for the all-ones k x k
  * matrix, as it must.  out[0] = 1 (empty product, T = S = empty). */
+static double ryser_subset(int n, const double *A, uint32_t S)
+{
+    double total = 0.0;
+    uint32_t T = S;
+    for (;;) {
+        double prod = 1.0;
+        for (int i = 0; i < n; ++i) {
+            if (!(S >> i & 1u)) continue;
+            double rs = 0.0;
+            for (int j = 0; j < n; ++j) if (T >> j & 1u) rs += A[i * n + j];
+            prod *= rs;
+        }
+#if ORACLE_PLANT == 5
+        int sgn = (popcount32(T) & 1) ? -1 : 1;
+#else
+        int sgn = ((popcount32(S) - popcount32(T)) & 1) ? -1 : 1;
+#endif
+        total += sgn * prod;
+        if (T == 0) break;
+        T = (T - 1) & S;
+    }
+    return total;
+}
+
 int apm_oracle_perm_minors(int n, const double *A, double *out)
 {
     if (n < 0 || n > ORACLE_MAX_N) return -1;
     const uint32_t nm = 1u << n;
-    for (uint32_t S = 0; S < nm; ++S) {
-        double total = 0.0;
-        uint32_t T = S;
-        for (;;) {
-            double prod = 1.0;
-            for (int i = 0; i < n; ++i) {
-                if (!(S >> i & 1u)) continue;
-                double rs = 0.0;
-                for (int j = 0; j < n; ++j) if (T >> j & 1u) rs += A[i * n + j];
-                prod *= rs;
-            }
-#if ORACLE_PLANT == 5
-            int sgn = (popcount32(T) & 1) ? -1 : 1;
-#else
-            int sgn = ((popcount32(S) - popcount32(T)) & 1) ? -1 : 1;
-#endif
-            total += sgn * prod;
-            if (T == 0) break;
-            T = (T - 1) & S;
-        }
-        out[S] = total;
+    for (uint32_t S = 0; S < nm; ++S) out[S] = ryser_subset(n, A, S);
+    return 0;
+}
+
+/* per(A[S]) for the listed masks only (same formula, same code as above). */
+int apm_oracle_perm_minors_masks(int n, const double *A, int count, const uint32_t *masks, double *out)
+{
+    if (n < 0 || n > ORACLE_MAX_N || count < 0) return -1;
+    for (int m = 0; m < count; ++m) {
+        if (n < 32 && (masks[m] >> n) != 0u) return -1;
+        out[m] = ryser_subset(n, A, masks[m]);
     }
     return 0;
 }

@@ -25,6 +25,12 @@ def test_perm_pins(oracle_mod, pin):
     pin(oracle_mod.perm_minors)
 
 
+@pytest.mark.parametrize("pin", P.PERM_PINS, ids=lambda f: f.__name__)
+def test_perm_masks_pins(oracle_mod, pin):
+    """The mask-list entry point (used to sample large orders) meets the same pins."""
+    pin(lambda A: oracle_mod.perm_minors_at(A, np.arange(1 << np.asarray(A).shape[0], dtype=np.uint32)))
+
+
 def test_ragged_matches_uniform(oracle_mod):
     rng = np.random.default_rng(5)
     mats = [rng.standard_normal((k, k)) for k in (3, 1, 6, 4)]

@@ -49,6 +49,31 @@ def test_gauss_orders(apm, oracle_mod, n):
         assert np.all(np.abs(got[b] - ref[b]) <= TOL * scale(A[b])), n
 
 
+def test_gauss_order_13(apm, oracle_mod):
+    """Orders above 12 split their highest indices over workgroups (one per subset of them)."""
+    A = W.gauss_batch(1, 13, seed=413)
+    got = run(apm, A)
+    ref = oracle_mod.perm_minors(A)
+    assert np.all(np.abs(got[0] - ref[0]) <= TOL * scale(A[0]))
+
+
+@pytest.mark.parametrize("n", [15, 16])
+def test_gauss_large_orders_sampled(apm, oracle_mod, n):
+    """Sampled subsets at the largest orders: every subset of the workgroup-split indices
+    (each workgroup's full set), the full set, and random subsets."""
+    A = W.gauss_batch(2, n, seed=400 + n)
+    got = run(apm, A)
+    rng = np.random.default_rng(n)
+    hi = [(m << 12) | 0xFFF for m in range(1 << (n - 12))]
+    masks = np.unique(np.concatenate([np.array(hi, dtype=np.uint32),
+                                      rng.integers(0, 1 << n, 64, dtype=np.uint32),
+                                      np.array([0, (1 << n) - 1], dtype=np.uint32)]))
+    for b in range(2):
+        ref = oracle_mod.perm_minors_at(A[b], masks)
+        sc = scale(A[b])[masks]
+        assert np.all(np.abs(got[b][masks] - ref) <= TOL * sc), n
+
+
 def test_all_ones_factorials(apm):
     n = 10
     got = run(apm, np.ones((1, n, n)))[0]
