@@ -170,14 +170,22 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
         const U4 d1 = draws(a, w, 1);
         const float* lg = logits + (size_t)w * stride;
         const int per_bin = a.n_tau / a.n_bin;
-        // site distribution: lane owns the contiguous block [j0, j1)
+        // site distribution: lane owns the contiguous block [j0, j1); up to kPc of its terms
+        // exp(logit - max) are kept in registers for the draw and for q~
         const int P = (L2 + kWave - 1) / kWave;
         const int j0 = min(L2, lane * P), j1 = min(L2, j0 + P);
         double mx = -INFINITY;
         for (int j = j0; j < j1; ++j) mx = fmax(mx, (double)lg[j]);
         mx = wave_max(mx);
+        constexpr int kPc = 8;
+        double pc[kPc];
         double part = 0.0;
-        for (int j = j0; j < j1; ++j) part += exp((double)lg[j] - mx);
+#pragma unroll
+        for (int u = 0; u < kPc; ++u) {
+            pc[u] = j0 + u < j1 ? exp((double)lg[j0 + u] - mx) : 0.0;
+            part += pc[u];
+        }
+        for (int j = j0 + kPc; j < j1; ++j) part += exp((double)lg[j] - mx);
         const double incl = wave_scan(part);
         double excl = __shfl_up(incl, 1);
         if (lane == 0) excl = 0.0;
@@ -193,7 +201,10 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
             int cand = 0x7FFFFFFF, lastpos = -1;
             double run = excl;
             for (int j = j0; j < j1; ++j) {
-                const double p = exp((double)lg[j] - mx);
+                double p = 0.0;
+#pragma unroll
+                for (int u = 0; u < kPc; ++u) p = (j == j0 + u) ? pc[u] : p;
+                if (j >= j0 + kPc) p = exp((double)lg[j] - mx);
                 run += p;
                 if (p > 0.0) {
                     lastpos = j;

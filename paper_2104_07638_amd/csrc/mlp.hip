@@ -7,8 +7,9 @@
 //   D result  (16 x 16, M x N): lane l holds D[4 (l / 16) + 0..3][l % 16]
 // With the weights as A and the activations (features x batch) as B, the D tile of 16
 // output features is exactly the B operand of the next layer's k-step over those
-// features, so activations stay in registers from layer to layer.  One wavefront
-// handles 32 batch rows (two N tiles sharing every weight load).
+// features.  The forward pass runs one workgroup per 32 batch rows (two N tiles sharing
+// every weight load); its wavefronts split each layer's output features and pass the
+// activations on through LDS.
 //
 // Backward: the hidden gradients are chained the same way through the transposed
 // weights (W^T kept as a second BF16 copy); the weight gradients dW = dZ^T H sum over
@@ -67,21 +68,41 @@ __device__ __forceinline__ void store_t(uint16_t* dst, int B, int f0, int r, v4s
     for (int j = 0; j < 4; ++j) dst[(size_t)(f0 + j) * B + r] = (uint16_t)v[j];
 }
 
-// one hidden layer: in = B operands over KS k-steps, out = 8 feature tiles of tanh(W in + b)
+// Forward pass: one workgroup of kFwdWaves wavefronts per 32 batch rows.  The wavefronts
+// split the output features of every layer (wave v computes hidden tiles 2v, 2v+1 and output
+// tiles v, v + kFwdWaves, ...) and exchange the BF16 activations through LDS between layers,
+// already in B-operand order.  Each wavefront needs only its slice of the weights and loads
+// all of it up front (straight from L2, one batch of independent loads), so the three
+// layers wait for memory once.
+constexpr int kFwdWaves = 4;
+constexpr int kMtPerWave = 8 / kFwdWaves;
+constexpr int kW3Pre = 6;    // output tiles per wavefront whose weights are loaded up front
+
 template <int KS>
-__device__ __forceinline__ void hidden_layer(const uint16_t* __restrict__ W, const float* __restrict__ b,
-                                             const v4s (&in)[2][KS], v4s (&out)[2][8], int row0, int B,
+__device__ __forceinline__ void load_slice(const uint16_t* __restrict__ W, int mt0, v4s (&a)[kMtPerWave][KS])
+{
+    const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < kMtPerWave; ++m)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) a[m][ks] = ld4(W + (size_t)(16 * (mt0 + m) + r16) * (16 * KS) + 16 * ks + 4 * g);
+}
+
+// tanh(W in + b) for the hidden tiles mt0 .. mt0+kMtPerWave-1 of both row tiles
+template <int KS>
+__device__ __forceinline__ void hidden_slice(const v4s (&a)[kMtPerWave][KS], const float* __restrict__ b,
+                                             const v4s (&in)[2][KS], int mt0, v4s* act_out, int row0, int B,
                                              float* save, uint16_t* save_t)
 {
     const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
+    for (int m = 0; m < kMtPerWave; ++m) {
+        const int mt = mt0 + m;
         v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const v4s a = ld4(W + (size_t)(16 * mt + r16) * (16 * KS) + 16 * ks + 4 * g);
-            a0 = mfma(a, in[0][ks], a0);
-            a1 = mfma(a, in[1][ks], a1);
+            a0 = mfma(a[m][ks], in[0][ks], a0);
+            a1 = mfma(a[m][ks], in[1][ks], a1);
         }
         const int f0 = 16 * mt + 4 * g;
         const v4f bb = *reinterpret_cast<const v4f*>(b + f0);
@@ -93,27 +114,41 @@ __device__ __forceinline__ void hidden_layer(const uint16_t* __restrict__ W, con
             h[1] = tanh_f(z[1]);
             h[2] = tanh_f(z[2]);
             h[3] = tanh_f(z[3]);
-            out[nt][mt] = pack_bf(h);
+            const v4s hb = pack_bf(h);
+            act_out[(mt * 2 + nt) * 64 + lane] = hb;
             const int r = row0 + 16 * nt + r16;
             if (save) *reinterpret_cast<v4f*>(save + (size_t)r * H + f0) = h;
-            if (save_t) store_t(save_t, B, f0, r, out[nt][mt]);
+            if (save_t) store_t(save_t, B, f0, r, hb);
         }
     }
 }
 
 template <int KS1>
-__global__ __launch_bounds__(64) void mlp_fwd_kernel(const uint16_t* __restrict__ w, const float* __restrict__ bias,
-                                                     const uint16_t* __restrict__ x, int B, int Op,
-                                                     float* __restrict__ out, float* h1s, float* h2s,
-                                                     uint16_t* actT)
+__global__ __launch_bounds__(64 * kFwdWaves) void mlp_fwd_kernel(const uint16_t* __restrict__ w,
+                                                                 const float* __restrict__ bias,
+                                                                 const uint16_t* __restrict__ x, int B, int Op,
+                                                                 float* __restrict__ out, float* h1s, float* h2s,
+                                                                 uint16_t* actT)
 {
     constexpr int DP = 16 * KS1;
-    const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
+    __shared__ v4s act1[8 * 2 * 64], act2[8 * 2 * 64];   // [feature tile][row tile][lane]
+    const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4, wv = threadIdx.x >> 6;
     const int row0 = blockIdx.x * 32;
     const uint16_t* W1 = w;
     const uint16_t* W2 = W1 + H * DP;
     const uint16_t* W3 = W2 + H * H;
 
+    const int ntile = Op / 16;
+    v4s w1[kMtPerWave][KS1], w2[kMtPerWave][8], w3[kW3Pre][8];
+    load_slice<KS1>(W1, kMtPerWave * wv, w1);
+    load_slice<8>(W2, kMtPerWave * wv, w2);
+#pragma unroll
+    for (int u = 0; u < kW3Pre; ++u) {
+        const int t = wv + u * kFwdWaves;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+            if (t < ntile) w3[u][ks] = ld4(W3 + (size_t)(16 * t + r16) * H + 16 * ks + 4 * g);
+    }
     v4s xo[2][KS1];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
@@ -121,26 +156,49 @@ __global__ __launch_bounds__(64) void mlp_fwd_kernel(const uint16_t* __restrict_
         for (int ks = 0; ks < KS1; ++ks) {
             const int r = row0 + 16 * nt + r16;
             xo[nt][ks] = ld4(x + (size_t)r * DP + 16 * ks + 4 * g);
-            if (actT) store_t(actT, B, 16 * ks + 4 * g, r, xo[nt][ks]);
+            if (actT && wv == 0) store_t(actT, B, 16 * ks + 4 * g, r, xo[nt][ks]);
         }
+    hidden_slice<KS1>(w1, bias, xo, kMtPerWave * wv, act1, row0, B, h1s, actT ? actT + (size_t)DP * B : nullptr);
+    __syncthreads();
 
-    v4s h1o[2][8], h2o[2][8];
-    hidden_layer<KS1>(W1, bias, xo, h1o, row0, B, h1s, actT ? actT + (size_t)DP * B : nullptr);
-    hidden_layer<8>(W2, bias + H, h1o, h2o, row0, B, h2s, actT ? actT + (size_t)(DP + H) * B : nullptr);
+    v4s h1o[2][8];
+#pragma unroll
+    for (int kt = 0; kt < 8; ++kt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) h1o[nt][kt] = act1[(kt * 2 + nt) * 64 + lane];
+    hidden_slice<8>(w2, bias + H, h1o, kMtPerWave * wv, act2, row0, B, h2s,
+                    actT ? actT + (size_t)(DP + H) * B : nullptr);
+    __syncthreads();
 
+    v4s h2o[2][8];
+#pragma unroll
+    for (int kt = 0; kt < 8; ++kt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) h2o[nt][kt] = act2[(kt * 2 + nt) * 64 + lane];
     const float* b3 = bias + 2 * H;
-    for (int ot = 0; ot < Op / 16; ++ot) {
+    auto out_tile = [&](int t, const v4s (&a)[8]) {
         v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
-            const v4s a = ld4(W3 + (size_t)(16 * ot + r16) * H + 16 * ks + 4 * g);
-            a0 = mfma(a, h2o[0][ks], a0);
-            a1 = mfma(a, h2o[1][ks], a1);
+            a0 = mfma(a[ks], h2o[0][ks], a0);
+            a1 = mfma(a[ks], h2o[1][ks], a1);
         }
-        const int f0 = 16 * ot + 4 * g;
+        const int f0 = 16 * t + 4 * g;
         const v4f bb = *reinterpret_cast<const v4f*>(b3 + f0);
         *reinterpret_cast<v4f*>(out + (size_t)(row0 + r16) * Op + f0) = a0 + bb;
         *reinterpret_cast<v4f*>(out + (size_t)(row0 + 16 + r16) * Op + f0) = a1 + bb;
+    };
+#pragma unroll
+    for (int u = 0; u < kW3Pre; ++u) {
+        const int t = wv + u * kFwdWaves;
+        if (t < ntile) out_tile(t, w3[u]);
+    }
+    // tiles beyond the preloaded ones (wide output layers)
+    for (int t = wv + kW3Pre * kFwdWaves; t < ntile; t += kFwdWaves) {
+        v4s a[8];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) a[ks] = ld4(W3 + (size_t)(16 * t + r16) * H + 16 * ks + 4 * g);
+        out_tile(t, a);
     }
 }
 
@@ -349,7 +407,7 @@ hipError_t mlp_forward_launch(const MlpNet& net, const uint16_t* x, int B, float
     float* h1 = wk ? wk->h1 : nullptr;
     float* h2 = wk ? wk->h2 : nullptr;
     uint16_t* actT = wk ? wk->actT : nullptr;
-    const dim3 grid((unsigned)(B / 32)), block(64);
+    const dim3 grid((unsigned)(B / 32)), block(64 * kFwdWaves);
     switch (net.dp / 16) {
     case 1: hipLaunchKernelGGL(mlp_fwd_kernel<1>, grid, block, 0, st, net.w, bias, x, B, net.op, out, h1, h2, actT); break;
     case 2: hipLaunchKernelGGL(mlp_fwd_kernel<2>, grid, block, 0, st, net.w, bias, x, B, net.op, out, h1, h2, actT); break;
