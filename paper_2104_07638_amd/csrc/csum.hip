@@ -221,6 +221,9 @@ __device__ __forceinline__ double weight(const CsArgs& g, int64_t base, int64_t 
 #ifndef APM_CS_LB_LARGE
 #define APM_CS_LB_LARGE 4
 #endif
+#ifndef APM_CS_GMUL_SMALL
+#define APM_CS_GMUL_SMALL 2   // one-wavefront problems (m <= 10)
+#endif
 #ifndef APM_CS_GMUL
 #define APM_CS_GMUL 2
 #endif
@@ -268,7 +271,8 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
     const int nout = rk_off[r + 1] - rk_off[r];
     const int items = TRI ? (1 << r) - 1 : (1 << r);
     int G = 1;
-    while (G * 2 <= kWave && nout * G * APM_CS_GMUL <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
+    constexpr int GMUL = NT == kWave ? APM_CS_GMUL_SMALL : APM_CS_GMUL;
+    while (G * 2 <= kWave && nout * G * GMUL <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
     const int per_pass = NT / G;
     for (int ob = 0; ob < nout; ob += per_pass) {
         const int o = ob + tid / G;
@@ -310,6 +314,34 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
     }
 }
 
+// Rows of a block (H bits) sorted by rank: tab[H] lists the masks of popcount 0, 1, ...,
+// off[H][r] is where rank r starts.
+struct RankTables {
+    uint16_t tab[8][128];
+    int off[8][9];
+};
+
+constexpr RankTables make_rank_tables()
+{
+    RankTables t{};
+    for (int h = 0; h < 8; ++h) {
+        int pos = 0;
+        for (int r = 0; r <= h; ++r) {
+            t.off[h][r] = pos;
+            for (int x = 0; x < (1 << h); ++x) {
+                int c = 0;
+                for (int y = x; y; y &= y - 1) ++c;
+                if (c == r) t.tab[h][pos++] = (uint16_t)x;
+            }
+        }
+        t.off[h][h + 1] = pos;
+    }
+    return t;
+}
+
+__constant__ RankTables kRank = make_rank_tables();
+
+
 // Problem (matrix b, root j): solve (*) for the m = n-1-j vertices above j.
 template <int M>
 __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even, double* lds_c, double* lds_b,
@@ -323,20 +355,39 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
     const int64_t sroot = base + (int64_t(1) << j);  // element index of S = {j}
     double* c = g.c;
 
-    if (tid == 0) {                                 // rows of a block sorted by rank
-        int pos = 0;
-        for (int r = 0; r <= H; ++r) {
-            rk_off[r] = pos;
-            for (int x = 0; x < (1 << H); ++x)
-                if (__builtin_popcount(x) == r) rk_tab[pos++] = (uint16_t)x;
+    static_assert(H < 8, "rank tables cover rows of up to 7 bits");
+    for (int i = tid; i < (1 << H); i += NT) rk_tab[i] = kRank.tab[H][i];
+    if (tid <= H + 1) rk_off[tid] = kRank.off[H][tid];
+    // rooted problem in one block: a0[x] = a[2x + 1] and b[x] = a[2x] are neighbours, so
+    // one 16-byte load per x stages both (the block's own b is staged later otherwise)
+    constexpr bool kOneBlock = CP::TB == 0;
+    const bool pair_stage = kOneBlock && j == 0 && !(base & 1);
+    if (pair_stage) {
+        for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+            const double2 u = *reinterpret_cast<const double2*>(g.up + base + 2 * x1);
+            double w0, w1;
+            if (g.weights) {
+                w0 = u.x;
+                w1 = u.y;
+            } else if (g.dn) {
+                const double2 d = *reinterpret_cast<const double2*>(g.dn + base + 2 * x1);
+                w0 = u.x * d.x;
+                w1 = u.y * d.y;
+            } else {
+                w0 = u.x * u.x;
+                w1 = u.y * u.y;
+            }
+            lds_b[sw<LB>(x1)] = x1 ? w0 : 0.0;
+            lds_r[sw<LB>(x1)] = w1;
         }
-        rk_off[H + 1] = pos;
     }
     for (int x2 = 0; x2 < (1 << CP::TB); ++x2) {
         // right-hand side a0 of the block
-        for (int x1 = tid; x1 < (1 << P); x1 += NT) {
-            const int64_t x = ((int64_t)x2 << P) | x1;
-            lds_r[sw<LB>(x1)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
+        if (!pair_stage) {
+            for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+                const int64_t x = ((int64_t)x2 << P) | x1;
+                lds_r[sw<LB>(x1)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
+            }
         }
         // cross-block contributions: every Y2 subsetneq X2
         for (uint32_t y2 = 0; y2 < (uint32_t)x2; ++y2) {
@@ -352,8 +403,11 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
         }
         // the block's own triangular solve, with b of block 0
         __syncthreads();
-        for (int x1 = tid; x1 < (1 << P); x1 += NT) lds_b[sw<LB>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
-        __syncthreads();
+        if (!pair_stage) {
+            for (int x1 = tid; x1 < (1 << P); x1 += NT)
+                lds_b[sw<LB>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
+            __syncthreads();
+        }
         for (int r = 0; r <= H; ++r) {
             rank_pass<M, true>(r, rk_tab, rk_off, lds_c, lds_b, lds_r, lds_c);
             __syncthreads();
