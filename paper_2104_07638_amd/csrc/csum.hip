@@ -283,8 +283,14 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
 #pragma unroll
         for (int i = 0; i < W; ++i) acc[i] = 0.0;
         if (valid) {
-            for (int k = s; k < items; k += G) {
-                const uint32_t yh = pdep_u32((uint32_t)k, xh);
+            // pair k = s + G t has Yh = pdep(s) | pdep(t) over the bits of Xh above its lowest
+            // log2(G) ones: the second part steps through the subsets of those bits in order
+            const uint32_t ys = pdep_u32((uint32_t)s, xh);
+            uint32_t xhi = xh;
+            for (int gg = 1; gg < G; gg <<= 1) xhi &= xhi - 1u;
+            uint32_t z = 0;
+            for (int k = s; k < items; k += G, z = (z - xhi) & xhi) {
+                const uint32_t yh = ys | z;
                 if constexpr (LB >= 3) {
                     conv_rows_split<LB>(cb, (int)yh, bb, (int)(xh ^ yh), acc);
                 } else {
