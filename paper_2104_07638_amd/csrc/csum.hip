@@ -69,6 +69,23 @@ __device__ __forceinline__ int sw(int x1)
     }
 }
 
+// Byte address of the swizzled pair p of a row: the row starts at row * 8W bytes, a multiple
+// of the 16-byte pair slots it spans, so the pair's slot (p ^ (row & pm)) is the row's
+// address with bits 4.. XORed by p: one XOR per load.
+template <int LB>
+__device__ __forceinline__ uint32_t row_addr(int row)
+{
+    constexpr int W = 1 << LB;
+    constexpr int pm = (W >> 1) - 1;
+    return (uint32_t)row * (8u * W) + ((uint32_t)(row & pm) << 4);
+}
+
+template <int LB>
+__device__ __forceinline__ double2 ld_pair(const double* buf, uint32_t a, int p)
+{
+    return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(buf) + (a ^ ((uint32_t)p << 4)));
+}
+
 template <int LB>
 __device__ __forceinline__ void load_row(const double* buf, int row, double (&v)[1 << LB])
 {
@@ -77,11 +94,10 @@ __device__ __forceinline__ void load_row(const double* buf, int row, double (&v)
 #pragma unroll
         for (int i = 0; i < W; ++i) v[i] = buf[row * W + i];
     } else {
-        constexpr int pm = (W >> 1) - 1;
-        const double* r = buf + row * W;
+        const uint32_t a = row_addr<LB>(row);
 #pragma unroll
         for (int p = 0; p < W / 2; ++p) {
-            const double2 t = *reinterpret_cast<const double2*>(r + 2 * (p ^ (row & pm)));
+            const double2 t = ld_pair<LB>(buf, a, p);
             v[2 * p] = t.x;
             v[2 * p + 1] = t.y;
         }
@@ -120,12 +136,10 @@ template <int LB>
 __device__ __forceinline__ void load_half(const double* buf, int row, int half, double (&v)[1 << (LB - 1)])
 {
     constexpr int W = 1 << LB;
-    constexpr int pm = (W >> 1) - 1;
-    const double* r = buf + row * W;
+    const uint32_t a = row_addr<LB>(row);
 #pragma unroll
     for (int p = 0; p < W / 4; ++p) {
-        const int pp = p + half * (W / 4);
-        const double2 t = *reinterpret_cast<const double2*>(r + 2 * (pp ^ (row & pm)));
+        const double2 t = ld_pair<LB>(buf, a, p + half * (W / 4));
         v[2 * p] = t.x;
         v[2 * p + 1] = t.y;
     }
@@ -249,11 +263,11 @@ __device__ __forceinline__ void store_row(double* buf, int row, const double (&v
 #pragma unroll
         for (int i = 0; i < W; ++i) buf[row * W + i] = v[i];
     } else {
-        constexpr int pm = (W >> 1) - 1;
-        double* r = buf + row * W;
+        const uint32_t a = row_addr<LB>(row);
 #pragma unroll
         for (int p = 0; p < W / 2; ++p)
-            *reinterpret_cast<double2*>(r + 2 * (p ^ (row & pm))) = make_double2(v[2 * p], v[2 * p + 1]);
+            *reinterpret_cast<double2*>(reinterpret_cast<char*>(buf) + (a ^ ((uint32_t)p << 4))) =
+                make_double2(v[2 * p], v[2 * p + 1]);
     }
 }
 
