@@ -300,6 +300,37 @@ def test_mc_evaluate_resolve(apm):
     assert np.all(ch.sign.cpu().numpy()[both] == sg_ref[both])
 
 
+@pytest.mark.parametrize("n", [12, 13])
+def test_mc_evaluate_orders(apm, n):
+    """Up to n = 12 the connected-sum kernel hands the acceptance step only (c[V], d[V]);
+    above, c[V] and d[V] come from the full c[] and minors arrays.  Both against the oracle,
+    with the resolution cutoff on."""
+    model = wl.McModel(n=n, L=16, mu=0.0, beta=4.0, n_tau=128, n_bin=16, resolve=1e-10)
+    s = _Setup(apm, model, 128, seed=11)
+    mix = s.states.copy()
+    mix[64:] = wl.mc_initial_states(64, model, seed=11)
+    ch = apm.McChain(mix)
+    work = apm.mc_work(s.m, s.W, False)
+    apm.mc_evaluate(s.m, ch, work)
+    lw = ch.logw.cpu().numpy()
+    sg = ch.sign.cpu().numpy()
+    from oracle import connected_sums, cs_scale, metrics
+    M = omc.matrices(model, s.g0, mix)
+    m = omc.minors(M)
+    c = connected_sums(m * m, 0)
+    d = cs_scale(m * m, c, 0)[:, -1]
+    tabs = metrics.cdet_tolerance(M, m, c)[:, -1]
+    cv = c[:, -1]
+    ref_ok = np.abs(cv) >= 1e-10 * d
+    near = np.abs(np.abs(cv) - 1e-10 * d) <= 2 * tabs
+    assert np.all((np.isfinite(lw) == ref_ok) | near)
+    assert ref_ok[:64].sum() >= 56
+    both = np.isfinite(lw) & ref_ok
+    assert np.all(np.abs(np.exp(lw[both]) - np.abs(cv[both])) <= tabs[both])
+    resolved = both & (np.abs(cv) > 2.0 * tabs)
+    assert np.all(sg[resolved] == np.sign(cv[resolved]))
+
+
 def test_mc_evaluate(apm):
     s = _Setup(apm, CFG5, 512, seed=3)
     mix = s.states.copy()
