@@ -18,6 +18,14 @@
  *     batch arrives.  Mixed-order calls (n_uniform == 0) share that workspace: they
  *     must not overlap in time on one device (order them on one stream).  A call that
  *     would grow it must not be the first such call inside a graph capture.
+ *     Uniform-order calls of apm_all_minors keep one more small buffer per (device,
+ *     stream): the queue of matrices whose pivot corrections in the top tree levels are
+ *     applied by a follow-up launch.  Calls on one stream are ordered by the stream.
+ *     The queue is allocated and grown only outside stream capture; a captured call
+ *     whose stream has no queue of the batch's size applies those corrections inside
+ *     the minors kernel (same results, bit for bit).  A graph that did capture a queue
+ *     uses the capturing stream's buffer: its replays must not overlap direct calls on
+ *     that stream.
  *   - Calls are asynchronous: arguments are validated on the host, work is
  *     enqueued on `stream`, and the call returns.  Results are valid once the
  *     stream has been synchronised.  Argument errors return before anything is
@@ -107,6 +115,9 @@ typedef struct {
  *   info    [B] int32 or NULL: >= 0 number of shifted pivots of matrix b;
  *           -2 non-finite input (outputs set to NaN); -3 a non-finite output.
  *   opt     options or NULL.
+ * A uniform batch whose tree has between one and five top levels (n - 6 minus the
+ * lane-subtree order; fp64 at n = 12..16) enqueues the minors launch and then one
+ * launch per top level for the deferred pivot corrections (ownership notes above).
  * Returns APM_OK, APM_EINVAL (bad argument), APM_EUNSUPPORTED (n > APM_MAX_N), or
  * APM_EDEVICE (launch failure).
  */

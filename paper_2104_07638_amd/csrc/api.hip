@@ -1,7 +1,9 @@
 // api.hip -- the C ABI of libapm.so: argument validation, workspaces, launches.
 #include <math.h>
 #include <stdlib.h>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "../../include/apm.h"
@@ -59,6 +61,45 @@ apm_status get_workspace(int64_t batch, int32_t** counter, int32_t** order, int6
     *ooff = reinterpret_cast<int64_t*>(p + 256 + (size_t)w.cap * 12);
     *cus = w.cus;
     return APM_OK;
+}
+
+// Per-(device, stream) queue of deferred top-level corrections for uniform batches.  Each
+// use leaves it zeroed; a call that failed after using it marks it for re-zeroing.  It is
+// only (re)allocated or re-zeroed outside stream capture: a captured call that would need
+// that runs the corrections inside the minors kernel instead.
+struct TopQueue {
+    void* buf = nullptr;
+    int64_t cap = 0;
+    bool dirty = false;
+};
+std::map<std::pair<int, hipStream_t>, TopQueue> g_topq;
+
+int32_t* get_topq(hipStream_t st, int64_t batch, int32_t* cap_out, TopQueue** q_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    TopQueue& q = g_topq[std::make_pair(dev, st)];
+    if (q.cap < batch || q.dirty) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+        if (q.cap < batch) {
+            if (q.buf) (void)hipFree(q.buf);
+            q.buf = nullptr;
+            q.cap = 0;
+            const int64_t cap = batch < 4096 ? 4096 : batch;
+            if (hipMalloc(&q.buf, (size_t)apm::fpm_topq_bytes(cap)) != hipSuccess) {
+                q.buf = nullptr;
+                return nullptr;
+            }
+            q.cap = cap;
+        }
+        if (hipMemsetAsync(q.buf, 0, (size_t)apm::fpm_topq_bytes(q.cap), st) != hipSuccess) return nullptr;
+        q.dirty = false;
+    }
+    *cap_out = (int32_t)q.cap;
+    *q_out = &q;
+    return static_cast<int32_t*>(q.buf);
 }
 
 bool bad_batch(const apm_batch* bd, int nmax)
@@ -139,11 +180,19 @@ apm_status apm_all_minors(apm_dtype dt, const void* A, const apm_batch* bd, void
     L.tau = (opt && opt->piv_tol > 0) ? opt->piv_tol : tau_def;
     L.perturb = !(flags & APM_NO_PERTURB);
     L.out_f64 = out_f64;
+    TopQueue* tq = nullptr;
     if (bd->n_uniform == 0) {
         apm_status s = get_workspace(bd->batch, &L.counter, &L.order, &L.ioff_ws, &L.ooff_ws, &L.n_workers);
         if (s != APM_OK) return s;
+    } else if (bd->batch <= INT32_MAX / 2) {
+        L.topq = get_topq((hipStream_t)stream, bd->batch, &L.topq_cap, &tq);
     }
-    return from_hip(apm::fpm_launch(L, (hipStream_t)stream));
+    const hipError_t e = apm::fpm_launch(L, (hipStream_t)stream);
+    if (e != hipSuccess && tq) {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        tq->dirty = true;
+    }
+    return from_hip(e);
 }
 
 int32_t apm_minors_k0(apm_dtype dt, int32_t n)

@@ -25,7 +25,13 @@ struct LaunchMinors {
     int64_t* ooff_ws;          // ragged: workspace [batch] packed output offsets (if out_off == NULL)
     int n_workers;             // ragged: number of compute units (persistent grid sizing)
     int force_k0;              // > 0: lane-subtree order to use (autotuning); 0: the table
+    int32_t* topq;             // uniform batches: deferred top-level correction queue (NULL: none)
+    int32_t topq_cap;          // its capacity in entries
 };
+
+// Bytes of a deferred-correction queue for `batch` matrices (zeroed once at allocation;
+// each use leaves it zeroed).
+int64_t fpm_topq_bytes(int64_t batch);
 
 hipError_t fpm_launch(const LaunchMinors& L, hipStream_t st);
 

@@ -112,7 +112,18 @@ struct Opts {
     double tau;      // relative pivot threshold
     bool perturb;
     bool out_f64;
+    int* topq;       // deferred top-level corrections (NULL: applied by the wavefront itself)
+    int topq_cap;    // entries the queue holds
 };
+
+// Deferred top-level corrections.  A wavefront whose matrix has shifted pivots in the top
+// levels records (output pointers, exponent of s, per-chunk shift exponents) in a queue
+// instead of applying the corrections itself; a follow-up launch applies them with a
+// whole workgroup per matrix.  Queue layout (int32): [0] entries, [1] workgroups done,
+// entries of kTopEntryInts from int 64 on: out (2), ex (2), es_true (1), shift bytes.
+constexpr int kTopDeferMaxT = 5;
+constexpr int kTopEntryInts = 16;
+constexpr int kTopHead = 64;
 
 // Matrix-wide parameters of the pivot shift.
 struct PivCtl {
@@ -633,7 +644,29 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
 
     // ---- top-level corrections, deepest first ---------------------------------------
     if constexpr (T > 0) {
-        if (any_top) {
+        bool deferred = false;
+        if constexpr (T <= kTopDeferMaxT) {
+            if (any_top && o.topq) {
+                int idx = 0;
+                if (lane == 0) idx = atomicAdd(o.topq, 1);
+                idx = __shfl(idx, 0);
+                if (idx < o.topq_cap) {
+                    deferred = true;
+                    int* ent = o.topq + kTopHead + idx * kTopEntryInts;
+                    if (lane == 0) {
+                        const uint64_t po = reinterpret_cast<uint64_t>(out), pe = reinterpret_cast<uint64_t>(ex);
+                        ent[0] = (int)(uint32_t)po;
+                        ent[1] = (int)(uint32_t)(po >> 32);
+                        ent[2] = (int)(uint32_t)pe;
+                        ent[3] = (int)(uint32_t)(pe >> 32);
+                        ent[4] = pc.es_true;
+                    }
+                    int8_t* tv = reinterpret_cast<int8_t*>(ent + 5);
+                    for (int c = lane; c < (1 << T); c += kWave) tv[c] = tevc[c];
+                }
+            }
+        }
+        if (any_top && !deferred) {
             wave_mem_fence();
             for (int d = T - 1; d >= 0; --d) {
                 const int step = 1 << (T - 1 - d);
@@ -695,6 +728,69 @@ __global__ __launch_bounds__(64) APM_FPM_OCC void fpm_uniform_kernel(const typen
     if (info && lane_id() == 0) info[b] = r;
 }
 
+// Deferred top-level corrections (see Opts), one launch per level d, deepest first: the work
+// items (queued matrix, shifted node at level d, tile of kTopTile minors of its strict right
+// subtree) are spread over the whole grid, with the same updates as the in-wavefront path.
+// The launch for level 0 also resets the queue: the last workgroup to finish zeroes it.
+constexpr int kTopTile = 1024;
+
+template <class F, int N, int K0MAX>
+__global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int f64, int d, int last)
+{
+    using P = Plan<N, K0MAX>;
+    constexpr int T = P::T, K = P::K;
+    const int tid = threadIdx.x;
+    if constexpr (T > 0 && T <= kTopDeferMaxT) {
+        int count = __hip_atomic_load(topq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (count > cap) count = cap;
+        const int step = 1 << (T - 1 - d);
+        const int nodes = 1 << d;                                   // level-d nodes: c = step (2q + 1)
+        const int64_t half = int64_t(1) << (N - 1 - d);
+        const int64_t tiles = (half + kTopTile - 1) / kTopTile;
+        const int64_t items = (int64_t)count * nodes * tiles;
+        for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+            const int e = (int)(w / ((int64_t)nodes * tiles));
+            const int q = (int)((w / tiles) % nodes);
+            const int64_t t = w % tiles;
+            const int* ent = topq + kTopHead + e * kTopEntryInts;
+            const int c = step * (2 * q + 1);
+            const int de = reinterpret_cast<const int8_t*>(ent + 5)[c];
+            if (de == kNoEv) continue;
+            void* out = reinterpret_cast<void*>((uint64_t)(uint32_t)ent[0] | ((uint64_t)(uint32_t)ent[1] << 32));
+            int16_t* ex = reinterpret_cast<int16_t*>((uint64_t)(uint32_t)ent[2] | ((uint64_t)(uint32_t)ent[3] << 32));
+            const double Ct = ldexp(1.0, ent[4] + de);
+            const int64_t start = (int64_t)c << K, end = start + half;
+            const int64_t i0 = start + 1 + t * kTopTile;
+            constexpr int kU = kTopTile / 256;
+            typename F::V va[kU], vb[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t i = i0 + tid + 256 * u;
+                if (i < end) {
+                    va[u] = F::load_v(out, ex, i, f64 != 0);
+                    vb[u] = F::load_v(out, ex, i - half, f64 != 0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t i = i0 + tid + 256 * u;
+                if (i < end) F::store_v(out, ex, i, F::sub_scaled(va[u], Ct, vb[u]), f64 != 0);
+            }
+        }
+    }
+    if (last) {
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            const int done = atomicAdd(topq + 1, 1);
+            if (done == (int)gridDim.x - 1) {
+                atomicExch(topq, 0);
+                atomicExch(topq + 1, 0);
+            }
+        }
+    }
+}
+
 }  // namespace apm
 
 
@@ -720,6 +816,8 @@ inline int env_k0()
     return e ? atoi(e) : 0;
 }
 
+constexpr int kTopFixGroups = 1024;   // workgroups of each deferred-correction launch
+
 template <class F, int N, int K0>
 hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
 {
@@ -730,10 +828,19 @@ hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
                                            (int)Ly::bytes);
         if (e != hipSuccess) return e;
     }
-    Opts o{L.tau, L.perturb, L.out_f64};
+    constexpr bool kDefer = Plan<N, K0>::T > 0 && Plan<N, K0>::T <= kTopDeferMaxT;
+    int* topq = kDefer ? L.topq : nullptr;
+    Opts o{L.tau, L.perturb, L.out_f64, topq, L.topq_cap};
     hipLaunchKernelGGL(kern, dim3((unsigned)L.batch), dim3(64), Ly::bytes, st,
                        static_cast<const typename F::In*>(L.A), L.out, L.ex, L.info, L.batch, L.in_off, L.out_off, o);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !topq) return e;
+    for (int d = Plan<N, K0>::T - 1; d >= 0 && e == hipSuccess; --d) {
+        hipLaunchKernelGGL((fpm_topfix_kernel<F, N, K0>), dim3(kTopFixGroups), dim3(256), 0, st, topq, L.topq_cap,
+                           L.out_f64 ? 1 : 0, d, d == 0 ? 1 : 0);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 template <class F, int N, int K0>
@@ -871,7 +978,7 @@ hipError_t fpm_launch_ragged(const LaunchMinors& L, hipStream_t st)
     if (per_cu < 1) per_cu = 1;
     int64_t grid = (int64_t)per_cu * (L.n_workers > 0 ? L.n_workers : 256);
     if (grid > L.batch) grid = L.batch;
-    Opts o{L.tau, L.perturb, L.out_f64};
+    Opts o{L.tau, L.perturb, L.out_f64, nullptr, 0};   // mixed orders: corrections in the wavefront
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), bytes, st, static_cast<const typename F::In*>(L.A),
                        L.out, L.ex, L.info, L.batch, L.n, ioff, ooff, L.order, L.counter, o);
     return hipGetLastError();

@@ -232,3 +232,35 @@ def test_autotuned_layout(apm, oracle_mod, dtype, n):
         out, info = run(apm, A, dtype)
         ref = oracle_mod.minors(A)
         assert metrics.max_mixed_err(out, ref, A) <= (TOL64 if dtype == "r64" else 1e-4)
+
+
+def test_deferred_top_corrections_match_in_wave(apm, oracle_mod):
+    """Uniform batches queue their top-level pivot corrections for a follow-up launch; a
+    captured call on a stream without a queue of that size applies them inside the minors
+    kernel.  Both orders of work give the same bits, and both match the oracle."""
+    import torch
+    n, B = 12, 4104                                    # more matrices than a fresh queue holds
+    A = W.lattice_batch(B, n, W.Lattice(16, 1.0, 0.2, 4.0), seed=77)
+    A[::8] = W.zero_diagonal(A[::8])                   # spine shifts, the top level included
+    At = torch.from_numpy(A).cuda()
+    out = torch.empty((B, 1 << n), dtype=torch.float64, device="cuda")
+    info = torch.empty(B, dtype=torch.int32, device="cuda")
+    apm.all_minors(At, "r64", out=out, info=info, tau=1e-3)   # queued corrections
+    apm.all_minors(At, "r64", out=out, info=info, tau=1e-3)   # the queue was left ready for reuse
+    torch.cuda.synchronize()
+    eager, eager_info = out.clone(), info.clone()
+    g = torch.cuda.CUDAGraph()
+    out2 = torch.empty_like(out)
+    info2 = torch.empty_like(info)
+    with torch.cuda.graph(g):
+        apm.all_minors(At, "r64", out=out2, info=info2, tau=1e-3)
+    for _ in range(2):
+        out2.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out2, eager)
+        assert torch.equal(info2, eager_info)
+    assert int((eager_info > 0).sum()) >= B // 8
+    sel = np.arange(0, B, 97)
+    ref = oracle_mod.minors(A[sel])
+    assert metrics.max_mixed_err(eager[sel].cpu().numpy(), ref, A[sel]) <= 1e-8
