@@ -816,7 +816,7 @@ inline int env_k0()
     return e ? atoi(e) : 0;
 }
 
-constexpr int kTopFixGroups = 1024;   // workgroups of each deferred-correction launch
+constexpr int kTopFixGroups = 256;    // workgroups of each deferred-correction launch
 
 template <class F, int N, int K0>
 hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
