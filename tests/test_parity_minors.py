@@ -264,3 +264,61 @@ def test_deferred_top_corrections_match_in_wave(apm, oracle_mod):
     sel = np.arange(0, B, 97)
     ref = oracle_mod.minors(A[sel])
     assert metrics.max_mixed_err(eager[sel].cpu().numpy(), ref, A[sel]) <= 1e-8
+
+
+def test_full_bench_batch_sampled(apm, oracle_mod):
+    """The timed workload at its full size and in its launch configuration: 8192 order-16
+    lattice matrices (L=32, t=1, mu=-0.5, beta=5), every 64th made near-singular, one
+    uniform fp64 call with the default threshold (the deferred top-level corrections
+    included).  Sampled matrices (all stressed ones among them) and sampled masks against
+    LU per subset; the rooted connected sums of some of them against the direct recursion
+    on the GPU's own minors."""
+    import torch
+    n, B = 16, 8192
+    A = W.lattice_batch(B, n, W.Lattice(32, 1.0, -0.5, 5.0), seed=W.BASE_SEED)
+    A, log = W.inject_stress(A, every=64)
+    At = torch.from_numpy(A).cuda()
+    out, _, info = apm.all_minors(At, "r64")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(16)
+    stressed = [b for b, _, _ in log]
+    sel = sorted(set(stressed) | set(rng.choice(B, 96, replace=False).tolist()))
+    masks = np.unique(np.concatenate([rng.integers(0, 1 << n, 384, dtype=np.uint32),
+                                      np.array([0, 1, (1 << n) - 1, 0x8000, 0x7FFF], dtype=np.uint32)]))
+    got = out[sel][:, torch.from_numpy(masks.astype(np.int64)).cuda()].cpu().numpy()
+    assert np.all(info.cpu().numpy() >= 0)
+    for k, b in enumerate(sel):
+        ref = oracle_mod.minors_at(A[b], masks)
+        H = metrics.hadamard_bounds(A[b])[masks]
+        assert np.max(metrics.mixed_err(got[k], ref, H)) <= TOL64, b
+    cs = apm.connected_sums(out[sel[:4]].contiguous())
+    torch.cuda.synchronize()
+    m = out[sel[:4]].cpu().numpy()
+    cref = oracle_mod.connected_sums(m * m, 0)
+    tol = 1e-10 * oracle_mod.cs_scale(m * m, cref, 0) + 1e-300
+    assert np.all(np.abs(cs.cpu().numpy() - cref) <= tol)
+
+
+def test_full_bench_batch_fp32_scaled_sampled(apm, oracle_mod):
+    """The fp32-scaled variant on the full timed batch: sampled matrices and masks within
+    the 1e-4 gate, except the injected near-singular matrices, whose minors of relative
+    size 1e-12 fp32 updates resolve only to about 2e-4 of their Hadamard bound."""
+    import torch
+    n, B = 16, 8192
+    A = W.lattice_batch(B, n, W.Lattice(32, 1.0, -0.5, 5.0), seed=W.BASE_SEED)
+    A, log = W.inject_stress(A, every=64)
+    out, ex, info = apm.all_minors(torch.from_numpy(A).cuda(), "r32s")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(32)
+    stressed = sorted(b for b, _, _ in log)
+    normal = sorted(set(rng.choice(B, 64, replace=False).tolist()) - set(stressed))
+    masks = np.unique(np.concatenate([rng.integers(0, 1 << n, 256, dtype=np.uint32),
+                                      np.array([0, (1 << n) - 1], dtype=np.uint32)]))
+    idx = torch.from_numpy(masks.astype(np.int64)).cuda()
+    for group, gate in ((normal, TOL32), (stressed, 2.5e-4)):
+        val = apm.decode_scaled(out[group][:, idx], ex[group][:, idx]).cpu().numpy()
+        for k, b in enumerate(group):
+            ref = oracle_mod.minors_at(A[b], masks)
+            H = metrics.hadamard_bounds(A[b])[masks]
+            assert np.max(metrics.mixed_err(val[k], ref, H)) <= gate, b
+    assert np.all(info.cpu().numpy() >= 0)
