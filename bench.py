@@ -256,29 +256,18 @@ def run_extra(torch, apm, W, np, steps):
 
     ms_c = time_fn(torch, csum, max(2, steps // 4))
 
-    # the whole pipeline (queue preparation, persistent minors launch, connected sums)
-    # captured once in a HIP graph and replayed
-    def pipeline():
-        apm.all_minors_ragged(flat, n_t, 16, "r64", out=mm, out_off=ooff)
-        csum()
-
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        pipeline()
-    torch.cuda.current_stream().wait_stream(side)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        pipeline()
-    ms_g = time_fn(torch, graph.replay, max(2, steps // 4))
-    del graph
+    # the whole pipeline (queue preparation, persistent minors launch, connected sums) as
+    # one CDet plan: recorded once into a HIP graph by the library, one launch per step
+    plan = apm.plan_cdet(flat, mm, cc, batch=bd)
+    ms_g = time_fn(torch, plan.launch, max(2, steps // 4))
+    plan.close()
     fma = float(np.sum(3.0 ** (ns.astype(np.float64) - 1)))
     ex["mixed_n10_16_8192_cdet"] = {
         "minors_ms": round(ms_m, 4), "minors_GBs": round((8 * float(np.sum(ns.astype(np.float64) ** 2)) + 8 * tot)
                                                           / (ms_m * 1e-3) / 1e9, 1),
         "csum_ms": round(ms_c, 4), "csum_fma": fma, "csum_TFLOPs": round(2 * fma / (ms_c * 1e-3) / 1e12, 2),
         "csum_frac_fp64_peak": round(2 * fma / (ms_c * 1e-3) / 78.6e12, 4),
-        "graph_ms": round(ms_g, 4), "matrices_per_s": round(8192 / (ms_g * 1e-3), 1)}
+        "plan_ms": round(ms_g, 4), "matrices_per_s": round(8192 / (ms_g * 1e-3), 1)}
     del mm, cc, flat
     # permanent principal minors: 2048 real n = 12, entries N(0,1)/sqrt(12)
     P = torch.from_numpy(W.gauss_batch(2048, 12)).cuda()

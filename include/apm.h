@@ -176,11 +176,100 @@ apm_status apm_autotune_minors(apm_dtype dt, int32_t n, int32_t batch, int32_t *
  * -1 for bad arguments.  Host-only. */
 int32_t apm_minors_k0(apm_dtype dt, int32_t n);
 
+/*
+ * Plans -- one of the operations above, or the CDet pipeline, bound to fixed buffers and
+ * shapes, prepared once and enqueued many times (the Monte Carlo use: the same batch
+ * shapes every step, new matrix values in the same buffers).
+ *
+ * apm_plan_create validates the description as the direct call would, allocates the
+ * plan's own workspace (queue head and order, packed offsets, deferred-correction queue;
+ * never shared with direct calls or other plans), pins the lane-subtree order of uniform
+ * minors (timing every instantiated order first with APM_PLAN_AUTOTUNE, as
+ * apm_autotune_minors does, when the process has no tuned value for that dtype and order
+ * yet), and records the whole launch sequence once into a HIP graph on a private stream.
+ * apm_plan_launch then enqueues that graph on the caller's stream: one launch call for the
+ * whole sequence, with results bit-identical to the direct calls.  With APM_PLAN_EAGER the
+ * plan records nothing and each launch enqueues the kernels one by one (same results).
+ *
+ * The caller keeps every buffer named in the description (and the device arrays of its
+ * apm_batch) alive and at the same addresses until apm_plan_destroy; their contents may
+ * change between launches.  create allocates, zeroes the workspace and (autotuning)
+ * times kernels on buffers of its own, synchronising its private stream: call it outside
+ * timed regions and outside stream capture.  It enqueues nothing on the caller's buffers.
+ * The plan belongs to the device current at create; launch it with that device current.
+ * Launches of one plan must be ordered (one stream, or events): two launches in flight
+ * at once share its workspace.  Launches of different plans are independent.
+ * apm_plan_destroy waits for the device to finish its work before freeing the plan (it
+ * frees device memory).
+ */
+typedef enum {
+    APM_PLAN_MINORS = 0,          /* apm_all_minors(dtype, A, &batch, minors, exp, info, &opts)     */
+    APM_PLAN_CONNECTED_SUMS = 1,  /* apm_connected_sums(m_up, m_dn, &batch, c, cs_mode)            */
+    APM_PLAN_PERM_MINORS = 2,     /* apm_all_perm_minors(A, &batch, perm)                          */
+    APM_PLAN_CDET = 3             /* Sec. V.A: minors of A (and of A_dn), then the connected sums
+                                     c of the weights a[S] = det A[S] det A_dn[S] (A_dn == NULL:
+                                     a = det A[S]^2); the three launches in one graph            */
+} apm_plan_kind;
+
+#define APM_PLAN_AUTOTUNE 1u      /* tune the lane-subtree order of uniform minors before recording */
+#define APM_PLAN_EAGER 2u         /* record no graph; launch enqueues the kernels directly           */
+
+typedef struct {
+    apm_plan_kind kind;
+    apm_dtype dtype;              /* MINORS: any; CDET: APM_R64, or APM_R32S with APM_OUT_F64 in
+                                     opts.flags (the sums take fp64 minors); others: ignored       */
+    apm_batch batch;              /* copied at create; the device arrays it names are not          */
+    const void *A;                /* MINORS, CDET: matrices as for apm_all_minors; PERM: fp64      */
+    const void *A_dn;             /* CDET: second matrix set of the same shapes, or NULL           */
+    void *minors;                 /* MINORS: output as for apm_all_minors; CDET: fp64 minors of A  */
+    void *minors_dn;              /* CDET with A_dn: fp64 minors of A_dn; else NULL                */
+    int16_t *exp;                 /* MINORS: as for apm_all_minors; else NULL                      */
+    int32_t *info;                /* MINORS, CDET: [B] info of A, or NULL                          */
+    int32_t *info_dn;             /* CDET with A_dn: [B] info of A_dn, or NULL                     */
+    const double *m_up;           /* CONNECTED_SUMS: inputs as for apm_connected_sums              */
+    const double *m_dn;
+    double *c;                    /* CONNECTED_SUMS, CDET: output connected sums                   */
+    double *perm;                 /* PERM_MINORS: output                                           */
+    uint32_t cs_mode;             /* CONNECTED_SUMS: as for apm_connected_sums; CDET: APM_CS_ROOTED
+                                     or APM_CS_ALL                                                 */
+    apm_opts opts;                /* MINORS, CDET: options by value ({0, 0} = defaults)            */
+    uint32_t flags;               /* APM_PLAN_AUTOTUNE | APM_PLAN_EAGER                            */
+} apm_plan_desc;
+
+typedef struct apm_plan apm_plan;
+
+/* Create a plan from *d (host pointer).  On success *out receives it (NULL on failure).
+ * Fields a kind does not use must be NULL / 0.  In CDET, batch.in_off indexes A and A_dn
+ * and batch.out_off indexes minors, minors_dn and c.
+ * Must not be called while a stream capture is in progress on this thread (it allocates
+ * and synchronises).
+ * Returns APM_OK, APM_EINVAL (bad or inconsistent description, NULL d or out),
+ * APM_EUNSUPPORTED, APM_ENOMEM or APM_EDEVICE. */
+apm_status apm_plan_create(const apm_plan_desc *d, apm_plan **out);
+
+/* Enqueue the plan's work on `stream`.  Returns APM_OK, APM_EINVAL (NULL plan, another
+ * device current) or APM_EDEVICE. */
+apm_status apm_plan_launch(apm_plan *p, apm_stream stream);
+
+/* Lane-subtree order pinned in a uniform minors or CDET plan (0 for other plans or a
+ * mixed-order batch), and whether the plan holds a graph (1) or launches eagerly (0).
+ * Host-only; -1 for a NULL plan. */
+int32_t apm_plan_k0(const apm_plan *p);
+int32_t apm_plan_graphed(const apm_plan *p);
+
+/* Free the plan, its graph, stream and workspace (NULL is a no-op). */
+void apm_plan_destroy(apm_plan *p);
+
 /* Human-readable name of a status code (static string). */
 const char *apm_status_str(apm_status s);
 
 /* The last HIP error seen by the library on this thread, as a HIP error code (0 = none). */
 int apm_last_hip_error(void);
+
+/* Status form of the same record: APM_OK if the library has seen no HIP failure on this
+ * thread since the previous call of this function, else APM_ENOMEM (an allocation failed)
+ * or APM_EDEVICE; each call clears the record (apm_last_hip_error keeps its value). */
+apm_status apm_last_device_error(void);
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int apm_version(void);

@@ -31,6 +31,8 @@ APM_R64, APM_R32S, APM_C128, APM_C64S = 0, 1, 2, 3
 APM_MAX_N, APM_MAX_N_CS, APM_MAX_N_PERM = 20, 20, 16
 APM_OUT_F64, APM_NO_PERTURB = 1, 2
 APM_CS_ROOTED, APM_CS_ALL, APM_CS_WEIGHTS = 0, 1, 2
+APM_PLAN_MINORS, APM_PLAN_CONNECTED_SUMS, APM_PLAN_PERM_MINORS, APM_PLAN_CDET = 0, 1, 2, 3
+APM_PLAN_AUTOTUNE, APM_PLAN_EAGER = 1, 2
 
 DTYPES = {"r64": APM_R64, "r32s": APM_R32S, "c128": APM_C128, "c64s": APM_C64S}
 
@@ -40,7 +42,8 @@ EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_s
            "apm_mlp_param_count", "apm_mlp_weight_count", "apm_mlp_work_bytes", "apm_mlp_sync",
            "apm_mlp_forward", "apm_mlp_backward", "apm_mlp_adam", "apm_mc_work_bytes", "apm_mc_evaluate",
            "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
-           "apm_minors_k0")
+           "apm_minors_k0", "apm_plan_create", "apm_plan_launch", "apm_plan_k0", "apm_plan_graphed",
+           "apm_plan_destroy", "apm_last_device_error")
 
 APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
@@ -52,6 +55,15 @@ class apm_batch(ctypes.Structure):
 
 class apm_opts(ctypes.Structure):
     _fields_ = [("piv_tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class apm_plan_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("dtype", ctypes.c_int), ("batch", apm_batch), ("A", ctypes.c_void_p),
+                ("A_dn", ctypes.c_void_p), ("minors", ctypes.c_void_p), ("minors_dn", ctypes.c_void_p),
+                ("exp", ctypes.c_void_p), ("info", ctypes.c_void_p), ("info_dn", ctypes.c_void_p),
+                ("m_up", ctypes.c_void_p), ("m_dn", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p), ("cs_mode", ctypes.c_uint32), ("opts", apm_opts),
+                ("flags", ctypes.c_uint32)]
 
 
 class apm_mlp(ctypes.Structure):
@@ -109,6 +121,17 @@ def _load():
     lib.apm_autotune_minors.restype = ctypes.c_int
     lib.apm_minors_k0.argtypes = [ctypes.c_int, i32]
     lib.apm_minors_k0.restype = i32
+    lib.apm_plan_create.argtypes = [ctypes.POINTER(apm_plan_desc), ctypes.POINTER(vp)]
+    lib.apm_plan_create.restype = ctypes.c_int
+    lib.apm_plan_launch.argtypes = [vp, vp]
+    lib.apm_plan_launch.restype = ctypes.c_int
+    lib.apm_plan_k0.argtypes = [vp]
+    lib.apm_plan_k0.restype = i32
+    lib.apm_plan_graphed.argtypes = [vp]
+    lib.apm_plan_graphed.restype = i32
+    lib.apm_plan_destroy.argtypes = [vp]
+    lib.apm_plan_destroy.restype = None
+    lib.apm_last_device_error.restype = ctypes.c_int
     P = ctypes.POINTER
     for name in ("apm_mlp_param_count", "apm_mlp_weight_count"):
         getattr(lib, name).argtypes = [i32, i32]
@@ -163,6 +186,30 @@ def apm_last_hip_error():
 
 def apm_version():
     return _lib.apm_version()
+
+
+def apm_last_device_error():
+    return _lib.apm_last_device_error()
+
+
+def apm_plan_create(desc, out):
+    return _lib.apm_plan_create(ctypes.byref(desc) if desc is not None else None, out)
+
+
+def apm_plan_launch(plan, stream):
+    return _lib.apm_plan_launch(plan, stream)
+
+
+def apm_plan_k0(plan):
+    return _lib.apm_plan_k0(plan)
+
+
+def apm_plan_graphed(plan):
+    return _lib.apm_plan_graphed(plan)
+
+
+def apm_plan_destroy(plan):
+    _lib.apm_plan_destroy(plan)
 
 
 def apm_autotune_minors(dt, n, batch, k0, stream):
@@ -287,6 +334,89 @@ def decode_scaled(m, e):
         s = torch.ldexp(torch.ones_like(e, dtype=torch.float64), e.to(torch.float64))
         return m.to(torch.complex128) * s
     return torch.ldexp(m.to(torch.float64), e.to(torch.float64))
+
+
+class Plan:
+    """An ``apm_plan``: one operation (or the CDet pipeline) bound to fixed device tensors,
+    recorded once into a HIP graph by the library and enqueued by ``launch()``.
+
+    Build one with the ``plan_*`` helpers below; the plan keeps references to every tensor
+    it names, so they stay allocated (their values may change between launches)."""
+
+    def __init__(self, desc, keep, where):
+        self._keep = keep
+        self._h = ctypes.c_void_p()
+        _check(apm_plan_create(desc, ctypes.byref(self._h)), where)
+
+    def launch(self, stream=None):
+        _check(apm_plan_launch(self._h, _stream(stream)), "apm_plan_launch")
+
+    @property
+    def k0(self):
+        return apm_plan_k0(self._h)
+
+    @property
+    def graphed(self):
+        return bool(apm_plan_graphed(self._h))
+
+    def close(self):
+        if self._h:
+            apm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "_h", None):
+            self.close()
+
+
+def _plan_flags(autotune, eager):
+    return (APM_PLAN_AUTOTUNE if autotune else 0) | (APM_PLAN_EAGER if eager else 0)
+
+
+def plan_minors(A, out, dtype="r64", *, exp=None, info=None, out_f64=False, tau=0.0, perturb=True,
+                batch=None, autotune=False, eager=False):
+    """Plan of ``all_minors`` (uniform (B, n, n) ``A``) or, with ``batch`` (an apm_batch
+    from ``make_batch`` whose device arrays the caller keeps), of a mixed-order batch."""
+    bd = batch if batch is not None else make_batch(A.shape[0], A.shape[1])
+    flags = (APM_OUT_F64 if out_f64 else 0) | (0 if perturb else APM_NO_PERTURB)
+    d = apm_plan_desc(kind=APM_PLAN_MINORS, dtype=DTYPES[dtype], batch=bd, A=A.data_ptr(),
+                      minors=out.data_ptr(), exp=None if exp is None else exp.data_ptr(),
+                      info=None if info is None else info.data_ptr(), opts=apm_opts(float(tau), flags),
+                      flags=_plan_flags(autotune, eager))
+    return Plan(d, (A, out, exp, info, bd), "apm_plan_create(minors)")
+
+
+def plan_connected_sums(m_up, c, *, m_dn=None, mode=APM_CS_ROOTED, weights=False, batch=None, eager=False):
+    """Plan of ``connected_sums`` on (B, 2**n) tensors, or on a mixed-order ``batch``."""
+    if batch is None:
+        B, nm = m_up.shape
+        batch = make_batch(B, nm.bit_length() - 1)
+    d = apm_plan_desc(kind=APM_PLAN_CONNECTED_SUMS, batch=batch, m_up=m_up.data_ptr(),
+                      m_dn=None if m_dn is None else m_dn.data_ptr(), c=c.data_ptr(),
+                      cs_mode=mode | (APM_CS_WEIGHTS if weights else 0), flags=_plan_flags(False, eager))
+    return Plan(d, (m_up, m_dn, c, batch), "apm_plan_create(connected sums)")
+
+
+def plan_perm_minors(A, out, *, batch=None, eager=False):
+    """Plan of ``all_perm_minors`` (uniform (B, n, n) ``A``, or a mixed-order ``batch``)."""
+    bd = batch if batch is not None else make_batch(A.shape[0], A.shape[1])
+    d = apm_plan_desc(kind=APM_PLAN_PERM_MINORS, batch=bd, A=A.data_ptr(), perm=out.data_ptr(),
+                      flags=_plan_flags(False, eager))
+    return Plan(d, (A, out, bd), "apm_plan_create(perm minors)")
+
+
+def plan_cdet(A, minors, c, *, A_dn=None, minors_dn=None, info=None, info_dn=None, dtype="r64",
+              mode=APM_CS_ROOTED, tau=0.0, perturb=True, batch=None, autotune=False, eager=False):
+    """Plan of the CDet pipeline of Sec. V.A: the fp64 minors of ``A`` (and ``A_dn``) and the
+    connected sums ``c`` of a = det A[S] det A_dn[S] (a = det A[S]^2 without ``A_dn``)."""
+    bd = batch if batch is not None else make_batch(A.shape[0], A.shape[1])
+    flags = (APM_OUT_F64 if dtype == "r32s" else 0) | (0 if perturb else APM_NO_PERTURB)
+    p = (lambda t: None if t is None else t.data_ptr())
+    d = apm_plan_desc(kind=APM_PLAN_CDET, dtype=DTYPES[dtype], batch=bd, A=A.data_ptr(), A_dn=p(A_dn),
+                      minors=minors.data_ptr(), minors_dn=p(minors_dn), info=p(info), info_dn=p(info_dn),
+                      c=c.data_ptr(), cs_mode=mode, opts=apm_opts(float(tau), flags),
+                      flags=_plan_flags(autotune, eager))
+    return Plan(d, (A, A_dn, minors, minors_dn, info, info_dn, c, bd), "apm_plan_create(cdet)")
 
 
 # ----------------------------------------------------------------- Monte Carlo + proposal network

@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <map>
 #include <mutex>
+#include <new>
 #include <utility>
 #include <vector>
 
@@ -12,11 +13,13 @@
 namespace {
 
 thread_local int g_last_hip_error = 0;
+thread_local int g_unreported_hip_error = 0;   // cleared by apm_last_device_error
 
 apm_status from_hip(hipError_t e)
 {
     if (e == hipSuccess) return APM_OK;
     g_last_hip_error = (int)e;
+    g_unreported_hip_error = (int)e;
     if (e == hipErrorOutOfMemory) return APM_ENOMEM;
     return APM_EDEVICE;
 }
@@ -112,6 +115,96 @@ bool bad_batch(const apm_batch* bd, int nmax)
     return false;
 }
 
+// Argument checks and launch descriptions shared by the direct calls and the plans.  On
+// APM_OK with *noop set the batch is empty and nothing is to be enqueued.
+apm_status minors_args(apm_dtype dt, const void* A, const apm_batch* bd, void* minors, int16_t* exp,
+                       int32_t* info, const apm_opts* opt, apm::LaunchMinors* L, bool* noop)
+{
+    *noop = false;
+    if ((int)dt < 0 || (int)dt > 3) return APM_EINVAL;
+    if (bad_batch(bd, APM_MAX_N)) return APM_EINVAL;
+    const bool scaled = (dt == APM_R32S || dt == APM_C64S);
+    const uint32_t flags = opt ? opt->flags : 0u;
+    if (flags & ~(APM_OUT_F64 | APM_NO_PERTURB)) return APM_EINVAL;
+    const bool out_f64 = (flags & APM_OUT_F64) != 0;
+    if (opt && !isfinite(opt->piv_tol)) return APM_EINVAL;
+    if (bd->n_uniform > APM_MAX_N || bd->n_max > APM_MAX_N) return APM_EUNSUPPORTED;
+    if (bd->batch == 0) {
+        *noop = true;
+        return APM_OK;
+    }
+    if (!A || !minors) return APM_EINVAL;
+    if (scaled && !out_f64 && !exp) return APM_EINVAL;
+    if ((!scaled || out_f64) && exp) return APM_EINVAL;
+    *L = apm::LaunchMinors{};
+    L->dtype = (int)dt;
+    L->A = A;
+    L->out = minors;
+    L->ex = exp;
+    L->info = info;
+    L->batch = bd->batch;
+    L->n_uniform = bd->n_uniform;
+    L->n = bd->n;
+    L->n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N;
+    L->in_off = bd->in_off;
+    L->out_off = bd->out_off;
+    const double tau_def = scaled ? 1e-3 : 1e-4;
+    L->tau = (opt && opt->piv_tol > 0) ? opt->piv_tol : tau_def;
+    L->perturb = !(flags & APM_NO_PERTURB);
+    L->out_f64 = out_f64;
+    return APM_OK;
+}
+
+apm_status cs_args(const double* m_up, const double* m_dn, const apm_batch* bd, double* c, uint32_t mode,
+                   apm::LaunchCS* L, bool* noop)
+{
+    *noop = false;
+    if (bad_batch(bd, APM_MAX_N_CS)) return APM_EINVAL;
+    if (mode & ~(APM_CS_ALL | APM_CS_WEIGHTS)) return APM_EINVAL;
+    if ((mode & APM_CS_WEIGHTS) && m_dn) return APM_EINVAL;
+    if (bd->n_uniform > APM_MAX_N_CS || bd->n_max > APM_MAX_N_CS) return APM_EUNSUPPORTED;
+    if (bd->in_off != bd->out_off) return APM_EINVAL;   // one offset array indexes inputs and output
+    if (bd->batch == 0) {
+        *noop = true;
+        return APM_OK;
+    }
+    if (!m_up || !c) return APM_EINVAL;
+    if (c == m_up || c == m_dn) return APM_EINVAL;      // the output must not alias the inputs
+    *L = apm::LaunchCS{};
+    L->m_up = m_up;
+    L->m_dn = m_dn;
+    L->c = c;
+    L->batch = bd->batch;
+    L->n_uniform = bd->n_uniform;
+    L->n = bd->n;
+    L->n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N_CS;
+    L->off = bd->out_off;
+    L->mode = mode;
+    return APM_OK;
+}
+
+apm_status perm_args(const double* A, const apm_batch* bd, double* perm, apm::LaunchPerm* L, bool* noop)
+{
+    *noop = false;
+    if (bad_batch(bd, APM_MAX_N_PERM)) return APM_EINVAL;
+    if (bd->n_uniform > APM_MAX_N_PERM || bd->n_max > APM_MAX_N_PERM) return APM_EUNSUPPORTED;
+    if (bd->batch == 0) {
+        *noop = true;
+        return APM_OK;
+    }
+    if (!A || !perm) return APM_EINVAL;
+    *L = apm::LaunchPerm{};
+    L->A = A;
+    L->out = perm;
+    L->batch = bd->batch;
+    L->n_uniform = bd->n_uniform;
+    L->n = bd->n;
+    L->n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N_PERM;
+    L->in_off = bd->in_off;
+    L->out_off = bd->out_off;
+    return APM_OK;
+}
+
 // Packed default offsets of a ragged batch given without offset arrays: the queue
 // preparation kernel writes the prefix sums of n_b^2 and 2^n_b into the workspace.
 apm_status packed_offsets(const apm_batch* bd, hipStream_t st, const int64_t** ioff, const int64_t** ooff)
@@ -126,6 +219,182 @@ apm_status packed_offsets(const apm_batch* bd, hipStream_t st, const int64_t** i
     *ioff = L.ioff_ws;
     *ooff = L.ooff_ws;
     return APM_OK;
+}
+
+}  // namespace
+
+// A plan: the launch descriptions of one operation (or of the CDet pipeline) bound to the
+// caller's buffers and to a workspace of its own, recorded once into a graph.
+struct apm_plan {
+    apm_plan_kind kind = APM_PLAN_MINORS;
+    bool noop = false;            // empty batch: launches enqueue nothing
+    bool has_dn = false;          // CDET with a second matrix set
+    bool prep = false;            // CS / PERM on a mixed-order batch without offsets
+    int dev = 0;
+    int k0 = 0;                   // pinned lane-subtree order (uniform minors), else 0
+    apm::LaunchMinors Lm{}, Lm_dn{}, Lprep{};
+    apm::LaunchCS Lc{};
+    apm::LaunchPerm Lp{};
+    void* ws = nullptr;           // counter | order | ioff | ooff | deferred-correction queue
+    size_t ws_bytes = 0;
+    bool dirty = false;           // an eager launch failed after the queue was used
+    hipStream_t ps = nullptr;     // private stream the graph is recorded on
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+};
+
+namespace {
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+hipError_t plan_enqueue(const apm_plan* p, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    switch (p->kind) {
+    case APM_PLAN_MINORS:
+        return apm::fpm_launch(p->Lm, st);
+    case APM_PLAN_CONNECTED_SUMS:
+        if (p->prep) e = apm::fpm_prep_launch(p->Lprep, st);
+        if (e == hipSuccess) e = apm::cs_launch(p->Lc, st);
+        return e;
+    case APM_PLAN_PERM_MINORS:
+        if (p->prep) e = apm::fpm_prep_launch(p->Lprep, st);
+        if (e == hipSuccess) e = apm::perm_launch(p->Lp, st);
+        return e;
+    case APM_PLAN_CDET:
+        e = apm::fpm_launch(p->Lm, st);
+        if (e == hipSuccess && p->has_dn) e = apm::fpm_launch(p->Lm_dn, st);
+        if (e == hipSuccess) e = apm::cs_launch(p->Lc, st);
+        return e;
+    }
+    return hipErrorInvalidValue;
+}
+
+// Checks of a plan description; fills the launch descriptions (without workspace).
+apm_status plan_args(const apm_plan_desc* d, apm_plan* p)
+{
+    const apm_batch* bd = &d->batch;
+    p->kind = d->kind;
+    if (d->flags & ~(APM_PLAN_AUTOTUNE | APM_PLAN_EAGER)) return APM_EINVAL;
+    bool noop = false, noop2 = false;
+    apm_status s = APM_OK;
+    switch (d->kind) {
+    case APM_PLAN_MINORS:
+        if (d->A_dn || d->minors_dn || d->info_dn || d->m_up || d->m_dn || d->c || d->perm || d->cs_mode)
+            return APM_EINVAL;
+        s = minors_args(d->dtype, d->A, bd, d->minors, d->exp, d->info, &d->opts, &p->Lm, &noop);
+        break;
+    case APM_PLAN_CONNECTED_SUMS:
+        if (d->A || d->A_dn || d->minors || d->minors_dn || d->exp || d->info || d->info_dn || d->perm)
+            return APM_EINVAL;
+        s = cs_args(d->m_up, d->m_dn, bd, d->c, d->cs_mode, &p->Lc, &noop);
+        break;
+    case APM_PLAN_PERM_MINORS:
+        if (d->A_dn || d->minors || d->minors_dn || d->exp || d->info || d->info_dn || d->m_up || d->m_dn ||
+            d->c || d->cs_mode)
+            return APM_EINVAL;
+        s = perm_args(static_cast<const double*>(d->A), bd, d->perm, &p->Lp, &noop);
+        break;
+    case APM_PLAN_CDET: {
+        if (d->exp || d->m_up || d->m_dn || d->perm) return APM_EINVAL;
+        const bool f64 = (d->opts.flags & APM_OUT_F64) != 0;
+        if (!(d->dtype == APM_R64 || (d->dtype == APM_R32S && f64))) return APM_EINVAL;
+        if (d->cs_mode & ~APM_CS_ALL) return APM_EINVAL;
+        if ((d->A_dn == nullptr) != (d->minors_dn == nullptr)) return APM_EINVAL;
+        if (!d->A_dn && d->info_dn) return APM_EINVAL;
+        if (d->minors && (d->minors == d->minors_dn || d->minors == (void*)d->c || d->minors_dn == (void*)d->c))
+            return APM_EINVAL;
+        s = minors_args(d->dtype, d->A, bd, d->minors, nullptr, d->info, &d->opts, &p->Lm, &noop);
+        if (s == APM_OK && d->A_dn)
+            s = minors_args(d->dtype, d->A_dn, bd, d->minors_dn, nullptr, d->info_dn, &d->opts, &p->Lm_dn, &noop2);
+        apm_batch cb = *bd;
+        cb.in_off = bd->out_off;
+        if (s == APM_OK)
+            s = cs_args(static_cast<const double*>(d->minors), static_cast<const double*>(d->minors_dn), &cb, d->c,
+                        d->cs_mode, &p->Lc, &noop2);
+        p->has_dn = d->A_dn != nullptr;
+        break;
+    }
+    default:
+        return APM_EINVAL;
+    }
+    if (s != APM_OK) return s;
+    p->noop = noop;
+    return APM_OK;
+}
+
+// Allocates and zeroes the plan's workspace and points the launch descriptions at it.
+apm_status plan_workspace(const apm_plan_desc* d, apm_plan* p)
+{
+    const apm_batch* bd = &d->batch;
+    const int64_t B = bd->batch;
+    const bool ragged = bd->n_uniform == 0;
+    const bool minors = d->kind == APM_PLAN_MINORS || d->kind == APM_PLAN_CDET;
+    p->prep = ragged && ((d->kind == APM_PLAN_CONNECTED_SUMS && !bd->out_off) ||
+                         (d->kind == APM_PLAN_PERM_MINORS && (!bd->in_off || !bd->out_off)));
+    const bool need_ragged = ragged && (minors || p->prep);
+    const bool need_topq = !ragged && minors && B <= INT32_MAX / 2;
+    const size_t o_order = 256, o_ioff = o_order + round256((size_t)B * 4), o_ooff = o_ioff + round256((size_t)B * 8),
+                 o_topq = need_ragged ? o_ooff + round256((size_t)B * 8) : 0;
+    p->ws_bytes = need_topq ? o_topq + (size_t)apm::fpm_topq_bytes(B) : o_topq;
+    if (p->ws_bytes == 0) return APM_OK;
+    hipError_t e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e != hipSuccess) {
+        p->ws = nullptr;
+        return from_hip(e);
+    }
+    e = hipMemsetAsync(p->ws, 0, p->ws_bytes, p->ps);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
+    if (e != hipSuccess) return from_hip(e);
+    char* w = static_cast<char*>(p->ws);
+    int cus = 0;
+    if (need_ragged) {
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->dev);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    auto bind = [&](apm::LaunchMinors& L) {
+        if (need_ragged) {
+            L.counter = reinterpret_cast<int32_t*>(w);
+            L.order = reinterpret_cast<int32_t*>(w + o_order);
+            L.ioff_ws = reinterpret_cast<int64_t*>(w + o_ioff);
+            L.ooff_ws = reinterpret_cast<int64_t*>(w + o_ooff);
+            L.n_workers = cus;
+        }
+        if (need_topq) {
+            L.topq = reinterpret_cast<int32_t*>(w + o_topq);
+            L.topq_cap = (int32_t)B;
+        }
+    };
+    if (minors) {
+        bind(p->Lm);
+        if (p->has_dn) bind(p->Lm_dn);
+        if (d->kind == APM_PLAN_CDET && ragged && !bd->out_off) p->Lc.off = p->Lm.ooff_ws;
+    }
+    if (p->prep) {
+        p->Lprep.batch = bd->batch;
+        p->Lprep.n = bd->n;
+        bind(p->Lprep);
+        if (d->kind == APM_PLAN_CONNECTED_SUMS) {
+            p->Lc.off = p->Lprep.ooff_ws;
+        } else {
+            if (!p->Lp.in_off) p->Lp.in_off = p->Lprep.ioff_ws;
+            if (!p->Lp.out_off) p->Lp.out_off = p->Lprep.ooff_ws;
+        }
+    }
+    return APM_OK;
+}
+
+void plan_free(apm_plan* p)
+{
+    if (!p) return;
+    if (p->ge) (void)hipGraphExecDestroy(p->ge);
+    if (p->g) (void)hipGraphDestroy(p->g);
+    if (p->ps) {
+        (void)hipStreamSynchronize(p->ps);
+        (void)hipStreamDestroy(p->ps);
+    }
+    if (p->ws) (void)hipFree(p->ws);
+    delete p;
 }
 
 }  // namespace
@@ -146,43 +415,26 @@ const char* apm_status_str(apm_status s)
 
 int apm_last_hip_error(void) { return g_last_hip_error; }
 
+apm_status apm_last_device_error(void)
+{
+    const int e = g_unreported_hip_error;
+    g_unreported_hip_error = 0;
+    if (e == 0) return APM_OK;
+    return e == (int)hipErrorOutOfMemory ? APM_ENOMEM : APM_EDEVICE;
+}
+
 int apm_version(void) { return 100; }
 
 apm_status apm_all_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* minors, int16_t* exp,
                           int32_t* info, const apm_opts* opt, apm_stream stream)
 {
-    if ((int)dt < 0 || (int)dt > 3) return APM_EINVAL;
-    if (bad_batch(bd, APM_MAX_N)) return APM_EINVAL;
-    const bool scaled = (dt == APM_R32S || dt == APM_C64S);
-    const uint32_t flags = opt ? opt->flags : 0u;
-    if (flags & ~(APM_OUT_F64 | APM_NO_PERTURB)) return APM_EINVAL;
-    const bool out_f64 = (flags & APM_OUT_F64) != 0;
-    if (opt && !isfinite(opt->piv_tol)) return APM_EINVAL;
-    if (bd->n_uniform > APM_MAX_N || bd->n_max > APM_MAX_N) return APM_EUNSUPPORTED;
-    if (bd->batch == 0) return APM_OK;
-    if (!A || !minors) return APM_EINVAL;
-    if (scaled && !out_f64 && !exp) return APM_EINVAL;
-    if ((!scaled || out_f64) && exp) return APM_EINVAL;
-
     apm::LaunchMinors L{};
-    L.dtype = (int)dt;
-    L.A = A;
-    L.out = minors;
-    L.ex = exp;
-    L.info = info;
-    L.batch = bd->batch;
-    L.n_uniform = bd->n_uniform;
-    L.n = bd->n;
-    L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N;
-    L.in_off = bd->in_off;
-    L.out_off = bd->out_off;
-    const double tau_def = scaled ? 1e-3 : 1e-4;
-    L.tau = (opt && opt->piv_tol > 0) ? opt->piv_tol : tau_def;
-    L.perturb = !(flags & APM_NO_PERTURB);
-    L.out_f64 = out_f64;
+    bool noop = false;
+    apm_status s = minors_args(dt, A, bd, minors, exp, info, opt, &L, &noop);
+    if (s != APM_OK || noop) return s;
     TopQueue* tq = nullptr;
     if (bd->n_uniform == 0) {
-        apm_status s = get_workspace(bd->batch, &L.counter, &L.order, &L.ioff_ws, &L.ooff_ws, &L.n_workers);
+        s = get_workspace(bd->batch, &L.counter, &L.order, &L.ioff_ws, &L.ooff_ws, &L.n_workers);
         if (s != APM_OK) return s;
     } else if (bd->batch <= INT32_MAX / 2) {
         L.topq = get_topq((hipStream_t)stream, bd->batch, &L.topq_cap, &tq);
@@ -275,27 +527,13 @@ apm_status apm_autotune_minors(apm_dtype dt, int32_t n, int32_t batch, int32_t* 
 apm_status apm_connected_sums(const double* m_up, const double* m_dn, const apm_batch* bd, double* c,
                               uint32_t mode, apm_stream stream)
 {
-    if (bad_batch(bd, APM_MAX_N_CS)) return APM_EINVAL;
-    if (mode & ~(APM_CS_ALL | APM_CS_WEIGHTS)) return APM_EINVAL;
-    if ((mode & APM_CS_WEIGHTS) && m_dn) return APM_EINVAL;
-    if (bd->n_uniform > APM_MAX_N_CS || bd->n_max > APM_MAX_N_CS) return APM_EUNSUPPORTED;
-    if (bd->in_off != bd->out_off) return APM_EINVAL;   // one offset array indexes inputs and output
-    if (bd->batch == 0) return APM_OK;
-    if (!m_up || !c) return APM_EINVAL;
-    if (c == m_up || c == m_dn) return APM_EINVAL;      // the output must not alias the inputs
     apm::LaunchCS L{};
-    L.m_up = m_up;
-    L.m_dn = m_dn;
-    L.c = c;
-    L.batch = bd->batch;
-    L.n_uniform = bd->n_uniform;
-    L.n = bd->n;
-    L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N_CS;
-    L.off = bd->out_off;
-    L.mode = mode;
+    bool noop = false;
+    apm_status s = cs_args(m_up, m_dn, bd, c, mode, &L, &noop);
+    if (s != APM_OK || noop) return s;
     if (bd->n_uniform == 0 && !L.off) {
         const int64_t* ioff = nullptr;
-        apm_status s = packed_offsets(bd, (hipStream_t)stream, &ioff, &L.off);
+        s = packed_offsets(bd, (hipStream_t)stream, &ioff, &L.off);
         if (s != APM_OK) return s;
     }
     return from_hip(apm::cs_launch(L, (hipStream_t)stream));
@@ -303,27 +541,109 @@ apm_status apm_connected_sums(const double* m_up, const double* m_dn, const apm_
 
 apm_status apm_all_perm_minors(const double* A, const apm_batch* bd, double* perm, apm_stream stream)
 {
-    if (bad_batch(bd, APM_MAX_N_PERM)) return APM_EINVAL;
-    if (bd->n_uniform > APM_MAX_N_PERM || bd->n_max > APM_MAX_N_PERM) return APM_EUNSUPPORTED;
-    if (bd->batch == 0) return APM_OK;
-    if (!A || !perm) return APM_EINVAL;
     apm::LaunchPerm L{};
-    L.A = A;
-    L.out = perm;
-    L.batch = bd->batch;
-    L.n_uniform = bd->n_uniform;
-    L.n = bd->n;
-    L.n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N_PERM;
-    L.in_off = bd->in_off;
-    L.out_off = bd->out_off;
+    bool noop = false;
+    apm_status s = perm_args(A, bd, perm, &L, &noop);
+    if (s != APM_OK || noop) return s;
     if (bd->n_uniform == 0 && (!L.in_off || !L.out_off)) {
         const int64_t *ioff = nullptr, *ooff = nullptr;
-        apm_status s = packed_offsets(bd, (hipStream_t)stream, &ioff, &ooff);
+        s = packed_offsets(bd, (hipStream_t)stream, &ioff, &ooff);
         if (s != APM_OK) return s;
         if (!L.in_off) L.in_off = ioff;
         if (!L.out_off) L.out_off = ooff;
     }
     return from_hip(apm::perm_launch(L, (hipStream_t)stream));
 }
+
+apm_status apm_plan_create(const apm_plan_desc* d, apm_plan** out)
+{
+    if (!out) return APM_EINVAL;
+    *out = nullptr;
+    if (!d) return APM_EINVAL;
+    apm_plan* p = new (std::nothrow) apm_plan();
+    if (!p) return APM_ENOMEM;
+    apm_status s = plan_args(d, p);
+    hipError_t e = hipSuccess;
+    if (s == APM_OK && !p->noop) {
+        e = hipGetDevice(&p->dev);
+        if (e != hipSuccess) s = from_hip(e);
+    }
+    if (s == APM_OK && !p->noop) {
+        e = hipStreamCreateWithFlags(&p->ps, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            p->ps = nullptr;
+            s = from_hip(e);
+        }
+    }
+    if (s == APM_OK && !p->noop) s = plan_workspace(d, p);
+    const bool uniform_minors = (d->kind == APM_PLAN_MINORS || d->kind == APM_PLAN_CDET) && d->batch.n_uniform > 0;
+    if (s == APM_OK && !p->noop && uniform_minors) {
+        const int n = d->batch.n_uniform;
+        if ((d->flags & APM_PLAN_AUTOTUNE) && apm::tuned_k0((int)d->dtype, n) <= 0 && !getenv("APM_K0")) {
+            // the synthetic tuning batch: the plan's size, at most 8192 matrices and 2 GiB of output
+            int32_t tb = d->batch.batch < 8192 ? d->batch.batch : 8192;
+            while (tb > 256 && ((int64_t)tb << n) * 16 > ((int64_t)1 << 31)) tb /= 2;
+            s = apm_autotune_minors(d->dtype, n, tb, nullptr, p->ps);
+        }
+        if (s == APM_OK) {
+            p->k0 = apm_minors_k0(d->dtype, n);
+            p->Lm.force_k0 = p->k0;
+            p->Lm_dn.force_k0 = p->k0;
+        }
+    }
+    if (s == APM_OK && !p->noop && !(d->flags & APM_PLAN_EAGER)) {
+        e = hipStreamBeginCapture(p->ps, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t e_rec = plan_enqueue(p, p->ps);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(p->ps, &g);
+            p->g = g;
+            if (e == hipSuccess) e = e_rec;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->ge, p->g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            p->ge = nullptr;
+            s = from_hip(e);
+        }
+    }
+    if (s != APM_OK) {
+        plan_free(p);
+        return s;
+    }
+    *out = p;
+    return APM_OK;
+}
+
+apm_status apm_plan_launch(apm_plan* p, apm_stream stream)
+{
+    if (!p) return APM_EINVAL;
+    if (p->noop) return APM_OK;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e);
+    if (dev != p->dev) return APM_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    if (p->ge) return from_hip(hipGraphLaunch(p->ge, st));
+    if (p->dirty) {
+        // a failed eager launch may have left deferred corrections queued: clear them
+        // (outside capture only; an eager plan is not recorded while in this state)
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        e = hipStreamIsCapturing(st, &cs);
+        if (e != hipSuccess) return from_hip(e);
+        if (cs != hipStreamCaptureStatusNone) return APM_EINVAL;
+        e = hipMemsetAsync(p->ws, 0, p->ws_bytes, st);
+        if (e != hipSuccess) return from_hip(e);
+        p->dirty = false;
+    }
+    e = plan_enqueue(p, st);
+    if (e != hipSuccess) p->dirty = true;
+    return from_hip(e);
+}
+
+int32_t apm_plan_k0(const apm_plan* p) { return p ? p->k0 : -1; }
+
+int32_t apm_plan_graphed(const apm_plan* p) { return p ? (p->ge != nullptr ? 1 : 0) : -1; }
+
+void apm_plan_destroy(apm_plan* p) { plan_free(p); }
 
 }  // extern "C"

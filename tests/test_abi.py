@@ -20,7 +20,7 @@ def _declared():
     for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
         if h.endswith(".h"):
             src = open(os.path.join(ROOT, "include", h)).read()
-            names |= set(re.findall(r"^\s*(?:apm_status|const char|int|int32_t|int64_t)\s*\*?\s*(apm_\w+)\s*\(", src,
+            names |= set(re.findall(r"^\s*(?:apm_status|const char|int|int32_t|int64_t|void)\s*\*?\s*(apm_\w+)\s*\(", src,
                                     re.M))
     return sorted(names)
 
@@ -137,3 +137,67 @@ def test_autotune_validation(apm):
     assert apm.apm_autotune_minors(0, 10, 0, None, None) == apm.APM_EINVAL
     assert apm.apm_minors_k0(0, 16) in (3, 4, 5) and apm.apm_minors_k0(2, 14) in (2, 3)
     assert apm.apm_minors_k0(0, 0) == -1 and apm.apm_minors_k0(5, 8) == -1
+
+
+def _plan(apm, **kw):
+    d = apm.apm_plan_desc(**kw)
+    h = ctypes.c_void_p()
+    rc = apm.apm_plan_create(d, ctypes.byref(h))
+    if rc != apm.APM_OK:
+        assert not h.value       # no plan handed out on failure
+    return rc, h
+
+
+def test_plan_validation(apm):
+    K = apm
+    h = ctypes.c_void_p()
+    assert apm.apm_plan_create(None, ctypes.byref(h)) == apm.APM_EINVAL
+    assert apm._lib.apm_plan_create(ctypes.byref(apm.apm_plan_desc()), None) == apm.APM_EINVAL
+    assert apm.apm_plan_launch(None, None) == apm.APM_EINVAL
+    assert apm.apm_plan_k0(None) == -1 and apm.apm_plan_graphed(None) == -1
+    apm.apm_plan_destroy(None)
+    bd = _bd(apm)
+    assert _plan(apm, kind=9, batch=bd, A=P, minors=P)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_MINORS, batch=bd, A=P, minors=P, flags=8)[0] == K.APM_EINVAL
+    # the checks of the direct call apply
+    assert _plan(apm, kind=K.APM_PLAN_MINORS, batch=bd, A=None, minors=P)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_MINORS, batch=_bd(apm, n=21), A=P, minors=P)[0] == K.APM_EUNSUPPORTED
+    assert _plan(apm, kind=K.APM_PLAN_MINORS, dtype=1, batch=bd, A=P, minors=P)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_PERM_MINORS, batch=_bd(apm, n=17), A=P, perm=P)[0] == K.APM_EUNSUPPORTED
+    assert _plan(apm, kind=K.APM_PLAN_CONNECTED_SUMS, batch=bd, m_up=P, c=P)[0] == K.APM_EINVAL   # aliasing
+    assert _plan(apm, kind=K.APM_PLAN_CONNECTED_SUMS, batch=_bd(apm, ioff=P), m_up=P,
+                 c=ctypes.c_void_p(32))[0] == K.APM_EINVAL                                      # two offsets
+    # fields another kind uses must be empty
+    assert _plan(apm, kind=K.APM_PLAN_MINORS, batch=bd, A=P, minors=P, c=P)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_PERM_MINORS, batch=bd, A=P, perm=P, minors=P)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_CONNECTED_SUMS, batch=bd, m_up=P, c=ctypes.c_void_p(32),
+                 A=P)[0] == K.APM_EINVAL
+    # CDet: fp64 minors only (r64, or r32s with fp64 output), consistent second set, no aliasing
+    q, r, t = ctypes.c_void_p(32), ctypes.c_void_p(48), ctypes.c_void_p(64)
+    assert _plan(apm, kind=K.APM_PLAN_CDET, dtype=2, batch=bd, A=P, minors=q, c=r)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_CDET, dtype=1, batch=bd, A=P, minors=q, c=r)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_CDET, batch=bd, A=P, A_dn=P, minors=q, c=r)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_CDET, batch=bd, A=P, minors=q, minors_dn=t, c=r)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_CDET, batch=bd, A=P, minors=q, c=q)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_CDET, batch=bd, A=P, A_dn=P, minors=q, minors_dn=q, c=r)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_CDET, batch=bd, A=P, minors=q, c=r, cs_mode=2)[0] == K.APM_EINVAL
+    assert _plan(apm, kind=K.APM_PLAN_CDET, batch=bd, A=P, minors=q, c=r, info_dn=t)[0] == K.APM_EINVAL
+    # an empty batch gives a plan whose launches enqueue nothing (no device needed)
+    rc, h = _plan(apm, kind=K.APM_PLAN_CDET, batch=_bd(apm, batch=0), A=P, minors=q, c=r)
+    assert rc == K.APM_OK and h.value
+    assert apm.apm_plan_launch(h, None) == K.APM_OK
+    assert apm.apm_plan_k0(h) == 0 and apm.apm_plan_graphed(h) == 0
+    apm.apm_plan_destroy(h)
+
+
+def test_device_error_record(apm):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("needs a host without a GPU to force a HIP failure")
+    apm.apm_last_device_error()                       # clear
+    assert apm.apm_last_device_error() == apm.APM_OK
+    rc, h = _plan(apm, kind=apm.APM_PLAN_MINORS, batch=_bd(apm), A=P, minors=ctypes.c_void_p(32))
+    assert rc == apm.APM_EDEVICE                      # no device: the plan cannot be made
+    assert apm.apm_last_device_error() == apm.APM_EDEVICE
+    assert apm.apm_last_device_error() == apm.APM_OK  # cleared by the read
+    assert apm.apm_last_hip_error() != 0              # the HIP code stays
