@@ -258,7 +258,8 @@ def run_extra(torch, apm, W, np, steps):
 
     # the whole pipeline (queue preparation, persistent minors launch, connected sums) as
     # one CDet plan: recorded once into a HIP graph by the library, one launch per step
-    plan = apm.plan_cdet(flat, mm, cc, batch=bd)
+    # (matrices packed in `flat`, minors and sums at the offsets `ooff`)
+    plan = apm.plan_cdet(flat, mm, cc, n=n_t, n_max=16, out_off=ooff)
     ms_g = time_fn(torch, plan.launch, max(2, steps // 4))
     plan.close()
     fma = float(np.sum(3.0 ** (ns.astype(np.float64) - 1)))

@@ -373,50 +373,66 @@ def _plan_flags(autotune, eager):
     return (APM_PLAN_AUTOTUNE if autotune else 0) | (APM_PLAN_EAGER if eager else 0)
 
 
+def _plan_batch(A, n, n_max, in_off, out_off):
+    """Uniform batch from the (B, n, n) shape of A, or a mixed-order one from device int32
+    orders ``n`` (matrices packed by default, ``in_off`` / ``out_off`` int64 offsets)."""
+    if n is None:
+        if in_off is not None or out_off is not None:
+            raise ValueError("offsets are taken with per-matrix orders n only")
+        return make_batch(A.shape[0], A.shape[1])
+    return make_batch(n.numel(), 0, n, n_max, in_off, out_off)
+
+
 def plan_minors(A, out, dtype="r64", *, exp=None, info=None, out_f64=False, tau=0.0, perturb=True,
-                batch=None, autotune=False, eager=False):
-    """Plan of ``all_minors`` (uniform (B, n, n) ``A``) or, with ``batch`` (an apm_batch
-    from ``make_batch`` whose device arrays the caller keeps), of a mixed-order batch."""
-    bd = batch if batch is not None else make_batch(A.shape[0], A.shape[1])
+                n=None, n_max=0, in_off=None, out_off=None, autotune=False, eager=False):
+    """Plan of ``all_minors`` (uniform (B, n, n) ``A``) or of a mixed-order batch (orders
+    ``n``, matrices in the flat ``A``)."""
+    bd = _plan_batch(A, n, n_max, in_off, out_off)
     flags = (APM_OUT_F64 if out_f64 else 0) | (0 if perturb else APM_NO_PERTURB)
     d = apm_plan_desc(kind=APM_PLAN_MINORS, dtype=DTYPES[dtype], batch=bd, A=A.data_ptr(),
                       minors=out.data_ptr(), exp=None if exp is None else exp.data_ptr(),
                       info=None if info is None else info.data_ptr(), opts=apm_opts(float(tau), flags),
                       flags=_plan_flags(autotune, eager))
-    return Plan(d, (A, out, exp, info, bd), "apm_plan_create(minors)")
+    return Plan(d, (A, out, exp, info, n, in_off, out_off), "apm_plan_create(minors)")
 
 
-def plan_connected_sums(m_up, c, *, m_dn=None, mode=APM_CS_ROOTED, weights=False, batch=None, eager=False):
-    """Plan of ``connected_sums`` on (B, 2**n) tensors, or on a mixed-order ``batch``."""
-    if batch is None:
+def plan_connected_sums(m_up, c, *, m_dn=None, mode=APM_CS_ROOTED, weights=False, n=None, n_max=0, off=None,
+                        eager=False):
+    """Plan of ``connected_sums`` on (B, 2**n) tensors, or on a mixed-order batch (orders
+    ``n``; ``off`` indexes the inputs and the output, packed by default)."""
+    if n is None:
         B, nm = m_up.shape
-        batch = make_batch(B, nm.bit_length() - 1)
-    d = apm_plan_desc(kind=APM_PLAN_CONNECTED_SUMS, batch=batch, m_up=m_up.data_ptr(),
+        bd = make_batch(B, nm.bit_length() - 1)
+    else:
+        bd = make_batch(n.numel(), 0, n, n_max, off, off)
+    d = apm_plan_desc(kind=APM_PLAN_CONNECTED_SUMS, batch=bd, m_up=m_up.data_ptr(),
                       m_dn=None if m_dn is None else m_dn.data_ptr(), c=c.data_ptr(),
                       cs_mode=mode | (APM_CS_WEIGHTS if weights else 0), flags=_plan_flags(False, eager))
-    return Plan(d, (m_up, m_dn, c, batch), "apm_plan_create(connected sums)")
+    return Plan(d, (m_up, m_dn, c, n, off), "apm_plan_create(connected sums)")
 
 
-def plan_perm_minors(A, out, *, batch=None, eager=False):
-    """Plan of ``all_perm_minors`` (uniform (B, n, n) ``A``, or a mixed-order ``batch``)."""
-    bd = batch if batch is not None else make_batch(A.shape[0], A.shape[1])
+def plan_perm_minors(A, out, *, n=None, n_max=0, in_off=None, out_off=None, eager=False):
+    """Plan of ``all_perm_minors`` (uniform (B, n, n) ``A``, or a mixed-order batch)."""
+    bd = _plan_batch(A, n, n_max, in_off, out_off)
     d = apm_plan_desc(kind=APM_PLAN_PERM_MINORS, batch=bd, A=A.data_ptr(), perm=out.data_ptr(),
                       flags=_plan_flags(False, eager))
-    return Plan(d, (A, out, bd), "apm_plan_create(perm minors)")
+    return Plan(d, (A, out, n, in_off, out_off), "apm_plan_create(perm minors)")
 
 
 def plan_cdet(A, minors, c, *, A_dn=None, minors_dn=None, info=None, info_dn=None, dtype="r64",
-              mode=APM_CS_ROOTED, tau=0.0, perturb=True, batch=None, autotune=False, eager=False):
+              mode=APM_CS_ROOTED, tau=0.0, perturb=True, n=None, n_max=0, in_off=None, out_off=None,
+              autotune=False, eager=False):
     """Plan of the CDet pipeline of Sec. V.A: the fp64 minors of ``A`` (and ``A_dn``) and the
-    connected sums ``c`` of a = det A[S] det A_dn[S] (a = det A[S]^2 without ``A_dn``)."""
-    bd = batch if batch is not None else make_batch(A.shape[0], A.shape[1])
+    connected sums ``c`` of a = det A[S] det A_dn[S] (a = det A[S]^2 without ``A_dn``).
+    Mixed orders: ``in_off`` indexes the matrices, ``out_off`` the minors and the sums."""
+    bd = _plan_batch(A, n, n_max, in_off, out_off)
     flags = (APM_OUT_F64 if dtype == "r32s" else 0) | (0 if perturb else APM_NO_PERTURB)
     p = (lambda t: None if t is None else t.data_ptr())
     d = apm_plan_desc(kind=APM_PLAN_CDET, dtype=DTYPES[dtype], batch=bd, A=A.data_ptr(), A_dn=p(A_dn),
                       minors=minors.data_ptr(), minors_dn=p(minors_dn), info=p(info), info_dn=p(info_dn),
                       c=c.data_ptr(), cs_mode=mode, opts=apm_opts(float(tau), flags),
                       flags=_plan_flags(autotune, eager))
-    return Plan(d, (A, A_dn, minors, minors_dn, info, info_dn, c, bd), "apm_plan_create(cdet)")
+    return Plan(d, (A, A_dn, minors, minors_dn, info, info_dn, c, n, in_off, out_off), "apm_plan_create(cdet)")
 
 
 # ----------------------------------------------------------------- Monte Carlo + proposal network

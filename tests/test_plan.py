@@ -120,8 +120,7 @@ def test_plan_minors_ragged(apm, oracle_mod):
     A = torch.empty_like(flat)
     out = torch.empty(tot, dtype=torch.float64, device="cuda")
     info = torch.empty(700, dtype=torch.int32, device="cuda")
-    bd = apm.make_batch(700, 0, n_t, 16)
-    plan = apm.plan_minors(A, out, "r64", info=info, batch=bd)
+    plan = apm.plan_minors(A, out, "r64", info=info, n=n_t, n_max=16)
     ref = torch.empty_like(out)
     for r in range(3):
         A.copy_(flat * (1.0 + r))
@@ -168,7 +167,7 @@ def test_plan_connected_sums_ragged_packed(apm):
     apm.all_minors_ragged(flat, n_t, 14, "r64", out=m)
     c = torch.empty_like(m)
     bd = apm.make_batch(300, 0, n_t, 14)
-    plan = apm.plan_connected_sums(m, c, batch=bd)
+    plan = apm.plan_connected_sums(m, c, n=n_t, n_max=14)
     plan.launch()
     ref = torch.empty_like(m)
     assert apm.apm_connected_sums(apm._ptr(m), None, bd, apm._ptr(ref), apm.APM_CS_ROOTED, apm._stream(None)) == 0
@@ -202,7 +201,7 @@ def test_plan_perm_minors(apm, oracle_mod):
     bd = apm.make_batch(200, 0, n_t, 13)
     o2 = torch.empty(tot, dtype=torch.float64, device="cuda")
     r2 = torch.empty_like(o2)
-    plan2 = apm.plan_perm_minors(flat, o2, batch=bd)
+    plan2 = apm.plan_perm_minors(flat, o2, n=n_t, n_max=13)
     plan2.launch()
     assert apm.apm_all_perm_minors(apm._ptr(flat), bd, apm._ptr(r2), apm._stream(None)) == 0
     torch.cuda.synchronize()
@@ -240,7 +239,7 @@ def test_plan_cdet_ragged_and_r32s(apm):
     mm = torch.empty(tot, dtype=torch.float64, device="cuda")
     c = torch.empty_like(mm)
     bd = apm.make_batch(500, 0, n_t, 16)
-    plan = apm.plan_cdet(flat, mm, c, batch=bd)
+    plan = apm.plan_cdet(flat, mm, c, n=n_t, n_max=16)
     plan.launch()
     plan.launch()
     m_ref = torch.empty_like(mm)
@@ -250,6 +249,21 @@ def test_plan_cdet_ragged_and_r32s(apm):
                                   apm._stream(None)) == 0
     torch.cuda.synchronize()
     assert same(mm, m_ref) and same(c, c_ref)
+    # explicit output offsets with gaps between the matrices (matrices still packed)
+    sizes = np.left_shift(1, ns.astype(np.int64))
+    oo_np = np.concatenate([[0], np.cumsum(sizes + 8)[:-1]]).astype(np.int64)
+    oo = torch.from_numpy(oo_np).cuda()
+    tot2 = int(oo_np[-1] + sizes[-1])
+    m2 = torch.full((tot2,), 5.0, dtype=torch.float64, device="cuda")
+    c2 = torch.full_like(m2, 5.0)
+    plan2 = apm.plan_cdet(flat, m2, c2, n=n_t, n_max=16, out_off=oo)
+    plan2.launch()
+    torch.cuda.synchronize()
+    for b in range(0, 500, 37):
+        seg2 = slice(int(oo_np[b]), int(oo_np[b] + sizes[b]))
+        seg = slice(int(sizes[:b].sum()), int(sizes[:b + 1].sum()))
+        assert same(m2[seg2], m_ref[seg]) and same(c2[seg2], c_ref[seg]), b
+    assert torch.all(m2[int(oo_np[1]) - 8:int(oo_np[1])] == 5.0)        # gaps untouched
     # fp32-scaled minors with fp64 output feeding the sums
     A = lattice_t(128, 13, 102)
     m32 = torch.empty((128, 1 << 13), dtype=torch.float64, device="cuda")
