@@ -55,12 +55,29 @@ __device__ __forceinline__ uint32_t pdep_u32(uint32_t k, uint32_t mask)
     return r;
 }
 
-// Element X1 of an LDS block with rows of 2^LB values, pairs swizzled by row.
-template <int LB>
+// LDS block layouts.  The c' and b blocks, read row by row by many lanes at once, have rows
+// padded to 2^LB + 2 values: row r starts 16 bytes further round the banks than row r-1, and
+// each 16-byte pair of a row sits at a fixed offset from the row start (an immediate of the
+// load).  The right-hand-side block (one reader per row) keeps unpadded rows with the pairs
+// swizzled by row (pair slot p XOR (row mod W/2)).
+#ifndef APM_CS_PAD
+#define APM_CS_PAD 1
+#endif
+constexpr bool kPad = APM_CS_PAD != 0;
+
+// doubles of a block of 2^P values with rows of 2^LB values
+template <int P, int LB, bool PAD>
+constexpr int block_len() { return (PAD && LB >= 2) ? (1 << P) + (2 << (P - LB)) : (1 << P); }
+
+// Element X1 of an LDS block.
+template <int LB, bool PAD>
 __device__ __forceinline__ int sw(int x1)
 {
     if constexpr (LB <= 1) {
         return x1;
+    } else if constexpr (PAD) {
+        constexpr int W = 1 << LB;
+        return (x1 >> LB) * (W + 2) + (x1 & (W - 1));
     } else {
         constexpr int W = 1 << LB;
         constexpr int pm = (W >> 1) - 1;
@@ -69,24 +86,26 @@ __device__ __forceinline__ int sw(int x1)
     }
 }
 
-// Byte address of the swizzled pair p of a row: the row starts at row * 8W bytes, a multiple
-// of the 16-byte pair slots it spans, so the pair's slot (p ^ (row & pm)) is the row's
-// address with bits 4.. XORed by p: one XOR per load.
-template <int LB>
+// Byte address of a row.  Swizzled rows start at row * 8W bytes, a multiple of the 16-byte
+// pair slots they span, so the slot (p ^ (row & pm)) of pair p is the row's address with
+// bits 4.. XORed by p: one XOR per load.
+template <int LB, bool PAD>
 __device__ __forceinline__ uint32_t row_addr(int row)
 {
     constexpr int W = 1 << LB;
     constexpr int pm = (W >> 1) - 1;
+    if constexpr (PAD) return __umul24((uint32_t)row, 8u * (W + 2));
     return (uint32_t)row * (8u * W) + ((uint32_t)(row & pm) << 4);
 }
 
-template <int LB>
+template <int LB, bool PAD>
 __device__ __forceinline__ double2 ld_pair(const double* buf, uint32_t a, int p)
 {
+    if constexpr (PAD) return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(buf) + a + (p << 4));
     return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(buf) + (a ^ ((uint32_t)p << 4)));
 }
 
-template <int LB>
+template <int LB, bool PAD>
 __device__ __forceinline__ void load_row(const double* buf, int row, double (&v)[1 << LB])
 {
     constexpr int W = 1 << LB;
@@ -94,10 +113,10 @@ __device__ __forceinline__ void load_row(const double* buf, int row, double (&v)
 #pragma unroll
         for (int i = 0; i < W; ++i) v[i] = buf[row * W + i];
     } else {
-        const uint32_t a = row_addr<LB>(row);
+        const uint32_t a = row_addr<LB, PAD>(row);
 #pragma unroll
         for (int p = 0; p < W / 2; ++p) {
-            const double2 t = ld_pair<LB>(buf, a, p);
+            const double2 t = ld_pair<LB, PAD>(buf, a, p);
             v[2 * p] = t.x;
             v[2 * p + 1] = t.y;
         }
@@ -136,10 +155,10 @@ template <int LB>
 __device__ __forceinline__ void load_half(const double* buf, int row, int half, double (&v)[1 << (LB - 1)])
 {
     constexpr int W = 1 << LB;
-    const uint32_t a = row_addr<LB>(row);
+    const uint32_t a = row_addr<LB, kPad>(row);
 #pragma unroll
     for (int p = 0; p < W / 4; ++p) {
-        const double2 t = ld_pair<LB>(buf, a, p + half * (W / 4));
+        const double2 t = ld_pair<LB, kPad>(buf, a, p + half * (W / 4));
         v[2 * p] = t.x;
         v[2 * p + 1] = t.y;
     }
@@ -255,7 +274,7 @@ struct CsPlan {
 // One rank pass over the rows of a block: TRI (rows of rank r of block X2, pairs
 // Yh subsetneq Xh, then the in-row triangular solve) or CONV (pairs Yh subset of Xh,
 // result subtracted from the right-hand side in the output).
-template <int LB>
+template <int LB, bool PAD>
 __device__ __forceinline__ void store_row(double* buf, int row, const double (&v)[1 << LB])
 {
     constexpr int W = 1 << LB;
@@ -263,10 +282,10 @@ __device__ __forceinline__ void store_row(double* buf, int row, const double (&v
 #pragma unroll
         for (int i = 0; i < W; ++i) buf[row * W + i] = v[i];
     } else {
-        const uint32_t a = row_addr<LB>(row);
+        const uint32_t a = row_addr<LB, PAD>(row);
 #pragma unroll
         for (int p = 0; p < W / 2; ++p)
-            *reinterpret_cast<double2*>(reinterpret_cast<char*>(buf) + (a ^ ((uint32_t)p << 4))) =
+            *reinterpret_cast<double2*>(reinterpret_cast<char*>(buf) + (PAD ? a + (p << 4) : (a ^ ((uint32_t)p << 4)))) =
                 make_double2(v[2 * p], v[2 * p + 1]);
     }
 }
@@ -309,8 +328,8 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
                     conv_rows_split<LB>(cb, (int)yh, bb, (int)(xh ^ yh), acc);
                 } else {
                     double f[W], gg[W];
-                    load_row<LB>(cb, (int)yh, f);
-                    load_row<LB>(bb, (int)(xh ^ yh), gg);
+                    load_row<LB, kPad>(cb, (int)yh, f);
+                    load_row<LB, kPad>(bb, (int)(xh ^ yh), gg);
                     conv_tile<LB>(f, gg, acc);
                 }
             }
@@ -319,16 +338,16 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
         group_sum<W>(acc, G);
         if (valid && s == G - 1) {
             double rr[W];
-            load_row<LB>(rb, (int)xh, rr);
+            load_row<LB, false>(rb, (int)xh, rr);
 #pragma unroll
             for (int i = 0; i < W; ++i) rr[i] += acc[i];
             if constexpr (TRI) {
                 double g0[W];
-                load_row<LB>(bb, 0, g0);
+                load_row<LB, kPad>(bb, 0, g0);
                 tri_tile<LB>(rr, g0);
-                store_row<LB>(cb_out, (int)xh, rr);
+                store_row<LB, kPad>(cb_out, (int)xh, rr);
             } else {
-                store_row<LB>(rb, (int)xh, rr);
+                store_row<LB, false>(rb, (int)xh, rr);
             }
         }
     }
@@ -397,8 +416,8 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                 w0 = u.x * u.x;
                 w1 = u.y * u.y;
             }
-            lds_b[sw<LB>(x1)] = x1 ? w0 : 0.0;
-            lds_r[sw<LB>(x1)] = w1;
+            lds_b[sw<LB, kPad>(x1)] = x1 ? w0 : 0.0;
+            lds_r[sw<LB, false>(x1)] = w1;
         }
     }
     for (int x2 = 0; x2 < (1 << CP::TB); ++x2) {
@@ -406,7 +425,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
         if (!pair_stage) {
             for (int x1 = tid; x1 < (1 << P); x1 += NT) {
                 const int64_t x = ((int64_t)x2 << P) | x1;
-                lds_r[sw<LB>(x1)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
+                lds_r[sw<LB, false>(x1)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
             }
         }
         // cross-block contributions: every Y2 subsetneq X2
@@ -415,8 +434,8 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
             const uint32_t d2 = (uint32_t)x2 ^ y2;
             __syncthreads();
             for (int x1 = tid; x1 < (1 << P); x1 += NT) {
-                lds_c[sw<LB>(x1)] = c[sroot + ((((int64_t)y2 << P) | x1) << jsh)];
-                lds_b[sw<LB>(x1)] = weight(g, base, (((int64_t)d2 << P) | x1) << jsh);
+                lds_c[sw<LB, kPad>(x1)] = c[sroot + ((((int64_t)y2 << P) | x1) << jsh)];
+                lds_b[sw<LB, kPad>(x1)] = weight(g, base, (((int64_t)d2 << P) | x1) << jsh);
             }
             __syncthreads();
             for (int r = 0; r <= H; ++r) rank_pass<M, false>(r, rk_tab, rk_off, lds_c, lds_b, lds_r, nullptr);
@@ -425,7 +444,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
         __syncthreads();
         if (!pair_stage) {
             for (int x1 = tid; x1 < (1 << P); x1 += NT)
-                lds_b[sw<LB>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
+                lds_b[sw<LB, kPad>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
             __syncthreads();
         }
         for (int r = 0; r <= H; ++r) {
@@ -438,7 +457,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                 // d[V] = |a[V]| + sum_{X full-exclusive} |c'[X]| |b[full \ X]|, with a[V] = a0[full]
                 constexpr int full = (1 << P) - 1;
                 double part = 0.0;
-                for (int x1 = tid; x1 < full; x1 += NT) part += fabs(lds_c[sw<LB>(x1)]) * fabs(lds_b[sw<LB>(full ^ x1)]);
+                for (int x1 = tid; x1 < full; x1 += NT) part += fabs(lds_c[sw<LB, kPad>(x1)]) * fabs(lds_b[sw<LB, kPad>(full ^ x1)]);
                 for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
                 if constexpr (NT > kWave) {
                     __syncthreads();
@@ -448,8 +467,8 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                     for (int w = 0; w < NT / kWave; ++w) part += lds_b[w];
                 }
                 if (tid == 0) {
-                    g.summ[0] = lds_c[sw<LB>(full)];
-                    g.summ[1] = fabs(lds_r[sw<LB>(full)]) + part;
+                    g.summ[0] = lds_c[sw<LB, kPad>(full)];
+                    g.summ[1] = fabs(lds_r[sw<LB, false>(full)]) + part;
                 }
                 return;
             }
@@ -459,12 +478,12 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
             for (int x1 = tid; x1 < (1 << P); x1 += NT) {
                 const int64_t x = ((int64_t)x2 << P) | x1;
                 *reinterpret_cast<double2*>(c + base + 2 * x) = make_double2(0.0,
-                                                                             lds_c[sw<LB>(x1)]);
+                                                                             lds_c[sw<LB, kPad>(x1)]);
             }
         } else {
             for (int x1 = tid; x1 < (1 << P); x1 += NT) {
                 const int64_t x = ((int64_t)x2 << P) | x1;
-                c[sroot + (x << jsh)] = lds_c[sw<LB>(x1)];
+                c[sroot + (x << jsh)] = lds_c[sw<LB, kPad>(x1)];
                 if (zero_even) c[base + 2 * x] = 0.0;
             }
         }
@@ -476,9 +495,10 @@ template <int M>
 __global__ __launch_bounds__(cs_threads<M>()) void cs_kernel(CsArgs g, int32_t batch, int n_uniform,
                                                              const int32_t* nv, const int64_t* off, int roots)
 {
-    __shared__ __align__(16) double lds_c[1 << CsPlan<M>::P];
-    __shared__ __align__(16) double lds_b[1 << CsPlan<M>::P];
-    __shared__ __align__(16) double lds_r[1 << CsPlan<M>::P];
+    using CP = CsPlan<M>;
+    __shared__ __align__(16) double lds_c[block_len<CP::P, CP::LB, kPad>()];
+    __shared__ __align__(16) double lds_b[block_len<CP::P, CP::LB, kPad>()];
+    __shared__ __align__(16) double lds_r[block_len<CP::P, CP::LB, false>()];
     __shared__ uint16_t rk_tab[1 << CsPlan<M>::H];
     __shared__ int rk_off[CsPlan<M>::H + 2];
     const int b = blockIdx.x / roots;
