@@ -260,6 +260,12 @@ __device__ __forceinline__ double weight(const CsArgs& g, int64_t base, int64_t 
 #ifndef APM_CS_GMUL
 #define APM_CS_GMUL 2
 #endif
+#ifndef APM_CS_GMUL_TRI
+#define APM_CS_GMUL_TRI 2
+#endif
+#ifndef APM_CS_SCHED
+#define APM_CS_SCHED 1
+#endif
 
 template <int M>
 struct CsPlan {
@@ -293,63 +299,121 @@ __device__ __forceinline__ void store_row(double* buf, int row, const double (&v
 // One rank pass over the rows Xh of rank r of a block: TRI (pairs Yh subsetneq Xh, then
 // the in-row triangular solve; the finished row goes to cb_out) or CONV (pairs Yh subset
 // of Xh).  Either way the result updates the right-hand-side row in rb.
-template <int M, bool TRI>
-__device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const int* rk_off, const double* cb,
+// One row group: lane s of the G lanes of row Xh takes the pairs s, s + G, ... of the row
+// (Yh subsetneq Xh for TRI, Yh subset of Xh for CONV); the partial rows are summed over the
+// group and the last lane updates the right-hand-side row in rb (TRI: then solves the row
+// in place and writes it to cb_out).  Every lane of the wavefront calls it with the same G.
+template <int M, bool TRI, int GC = 0>
+__device__ __forceinline__ void row_group(bool valid, uint32_t xh, int items, int G, int s, const double* cb,
                                           const double* bb, double* rb, double* cb_out)
 {
     using CP = CsPlan<M>;
     constexpr int LB = CP::LB, W = 1 << LB;
+    if constexpr (GC > 0) G = GC;
+    double acc[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) acc[i] = 0.0;
+    if (valid) {
+        // pair k = s + G t has Yh = pdep(s) | pdep(t) over the bits of Xh above its lowest
+        // log2(G) ones: the second part steps through the subsets of those bits in order
+        const uint32_t ys = pdep_u32((uint32_t)s, xh);
+        uint32_t xhi = xh;
+        for (int gg = 1; gg < G; gg <<= 1) xhi &= xhi - 1u;
+        uint32_t z = 0;
+        for (int k = s; k < items; k += G, z = (z - xhi) & xhi) {
+            const uint32_t yh = ys | z;
+            if constexpr (LB >= 3) {
+                conv_rows_split<LB>(cb, (int)yh, bb, (int)(xh ^ yh), acc);
+            } else {
+                double f[W], gg[W];
+                load_row<LB, kPad>(cb, (int)yh, f);
+                load_row<LB, kPad>(bb, (int)(xh ^ yh), gg);
+                conv_tile<LB>(f, gg, acc);
+            }
+        }
+    }
+    // sum the G partial rows (consecutive lanes of one wavefront) into the last lane
+    group_sum<W>(acc, G);
+    if (valid && s == G - 1) {
+        double rr[W];
+        load_row<LB, false>(rb, (int)xh, rr);
+#pragma unroll
+        for (int i = 0; i < W; ++i) rr[i] += acc[i];
+        if constexpr (TRI) {
+            double g0[W];
+            load_row<LB, kPad>(bb, 0, g0);
+            tri_tile<LB>(rr, g0);
+            store_row<LB, kPad>(cb_out, (int)xh, rr);
+        } else {
+            store_row<LB, false>(rb, (int)xh, rr);
+        }
+    }
+}
+
+// One rank pass over the rows Xh of rank r of a block, G lanes per row (G the largest power
+// of two with nout G GMUL <= threads, G <= 64 and G <= the pairs of a row).
+template <int M, bool TRI>
+__device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const int* rk_off, const double* cb,
+                                          const double* bb, double* rb, double* cb_out)
+{
     constexpr int NT = cs_threads<M>();
     const int tid = threadIdx.x;
     const int nout = rk_off[r + 1] - rk_off[r];
     const int items = TRI ? (1 << r) - 1 : (1 << r);
     int G = 1;
-    constexpr int GMUL = NT == kWave ? APM_CS_GMUL_SMALL : APM_CS_GMUL;
+    constexpr int GMUL = NT == kWave ? APM_CS_GMUL_SMALL : (TRI ? APM_CS_GMUL_TRI : APM_CS_GMUL);
     while (G * 2 <= kWave && nout * G * GMUL <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
     const int per_pass = NT / G;
     for (int ob = 0; ob < nout; ob += per_pass) {
         const int o = ob + tid / G;
-        const int s = tid % G;
         const bool valid = o < nout;
-        const uint32_t xh = valid ? rk_tab[rk_off[r] + o] : 0u;
-        double acc[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i) acc[i] = 0.0;
-        if (valid) {
-            // pair k = s + G t has Yh = pdep(s) | pdep(t) over the bits of Xh above its lowest
-            // log2(G) ones: the second part steps through the subsets of those bits in order
-            const uint32_t ys = pdep_u32((uint32_t)s, xh);
-            uint32_t xhi = xh;
-            for (int gg = 1; gg < G; gg <<= 1) xhi &= xhi - 1u;
-            uint32_t z = 0;
-            for (int k = s; k < items; k += G, z = (z - xhi) & xhi) {
-                const uint32_t yh = ys | z;
-                if constexpr (LB >= 3) {
-                    conv_rows_split<LB>(cb, (int)yh, bb, (int)(xh ^ yh), acc);
-                } else {
-                    double f[W], gg[W];
-                    load_row<LB, kPad>(cb, (int)yh, f);
-                    load_row<LB, kPad>(bb, (int)(xh ^ yh), gg);
-                    conv_tile<LB>(f, gg, acc);
-                }
-            }
+        row_group<M, TRI>(valid, valid ? rk_tab[rk_off[r] + o] : 0u, items, G, tid % G, cb, bb, rb, cb_out);
+    }
+}
+
+// CONV of a block with 7 row bits on four wavefronts: the rows are independent, so the
+// ranks need no order and each wavefront takes a fixed share of them.  A wave task is G
+// lanes per row over one or two rank segments (rank, first row, rows); the shares below
+// minimise the largest per-wavefront cost over every choice of G per rank (cost per task:
+// 120 per pair step of a lane, 48 per summation level, 120 for the row update and set-up):
+//   wave 0: rank 5, G = 2 (42 lanes, 16 steps)
+//   wave 1: rank 4, G = 1 (35 lanes, 16 steps)
+//   wave 2: rank 6, G = 8 (56 lanes, 8 steps); ranks 2 and 0, G = 1 (22 lanes, 4 steps)
+//   wave 3: ranks 3 and 1, G = 1 (42 lanes, 8 steps); rank 7, G = 64 (2 steps)
+template <int M, int G>
+__device__ __forceinline__ void conv_task(int lane, int r1, int k1, int r2, int k2, const uint16_t* rk_tab,
+                                          const int* rk_off, const double* cb, const double* bb, double* rb)
+{
+    const int q = lane / G;
+    const bool in1 = q < k1, in2 = !in1 && q < k1 + k2;
+    const int r = in1 ? r1 : r2;
+    const int o = in1 ? q : q - k1;
+    const bool valid = in1 || in2;
+    const uint32_t xh = valid ? rk_tab[rk_off[r] + o] : 0u;
+    row_group<M, false, G>(valid, xh, 1 << r, G, lane % G, cb, bb, rb, nullptr);
+}
+
+template <int M>
+__device__ __forceinline__ void conv_block(const uint16_t* rk_tab, const int* rk_off, const double* cb,
+                                           const double* bb, double* rb)
+{
+    constexpr int H = CsPlan<M>::H;
+    if constexpr (H == 7 && cs_threads<M>() == 4 * kWave && APM_CS_SCHED) {
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+        const int lane = (int)(threadIdx.x % kWave);
+        if (wave == 0) {
+            conv_task<M, 2>(lane, 5, 21, 0, 0, rk_tab, rk_off, cb, bb, rb);
+        } else if (wave == 1) {
+            conv_task<M, 1>(lane, 4, 35, 0, 0, rk_tab, rk_off, cb, bb, rb);
+        } else if (wave == 2) {
+            conv_task<M, 8>(lane, 6, 7, 0, 0, rk_tab, rk_off, cb, bb, rb);
+            conv_task<M, 1>(lane, 2, 21, 0, 1, rk_tab, rk_off, cb, bb, rb);
+        } else {
+            conv_task<M, 1>(lane, 3, 35, 1, 7, rk_tab, rk_off, cb, bb, rb);
+            conv_task<M, 64>(lane, 7, 1, 0, 0, rk_tab, rk_off, cb, bb, rb);
         }
-        // sum the G partial rows (consecutive lanes of one wavefront) into the last lane
-        group_sum<W>(acc, G);
-        if (valid && s == G - 1) {
-            double rr[W];
-            load_row<LB, false>(rb, (int)xh, rr);
-#pragma unroll
-            for (int i = 0; i < W; ++i) rr[i] += acc[i];
-            if constexpr (TRI) {
-                double g0[W];
-                load_row<LB, kPad>(bb, 0, g0);
-                tri_tile<LB>(rr, g0);
-                store_row<LB, kPad>(cb_out, (int)xh, rr);
-            } else {
-                store_row<LB, false>(rb, (int)xh, rr);
-            }
-        }
+    } else {
+        for (int r = 0; r <= H; ++r) rank_pass<M, false>(r, rk_tab, rk_off, cb, bb, rb, nullptr);
     }
 }
 
@@ -438,7 +502,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                 lds_b[sw<LB, kPad>(x1)] = weight(g, base, (((int64_t)d2 << P) | x1) << jsh);
             }
             __syncthreads();
-            for (int r = 0; r <= H; ++r) rank_pass<M, false>(r, rk_tab, rk_off, lds_c, lds_b, lds_r, nullptr);
+            conv_block<M>(rk_tab, rk_off, lds_c, lds_b, lds_r);
         }
         // the block's own triangular solve, with b of block 0
         __syncthreads();
