@@ -11,18 +11,19 @@
 // a triangular subset convolution of 3^m multiply-adds.  Rooted mode solves (*) for j = 0;
 // "all" mode solves it for every j (independent problems, one workgroup each).
 //
-// Blocking (one 256-thread workgroup per problem):
+// Blocking (one workgroup per problem: one wavefront up to 10 bits, four above):
 //   * X = (X2, X1): X1 = the low P = min(m, 11) bits, X2 = the rest.  Blocks of 2^P values
-//     are staged in LDS (c' block, b block and the right-hand side, 16 KiB each).  Block X2 needs every block
-//     Y2 subsetneq X2 (a full subset convolution of two blocks, "conv") and then the
+//     are staged in LDS (c' block, b block and the right-hand side).  Block X2 needs every
+//     block Y2 subsetneq X2 (a full subset convolution of two blocks, "conv") and then the
 //     triangular solve (*) restricted to the block ("tri") with the b block of X2 = 0.
-//     The running right-hand side a0 - sum(conv) lives in the output array.
-//   * inside a block, X1 = (Xh, Xl) with Xl the low LB = min(P, 5) bits held in registers:
-//     one (Xh, Yh) pair is a 5-bit subset convolution of two 32-value rows, 243 FMAs for
-//     64 LDS loads.  Rows Xh are processed rank by rank (|Xh|); the 2^|Xh| pairs of a row
-//     are split over G lanes of one wavefront and summed with DPP row shifts.
-//   * LDS rows are swizzled per 16-byte pair so that lanes reading different rows at the
-//     same column spread over the banks.
+//   * inside a block, X1 = (Xh, Xl) with Xl the low LB bits held in registers (LB = 4, or
+//     3 for problems of at most 9 bits): one (Xh, Yh) pair is an LB-bit subset convolution
+//     of two rows of 2^LB values (81 FMAs for 32 loaded values at LB = 4).  The 2^|Xh|
+//     pairs of a row are split over G lanes of one wavefront and summed with DPP row
+//     shifts.  tri takes the rows rank by rank (|Xh|); conv rows are independent and
+//     follow a fixed balanced schedule over the four wavefronts.
+//   * the c' and b blocks have padded rows (see the layouts below), so that lanes reading
+//     different rows at the same column spread over the LDS banks.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -249,7 +250,7 @@ __device__ __forceinline__ double weight(const CsArgs& g, int64_t base, int64_t 
 }
 
 #ifndef APM_CS_LB_SMALL
-#define APM_CS_LB_SMALL 4
+#define APM_CS_LB_SMALL 3     // problems of at most 9 bits
 #endif
 #ifndef APM_CS_LB_LARGE
 #define APM_CS_LB_LARGE 4
@@ -271,7 +272,7 @@ template <int M>
 struct CsPlan {
     static constexpr int P = M < kPmax ? M : kPmax;     // block bits
     static constexpr int TB = M - P;                    // block-index bits
-    static constexpr int LBW = M <= 10 ? APM_CS_LB_SMALL : APM_CS_LB_LARGE;
+    static constexpr int LBW = M <= 9 ? APM_CS_LB_SMALL : APM_CS_LB_LARGE;
     static constexpr int LB = P < LBW ? P : LBW;        // register tile bits
     static constexpr int H = P - LB;                    // row bits inside a block
     static constexpr int ROWS = 1 << H;
