@@ -304,7 +304,7 @@ __device__ __forceinline__ void store_row(double* buf, int row, const double (&v
 // (Yh subsetneq Xh for TRI, Yh subset of Xh for CONV); the partial rows are summed over the
 // group and the last lane updates the right-hand-side row in rb (TRI: then solves the row
 // in place and writes it to cb_out).  Every lane of the wavefront calls it with the same G.
-template <int M, bool TRI, int GC = 0>
+template <int M, bool TRI, int GC = 0, bool RPAD = false>
 __device__ __forceinline__ void row_group(bool valid, uint32_t xh, int items, int G, int s, const double* cb,
                                           const double* bb, double* rb, double* cb_out)
 {
@@ -337,7 +337,7 @@ __device__ __forceinline__ void row_group(bool valid, uint32_t xh, int items, in
     group_sum<W>(acc, G);
     if (valid && s == G - 1) {
         double rr[W];
-        load_row<LB, false>(rb, (int)xh, rr);
+        load_row<LB, RPAD>(rb, (int)xh, rr);
 #pragma unroll
         for (int i = 0; i < W; ++i) rr[i] += acc[i];
         if constexpr (TRI) {
@@ -346,14 +346,14 @@ __device__ __forceinline__ void row_group(bool valid, uint32_t xh, int items, in
             tri_tile<LB>(rr, g0);
             store_row<LB, kPad>(cb_out, (int)xh, rr);
         } else {
-            store_row<LB, false>(rb, (int)xh, rr);
+            store_row<LB, RPAD>(rb, (int)xh, rr);
         }
     }
 }
 
 // One rank pass over the rows Xh of rank r of a block, G lanes per row (G the largest power
 // of two with nout G GMUL <= threads, G <= 64 and G <= the pairs of a row).
-template <int M, bool TRI>
+template <int M, bool TRI, bool RPAD = false>
 __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const int* rk_off, const double* cb,
                                           const double* bb, double* rb, double* cb_out)
 {
@@ -368,7 +368,8 @@ __device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const i
     for (int ob = 0; ob < nout; ob += per_pass) {
         const int o = ob + tid / G;
         const bool valid = o < nout;
-        row_group<M, TRI>(valid, valid ? rk_tab[rk_off[r] + o] : 0u, items, G, tid % G, cb, bb, rb, cb_out);
+        row_group<M, TRI, 0, RPAD>(valid, valid ? rk_tab[rk_off[r] + o] : 0u, items, G, tid % G, cb, bb, rb,
+                                   cb_out);
     }
 }
 
@@ -458,6 +459,12 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
     const int jsh = j + 1;                          // X -> S = (1 << j) | (X << (j+1))
     const int64_t sroot = base + (int64_t(1) << j);  // element index of S = {j}
     double* c = g.c;
+    // right-hand side: its own block when there are cross-block terms; otherwise the c'
+    // block itself (row Xh is read as right-hand side and overwritten by its solution in
+    // the pass of its rank, after every row it depends on)
+    constexpr bool kInPlace = CP::TB == 0;
+    constexpr bool kRPad = kInPlace ? kPad : false;
+    double* rhs = kInPlace ? lds_c : lds_r;
 
     static_assert(H < 8, "rank tables cover rows of up to 7 bits");
     for (int i = tid; i < (1 << H); i += NT) rk_tab[i] = kRank.tab[H][i];
@@ -482,7 +489,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                 w1 = u.y * u.y;
             }
             lds_b[sw<LB, kPad>(x1)] = x1 ? w0 : 0.0;
-            lds_r[sw<LB, false>(x1)] = w1;
+            rhs[sw<LB, kRPad>(x1)] = w1;
         }
     }
     for (int x2 = 0; x2 < (1 << CP::TB); ++x2) {
@@ -490,7 +497,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
         if (!pair_stage) {
             for (int x1 = tid; x1 < (1 << P); x1 += NT) {
                 const int64_t x = ((int64_t)x2 << P) | x1;
-                lds_r[sw<LB, false>(x1)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
+                rhs[sw<LB, kRPad>(x1)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
             }
         }
         // cross-block contributions: every Y2 subsetneq X2
@@ -503,7 +510,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                 lds_b[sw<LB, kPad>(x1)] = weight(g, base, (((int64_t)d2 << P) | x1) << jsh);
             }
             __syncthreads();
-            conv_block<M>(rk_tab, rk_off, lds_c, lds_b, lds_r);
+            conv_block<M>(rk_tab, rk_off, lds_c, lds_b, rhs);
         }
         // the block's own triangular solve, with b of block 0
         __syncthreads();
@@ -512,8 +519,10 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                 lds_b[sw<LB, kPad>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
             __syncthreads();
         }
+        // a[V] for the summary (the in-place solve overwrites it)
+        const double a_full = (CP::TB == 0 && g.summ) ? rhs[sw<LB, kRPad>((1 << P) - 1)] : 0.0;
         for (int r = 0; r <= H; ++r) {
-            rank_pass<M, true>(r, rk_tab, rk_off, lds_c, lds_b, lds_r, lds_c);
+            rank_pass<M, true, kRPad>(r, rk_tab, rk_off, lds_c, lds_b, rhs, lds_c);
             __syncthreads();
         }
         if constexpr (CP::TB == 0) {
@@ -533,7 +542,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                 }
                 if (tid == 0) {
                     g.summ[0] = lds_c[sw<LB, kPad>(full)];
-                    g.summ[1] = fabs(lds_r[sw<LB, false>(full)]) + part;
+                    g.summ[1] = fabs(a_full) + part;
                 }
                 return;
             }
@@ -563,7 +572,8 @@ __global__ __launch_bounds__(cs_threads<M>()) void cs_kernel(CsArgs g, int32_t b
     using CP = CsPlan<M>;
     __shared__ __align__(16) double lds_c[block_len<CP::P, CP::LB, kPad>()];
     __shared__ __align__(16) double lds_b[block_len<CP::P, CP::LB, kPad>()];
-    __shared__ __align__(16) double lds_r[block_len<CP::P, CP::LB, false>()];
+    // problems of one block solve in place in the c' block: no separate right-hand side
+    __shared__ __align__(16) double lds_r[CP::TB == 0 ? 2 : block_len<CP::P, CP::LB, false>()];
     __shared__ uint16_t rk_tab[1 << CsPlan<M>::H];
     __shared__ int rk_off[CsPlan<M>::H + 2];
     const int b = blockIdx.x / roots;
