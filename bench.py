@@ -76,9 +76,12 @@ class Timer:
         self.e1.record()
         self.pairs.append((self.e0, self.e1))
 
-    def avg_ms(self):
+    def times_ms(self):
         self.torch.cuda.synchronize()
-        v = [a.elapsed_time(b) for a, b in self.pairs]
+        return [a.elapsed_time(b) for a, b in self.pairs]
+
+    def avg_ms(self):
+        v = self.times_ms()
         return sum(v) / len(v)
 
 
@@ -155,6 +158,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kern_ms = kt.avg_ms()
+    per_launch = sorted(kt.times_ms())
     value = B * args.steps / elapsed
     ms_per_step = elapsed * 1e3 / args.steps
     infos = info.cpu().numpy()
@@ -171,7 +175,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": f"fpm_uniform_kernel<FR64,{n},5>", "bytes_per_launch": bytes_per_matrix * B,
-                "kernel_ms": round(kern_ms, 4)}
+                "kernel_ms": round(kern_ms, 4), "kernel_ms_median": round(per_launch[len(per_launch) // 2], 4),
+                "kernel_ms_min": round(per_launch[0], 4)}
 
     # ---- fp32-scaled variant on the same batch (mantissa + int16 exponent output)
     out32 = torch.empty((B, 1 << n), dtype=torch.float32, device="cuda")
