@@ -14,6 +14,8 @@ bit k <-> row/column k, out[0] = det of the empty matrix = 1):
 * ``connected_sums(a, mode)`` -- Sec. V.A, Eq. (recursion), direct O(3^n) loop.
 * ``perm_minors(A)``       -- Sec. IV: Ryser's formula per subset, with the
                               (-1)^|S| factor the printed Eq. (ryser) drops.
+* ``xor_minors(A)``        -- Sec. III, XOR case: det of every one-row-per-block
+                              choice of a 2n x 2n block matrix, all leading depths.
 * ``g0``-independent: the oracle consumes host matrices built by ``workloads``.
 """
 from __future__ import annotations
@@ -74,6 +76,10 @@ def load_library(path: str):
     lib.apm_oracle_perm_minors_masks.restype = ctypes.c_int
     lib.apm_oracle_cs_scale.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int]
     lib.apm_oracle_cs_scale.restype = ctypes.c_int
+    for name in ("apm_oracle_xor_minors_r64", "apm_oracle_xor_minors_c128"):
+        fn = getattr(lib, name)
+        fn.argtypes = [ctypes.c_int, dp, dp]
+        fn.restype = ctypes.c_int
     return lib
 
 
@@ -158,6 +164,34 @@ def minors_complex(A, nthreads: int = 0, lib=None) -> np.ndarray:
                                              int(nthreads))
     if rc != 0:
         raise ValueError("oracle: bad matrix order")
+    return out[0] if single else out
+
+
+def xor_minors(A, lib=None) -> np.ndarray:
+    """XOR principal minors of 2n x 2n matrices of 2 x 2 blocks (Sec. III, XOR case).
+
+    For depth k = 1..n and every k-bit choice word alpha (bit i: row/column 2i + alpha_i
+    of block i kept), entry 2^k - 2 + alpha is det A[R, R], R = {2i + alpha_i : i < k};
+    the order-n minors are the last 2^n entries.  Real or complex input of shape
+    (B, 2n, 2n) or (2n, 2n); returns (B, 2^(n+1) - 2) (or one row)."""
+    A = np.asarray(A)
+    single = A.ndim == 2
+    if single:
+        A = A[None]
+    cplx = np.iscomplexobj(A)
+    A = np.ascontiguousarray(A, dtype=np.complex128 if cplx else np.float64)
+    B, w, _ = A.shape
+    if w % 2:
+        raise ValueError("xor_minors: the order must be even (2 x 2 blocks)")
+    n = w // 2
+    out = np.empty((B, (1 << (n + 1)) - 2), dtype=A.dtype)
+    L = _load(lib)
+    fn = L.apm_oracle_xor_minors_c128 if cplx else L.apm_oracle_xor_minors_r64
+    for b in range(B):
+        src = A[b].view(np.float64) if cplx else A[b]
+        dst = out[b].view(np.float64) if cplx else out[b]
+        if fn(n, _dp(src), _dp(dst)) != 0:
+            raise ValueError("oracle: bad matrix order")
     return out[0] if single else out
 
 

@@ -321,6 +321,72 @@ int apm_oracle_perm_minors_masks(int n, const double *A, int count, const uint32
 /* Matrix b has order n[b]; its input starts at element in_off[b] of A (for the
  * complex kernels: complex element, i.e. 2 doubles each) and its 2^n[b]
  * outputs start at element out_off[b] of out.  Returns 0, or -1 on a bad n. */
+/* XOR principal minors of a 2n x 2n matrix read as n x n blocks of 2 x 2 (Sec. III, the
+ * XOR case): the principal minors that keep exactly one of the rows/columns 2i, 2i+1 of
+ * every block i.  Besides the order-n ones, every leading choice is listed: for depth
+ * k = 1..n and every k-bit choice word alpha (bit i: row 2i + alpha_i of block i is kept),
+ *     out[2^k - 2 + alpha] = det A[R, R],   R = {2i + alpha_i : i < k},
+ * so the 2^n full-order minors are the last 2^n of the 2^(n+1) - 2 entries.  With the
+ * Keldysh block matrix of Sec. V.C these are the determinants of the branch assignments.
+ * Each determinant is a separate partial-pivoting LU of the gathered k x k matrix. */
+static void xor_rows(int k, uint32_t alpha, int *idx)
+{
+    for (int i = 0; i < k; ++i) {
+#if ORACLE_PLANT == 7
+        idx[i] = 2 * i + 1 - (int)(alpha >> i & 1u);
+#else
+        idx[i] = 2 * i + (int)(alpha >> i & 1u);
+#endif
+    }
+}
+
+static int64_t xor_index(int k, uint32_t alpha) { return ((int64_t)1 << k) - 2 + alpha; }
+
+/* column of the gathered matrix for kept row index r of block i */
+static int xor_col(int r)
+{
+#if ORACLE_PLANT == 8
+    return r ^ 1;
+#else
+    return r;
+#endif
+}
+
+int apm_oracle_xor_minors_r64(int n, const double *A, double *out)
+{
+    if (n < 1 || 2 * n > ORACLE_MAX_N) return -1;
+    const int w = 2 * n;
+    double sub[ORACLE_MAX_N * ORACLE_MAX_N];
+    int idx[ORACLE_MAX_N];
+    for (int k = 1; k <= n; ++k)
+        for (uint32_t alpha = 0; alpha < (1u << k); ++alpha) {
+            xor_rows(k, alpha, idx);
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) sub[a * k + b] = A[idx[a] * w + xor_col(idx[b])];
+            out[xor_index(k, alpha)] = det_real_inplace(k, sub);
+        }
+    return 0;
+}
+
+int apm_oracle_xor_minors_c128(int n, const double *A, double *out)
+{
+    if (n < 1 || 2 * n > ORACLE_MAX_N) return -1;
+    const int w = 2 * n;
+    double sub[2 * ORACLE_MAX_N * ORACLE_MAX_N];
+    int idx[ORACLE_MAX_N];
+    for (int k = 1; k <= n; ++k)
+        for (uint32_t alpha = 0; alpha < (1u << k); ++alpha) {
+            xor_rows(k, alpha, idx);
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) {
+                    sub[2 * (a * k + b)]     = A[2 * (idx[a] * w + xor_col(idx[b]))];
+                    sub[2 * (a * k + b) + 1] = A[2 * (idx[a] * w + xor_col(idx[b])) + 1];
+                }
+            det_cplx_inplace(k, sub, &out[2 * xor_index(k, alpha)]);
+        }
+    return 0;
+}
+
 typedef int (*oracle_fn)(int, const double *, double *);
 
 static int run_batch(oracle_fn fn, int width, int B, const int32_t *n, const int64_t *in_off,

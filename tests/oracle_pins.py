@@ -421,3 +421,90 @@ def pin_perm_invariances(perm):
 
 PERM_PINS = [pin_perm_all_ones, pin_perm_diagonal, pin_perm_bruteforce, pin_perm_I_plus_A,
              pin_perm_invariances]
+
+
+# ----------------------------------------------------------------------------------
+# XOR minors of 2n x 2n block matrices (Sec. III, XOR case; Sec. V.C)
+# ----------------------------------------------------------------------------------
+def _xor_depth(out, k):
+    return out[(1 << k) - 2:(1 << (k + 1)) - 2]
+
+
+def _xor_rows(k, alpha):
+    return [2 * i + (alpha >> i & 1) for i in range(k)]
+
+
+def pin_xor_leibniz(xor):
+    """Every entry against the permutation-sum determinant of its rows/columns."""
+    rng = _rng(71)
+    for n in (1, 2, 3):
+        for cplx in (False, True):
+            A = rng.standard_normal((2 * n, 2 * n))
+            if cplx:
+                A = A + 1j * rng.standard_normal((2 * n, 2 * n))
+            out = xor(A)
+            for k in range(1, n + 1):
+                seg = _xor_depth(out, k)
+                for alpha in range(1 << k):
+                    r = _xor_rows(k, alpha)
+                    ref = leibniz_det(A[np.ix_(r, r)])
+                    assert abs(seg[alpha] - ref) <= 1e-12 * max(1.0, abs(ref)), (n, k, alpha)
+
+
+def pin_xor_block_diagonal(xor):
+    """Zero blocks off the diagonal: each minor is the product of the kept diagonal entries."""
+    rng = _rng(72)
+    n = 6
+    A = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    for i in range(n):
+        A[2 * i:2 * i + 2, 2 * i:2 * i + 2] = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    out = xor(A)
+    d = np.diag(A)
+    for k in range(1, n + 1):
+        seg = _xor_depth(out, k)
+        ref = np.array([np.prod([d[r] for r in _xor_rows(k, a)]) for a in range(1 << k)])
+        assert close(seg, ref, 1e-13, 1e-15), k
+
+
+def pin_xor_branch_swap(xor):
+    """Swapping the two rows/columns of every block maps choice alpha to its complement."""
+    rng = _rng(73)
+    n = 5
+    A = rng.standard_normal((2 * n, 2 * n)) + 1j * rng.standard_normal((2 * n, 2 * n))
+    perm = np.arange(2 * n) ^ 1
+    out, out_s = xor(A), xor(A[np.ix_(perm, perm)])
+    for k in range(1, n + 1):
+        full = (1 << k) - 1
+        seg, seg_s = _xor_depth(out, k), _xor_depth(out_s, k)
+        assert close(seg_s, seg[np.arange(1 << k) ^ full], 1e-12, 1e-14), k
+
+
+def pin_xor_largest_time(xor):
+    """Keldysh block matrices: the row and column of the latest vertex do not depend on its
+    branch, so the branch-signed sum of the determinants vanishes at every depth, while
+    the unsigned sum does not."""
+    from workloads import keldysh_block
+    for b, A in enumerate(keldysh_block(3, 6, seed=74)):
+        out = xor(A)
+        for k in range(1, 7):
+            seg = _xor_depth(out, k)
+            sgn = np.array([(-1) ** bin(a).count("1") for a in range(1 << k)])
+            scale = np.abs(seg).sum()
+            assert scale > 0
+            assert abs(np.dot(sgn, seg)) <= 1e-13 * scale, (b, k)
+            assert abs(seg.sum()) > 1e-6 * scale or k == 1, (b, k)
+
+
+def pin_xor_lapack(xor):
+    """Order 5, every depth, against LAPACK's determinant of the gathered matrix."""
+    rng = _rng(75)
+    n = 5
+    A = rng.standard_normal((2 * n, 2 * n)) + 1j * rng.standard_normal((2 * n, 2 * n))
+    out = xor(A)
+    for k in range(1, n + 1):
+        seg = _xor_depth(out, k)
+        ref = np.array([np.linalg.det(A[np.ix_(_xor_rows(k, a), _xor_rows(k, a))]) for a in range(1 << k)])
+        assert close(seg, ref, 1e-12, 1e-13), k
+
+
+XOR_PINS = [pin_xor_leibniz, pin_xor_block_diagonal, pin_xor_branch_swap, pin_xor_largest_time, pin_xor_lapack]

@@ -25,6 +25,11 @@ def test_perm_pins(oracle_mod, pin):
     pin(oracle_mod.perm_minors)
 
 
+@pytest.mark.parametrize("pin", P.XOR_PINS, ids=lambda f: f.__name__)
+def test_xor_minor_pins(oracle_mod, pin):
+    pin(oracle_mod.xor_minors)
+
+
 @pytest.mark.parametrize("pin", P.PERM_PINS, ids=lambda f: f.__name__)
 def test_perm_masks_pins(oracle_mod, pin):
     """The mask-list entry point (used to sample large orders) meets the same pins."""

@@ -15,6 +15,8 @@ PLANTS = {
     4: ("cs", "extra term: root singleton counted twice"),
     5: ("perm", "Ryser sign without the (-1)^|S| factor"),
     6: ("cminors", "conjugated quotient in the complex elimination"),
+    7: ("xor", "the other row of every block kept"),
+    8: ("xor", "columns taken from the other branch of each block"),
 }
 
 
@@ -29,6 +31,8 @@ def test_planted_mistake_is_caught(oracle_mod, plant):
             fn, pins = (lambda A: oracle_mod.minors(A, lib=lib)), P.MINOR_PINS
         elif kind == "cminors":
             fn, pins = (lambda A: oracle_mod.minors_complex(A, lib=lib)), P.CMINOR_PINS
+        elif kind == "xor":
+            fn, pins = (lambda A: oracle_mod.xor_minors(A, lib=lib)), P.XOR_PINS
         elif kind == "cs":
             fn, pins = (lambda a, mode: oracle_mod.connected_sums(a, mode, lib=lib)), P.CS_PINS
         else:

@@ -90,3 +90,16 @@ def test_stress_injection_makes_tiny_ratio():
     s = np.abs(A[b]).max()
     ratio = np.linalg.det(A2[b][np.ix_(list(r) + [l], list(r) + [l])]) / np.linalg.det(A2[b][np.ix_(r, r)])
     assert abs(ratio - 1e-12 * s) < 1e-13 * s
+
+
+def test_keldysh_block_restricts_to_branch_matrices():
+    """Keeping row 2i + alpha_i of every block gives the matrix of branch assignment alpha
+    (same times for the same seed)."""
+    import numpy as np
+    import workloads as W
+    blk = W.keldysh_block(5, 7, seed=31)
+    mats = W.keldysh_batch(5, 7, seed=31)
+    _, br = W.keldysh_config(5, 7, seed=31)
+    for b in range(5):
+        r = [2 * i + int(br[b, i]) for i in range(7)]
+        np.testing.assert_array_equal(blk[b][np.ix_(r, r)], mats[b])

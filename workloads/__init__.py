@@ -155,6 +155,30 @@ def keldysh_batch(B, n, eps=0.5, n0=0.3, tmax=10.0, seed=BASE_SEED) -> np.ndarra
     return np.ascontiguousarray(M.astype(np.complex128))
 
 
+def keldysh_block(B, n, eps=0.5, n0=0.3, tmax=10.0, seed=BASE_SEED) -> np.ndarray:
+    """(B, 2n, 2n) complex128 Keldysh block matrices (Sec. V.C, real-time DiagMC).
+
+    Block (i, j) is [[G^{++}, G^{+-}], [G^{-+}, G^{--}]] at t_i - t_j with the propagators
+    of ``keldysh_batch``: row/column 2i + a is vertex i on branch a (0 = '+', 1 = '-').
+    Keeping one row of every block (row 2i + alpha_i) gives that function's matrix for the
+    branch assignment alpha.  Times t_i ~ U[0, tmax).
+    """
+    rng = _rng(seed)
+    t = rng.random((B, n)) * tmax
+    dt = t[:, :, None] - t[:, None, :]
+    ph = np.exp(-1j * eps * dt)
+    g_gt = -1j * (1.0 - n0) * ph
+    g_lt = 1j * n0 * ph
+    later = dt > 0.0
+    earlier = dt < 0.0
+    out = np.empty((B, 2 * n, 2 * n), dtype=np.complex128)
+    out[:, 0::2, 0::2] = np.where(later, g_gt, g_lt)      # ++ : time ordered
+    out[:, 1::2, 1::2] = np.where(earlier, g_gt, g_lt)    # -- : anti-time ordered
+    out[:, 0::2, 1::2] = g_lt                              # +- = G^<
+    out[:, 1::2, 0::2] = g_gt                              # -+ = G^>
+    return out
+
+
 def keldysh_config(B, n, eps=0.5, n0=0.3, tmax=10.0, seed=BASE_SEED):
     """Return (times, branches) used by ``keldysh_batch`` with the same seed."""
     rng = _rng(seed)
