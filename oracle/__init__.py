@@ -15,7 +15,8 @@ bit k <-> row/column k, out[0] = det of the empty matrix = 1):
 * ``perm_minors(A)``       -- Sec. IV: Ryser's formula per subset, with the
                               (-1)^|S| factor the printed Eq. (ryser) drops.
 * ``xor_minors(A)``        -- Sec. III, XOR case: det of every one-row-per-block
-                              choice of a 2n x 2n block matrix, all leading depths.
+                              choice of a 2n x 2n block matrix, and of the trailing
+                              k blocks for every depth k < n.
 * ``g0``-independent: the oracle consumes host matrices built by ``workloads``.
 """
 from __future__ import annotations
@@ -170,10 +171,11 @@ def minors_complex(A, nthreads: int = 0, lib=None) -> np.ndarray:
 def xor_minors(A, lib=None) -> np.ndarray:
     """XOR principal minors of 2n x 2n matrices of 2 x 2 blocks (Sec. III, XOR case).
 
-    For depth k = 1..n and every k-bit choice word alpha (bit i: row/column 2i + alpha_i
-    of block i kept), entry 2^k - 2 + alpha is det A[R, R], R = {2i + alpha_i : i < k};
-    the order-n minors are the last 2^n entries.  Real or complex input of shape
-    (B, 2n, 2n) or (2n, 2n); returns (B, 2^(n+1) - 2) (or one row)."""
+    For depth k = 1..n and every k-bit choice word beta over the k trailing blocks (bit i:
+    row/column 2(n-k+i) + beta_i of block n-k+i kept), entry 2^k - 2 + beta is
+    det A[R, R], R = {2(n-k+i) + beta_i : i < k}; the order-n minors (bit i <-> block i)
+    are the last 2^n entries.  Real or complex input of shape (B, 2n, 2n) or (2n, 2n);
+    returns (B, 2^(n+1) - 2) (or one row)."""
     A = np.asarray(A)
     single = A.ndim == 2
     if single:

@@ -323,19 +323,22 @@ int apm_oracle_perm_minors_masks(int n, const double *A, int count, const uint32
  * outputs start at element out_off[b] of out.  Returns 0, or -1 on a bad n. */
 /* XOR principal minors of a 2n x 2n matrix read as n x n blocks of 2 x 2 (Sec. III, the
  * XOR case): the principal minors that keep exactly one of the rows/columns 2i, 2i+1 of
- * every block i.  Besides the order-n ones, every leading choice is listed: for depth
- * k = 1..n and every k-bit choice word alpha (bit i: row 2i + alpha_i of block i is kept),
- *     out[2^k - 2 + alpha] = det A[R, R],   R = {2i + alpha_i : i < k},
- * so the 2^n full-order minors are the last 2^n of the 2^(n+1) - 2 entries.  With the
- * Keldysh block matrix of Sec. V.C these are the determinants of the branch assignments.
- * Each determinant is a separate partial-pivoting LU of the gathered k x k matrix. */
-static void xor_rows(int k, uint32_t alpha, int *idx)
+ * every block i.  The tree that computes them may take the blocks in any order; the
+ * paper fixes none for the lower-order minors it yields on the way.  Here the last block
+ * is taken first, so depth k lists the minors of the k trailing blocks: for k = 1..n and
+ * every k-bit choice word beta (bit i: row 2(n-k+i) + beta_i of block n-k+i is kept),
+ *     out[2^k - 2 + beta] = det A[R, R],   R = {2(n-k+i) + beta_i : i < k},
+ * and the 2^n full-order minors (bit i <-> block i) are the last 2^n of the 2^(n+1) - 2
+ * entries.  With the Keldysh block matrix of Sec. V.C these are the determinants of the
+ * branch assignments.  Each determinant is a separate partial-pivoting LU of the
+ * gathered k x k matrix. */
+static void xor_rows(int n, int k, uint32_t beta, int *idx)
 {
     for (int i = 0; i < k; ++i) {
 #if ORACLE_PLANT == 7
-        idx[i] = 2 * i + 1 - (int)(alpha >> i & 1u);
+        idx[i] = 2 * (n - k + i) + 1 - (int)(beta >> i & 1u);
 #else
-        idx[i] = 2 * i + (int)(alpha >> i & 1u);
+        idx[i] = 2 * (n - k + i) + (int)(beta >> i & 1u);
 #endif
     }
 }
@@ -360,7 +363,7 @@ int apm_oracle_xor_minors_r64(int n, const double *A, double *out)
     int idx[ORACLE_MAX_N];
     for (int k = 1; k <= n; ++k)
         for (uint32_t alpha = 0; alpha < (1u << k); ++alpha) {
-            xor_rows(k, alpha, idx);
+            xor_rows(n, k, alpha, idx);
             for (int a = 0; a < k; ++a)
                 for (int b = 0; b < k; ++b) sub[a * k + b] = A[idx[a] * w + xor_col(idx[b])];
             out[xor_index(k, alpha)] = det_real_inplace(k, sub);
@@ -376,7 +379,7 @@ int apm_oracle_xor_minors_c128(int n, const double *A, double *out)
     int idx[ORACLE_MAX_N];
     for (int k = 1; k <= n; ++k)
         for (uint32_t alpha = 0; alpha < (1u << k); ++alpha) {
-            xor_rows(k, alpha, idx);
+            xor_rows(n, k, alpha, idx);
             for (int a = 0; a < k; ++a)
                 for (int b = 0; b < k; ++b) {
                     sub[2 * (a * k + b)]     = A[2 * (idx[a] * w + xor_col(idx[b]))];

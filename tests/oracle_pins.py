@@ -430,8 +430,9 @@ def _xor_depth(out, k):
     return out[(1 << k) - 2:(1 << (k + 1)) - 2]
 
 
-def _xor_rows(k, alpha):
-    return [2 * i + (alpha >> i & 1) for i in range(k)]
+def _xor_rows(n, k, beta):
+    """Rows of the depth-k entry beta: one row of each of the k trailing blocks."""
+    return [2 * (n - k + i) + (beta >> i & 1) for i in range(k)]
 
 
 def pin_xor_leibniz(xor):
@@ -446,7 +447,7 @@ def pin_xor_leibniz(xor):
             for k in range(1, n + 1):
                 seg = _xor_depth(out, k)
                 for alpha in range(1 << k):
-                    r = _xor_rows(k, alpha)
+                    r = _xor_rows(n, k, alpha)
                     ref = leibniz_det(A[np.ix_(r, r)])
                     assert abs(seg[alpha] - ref) <= 1e-12 * max(1.0, abs(ref)), (n, k, alpha)
 
@@ -462,7 +463,7 @@ def pin_xor_block_diagonal(xor):
     d = np.diag(A)
     for k in range(1, n + 1):
         seg = _xor_depth(out, k)
-        ref = np.array([np.prod([d[r] for r in _xor_rows(k, a)]) for a in range(1 << k)])
+        ref = np.array([np.prod([d[r] for r in _xor_rows(n, k, a)]) for a in range(1 << k)])
         assert close(seg, ref, 1e-13, 1e-15), k
 
 
@@ -503,7 +504,7 @@ def pin_xor_lapack(xor):
     out = xor(A)
     for k in range(1, n + 1):
         seg = _xor_depth(out, k)
-        ref = np.array([np.linalg.det(A[np.ix_(_xor_rows(k, a), _xor_rows(k, a))]) for a in range(1 << k)])
+        ref = np.array([np.linalg.det(A[np.ix_(_xor_rows(n, k, a), _xor_rows(n, k, a))]) for a in range(1 << k)])
         assert close(seg, ref, 1e-12, 1e-13), k
 
 
