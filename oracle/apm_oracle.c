@@ -36,6 +36,7 @@
 #endif
 
 #define ORACLE_MAX_N 24
+#define ORACLE_MAX_W 32   /* widest 2n x 2n matrix of the XOR minors */
 
 /* ORACLE_PLANT selects a deliberate mistake, used only by the test that checks
  * that the pins catch plausible errors.  The shipped library is built with 0. */
@@ -357,10 +358,10 @@ static int xor_col(int r)
 
 int apm_oracle_xor_minors_r64(int n, const double *A, double *out)
 {
-    if (n < 1 || 2 * n > ORACLE_MAX_N) return -1;
+    if (n < 1 || 2 * n > ORACLE_MAX_W) return -1;
     const int w = 2 * n;
-    double sub[ORACLE_MAX_N * ORACLE_MAX_N];
-    int idx[ORACLE_MAX_N];
+    double sub[ORACLE_MAX_W * ORACLE_MAX_W];
+    int idx[ORACLE_MAX_W];
     for (int k = 1; k <= n; ++k)
         for (uint32_t alpha = 0; alpha < (1u << k); ++alpha) {
             xor_rows(n, k, alpha, idx);
@@ -373,10 +374,10 @@ int apm_oracle_xor_minors_r64(int n, const double *A, double *out)
 
 int apm_oracle_xor_minors_c128(int n, const double *A, double *out)
 {
-    if (n < 1 || 2 * n > ORACLE_MAX_N) return -1;
+    if (n < 1 || 2 * n > ORACLE_MAX_W) return -1;
     const int w = 2 * n;
-    double sub[2 * ORACLE_MAX_N * ORACLE_MAX_N];
-    int idx[ORACLE_MAX_N];
+    double sub[2 * ORACLE_MAX_W * ORACLE_MAX_W];
+    int idx[ORACLE_MAX_W];
     for (int k = 1; k <= n; ++k)
         for (uint32_t alpha = 0; alpha < (1u << k); ++alpha) {
             xor_rows(n, k, alpha, idx);
