@@ -62,6 +62,7 @@ typedef enum {
 #define APM_MAX_N 20          /* largest matrix order accepted by apm_all_minors          */
 #define APM_MAX_N_CS 20       /* largest order accepted by apm_connected_sums             */
 #define APM_MAX_N_PERM 16     /* largest order accepted by apm_all_perm_minors            */
+#define APM_MAX_N_XOR 16      /* most 2 x 2 blocks accepted by apm_xor_minors             */
 
 /* opaque HIP stream (binary compatible with hipStream_t); NULL = the default stream */
 typedef struct ihipStream_t *apm_stream;
@@ -155,6 +156,35 @@ apm_status apm_connected_sums(const double *m_up, const double *m_dn, const apm_
  * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED (n > APM_MAX_N_PERM) or APM_EDEVICE.
  */
 apm_status apm_all_perm_minors(const double *A, const apm_batch *bd, double *perm, apm_stream stream);
+
+/*
+ * apm_xor_minors -- XOR principal minors of 2n x 2n matrices of 2 x 2 blocks.
+ *
+ * Passage: Sec. III, the XOR case (the principal minors that keep exactly one of the
+ * rows/columns 2i, 2i+1 of every block i, computed by the binary tree of Schur
+ * complements whose two branches keep one row of the next block each), and Sec. V.C
+ * (with the Keldysh block matrix [[G++, G+-], [G-+, G--]] these are the determinants of
+ * all 2^n Keldysh index assignments; the lower-order ones come as side products).
+ *
+ *   dt      APM_R64 (double) or APM_C128 (complex128); others APM_EUNSUPPORTED.
+ *   A       [B x 2n x 2n] row-major input (device).
+ *   bd      uniform batch: n_uniform = n, the number of blocks (1 <= n <= APM_MAX_N_XOR);
+ *           per-matrix orders and offset arrays are not supported (APM_EUNSUPPORTED).
+ *   out     [B x (2^(n+1) - 2)] output (device).  The tree takes the last block first,
+ *           so depth k = 1..n lists the minors of the k trailing blocks: entry
+ *           2^k - 2 + beta is det A[R, R] with R = {2(n-k+i) + beta_i : i < k} (bit i of
+ *           beta chooses the row of block n-k+i).  The 2^n order-n minors (bit i <->
+ *           block i) are the last 2^n entries.
+ *   info    [B] int32 or NULL: 0, -2 non-finite input (outputs NaN), or -3 a non-finite
+ *           output (a zero pivot: this tree admits no pivot shift, Sec. III).
+ * Matrices with more than six blocks use a workspace of the library per (device,
+ * stream), 16 KB per matrix at n = 8 and 49 KB at n = 14 (complex128; half for double),
+ * grown outside stream capture only (a captured call that would grow it returns
+ * APM_EUNSUPPORTED).
+ * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED, APM_ENOMEM or APM_EDEVICE.
+ */
+apm_status apm_xor_minors(apm_dtype dt, const void *A, const apm_batch *bd, void *out, int32_t *info,
+                          apm_stream stream);
 
 /*
  * apm_autotune_minors -- pick the per-order layout of apm_all_minors by measurement.

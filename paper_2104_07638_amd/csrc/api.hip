@@ -105,6 +105,44 @@ int32_t* get_topq(hipStream_t st, int64_t batch, int32_t* cap_out, TopQueue** q_
     return static_cast<int32_t*>(q.buf);
 }
 
+// Per-(device, stream) workspace of the XOR minors' top levels (node matrices), grown on
+// demand outside stream capture; calls on one stream are ordered by the stream.
+struct XorWs {
+    void* buf = nullptr;
+    size_t cap = 0;
+};
+std::map<std::pair<int, hipStream_t>, XorWs> g_xws;
+
+apm_status get_xor_ws(hipStream_t st, size_t bytes, void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    XorWs& w = g_xws[std::make_pair(dev, st)];
+    if (w.cap < bytes) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        e = hipStreamIsCapturing(st, &cs);
+        if (e != hipSuccess) return from_hip(e);
+        if (cs != hipStreamCaptureStatusNone) return APM_EUNSUPPORTED;
+        if (w.buf) {
+            e = hipStreamSynchronize(st);   // earlier work on this stream may still use it
+            if (e != hipSuccess) return from_hip(e);
+            (void)hipFree(w.buf);
+        }
+        w.buf = nullptr;
+        w.cap = 0;
+        e = hipMalloc(&w.buf, bytes);
+        if (e != hipSuccess) {
+            w.buf = nullptr;
+            return from_hip(e);
+        }
+        w.cap = bytes;
+    }
+    *out = w.buf;
+    return APM_OK;
+}
+
 bool bad_batch(const apm_batch* bd, int nmax)
 {
     if (!bd || bd->batch < 0) return true;
@@ -553,6 +591,32 @@ apm_status apm_all_perm_minors(const double* A, const apm_batch* bd, double* per
         if (!L.out_off) L.out_off = ooff;
     }
     return from_hip(apm::perm_launch(L, (hipStream_t)stream));
+}
+
+apm_status apm_xor_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
+                          apm_stream stream)
+{
+    if ((int)dt < 0 || (int)dt > 3) return APM_EINVAL;
+    if (bad_batch(bd, APM_MAX_N_XOR)) return APM_EINVAL;
+    if (dt != APM_R64 && dt != APM_C128) return APM_EUNSUPPORTED;
+    if (bd->n_uniform == 0 || bd->in_off || bd->out_off) return APM_EUNSUPPORTED;
+    if (bd->n_uniform > APM_MAX_N_XOR) return APM_EUNSUPPORTED;
+    if (bd->batch == 0) return APM_OK;
+    if (!A || !out) return APM_EINVAL;
+    apm::LaunchXor L{};
+    L.dtype = (int)dt;
+    L.A = A;
+    L.out = out;
+    L.info = info;
+    L.batch = bd->batch;
+    L.n = bd->n_uniform;
+    L.ws_stride = apm::xor_ws_elems(L.n);
+    if (L.ws_stride > 0) {
+        const size_t bytes = (size_t)L.ws_stride * (size_t)bd->batch * (dt == APM_C128 ? 16 : 8);
+        apm_status s = get_xor_ws((hipStream_t)stream, bytes, &L.ws);
+        if (s != APM_OK) return s;
+    }
+    return from_hip(apm::xor_launch(L, (hipStream_t)stream));
 }
 
 apm_status apm_plan_create(const apm_plan_desc* d, apm_plan** out)

@@ -71,6 +71,21 @@ struct LaunchPerm {
 
 hipError_t perm_launch(const LaunchPerm& L, hipStream_t st);
 
+struct LaunchXor {
+    int dtype;                 // apm_dtype: R64 or C128
+    const void* A;             // [batch][2n][2n]
+    void* out;                 // [batch][2^(n+1) - 2]
+    int32_t* info;
+    int32_t batch;
+    int n;                     // blocks per matrix
+    void* ws;                  // top-level node matrices, ws_stride elements per matrix
+    int64_t ws_stride;
+};
+
+// Elements of top-level workspace per matrix with n blocks (0: none needed).
+int64_t xor_ws_elems(int n);
+hipError_t xor_launch(const LaunchXor& L, hipStream_t st);
+
 // ---------------------------------------------------------------- proposal network
 struct MlpNet {
     int dp, op;                // padded input / output sizes

@@ -201,3 +201,17 @@ def test_device_error_record(apm):
     assert apm.apm_last_device_error() == apm.APM_EDEVICE
     assert apm.apm_last_device_error() == apm.APM_OK  # cleared by the read
     assert apm.apm_last_hip_error() != 0              # the HIP code stays
+
+
+def test_xor_validation(apm):
+    f = apm.apm_xor_minors
+    assert f(2, P, _bd(apm, batch=0), P, None, None) == apm.APM_OK
+    assert f(9, P, _bd(apm), P, None, None) == apm.APM_EINVAL
+    assert f(1, P, _bd(apm), P, None, None) == apm.APM_EUNSUPPORTED          # r32s: not built
+    assert f(3, P, _bd(apm), P, None, None) == apm.APM_EUNSUPPORTED          # c64s: not built
+    assert f(2, P, _bd(apm, n=17), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(2, P, _bd(apm, n=0, nptr=P), P, None, None) == apm.APM_EUNSUPPORTED   # mixed orders
+    assert f(2, P, _bd(apm, ioff=P), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(2, None, _bd(apm), P, None, None) == apm.APM_EINVAL
+    assert f(2, P, _bd(apm), None, None, None) == apm.APM_EINVAL
+    assert f(2, P, None, P, None, None) == apm.APM_EINVAL

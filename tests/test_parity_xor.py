@@ -1,0 +1,120 @@
+"""GPU parity of the XOR minors (Sec. III XOR case; Sec. V.C Keldysh block matrices) with
+the oracle: element by element for every depth at small sizes (spanning the orders where
+the top levels run from the workspace), on sampled matrices at the full size of the
+benchmark, and the branch-signed sum that the largest-time identity sends to zero."""
+import numpy as np
+import pytest
+
+from oracle import metrics
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_07638_amd as m
+    return m
+
+
+def xor_hadamard(A):
+    """Hadamard bound prod_{i in R} ||A[i, R]||_2 of every entry's kept rows R, in output
+    order (depth k: R = {2(n-k+i) + beta_i})."""
+    n = A.shape[0] // 2
+    out = []
+    for k in range(1, n + 1):
+        beta = np.arange(1 << k)[:, None]
+        R = 2 * (n - k + np.arange(k))[None, :] + ((beta >> np.arange(k)[None, :]) & 1)
+        sub = A[R[:, :, None], R[:, None, :]]
+        out.append(np.prod(np.linalg.norm(sub, axis=2), axis=1))
+    return np.concatenate(out)
+
+
+def check(A, got, ref, tol=1e-10):
+    """Mixed error per entry against max(|ref|, Hadamard bound of the kept rows)."""
+    n = A.shape[0] // 2
+    e = metrics.mixed_err(got, ref, xor_hadamard(A))
+    assert e.max() <= tol, (n, float(e.max()), int(np.argmax(e)))
+
+
+@pytest.mark.parametrize("n", list(range(1, 10)))
+def test_keldysh_all_depths(apm, oracle_mod, n):
+    import torch
+    A = W.keldysh_block(6, n, seed=400 + n)
+    out, info = apm.xor_minors(torch.from_numpy(A).cuda())
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    got = out.cpu().numpy()
+    ref = oracle_mod.xor_minors(A)
+    for b in range(A.shape[0]):
+        check(A[b], got[b], ref[b])
+
+
+@pytest.mark.parametrize("n", [1, 3, 6, 7, 9])
+def test_random_real_and_complex(apm, oracle_mod, n):
+    import torch
+    rng = np.random.default_rng(410 + n)
+    for cplx in (False, True):
+        A = rng.standard_normal((5, 2 * n, 2 * n)) + 2.0 * np.eye(2 * n)
+        if cplx:
+            A = A + 1j * rng.standard_normal((5, 2 * n, 2 * n))
+        out, info = apm.xor_minors(torch.from_numpy(A).cuda())
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref = oracle_mod.xor_minors(A)
+        for b in range(5):
+            check(A[b], got[b], ref[b])
+
+
+def test_largest_time_on_gpu(apm):
+    """Branch-signed sums of the GPU's own minors vanish at every depth."""
+    import torch
+    n = 10
+    A = W.keldysh_block(64, n, seed=420)
+    out, _ = apm.xor_minors(torch.from_numpy(A).cuda())
+    got = out.cpu().numpy()
+    for k in range(1, n + 1):
+        seg = got[:, (1 << k) - 2:(1 << (k + 1)) - 2]
+        sgn = np.array([(-1) ** bin(a).count("1") for a in range(1 << k)])
+        assert np.all(np.abs(seg @ sgn) <= 1e-12 * np.abs(seg).sum(axis=1)), k
+
+
+def test_full_size_sampled(apm, oracle_mod):
+    """4096 Keldysh block matrices with 14 blocks (the benchmark's batch): sampled matrices
+    against the oracle at every depth, the largest-time identity on all of them."""
+    import torch
+    n = 14
+    A = W.keldysh_block(4096, n, seed=W.BASE_SEED + 4)
+    dA = torch.from_numpy(A).cuda()
+    out, info = apm.xor_minors(dA)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    sel = np.random.default_rng(4096).choice(4096, 6, replace=False)
+    got = out[torch.from_numpy(sel).cuda()].cpu().numpy()
+    ref = oracle_mod.xor_minors(A[sel])
+    for i in range(len(sel)):
+        check(A[sel[i]], got[i], ref[i])
+    full = out[:, (1 << n) - 2:]
+    sgn = torch.tensor([(-1.0) ** bin(a).count("1") for a in range(1 << n)], dtype=torch.float64, device="cuda")
+    s = (full * sgn).sum(dim=1).abs()
+    assert bool(torch.all(s <= 1e-12 * full.abs().sum(dim=1)))
+
+
+def test_error_codes(apm):
+    import torch
+    n = 7
+    A = W.keldysh_block(4, n, seed=430)
+    A[1, 3, 5] = np.nan                        # non-finite input
+    A[2, 2 * n - 1, 2 * n - 1] = 0.0           # zero pivot in the first decided block
+    out, info = apm.xor_minors(torch.from_numpy(A).cuda())
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    assert info[0] == 0 and info[1] == -2 and info[2] == -3 and info[3] == 0
+    assert bool(torch.all(torch.isnan(out[1].real)))
+    assert bool(torch.all(torch.isfinite(out[0].real)))
+    # an empty batch is a no-op
+    rc = apm.apm_xor_minors(apm.APM_C128, None, apm.make_batch(0, n), None, None, apm._stream(None))
+    assert rc == apm.APM_OK
