@@ -178,7 +178,7 @@ apm_status apm_all_perm_minors(const double *A, const apm_batch *bd, double *per
  *   info    [B] int32 or NULL: 0, -2 non-finite input (outputs NaN), or -3 a non-finite
  *           output (a zero pivot: this tree admits no pivot shift, Sec. III).
  * Matrices with more than six blocks use a workspace of the library per (device,
- * stream), 16 KB per matrix at n = 8 and 49 KB at n = 14 (complex128; half for double),
+ * stream), 3 KB per matrix at n = 8 and 47 KB at n = 14 (complex128; half for double),
  * grown outside stream capture only (a captured call that would grow it returns
  * APM_EUNSUPPORTED).
  * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED, APM_ENOMEM or APM_EDEVICE.

@@ -10,15 +10,19 @@
 // shift is made: its correction would need minors this tree never forms (the paper notes
 // the same), so a zero pivot leaves its subtree non-finite and info = -3.
 //
-// Mapping (one wavefront per matrix):
+// Mapping (one wavefront per matrix; lanes exchange through LDS with wavefront syncs only,
+// so the stores of the minors stay in flight):
 //   * the last block is decided first, so a node's remaining blocks are the leading ones
 //     and the pivot rows are the last two rows of its matrix; depth k of the output holds
 //     the minors of the k trailing blocks, and every subtree's outputs are contiguous;
 //   * top levels (d < T = n - Q): depth first over the 2^T depth-T nodes, the stack of
-//     node matrices (orders 2(n-1) ... 2(n-T)) in a workspace in global memory, each child
-//     computed by all lanes from the staged pivot row (scaled by 1/pivot) and column;
-//   * the last Q = min(n, 6) levels of each depth-T node: breadth first in LDS, all the
-//     children of a level computed by the lanes at once (at most 288 entries per level).
+//     node matrices (orders 2(n-1) ... 2(n-T+1)) in a workspace in global memory, half a
+//     row of the child per lane, with the pivot row (scaled by 1/pivot) staged in LDS; the
+//     depth-T node is written straight into LDS;
+//   * the last Q = min(n, 6) levels of each depth-T node: breadth first in LDS, one row of
+//     a child per lane, so each level is one pass (at most 64 rows, 288 entries);
+//   * every size is a compile-time constant (one kernel per number of blocks), so no index
+//     arithmetic divides at run time.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -32,7 +36,7 @@ constexpr int kXQ = 6;       // levels expanded breadth first in LDS
 constexpr int kXBuf = 288;   // largest such level: 8 nodes of order 6 (orders 12, 10, 8, ...)
 
 // Start of the depth-d node matrix (d >= 1) in a matrix's workspace, in elements.
-__host__ __device__ inline int64_t xor_top_off(int n, int d)
+__host__ __device__ constexpr int64_t xor_top_off(int n, int d)
 {
     int64_t s = 0;
     for (int l = 1; l < d; ++l) s += (int64_t)(2 * (n - l)) * (2 * (n - l));
@@ -40,25 +44,128 @@ __host__ __device__ inline int64_t xor_top_off(int n, int d)
 }
 
 template <class F>
+struct XorLds {
+    typename F::E buf[2][kXBuf];
+    typename F::E mn[2][1 << kXQ];   // minors of the nodes of the current and the next level
+    typename F::E wk[64];            // subtree levels: each child's pivot row times 1/pivot
+    typename F::E wv[32];            // top levels: pivot row times 1/pivot
+    typename F::E topm[17];          // minors along the top path
+};
+
+// Top level D of matrix order 2N: the child of the depth-D node on path s (half a row of
+// the child per lane), from the workspace (or the input at D = 0) to the workspace.
+template <class F, int N, int T, int D>
+__device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, typename F::E* st,
+                                        typename F::E* ob, XorLds<F>& sh, double& chk)
+{
+    if constexpr (D < T) {
+        using E = typename F::E;
+        constexpr int m = 2 * (N - D), mc = m - 2;
+        if (D >= d0) {
+            const int lane = threadIdx.x;
+            const E* P = D == 0 ? A0 : st + xor_top_off(N, D);
+            // the depth-T node (the subtree's root) goes straight to LDS
+            E* C = D == T - 1 ? &sh.buf[0][0] : st + xor_top_off(N, D + 1);
+            const int p = mc + ((s >> (T - 1 - D)) & 1);
+            // every load of the node first, then the arithmetic: one round trip per node.
+            // Lanes 2i and 2i+1 take the two halves of row i of the child.
+            constexpr int hm = (mc + 1) / 2;
+            const int i = lane >> 1, h0 = (lane & 1) * hm;
+            const E pv = P[p * m + p];
+            E row[hm], pc = F::zero(), pr = F::zero();
+            if (i < mc) {
+#pragma unroll
+                for (int j = 0; j < hm; ++j)
+                    if (h0 + j < mc) row[j] = P[i * m + h0 + j];
+                pc = P[i * m + p];
+            }
+            if (lane < mc) pr = P[p * m + lane];
+            const typename F::R r = F::recip(pv);
+            if (lane < mc) sh.wv[lane] = F::rowscale(pr, r);
+            if (lane == 0) {
+                const E mk = F::bmul(sh.topm[D], pv, 0);
+                sh.topm[D + 1] = mk;
+                ob[(int64_t(2) << D) - 2 + (s >> (T - 1 - D))] = mk;
+                chk += F::fincheck(mk);
+            }
+            wave_sync();
+            if (i < mc) {
+#pragma unroll
+                for (int j = 0; j < hm; ++j)
+                    if (h0 + j < mc) C[i * mc + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
+            }
+            if constexpr (D == T - 1) {
+                wave_sync();
+            } else {
+                wave_mem_fence();   // the child is the next level's node (and wv is rewritten)
+            }
+        }
+        xor_top<F, N, T, D + 1>(d0, s, A0, st, ob, sh, chk);
+    }
+}
+
+// Subtree level J of a Q-level subtree: the children of the 2^J nodes in buf[J & 1]
+// (order 2(Q - J)) into buf[(J + 1) & 1], one row of a child per lane.  base is where the
+// children's depth T+J+1 starts in the output (2^(T+J+1) - 2).
+template <class F, int Q, int J>
+__device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, XorLds<F>& sh, double& chk)
+{
+    if constexpr (J < Q) {
+        using E = typename F::E;
+        constexpr int cur = J & 1, nxt = cur ^ 1;
+        constexpr int m = 2 * (Q - J), mc = m - 2, kids = 2 << J;
+        static_assert(kids <= 64 && kids * mc <= 64, "one pass per level");
+        const int lane = threadIdx.x;
+        // child k of node k/2 keeps row mc + (k & 1) of the node's last block: its minor, and
+        // the pivot row times 1/pivot (lane k mc + j holds entry j)
+        if (lane < kids) {
+            const int p = mc + (lane & 1);
+            const E pv = sh.buf[cur][(lane >> 1) * m * m + p * m + p];
+            const E mk = F::bmul(sh.mn[cur][lane >> 1], pv, 0);
+            sh.mn[nxt][lane] = mk;
+            ob[base + ((int64_t)s << (J + 1)) + lane] = mk;
+            chk += F::fincheck(mk);
+        }
+        if constexpr (mc > 0) {
+            if (lane < kids * mc) {
+                const int k = lane / mc, j = lane - k * mc, p = mc + (k & 1);
+                const E* P = &sh.buf[cur][(k >> 1) * m * m];
+                sh.wk[lane] = F::rowscale(P[p * m + j], F::recip(P[p * m + p]));
+            }
+        }
+        wave_sync();
+        if constexpr (mc > 0) {
+            if (lane < kids * mc) {
+                const int k = lane / mc, i = lane - k * mc, p = mc + (k & 1);
+                const E* P = &sh.buf[cur][(k >> 1) * m * m];
+                const E ci = P[i * m + p];
+                const E* wr = &sh.wk[k * mc];
+                E* Cr = &sh.buf[nxt][k * mc * mc + i * mc];
+#pragma unroll
+                for (int j = 0; j < mc; ++j) Cr[j] = F::upd(P[i * m + j], ci, wr[j]);
+            }
+            wave_sync();
+        }
+        xor_sub<F, Q, J + 1>(2 * base + 2, s, ob, sh, chk);   // depth T+J+2 starts at 2^(T+J+2) - 2
+    }
+}
+
+template <class F, int N>
 __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict__ A, typename F::E* __restrict__ out,
-                                                 int32_t* __restrict__ info, int32_t batch, int n,
+                                                 int32_t* __restrict__ info, int32_t batch,
                                                  typename F::E* __restrict__ ws, int64_t ws_stride)
 {
     using E = typename F::E;
-    using R = typename F::R;
-    __shared__ E buf[2][kXBuf];
-    __shared__ E mn[2][1 << kXQ];   // minors of the nodes of the current and the next level
-    __shared__ R rc[1 << kXQ];      // reciprocal pivots of the next level's nodes
-    __shared__ E wv[32];            // top levels: pivot row times 1/pivot
-    __shared__ E cv[32];            // and pivot column
-    __shared__ E topm[17];          // minors along the top path
+    constexpr int Q = N < kXQ ? N : kXQ;
+    constexpr int T = N - Q;
+    constexpr int w = 2 * N;
+    __shared__ XorLds<F> sh;
     const int b = blockIdx.x;
     if (b >= batch) return;
     const int lane = threadIdx.x;
-    const int w = 2 * n;
     const E* A0 = A + (int64_t)b * w * w;
-    E* ob = out + (int64_t)b * ((int64_t(2) << n) - 2);
-    const int64_t nout = (int64_t(2) << n) - 2;
+    E* ob = out + (int64_t)b * ((int64_t(2) << N) - 2);
+    constexpr int64_t nout = (int64_t(2) << N) - 2;
 
     bool fin = true;
     for (int e = lane; e < w * w; e += 64) fin = fin && F::in_finite(A0[e]);
@@ -67,96 +174,52 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
         if (info && lane == 0) info[b] = -2;
         return;
     }
-    const int Q = n < kXQ ? n : kXQ;
-    const int T = n - Q;
     E* st = ws + (int64_t)b * ws_stride;
     double chk = 0.0;
-    if (lane == 0) topm[0] = F::one();
-
+    if (lane == 0) sh.topm[0] = F::one();
     for (int s = 0; s < (1 << T); ++s) {
         // top levels: redo the path below the first choice that changed from s - 1
         const int d0 = s ? T - 1 - (31 - __clz((unsigned)(s ^ (s - 1)))) : 0;
-        for (int d = d0; d < T; ++d) {
-            const int m = 2 * (n - d), mc = m - 2;
-            const E* P = d == 0 ? A0 : st + xor_top_off(n, d);
-            E* C = st + xor_top_off(n, d + 1);
-            const int p = mc + ((s >> (T - 1 - d)) & 1);
-            const E pv = P[p * m + p];
-            const R r = F::recip(pv);
-            if (lane < mc) {
-                wv[lane] = F::rowscale(P[p * m + lane], r);
-                cv[lane] = P[lane * m + p];
-            }
-            if (lane == 0) {
-                const E mk = F::bmul(topm[d], pv, 0);
-                topm[d + 1] = mk;
-                ob[(int64_t(2) << d) - 2 + (s >> (T - 1 - d))] = mk;
-                chk += F::fincheck(mk);
-            }
-            __syncthreads();
-            for (int e = lane; e < mc * mc; e += 64) {
-                const int i = e / mc, j = e - i * mc;
-                C[e] = F::upd(P[i * m + j], cv[i], wv[j]);
-            }
-            __syncthreads();
-        }
+        xor_top<F, N, T, 0>(d0, s, A0, st, ob, sh, chk);
         // the subtree of depth-T node s, breadth first in LDS
-        const int q = 2 * Q;
-        const E* S0 = T == 0 ? A0 : st + xor_top_off(n, T);
-        for (int e = lane; e < q * q; e += 64) buf[0][e] = S0[e];
-        if (lane == 0) mn[0][0] = topm[T];
-        __syncthreads();
-        for (int j = 0; j < Q; ++j) {
-            const int cur = j & 1, nxt = cur ^ 1;
-            const int m = 2 * (Q - j), mc = m - 2;
-            const int kids = 2 << j;
-            // child k of node k/2 keeps row mc + (k & 1) of the node's last block
-            if (lane < kids) {
-                const int node = lane >> 1, p = mc + (lane & 1);
-                const E pv = buf[cur][node * m * m + p * m + p];
-                const E mk = F::bmul(mn[cur][node], pv, 0);
-                mn[nxt][lane] = mk;
-                rc[lane] = F::recip(pv);
-                ob[(int64_t(2) << (T + j)) - 2 + ((int64_t)s << (j + 1)) + lane] = mk;
-                chk += F::fincheck(mk);
-            }
-            __syncthreads();
-            const int per = mc * mc;
-            for (int e = lane; e < kids * per; e += 64) {
-                const int k = e / per, rr = e - k * per, i = rr / mc, jj = rr - i * mc;
-                const int p = mc + (k & 1);
-                const E* P = &buf[cur][(k >> 1) * m * m];
-                buf[nxt][e] = F::upd(P[i * m + jj], P[i * m + p], F::rowscale(P[p * m + jj], rc[k]));
-            }
-            __syncthreads();
+        if constexpr (T == 0) {
+            for (int e = lane; e < w * w; e += 64) sh.buf[0][e] = A0[e];
         }
+        if (lane == 0) sh.mn[0][0] = sh.topm[T];
+        wave_sync();
+        xor_sub<F, Q, 0>((int64_t(2) << T) - 2, s, ob, sh, chk);
     }
     const bool bad = __any(chk == 0.0 ? 0 : 1);
     if (info && lane == 0) info[b] = bad ? -3 : 0;
+}
+
+template <class F, int N>
+hipError_t xor_launch_n(const LaunchXor& L, hipStream_t st)
+{
+    if constexpr (N > 16) {
+        return hipErrorInvalidValue;
+    } else {
+        if (L.n != N) return xor_launch_n<F, N + 1>(L, st);
+        hipLaunchKernelGGL((xor_kernel<F, N>), dim3((unsigned)L.batch), dim3(64), 0, st,
+                           static_cast<const typename F::E*>(L.A), static_cast<typename F::E*>(L.out), L.info,
+                           L.batch, static_cast<typename F::E*>(L.ws), L.ws_stride);
+        return hipGetLastError();
+    }
 }
 
 }  // namespace
 
 int64_t xor_ws_elems(int n)
 {
-    const int T = n > kXQ ? n - kXQ : 0;
-    return T > 0 ? xor_top_off(n, T + 1) : 0;
+    const int T = n > kXQ ? n - kXQ : 0;   // depths 1 .. T-1 live in the workspace, depth T in LDS
+    return T > 1 ? xor_top_off(n, T) : 0;
 }
 
 hipError_t xor_launch(const LaunchXor& L, hipStream_t st)
 {
-    if (L.dtype == 0) {
-        hipLaunchKernelGGL(xor_kernel<FR64>, dim3((unsigned)L.batch), dim3(64), 0, st,
-                           static_cast<const double*>(L.A), static_cast<double*>(L.out), L.info, L.batch, L.n,
-                           static_cast<double*>(L.ws), L.ws_stride);
-    } else if (L.dtype == 2) {
-        hipLaunchKernelGGL(xor_kernel<FC128>, dim3((unsigned)L.batch), dim3(64), 0, st,
-                           static_cast<const cd*>(L.A), static_cast<cd*>(L.out), L.info, L.batch, L.n,
-                           static_cast<cd*>(L.ws), L.ws_stride);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (L.dtype == 0) return xor_launch_n<FR64, 1>(L, st);
+    if (L.dtype == 2) return xor_launch_n<FC128, 1>(L, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace apm
