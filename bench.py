@@ -281,6 +281,23 @@ def run_extra(torch, apm, W, np, steps):
     ms = time_fn(torch, lambda: apm.all_perm_minors(P, out=po), steps)
     ex["perm_n12_2048"] = {"ms": round(ms, 4), "matrices_per_s": round(2048 / (ms * 1e-3), 1),
                            "products_per_s": round(2048 * 3 ** 12 / (ms * 1e-3), 1)}
+    # XOR minors (Keldysh-index determinants): 4096 Keldysh block matrices of 14 blocks
+    # (28 x 28 complex128), every branch assignment and the trailing-block side products
+    K2 = torch.from_numpy(W.keldysh_block(4096, 14, seed=W.BASE_SEED + 4)).cuda()
+    xo = torch.empty((4096, (2 << 14) - 2), dtype=torch.complex128, device="cuda")
+    xi = torch.empty(4096, dtype=torch.int32, device="cuda")
+    ms = time_fn(torch, lambda: apm.xor_minors(K2, out=xo, info=xi), steps)
+    by = K2.numel() * 16 + xo.numel() * 16
+    ex["xor_keldysh_n14_4096_c128"] = {"ms": round(ms, 4), "matrices_per_s": round(4096 / (ms * 1e-3), 1),
+                                       "GBs": round(by / (ms * 1e-3) / 1e9, 1),
+                                       "frac_hbm_peak": round(by / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    K2r = K2.real.contiguous()
+    xr = torch.empty((4096, (2 << 14) - 2), dtype=torch.float64, device="cuda")
+    ms = time_fn(torch, lambda: apm.xor_minors(K2r, out=xr, info=xi), steps)
+    by = K2r.numel() * 8 + xr.numel() * 8
+    ex["xor_n14_4096_r64"] = {"ms": round(ms, 4), "matrices_per_s": round(4096 / (ms * 1e-3), 1),
+                              "GBs": round(by / (ms * 1e-3) / 1e9, 1)}
+    del K2, xo, K2r, xr
     for k, v in ex.items():
         log(f"{k}: {v}")
     return ex
