@@ -33,7 +33,14 @@ namespace apm {
 namespace {
 
 constexpr int kXQ = 6;       // levels expanded breadth first in LDS
-constexpr int kXBuf = 288;   // largest such level: 8 nodes of order 6 (orders 12, 10, 8, ...)
+#ifndef APM_XOR_PAD
+#define APM_XOR_PAD 1
+#endif
+// Row stride of an order-m node matrix in LDS: one element of padding, so that lanes
+// reading the same column of different rows fall on different banks.
+__host__ __device__ constexpr int xs(int m) { return m + APM_XOR_PAD; }
+// largest level of the six-level subtree: 8 nodes of order 6 (6 rows of stride xs(6))
+constexpr int kXBuf = 8 * 6 * xs(6);
 
 // Start of the depth-d node matrix (d >= 1) in a matrix's workspace, in elements.
 __host__ __device__ constexpr int64_t xor_top_off(int n, int d)
@@ -66,6 +73,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             const E* P = D == 0 ? A0 : st + xor_top_off(N, D);
             // the depth-T node (the subtree's root) goes straight to LDS
             E* C = D == T - 1 ? &sh.buf[0][0] : st + xor_top_off(N, D + 1);
+            const int cs = D == T - 1 ? xs(mc) : mc;   // row stride of the child
             const int p = mc + ((s >> (T - 1 - D)) & 1);
             // every load of the node first, then the arithmetic: one round trip per node.
             // Lanes 2i and 2i+1 take the two halves of row i of the child.
@@ -92,7 +100,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             if (i < mc) {
 #pragma unroll
                 for (int j = 0; j < hm; ++j)
-                    if (h0 + j < mc) C[i * mc + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
+                    if (h0 + j < mc) C[i * cs + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
             }
             if constexpr (D == T - 1) {
                 wave_sync();
@@ -120,7 +128,7 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         // the pivot row times 1/pivot (lane k mc + j holds entry j)
         if (lane < kids) {
             const int p = mc + (lane & 1);
-            const E pv = sh.buf[cur][(lane >> 1) * m * m + p * m + p];
+            const E pv = sh.buf[cur][(lane >> 1) * m * xs(m) + p * xs(m) + p];
             const E mk = F::bmul(sh.mn[cur][lane >> 1], pv, 0);
             sh.mn[nxt][lane] = mk;
             ob[base + ((int64_t)s << (J + 1)) + lane] = mk;
@@ -129,20 +137,20 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         if constexpr (mc > 0) {
             if (lane < kids * mc) {
                 const int k = lane / mc, j = lane - k * mc, p = mc + (k & 1);
-                const E* P = &sh.buf[cur][(k >> 1) * m * m];
-                sh.wk[lane] = F::rowscale(P[p * m + j], F::recip(P[p * m + p]));
+                const E* P = &sh.buf[cur][(k >> 1) * m * xs(m)];
+                sh.wk[lane] = F::rowscale(P[p * xs(m) + j], F::recip(P[p * xs(m) + p]));
             }
         }
         wave_sync();
         if constexpr (mc > 0) {
             if (lane < kids * mc) {
                 const int k = lane / mc, i = lane - k * mc, p = mc + (k & 1);
-                const E* P = &sh.buf[cur][(k >> 1) * m * m];
-                const E ci = P[i * m + p];
+                const E* P = &sh.buf[cur][(k >> 1) * m * xs(m)];
+                const E ci = P[i * xs(m) + p];
                 const E* wr = &sh.wk[k * mc];
-                E* Cr = &sh.buf[nxt][k * mc * mc + i * mc];
+                E* Cr = &sh.buf[nxt][k * mc * xs(mc) + i * xs(mc)];
 #pragma unroll
-                for (int j = 0; j < mc; ++j) Cr[j] = F::upd(P[i * m + j], ci, wr[j]);
+                for (int j = 0; j < mc; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
             }
             wave_sync();
         }
@@ -183,7 +191,7 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
         xor_top<F, N, T, 0>(d0, s, A0, st, ob, sh, chk);
         // the subtree of depth-T node s, breadth first in LDS
         if constexpr (T == 0) {
-            for (int e = lane; e < w * w; e += 64) sh.buf[0][e] = A0[e];
+            for (int e = lane; e < w * w; e += 64) sh.buf[0][(e / w) * xs(w) + e % w] = A0[e];
         }
         if (lane == 0) sh.mn[0][0] = sh.topm[T];
         wave_sync();
