@@ -41,6 +41,10 @@ constexpr int kXQ = 6;       // levels expanded breadth first in LDS
 __host__ __device__ constexpr int xs(int m) { return m + APM_XOR_PAD; }
 // largest level of the six-level subtree: 8 nodes of order 6 (6 rows of stride xs(6))
 constexpr int kXBuf = 8 * 6 * xs(6);
+#ifndef APM_XOR_PRE
+#define APM_XOR_PRE 1     // keep the depth T-1 node (order 14) in LDS as well
+#endif
+constexpr int kXPre = APM_XOR_PRE ? 14 * xs(14) : 1;
 
 // Start of the depth-d node matrix (d >= 1) in a matrix's workspace, in elements.
 __host__ __device__ constexpr int64_t xor_top_off(int n, int d)
@@ -57,6 +61,7 @@ struct XorLds {
     typename F::E wk[64];            // subtree levels: each child's pivot row times 1/pivot
     typename F::E wv[32];            // top levels: pivot row times 1/pivot
     typename F::E topm[17];          // minors along the top path
+    typename F::E pre[kXPre];        // the depth T-1 node
 };
 
 // Top level D of matrix order 2N: the child of the depth-D node on path s (half a row of
@@ -70,24 +75,42 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
         constexpr int m = 2 * (N - D), mc = m - 2;
         if (D >= d0) {
             const int lane = threadIdx.x;
-            const E* P = D == 0 ? A0 : st + xor_top_off(N, D);
-            // the depth-T node (the subtree's root) goes straight to LDS
-            E* C = D == T - 1 ? &sh.buf[0][0] : st + xor_top_off(N, D + 1);
-            const int cs = D == T - 1 ? xs(mc) : mc;   // row stride of the child
+            // node and child: the input (D = 0), the workspace, or LDS for the depth T-1 node
+            // (when kept there) and the depth-T node; LDS rows have stride xs(order)
+            constexpr bool kPin = APM_XOR_PRE && T >= 2;
+            constexpr bool kPinP = kPin && D == T - 1, kLdsC = D == T - 1 || (kPin && D == T - 2);
+            constexpr int ps = kPinP ? xs(m) : m;
+            constexpr int cs = kLdsC ? xs(mc) : mc;
+            const E* P;
+            if constexpr (D == 0) {
+                P = A0;
+            } else if constexpr (kPinP) {
+                P = sh.pre;
+            } else {
+                P = st + xor_top_off(N, D);
+            }
+            E* C;
+            if constexpr (D == T - 1) {
+                C = &sh.buf[0][0];
+            } else if constexpr (kLdsC) {
+                C = sh.pre;
+            } else {
+                C = st + xor_top_off(N, D + 1);
+            }
             const int p = mc + ((s >> (T - 1 - D)) & 1);
             // every load of the node first, then the arithmetic: one round trip per node.
             // Lanes 2i and 2i+1 take the two halves of row i of the child.
             constexpr int hm = (mc + 1) / 2;
             const int i = lane >> 1, h0 = (lane & 1) * hm;
-            const E pv = P[p * m + p];
+            const E pv = P[p * ps + p];
             E row[hm], pc = F::zero(), pr = F::zero();
             if (i < mc) {
 #pragma unroll
                 for (int j = 0; j < hm; ++j)
-                    if (h0 + j < mc) row[j] = P[i * m + h0 + j];
-                pc = P[i * m + p];
+                    if (h0 + j < mc) row[j] = P[i * ps + h0 + j];
+                pc = P[i * ps + p];
             }
-            if (lane < mc) pr = P[p * m + lane];
+            if (lane < mc) pr = P[p * ps + lane];
             const typename F::R r = F::recip(pv);
             if (lane < mc) sh.wv[lane] = F::rowscale(pr, r);
             if (lane == 0) {
@@ -102,7 +125,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                 for (int j = 0; j < hm; ++j)
                     if (h0 + j < mc) C[i * cs + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
             }
-            if constexpr (D == T - 1) {
+            if constexpr (kLdsC) {
                 wave_sync();
             } else {
                 wave_mem_fence();   // the child is the next level's node (and wv is rewritten)
@@ -219,8 +242,10 @@ hipError_t xor_launch_n(const LaunchXor& L, hipStream_t st)
 
 int64_t xor_ws_elems(int n)
 {
-    const int T = n > kXQ ? n - kXQ : 0;   // depths 1 .. T-1 live in the workspace, depth T in LDS
-    return T > 1 ? xor_top_off(n, T) : 0;
+    // depths 1 .. G live in the workspace, the deeper top nodes in LDS
+    const int T = n > kXQ ? n - kXQ : 0;
+    const int G = (APM_XOR_PRE && T >= 2) ? T - 2 : T - 1;
+    return G >= 1 ? xor_top_off(n, G + 1) : 0;
 }
 
 hipError_t xor_launch(const LaunchXor& L, hipStream_t st)
