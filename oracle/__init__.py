@@ -14,6 +14,7 @@ bit k <-> row/column k, out[0] = det of the empty matrix = 1):
 * ``connected_sums(a, mode)`` -- Sec. V.A, Eq. (recursion), direct O(3^n) loop.
 * ``perm_minors(A)``       -- Sec. IV: Ryser's formula per subset, with the
                               (-1)^|S| factor the printed Eq. (ryser) drops.
+* ``xnor_minors(A)``       -- Sec. III, XNOR case: det of every whole-block subset.
 * ``xor_minors(A)``        -- Sec. III, XOR case: det of every one-row-per-block
                               choice of a 2n x 2n block matrix, and of the trailing
                               k blocks for every depth k < n.
@@ -77,7 +78,8 @@ def load_library(path: str):
     lib.apm_oracle_perm_minors_masks.restype = ctypes.c_int
     lib.apm_oracle_cs_scale.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int]
     lib.apm_oracle_cs_scale.restype = ctypes.c_int
-    for name in ("apm_oracle_xor_minors_r64", "apm_oracle_xor_minors_c128"):
+    for name in ("apm_oracle_xor_minors_r64", "apm_oracle_xor_minors_c128", "apm_oracle_xnor_minors_r64",
+                 "apm_oracle_xnor_minors_c128"):
         fn = getattr(lib, name)
         fn.argtypes = [ctypes.c_int, dp, dp]
         fn.restype = ctypes.c_int
@@ -189,6 +191,31 @@ def xor_minors(A, lib=None) -> np.ndarray:
     out = np.empty((B, (1 << (n + 1)) - 2), dtype=A.dtype)
     L = _load(lib)
     fn = L.apm_oracle_xor_minors_c128 if cplx else L.apm_oracle_xor_minors_r64
+    for b in range(B):
+        src = A[b].view(np.float64) if cplx else A[b]
+        dst = out[b].view(np.float64) if cplx else out[b]
+        if fn(n, _dp(src), _dp(dst)) != 0:
+            raise ValueError("oracle: bad matrix order")
+    return out[0] if single else out
+
+
+def xnor_minors(A, lib=None) -> np.ndarray:
+    """XNOR principal minors of 2n x 2n matrices of 2 x 2 blocks (Sec. III, XNOR case):
+    entry mask is det A[R, R], R = the two rows of every block i with bit i of mask set
+    (entry 0 = 1).  Real or complex input (B, 2n, 2n) or (2n, 2n); returns (B, 2^n)."""
+    A = np.asarray(A)
+    single = A.ndim == 2
+    if single:
+        A = A[None]
+    cplx = np.iscomplexobj(A)
+    A = np.ascontiguousarray(A, dtype=np.complex128 if cplx else np.float64)
+    B, w, _ = A.shape
+    if w % 2:
+        raise ValueError("xnor_minors: the order must be even (2 x 2 blocks)")
+    n = w // 2
+    out = np.empty((B, 1 << n), dtype=A.dtype)
+    L = _load(lib)
+    fn = L.apm_oracle_xnor_minors_c128 if cplx else L.apm_oracle_xnor_minors_r64
     for b in range(B):
         src = A[b].view(np.float64) if cplx else A[b]
         dst = out[b].view(np.float64) if cplx else out[b]

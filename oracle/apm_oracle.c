@@ -391,6 +391,60 @@ int apm_oracle_xor_minors_c128(int n, const double *A, double *out)
     return 0;
 }
 
+/* XNOR principal minors of a 2n x 2n matrix read as n x n blocks of 2 x 2 (Sec. III, the
+ * XNOR case): the principal minors that keep both or neither of the rows/columns 2i, 2i+1
+ * of every block i.  out[mask] = det A[R, R] with R = {2i, 2i+1 : bit i of mask set},
+ * out[0] = 1 (2^n entries).  Each determinant is a separate partial-pivoting LU of the
+ * gathered 2k x 2k matrix. */
+static int xnor_rows(int n, uint32_t mask, int *idx)
+{
+    int k = 0;
+    for (int i = 0; i < n; ++i)
+        if (mask >> i & 1u) {
+#if ORACLE_PLANT == 9
+            idx[k++] = 2 * i;
+            idx[k++] = 2 * i;
+#else
+            idx[k++] = 2 * i;
+            idx[k++] = 2 * i + 1;
+#endif
+        }
+    return k;
+}
+
+int apm_oracle_xnor_minors_r64(int n, const double *A, double *out)
+{
+    if (n < 1 || 2 * n > ORACLE_MAX_W) return -1;
+    const int w = 2 * n;
+    double sub[ORACLE_MAX_W * ORACLE_MAX_W];
+    int idx[ORACLE_MAX_W];
+    for (uint32_t mask = 0; mask < (1u << n); ++mask) {
+        const int k = xnor_rows(n, mask, idx);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) sub[a * k + b] = A[idx[a] * w + idx[b]];
+        out[mask] = det_real_inplace(k, sub);
+    }
+    return 0;
+}
+
+int apm_oracle_xnor_minors_c128(int n, const double *A, double *out)
+{
+    if (n < 1 || 2 * n > ORACLE_MAX_W) return -1;
+    const int w = 2 * n;
+    double sub[2 * ORACLE_MAX_W * ORACLE_MAX_W];
+    int idx[ORACLE_MAX_W];
+    for (uint32_t mask = 0; mask < (1u << n); ++mask) {
+        const int k = xnor_rows(n, mask, idx);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+                sub[2 * (a * k + b)]     = A[2 * (idx[a] * w + idx[b])];
+                sub[2 * (a * k + b) + 1] = A[2 * (idx[a] * w + idx[b]) + 1];
+            }
+        det_cplx_inplace(k, sub, &out[2 * mask]);
+    }
+    return 0;
+}
+
 typedef int (*oracle_fn)(int, const double *, double *);
 
 static int run_batch(oracle_fn fn, int width, int B, const int32_t *n, const int64_t *in_off,

@@ -509,3 +509,66 @@ def pin_xor_lapack(xor):
 
 
 XOR_PINS = [pin_xor_leibniz, pin_xor_block_diagonal, pin_xor_branch_swap, pin_xor_largest_time, pin_xor_lapack]
+
+
+# ----------------------------------------------------------------------------------
+# XNOR minors of 2n x 2n block matrices (Sec. III, XNOR case)
+# ----------------------------------------------------------------------------------
+def _xnor_rows(n, mask):
+    return [r for i in range(n) if mask >> i & 1 for r in (2 * i, 2 * i + 1)]
+
+
+def pin_xnor_leibniz(xnor):
+    rng = _rng(81)
+    for n in (1, 2, 3):
+        for cplx in (False, True):
+            A = rng.standard_normal((2 * n, 2 * n))
+            if cplx:
+                A = A + 1j * rng.standard_normal((2 * n, 2 * n))
+            out = xnor(A)
+            assert out[0] == 1.0
+            for mask in range(1, 1 << n):
+                r = _xnor_rows(n, mask)
+                ref = leibniz_det(A[np.ix_(r, r)])
+                assert abs(out[mask] - ref) <= 1e-12 * max(1.0, abs(ref)), (n, mask)
+
+
+def pin_xnor_block_diagonal(xnor):
+    """Zero blocks off the diagonal: the product of the kept 2 x 2 determinants."""
+    rng = _rng(82)
+    n = 7
+    A = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    d = []
+    for i in range(n):
+        blk = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+        A[2 * i:2 * i + 2, 2 * i:2 * i + 2] = blk
+        d.append(blk[0, 0] * blk[1, 1] - blk[0, 1] * blk[1, 0])
+    out = xnor(A)
+    ref = np.array([np.prod([d[i] for i in range(n) if m >> i & 1]) for m in range(1 << n)])
+    assert close(out, ref, 1e-13, 1e-15)
+
+
+def pin_xnor_block_similarity(xnor):
+    """A -> D A D^-1 with D block diagonal (invertible 2 x 2 blocks) leaves every whole-block
+    principal submatrix similar to the old one, so every XNOR minor is unchanged."""
+    rng = _rng(83)
+    n = 6
+    A = rng.standard_normal((2 * n, 2 * n)) + 1j * rng.standard_normal((2 * n, 2 * n))
+    D = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    for i in range(n):
+        D[2 * i:2 * i + 2, 2 * i:2 * i + 2] = rng.standard_normal((2, 2)) + 2.0 * np.eye(2)
+    out, out_s = xnor(A), xnor(D @ A @ np.linalg.inv(D))
+    assert close(out_s, out, 1e-10, 1e-12)
+
+
+def pin_xnor_lapack(xnor):
+    rng = _rng(84)
+    n = 5
+    A = rng.standard_normal((2 * n, 2 * n))
+    out = xnor(A)
+    ref = np.array([np.linalg.det(A[np.ix_(_xnor_rows(n, m), _xnor_rows(n, m))]) if m else 1.0
+                    for m in range(1 << n)])
+    assert close(out, ref, 1e-12, 1e-13)
+
+
+XNOR_PINS = [pin_xnor_leibniz, pin_xnor_block_diagonal, pin_xnor_block_similarity, pin_xnor_lapack]

@@ -25,6 +25,11 @@ def test_perm_pins(oracle_mod, pin):
     pin(oracle_mod.perm_minors)
 
 
+@pytest.mark.parametrize("pin", P.XNOR_PINS, ids=lambda f: f.__name__)
+def test_xnor_minor_pins(oracle_mod, pin):
+    pin(oracle_mod.xnor_minors)
+
+
 @pytest.mark.parametrize("pin", P.XOR_PINS, ids=lambda f: f.__name__)
 def test_xor_minor_pins(oracle_mod, pin):
     pin(oracle_mod.xor_minors)
