@@ -187,6 +187,22 @@ apm_status apm_xor_minors(apm_dtype dt, const void *A, const apm_batch *bd, void
                           apm_stream stream);
 
 /*
+ * apm_xnor_minors -- XNOR principal minors of 2n x 2n matrices of 2 x 2 blocks.
+ *
+ * Passage: Sec. III, the XNOR case (the principal minors that keep both or neither of the
+ * rows/columns 2i, 2i+1 of every block i, computed by the binary tree whose branches drop
+ * a block or take the Schur complement over it as a 2 x 2 pivot; no pivot corrections).
+ *
+ *   dt, A, bd, info, stream   as for apm_xor_minors (info -3: a singular pivot block).
+ *   out     [B x 2^n] output: entry mask is det A[R, R], R = the two rows of every block i
+ *           with bit i of mask set; entry 0 = 1.
+ * Uses the same per-(device, stream) workspace as apm_xor_minors.
+ * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED, APM_ENOMEM or APM_EDEVICE.
+ */
+apm_status apm_xnor_minors(apm_dtype dt, const void *A, const apm_batch *bd, void *out, int32_t *info,
+                           apm_stream stream);
+
+/*
  * apm_autotune_minors -- pick the per-order layout of apm_all_minors by measurement.
  *
  * The layout parameter is the order K0 of the per-lane register subtrees (the mid

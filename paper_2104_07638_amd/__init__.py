@@ -9,6 +9,7 @@ Operations (Simkovic & Ferrero, arXiv:2104.07638):
 * ``apm_all_perm_minors`` / ``all_perm_minors`` -- Sec. IV, O(3^n) permanent minors.
 * ``apm_xor_minors`` / ``xor_minors``         -- Sec. III (XOR case), Sec. V.C: the
   determinants of every Keldysh index assignment of a 2n x 2n block matrix.
+* ``apm_xnor_minors`` / ``xnor_minors``       -- Sec. III (XNOR case): whole-block minors.
 * ``apm_mc_*`` / ``apm_mlp_*`` (``include/apm_mc.h``) -- Metropolis-Hastings steps over
   vertex configurations weighted by |c[V]| (Sec. V.A), with a learned proposal network
   trained by the library's own forward/backward/Adam kernels (``Mlp``, ``mc_step``).
@@ -45,7 +46,7 @@ EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_s
            "apm_mlp_forward", "apm_mlp_backward", "apm_mlp_adam", "apm_mc_work_bytes", "apm_mc_evaluate",
            "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
            "apm_minors_k0", "apm_plan_create", "apm_plan_launch", "apm_plan_k0", "apm_plan_graphed",
-           "apm_plan_destroy", "apm_last_device_error", "apm_xor_minors")
+           "apm_plan_destroy", "apm_last_device_error", "apm_xor_minors", "apm_xnor_minors")
 
 APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
@@ -114,8 +115,9 @@ def _load():
     lib.apm_connected_sums.restype = ctypes.c_int
     lib.apm_all_perm_minors.argtypes = [vp, ctypes.POINTER(apm_batch), vp, vp]
     lib.apm_all_perm_minors.restype = ctypes.c_int
-    lib.apm_xor_minors.argtypes = [ctypes.c_int, vp, ctypes.POINTER(apm_batch), vp, vp, vp]
-    lib.apm_xor_minors.restype = ctypes.c_int
+    for name in ("apm_xor_minors", "apm_xnor_minors"):
+        getattr(lib, name).argtypes = [ctypes.c_int, vp, ctypes.POINTER(apm_batch), vp, vp, vp]
+        getattr(lib, name).restype = ctypes.c_int
     lib.apm_status_str.argtypes = [ctypes.c_int]
     lib.apm_status_str.restype = ctypes.c_char_p
     lib.apm_last_hip_error.restype = ctypes.c_int
@@ -182,6 +184,10 @@ def apm_all_perm_minors(A, bd, perm, stream):
 
 def apm_xor_minors(dt, A, bd, out, info, stream):
     return _lib.apm_xor_minors(int(dt), A, ctypes.byref(bd) if bd is not None else None, out, info, stream)
+
+
+def apm_xnor_minors(dt, A, bd, out, info, stream):
+    return _lib.apm_xnor_minors(int(dt), A, ctypes.byref(bd) if bd is not None else None, out, info, stream)
 
 
 def apm_status_str(s):
@@ -354,6 +360,24 @@ def xor_minors(A, *, out=None, info=None, stream=None):
         info = torch.empty(B, dtype=torch.int32, device=A.device)
     _check(apm_xor_minors(dt, _ptr(A), make_batch(B, n), _ptr(out), _ptr(info), _stream(stream)),
            "apm_xor_minors")
+    return out, info
+
+
+def xnor_minors(A, *, out=None, info=None, stream=None):
+    """XNOR principal minors of a (B, 2n, 2n) float64 or complex128 tensor of 2 x 2 blocks:
+    (B, 2**n), entry mask = det of the rows/columns of the blocks in mask (entry 0 = 1)."""
+    if A.dim() != 3 or A.shape[1] != A.shape[2] or A.shape[1] % 2:
+        raise ValueError("A must be (B, 2n, 2n)")
+    if not A.is_cuda or not A.is_contiguous() or A.dtype not in (torch.float64, torch.complex128):
+        raise TypeError("A must be a contiguous float64 or complex128 CUDA tensor")
+    B, n = A.shape[0], A.shape[1] // 2
+    dt = APM_C128 if A.dtype == torch.complex128 else APM_R64
+    if out is None:
+        out = torch.empty((B, 1 << n), dtype=A.dtype, device=A.device)
+    if info is None:
+        info = torch.empty(B, dtype=torch.int32, device=A.device)
+    _check(apm_xnor_minors(dt, _ptr(A), make_batch(B, n), _ptr(out), _ptr(info), _stream(stream)),
+           "apm_xnor_minors")
     return out, info
 
 

@@ -593,8 +593,10 @@ apm_status apm_all_perm_minors(const double* A, const apm_batch* bd, double* per
     return from_hip(apm::perm_launch(L, (hipStream_t)stream));
 }
 
-apm_status apm_xor_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
-                          apm_stream stream)
+namespace {
+
+apm_status block_minors(bool xnor, apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
+                        apm_stream stream)
 {
     if ((int)dt < 0 || (int)dt > 3) return APM_EINVAL;
     if (bad_batch(bd, APM_MAX_N_XOR)) return APM_EINVAL;
@@ -610,6 +612,7 @@ apm_status apm_xor_minors(apm_dtype dt, const void* A, const apm_batch* bd, void
     L.info = info;
     L.batch = bd->batch;
     L.n = bd->n_uniform;
+    L.xnor = xnor ? 1 : 0;
     L.ws_stride = apm::xor_ws_elems(L.n);
     if (L.ws_stride > 0) {
         const size_t bytes = (size_t)L.ws_stride * (size_t)bd->batch * (dt == APM_C128 ? 16 : 8);
@@ -617,6 +620,20 @@ apm_status apm_xor_minors(apm_dtype dt, const void* A, const apm_batch* bd, void
         if (s != APM_OK) return s;
     }
     return from_hip(apm::xor_launch(L, (hipStream_t)stream));
+}
+
+}  // namespace
+
+apm_status apm_xor_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
+                          apm_stream stream)
+{
+    return block_minors(false, dt, A, bd, out, info, stream);
+}
+
+apm_status apm_xnor_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
+                           apm_stream stream)
+{
+    return block_minors(true, dt, A, bd, out, info, stream);
 }
 
 apm_status apm_plan_create(const apm_plan_desc* d, apm_plan** out)

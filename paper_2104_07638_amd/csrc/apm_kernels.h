@@ -80,6 +80,7 @@ struct LaunchXor {
     int n;                     // blocks per matrix
     void* ws;                  // top-level node matrices, ws_stride elements per matrix
     int64_t ws_stride;
+    int xnor;                  // 0: XOR minors [batch][2^(n+1) - 2]; 1: XNOR minors [batch][2^n]
 };
 
 // Elements of top-level workspace per matrix with n blocks (0: none needed).

@@ -1,4 +1,4 @@
-// xor.hip -- XOR principal minors of 2n x 2n block matrices (Sec. III, XOR case) on gfx950.
+// xor.hip -- XOR and XNOR principal minors of 2n x 2n block matrices (Sec. III) on gfx950.
 //
 // A 2n x 2n matrix is read as n x n blocks of 2 x 2.  Its XOR minors keep exactly one
 // row/column of every block; with the Keldysh block matrix of Sec. V.C they are the
@@ -9,6 +9,12 @@
 // node's minor times the pivot (the ratio rule of Sec. II with a 1 x 1 pivot).  No pivot
 // shift is made: its correction would need minors this tree never forms (the paper notes
 // the same), so a zero pivot leaves its subtree non-finite and info = -3.
+//
+// The XNOR case (Sec. III) keeps both or neither row of every block.  Its tree has the
+// same shape: one child drops the last undecided block (the node's leading part, minor
+// unchanged), the other keeps it (the Schur complement over the 2 x 2 pivot block, minor
+// times the block's determinant).  Only the 2^n leaves are minors of distinct subsets;
+// they are written in block-mask order (bit i <-> block i kept).
 //
 // Mapping (one wavefront per matrix; lanes exchange through LDS with wavefront syncs only,
 // so the stores of the minors stay in flight):
@@ -59,14 +65,15 @@ struct XorLds {
     typename F::E buf[2][kXBuf];
     typename F::E mn[2][1 << kXQ];   // minors of the nodes of the current and the next level
     typename F::E wk[64];            // subtree levels: each child's pivot row times 1/pivot
-    typename F::E wv[32];            // top levels: pivot row times 1/pivot
+    typename F::E wv[32];            // top levels: pivot row times 1/pivot (XNOR: first row of
+    typename F::E wv2[32];           // the pivot block's inverse times the pivot rows, and second)
     typename F::E topm[17];          // minors along the top path
     typename F::E pre[kXPre];        // the depth T-1 node
 };
 
 // Top level D of matrix order 2N: the child of the depth-D node on path s (half a row of
 // the child per lane), from the workspace (or the input at D = 0) to the workspace.
-template <class F, int N, int T, int D>
+template <class F, int N, int T, int D, bool XN>
 __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, typename F::E* st,
                                         typename F::E* ob, XorLds<F>& sh, double& chk)
 {
@@ -97,33 +104,77 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             } else {
                 C = st + xor_top_off(N, D + 1);
             }
-            const int p = mc + ((s >> (T - 1 - D)) & 1);
+            const int a = (s >> (T - 1 - D)) & 1;
             // every load of the node first, then the arithmetic: one round trip per node.
             // Lanes 2i and 2i+1 take the two halves of row i of the child.
             constexpr int hm = (mc + 1) / 2;
             const int i = lane >> 1, h0 = (lane & 1) * hm;
-            const E pv = P[p * ps + p];
-            E row[hm], pc = F::zero(), pr = F::zero();
+            E row[hm];
             if (i < mc) {
 #pragma unroll
                 for (int j = 0; j < hm; ++j)
                     if (h0 + j < mc) row[j] = P[i * ps + h0 + j];
-                pc = P[i * ps + p];
             }
-            if (lane < mc) pr = P[p * ps + lane];
-            const typename F::R r = F::recip(pv);
-            if (lane < mc) sh.wv[lane] = F::rowscale(pr, r);
-            if (lane == 0) {
-                const E mk = F::bmul(sh.topm[D], pv, 0);
-                sh.topm[D + 1] = mk;
-                ob[(int64_t(2) << D) - 2 + (s >> (T - 1 - D))] = mk;
-                chk += F::fincheck(mk);
-            }
-            wave_sync();
-            if (i < mc) {
+            if constexpr (!XN) {
+                // child keeps row p of the last block: 1 x 1 pivot
+                const int p = mc + a;
+                const E pv = P[p * ps + p];
+                E pc = F::zero(), pr = F::zero();
+                if (i < mc) pc = P[i * ps + p];
+                if (lane < mc) pr = P[p * ps + lane];
+                const typename F::R r = F::recip(pv);
+                if (lane < mc) sh.wv[lane] = F::rowscale(pr, r);
+                if (lane == 0) {
+                    const E mk = F::bmul(sh.topm[D], pv, 0);
+                    sh.topm[D + 1] = mk;
+                    ob[(int64_t(2) << D) - 2 + (s >> (T - 1 - D))] = mk;
+                    chk += F::fincheck(mk);
+                }
+                wave_sync();
+                if (i < mc) {
 #pragma unroll
-                for (int j = 0; j < hm; ++j)
-                    if (h0 + j < mc) C[i * cs + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
+                    for (int j = 0; j < hm; ++j)
+                        if (h0 + j < mc) C[i * cs + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
+                }
+            } else if (a == 0) {
+                // XNOR, the block dropped: the leading part of the node, minor unchanged
+                if (lane == 0) sh.topm[D + 1] = sh.topm[D];
+                if (i < mc) {
+#pragma unroll
+                    for (int j = 0; j < hm; ++j)
+                        if (h0 + j < mc) C[i * cs + h0 + j] = row[j];
+                }
+            } else {
+                // XNOR, the block kept: 2 x 2 pivot block, its inverse applied to the pivot rows
+                const E a00 = P[mc * ps + mc], a01 = P[mc * ps + mc + 1];
+                const E a10 = P[(mc + 1) * ps + mc], a11 = P[(mc + 1) * ps + mc + 1];
+                E pc0 = F::zero(), pc1 = F::zero(), pr0 = F::zero(), pr1 = F::zero();
+                if (i < mc) {
+                    pc0 = P[i * ps + mc];
+                    pc1 = P[i * ps + mc + 1];
+                }
+                if (lane < mc) {
+                    pr0 = P[mc * ps + lane];
+                    pr1 = P[(mc + 1) * ps + lane];
+                }
+                const E det = F::det2(a00, a01, a10, a11);
+                const typename F::R r = F::recip(det);
+                if (lane < mc) {
+                    sh.wv[lane] = F::rowscale(F::upd(F::bmul(pr0, a11, 0), a01, pr1), r);
+                    sh.wv2[lane] = F::rowscale(F::upd(F::bmul(pr1, a00, 0), a10, pr0), r);
+                }
+                if (lane == 0) {
+                    const E mk = F::bmul(sh.topm[D], det, 0);
+                    sh.topm[D + 1] = mk;
+                    chk += F::fincheck(mk);
+                }
+                wave_sync();
+                if (i < mc) {
+#pragma unroll
+                    for (int j = 0; j < hm; ++j)
+                        if (h0 + j < mc)
+                            C[i * cs + h0 + j] = F::upd(F::upd(row[j], pc0, sh.wv[h0 + j]), pc1, sh.wv2[h0 + j]);
+                }
             }
             if constexpr (kLdsC) {
                 wave_sync();
@@ -131,14 +182,15 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                 wave_mem_fence();   // the child is the next level's node (and wv is rewritten)
             }
         }
-        xor_top<F, N, T, D + 1>(d0, s, A0, st, ob, sh, chk);
+        xor_top<F, N, T, D + 1, XN>(d0, s, A0, st, ob, sh, chk);
     }
 }
 
 // Subtree level J of a Q-level subtree: the children of the 2^J nodes in buf[J & 1]
 // (order 2(Q - J)) into buf[(J + 1) & 1], one row of a child per lane.  base is where the
-// children's depth T+J+1 starts in the output (2^(T+J+1) - 2).
-template <class F, int Q, int J>
+// children's depth T+J+1 starts in the output (2^(T+J+1) - 2; XOR only: the XNOR minors
+// are the 2^N leaves, written at the last level in block-mask order).
+template <class F, int Q, int J, bool XN>
 __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, XorLds<F>& sh, double& chk)
 {
     if constexpr (J < Q) {
@@ -147,41 +199,79 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         constexpr int m = 2 * (Q - J), mc = m - 2, kids = 2 << J;
         static_assert(kids <= 64 && kids * mc <= 64, "one pass per level");
         const int lane = threadIdx.x;
-        // child k of node k/2 keeps row mc + (k & 1) of the node's last block: its minor, and
-        // the pivot row times 1/pivot (lane k mc + j holds entry j)
-        if (lane < kids) {
-            const int p = mc + (lane & 1);
-            const E pv = sh.buf[cur][(lane >> 1) * m * xs(m) + p * xs(m) + p];
-            const E mk = F::bmul(sh.mn[cur][lane >> 1], pv, 0);
-            sh.mn[nxt][lane] = mk;
-            ob[base + ((int64_t)s << (J + 1)) + lane] = mk;
-            chk += F::fincheck(mk);
-        }
-        if constexpr (mc > 0) {
-            if (lane < kids * mc) {
-                const int k = lane / mc, j = lane - k * mc, p = mc + (k & 1);
-                const E* P = &sh.buf[cur][(k >> 1) * m * xs(m)];
-                sh.wk[lane] = F::rowscale(P[p * xs(m) + j], F::recip(P[p * xs(m) + p]));
+        if constexpr (!XN) {
+            // child k of node k/2 keeps row mc + (k & 1) of the node's last block: its minor,
+            // and the pivot row times 1/pivot (lane k mc + j holds entry j)
+            if (lane < kids) {
+                const int p = mc + (lane & 1);
+                const E pv = sh.buf[cur][(lane >> 1) * m * xs(m) + p * xs(m) + p];
+                const E mk = F::bmul(sh.mn[cur][lane >> 1], pv, 0);
+                sh.mn[nxt][lane] = mk;
+                ob[base + ((int64_t)s << (J + 1)) + lane] = mk;
+                chk += F::fincheck(mk);
+            }
+            if constexpr (mc > 0) {
+                if (lane < kids * mc) {
+                    const int k = lane / mc, j = lane - k * mc, p = mc + (k & 1);
+                    const E* P = &sh.buf[cur][(k >> 1) * m * xs(m)];
+                    sh.wk[lane] = F::rowscale(P[p * xs(m) + j], F::recip(P[p * xs(m) + p]));
+                }
+            }
+        } else {
+            // child 2v drops node v's last block (minor unchanged), child 2v+1 keeps it (minor
+            // times the pivot block's determinant; the inverse times the two pivot rows go to
+            // wk[v][0..1][...], lane 2 v mc + r mc + j holding entry j of row r)
+            if (lane < kids) {
+                const E* P = &sh.buf[cur][(lane >> 1) * m * xs(m)];
+                E mk = sh.mn[cur][lane >> 1];
+                if (lane & 1)
+                    mk = F::bmul(mk, F::det2(P[mc * xs(m) + mc], P[mc * xs(m) + mc + 1], P[(mc + 1) * xs(m) + mc],
+                                             P[(mc + 1) * xs(m) + mc + 1]), 0);
+                sh.mn[nxt][lane] = mk;
+                if constexpr (J == Q - 1) ob[((int64_t)s << Q) + lane] = mk;
+                chk += F::fincheck(mk);
+            }
+            if constexpr (mc > 0) {
+                if (lane < kids * mc) {
+                    const int v = lane / (2 * mc), rr = lane - v * 2 * mc, r = rr / mc, j = rr - r * mc;
+                    const E* P = &sh.buf[cur][v * m * xs(m)];
+                    const E a00 = P[mc * xs(m) + mc], a01 = P[mc * xs(m) + mc + 1];
+                    const E a10 = P[(mc + 1) * xs(m) + mc], a11 = P[(mc + 1) * xs(m) + mc + 1];
+                    const typename F::R rd = F::recip(F::det2(a00, a01, a10, a11));
+                    const E p0 = P[mc * xs(m) + j], p1 = P[(mc + 1) * xs(m) + j];
+                    sh.wk[lane] = r == 0 ? F::rowscale(F::upd(F::bmul(p0, a11, 0), a01, p1), rd)
+                                         : F::rowscale(F::upd(F::bmul(p1, a00, 0), a10, p0), rd);
+                }
             }
         }
         wave_sync();
         if constexpr (mc > 0) {
             if (lane < kids * mc) {
-                const int k = lane / mc, i = lane - k * mc, p = mc + (k & 1);
+                const int k = lane / mc, i = lane - k * mc;
                 const E* P = &sh.buf[cur][(k >> 1) * m * xs(m)];
-                const E ci = P[i * xs(m) + p];
-                const E* wr = &sh.wk[k * mc];
                 E* Cr = &sh.buf[nxt][k * mc * xs(mc) + i * xs(mc)];
+                if constexpr (!XN) {
+                    const E ci = P[i * xs(m) + mc + (k & 1)];
+                    const E* wr = &sh.wk[k * mc];
 #pragma unroll
-                for (int j = 0; j < mc; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
+                    for (int j = 0; j < mc; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
+                } else if ((k & 1) == 0) {
+#pragma unroll
+                    for (int j = 0; j < mc; ++j) Cr[j] = P[i * xs(m) + j];
+                } else {
+                    const E c0 = P[i * xs(m) + mc], c1 = P[i * xs(m) + mc + 1];
+                    const E* w0 = &sh.wk[(k >> 1) * 2 * mc];
+#pragma unroll
+                    for (int j = 0; j < mc; ++j) Cr[j] = F::upd(F::upd(P[i * xs(m) + j], c0, w0[j]), c1, w0[mc + j]);
+                }
             }
             wave_sync();
         }
-        xor_sub<F, Q, J + 1>(2 * base + 2, s, ob, sh, chk);   // depth T+J+2 starts at 2^(T+J+2) - 2
+        xor_sub<F, Q, J + 1, XN>(2 * base + 2, s, ob, sh, chk);   // XOR depth T+J+2 starts at 2^(T+J+2) - 2
     }
 }
 
-template <class F, int N>
+template <class F, int N, bool XN>
 __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict__ A, typename F::E* __restrict__ out,
                                                  int32_t* __restrict__ info, int32_t batch,
                                                  typename F::E* __restrict__ ws, int64_t ws_stride)
@@ -195,8 +285,8 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
     if (b >= batch) return;
     const int lane = threadIdx.x;
     const E* A0 = A + (int64_t)b * w * w;
-    E* ob = out + (int64_t)b * ((int64_t(2) << N) - 2);
-    constexpr int64_t nout = (int64_t(2) << N) - 2;
+    constexpr int64_t nout = XN ? (int64_t(1) << N) : (int64_t(2) << N) - 2;   // outputs per matrix
+    E* ob = out + (int64_t)b * nout;
 
     bool fin = true;
     for (int e = lane; e < w * w; e += 64) fin = fin && F::in_finite(A0[e]);
@@ -211,14 +301,14 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
     for (int s = 0; s < (1 << T); ++s) {
         // top levels: redo the path below the first choice that changed from s - 1
         const int d0 = s ? T - 1 - (31 - __clz((unsigned)(s ^ (s - 1)))) : 0;
-        xor_top<F, N, T, 0>(d0, s, A0, st, ob, sh, chk);
+        xor_top<F, N, T, 0, XN>(d0, s, A0, st, ob, sh, chk);
         // the subtree of depth-T node s, breadth first in LDS
         if constexpr (T == 0) {
             for (int e = lane; e < w * w; e += 64) sh.buf[0][(e / w) * xs(w) + e % w] = A0[e];
         }
         if (lane == 0) sh.mn[0][0] = sh.topm[T];
         wave_sync();
-        xor_sub<F, Q, 0>((int64_t(2) << T) - 2, s, ob, sh, chk);
+        xor_sub<F, Q, 0, XN>((int64_t(2) << T) - 2, s, ob, sh, chk);
     }
     const bool bad = __any(chk == 0.0 ? 0 : 1);
     if (info && lane == 0) info[b] = bad ? -3 : 0;
@@ -231,9 +321,15 @@ hipError_t xor_launch_n(const LaunchXor& L, hipStream_t st)
         return hipErrorInvalidValue;
     } else {
         if (L.n != N) return xor_launch_n<F, N + 1>(L, st);
-        hipLaunchKernelGGL((xor_kernel<F, N>), dim3((unsigned)L.batch), dim3(64), 0, st,
-                           static_cast<const typename F::E*>(L.A), static_cast<typename F::E*>(L.out), L.info,
-                           L.batch, static_cast<typename F::E*>(L.ws), L.ws_stride);
+        if (L.xnor) {
+            hipLaunchKernelGGL((xor_kernel<F, N, true>), dim3((unsigned)L.batch), dim3(64), 0, st,
+                               static_cast<const typename F::E*>(L.A), static_cast<typename F::E*>(L.out), L.info,
+                               L.batch, static_cast<typename F::E*>(L.ws), L.ws_stride);
+        } else {
+            hipLaunchKernelGGL((xor_kernel<F, N, false>), dim3((unsigned)L.batch), dim3(64), 0, st,
+                               static_cast<const typename F::E*>(L.A), static_cast<typename F::E*>(L.out), L.info,
+                               L.batch, static_cast<typename F::E*>(L.ws), L.ws_stride);
+        }
         return hipGetLastError();
     }
 }

@@ -215,3 +215,13 @@ def test_xor_validation(apm):
     assert f(2, None, _bd(apm), P, None, None) == apm.APM_EINVAL
     assert f(2, P, _bd(apm), None, None, None) == apm.APM_EINVAL
     assert f(2, P, None, P, None, None) == apm.APM_EINVAL
+
+
+def test_xnor_validation(apm):
+    f = apm.apm_xnor_minors
+    assert f(0, P, _bd(apm, batch=0), P, None, None) == apm.APM_OK
+    assert f(7, P, _bd(apm), P, None, None) == apm.APM_EINVAL
+    assert f(1, P, _bd(apm), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(0, P, _bd(apm, n=17), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(0, P, _bd(apm, ooff=P), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(0, P, _bd(apm), None, None, None) == apm.APM_EINVAL

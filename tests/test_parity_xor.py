@@ -1,7 +1,8 @@
 """GPU parity of the XOR minors (Sec. III XOR case; Sec. V.C Keldysh block matrices) with
 the oracle: element by element for every depth at small sizes (spanning the orders where
 the top levels run from the workspace), on sampled matrices at the full size of the
-benchmark, and the branch-signed sum that the largest-time identity sends to zero."""
+benchmark, and the branch-signed sum that the largest-time identity sends to zero.  The
+XNOR minors (Sec. III XNOR case) use the same kernel and are checked the same way."""
 import numpy as np
 import pytest
 
@@ -118,3 +119,54 @@ def test_error_codes(apm):
     # an empty batch is a no-op
     rc = apm.apm_xor_minors(apm.APM_C128, None, apm.make_batch(0, n), None, None, apm._stream(None))
     assert rc == apm.APM_OK
+
+
+def xnor_hadamard(A):
+    """Hadamard bound of the kept rows of every XNOR entry (block-mask order)."""
+    n = A.shape[0] // 2
+    out = np.ones(1 << n)
+    for mask in range(1, 1 << n):
+        r = [x for i in range(n) if mask >> i & 1 for x in (2 * i, 2 * i + 1)]
+        sub = A[np.ix_(r, r)]
+        out[mask] = np.prod(np.linalg.norm(sub, axis=1))
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 6, 7, 8, 10])
+def test_xnor_parity(apm, oracle_mod, n):
+    import torch
+    rng = np.random.default_rng(500 + n)
+    for cplx in (False, True):
+        A = rng.standard_normal((4, 2 * n, 2 * n)) + 3.0 * np.eye(2 * n)
+        if cplx:
+            A = A + 1j * rng.standard_normal((4, 2 * n, 2 * n))
+        out, info = apm.xnor_minors(torch.from_numpy(A).cuda())
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0)
+        got = out.cpu().numpy()
+        ref = oracle_mod.xnor_minors(A)
+        for b in range(4):
+            e = metrics.mixed_err(got[b], ref[b], xnor_hadamard(A[b]))
+            assert e.max() <= 1e-10, (n, cplx, b, float(e.max()))
+
+
+def test_xnor_keldysh_full_size_sampled(apm, oracle_mod):
+    """4096 Keldysh block matrices of 14 blocks, sampled matrices against the oracle."""
+    import torch
+    n = 14
+    A = W.keldysh_block(4096, n, seed=W.BASE_SEED + 4)
+    out, info = apm.xnor_minors(torch.from_numpy(A).cuda())
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    sel = np.random.default_rng(4097).choice(4096, 3, replace=False)
+    got = out[torch.from_numpy(sel).cuda()].cpu().numpy()
+    ref = oracle_mod.xnor_minors(A[sel])
+    masks = np.unique(np.concatenate([np.random.default_rng(1).integers(0, 1 << n, 400), [0, (1 << n) - 1]]))
+    for i in range(len(sel)):
+        H = np.ones(len(masks))
+        for t, mask in enumerate(masks):
+            r = [x for k in range(n) if mask >> k & 1 for x in (2 * k, 2 * k + 1)]
+            if r:
+                H[t] = np.prod(np.linalg.norm(A[sel[i]][np.ix_(r, r)], axis=1))
+        e = metrics.mixed_err(got[i][masks], ref[i][masks], H)
+        assert e.max() <= 1e-10, (int(sel[i]), float(e.max()))
