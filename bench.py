@@ -297,7 +297,13 @@ def run_extra(torch, apm, W, np, steps):
     by = K2r.numel() * 8 + xr.numel() * 8
     ex["xor_n14_4096_r64"] = {"ms": round(ms, 4), "matrices_per_s": round(4096 / (ms * 1e-3), 1),
                               "GBs": round(by / (ms * 1e-3) / 1e9, 1)}
-    del K2, xo, K2r, xr
+    # XNOR minors (whole-block subsets, Sec. III) of the same complex batch
+    xn = torch.empty((4096, 1 << 14), dtype=torch.complex128, device="cuda")
+    ms = time_fn(torch, lambda: apm.xnor_minors(K2, out=xn, info=xi), steps)
+    by = K2.numel() * 16 + xn.numel() * 16
+    ex["xnor_keldysh_n14_4096_c128"] = {"ms": round(ms, 4), "matrices_per_s": round(4096 / (ms * 1e-3), 1),
+                                        "GBs": round(by / (ms * 1e-3) / 1e9, 1)}
+    del K2, xo, K2r, xr, xn
     for k, v in ex.items():
         log(f"{k}: {v}")
     return ex
