@@ -15,6 +15,7 @@ bit k <-> row/column k, out[0] = det of the empty matrix = 1):
 * ``perm_minors(A)``       -- Sec. IV: Ryser's formula per subset, with the
                               (-1)^|S| factor the printed Eq. (ryser) drops.
 * ``xnor_minors(A)``       -- Sec. III, XNOR case: det of every whole-block subset.
+* ``leading_minors(A)``    -- Sec. III: det of every leading k x k submatrix.
 * ``xor_minors(A)``        -- Sec. III, XOR case: det of every one-row-per-block
                               choice of a 2n x 2n block matrix, and of the trailing
                               k blocks for every depth k < n.
@@ -79,7 +80,8 @@ def load_library(path: str):
     lib.apm_oracle_cs_scale.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int]
     lib.apm_oracle_cs_scale.restype = ctypes.c_int
     for name in ("apm_oracle_xor_minors_r64", "apm_oracle_xor_minors_c128", "apm_oracle_xnor_minors_r64",
-                 "apm_oracle_xnor_minors_c128"):
+                 "apm_oracle_xnor_minors_c128", "apm_oracle_leading_minors_r64",
+                 "apm_oracle_leading_minors_c128"):
         fn = getattr(lib, name)
         fn.argtypes = [ctypes.c_int, dp, dp]
         fn.restype = ctypes.c_int
@@ -216,6 +218,27 @@ def xnor_minors(A, lib=None) -> np.ndarray:
     out = np.empty((B, 1 << n), dtype=A.dtype)
     L = _load(lib)
     fn = L.apm_oracle_xnor_minors_c128 if cplx else L.apm_oracle_xnor_minors_r64
+    for b in range(B):
+        src = A[b].view(np.float64) if cplx else A[b]
+        dst = out[b].view(np.float64) if cplx else out[b]
+        if fn(n, _dp(src), _dp(dst)) != 0:
+            raise ValueError("oracle: bad matrix order")
+    return out[0] if single else out
+
+
+def leading_minors(A, lib=None) -> np.ndarray:
+    """Leading principal minors (Sec. III): entry k-1 is det A[:k, :k], k = 1..n.  Real or
+    complex (B, n, n) or (n, n); returns (B, n) (or one row)."""
+    A = np.asarray(A)
+    single = A.ndim == 2
+    if single:
+        A = A[None]
+    cplx = np.iscomplexobj(A)
+    A = np.ascontiguousarray(A, dtype=np.complex128 if cplx else np.float64)
+    B, n, _ = A.shape
+    out = np.empty((B, n), dtype=A.dtype)
+    L = _load(lib)
+    fn = L.apm_oracle_leading_minors_c128 if cplx else L.apm_oracle_leading_minors_r64
     for b in range(B):
         src = A[b].view(np.float64) if cplx else A[b]
         dst = out[b].view(np.float64) if cplx else out[b]

@@ -445,6 +445,47 @@ int apm_oracle_xnor_minors_c128(int n, const double *A, double *out)
     return 0;
 }
 
+/* Leading principal minors (Sec. III, "Leading principal minors"): out[k-1] = det of the
+ * leading k x k submatrix, k = 1..n (the subsets with masks 2^k - 1).  Each is a separate
+ * partial-pivoting LU of the gathered matrix. */
+static int lead_order(int k)
+{
+#if ORACLE_PLANT == 10
+    return k > 1 ? k - 1 : k;
+#else
+    return k;
+#endif
+}
+
+int apm_oracle_leading_minors_r64(int n, const double *A, double *out)
+{
+    if (n < 1 || n > ORACLE_MAX_W) return -1;
+    double sub[ORACLE_MAX_W * ORACLE_MAX_W];
+    for (int k = 1; k <= n; ++k) {
+        const int q = lead_order(k);
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b) sub[a * q + b] = A[a * n + b];
+        out[k - 1] = det_real_inplace(q, sub);
+    }
+    return 0;
+}
+
+int apm_oracle_leading_minors_c128(int n, const double *A, double *out)
+{
+    if (n < 1 || n > ORACLE_MAX_W) return -1;
+    double sub[2 * ORACLE_MAX_W * ORACLE_MAX_W];
+    for (int k = 1; k <= n; ++k) {
+        const int q = lead_order(k);
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b) {
+                sub[2 * (a * q + b)]     = A[2 * (a * n + b)];
+                sub[2 * (a * q + b) + 1] = A[2 * (a * n + b) + 1];
+            }
+        det_cplx_inplace(q, sub, &out[2 * (k - 1)]);
+    }
+    return 0;
+}
+
 typedef int (*oracle_fn)(int, const double *, double *);
 
 static int run_batch(oracle_fn fn, int width, int B, const int32_t *n, const int64_t *in_off,

@@ -572,3 +572,39 @@ def pin_xnor_lapack(xnor):
 
 
 XNOR_PINS = [pin_xnor_leibniz, pin_xnor_block_diagonal, pin_xnor_block_similarity, pin_xnor_lapack]
+
+
+# ----------------------------------------------------------------------------------
+# leading principal minors (Sec. III)
+# ----------------------------------------------------------------------------------
+def pin_lead_triangular(lead):
+    """Lower triangular: the running products of the diagonal."""
+    rng = _rng(91)
+    n = 12
+    A = np.tril(rng.standard_normal((n, n))) + 1j * np.tril(rng.standard_normal((n, n)))
+    assert close(lead(A), np.cumprod(np.diag(A)), 1e-13, 1e-15)
+
+
+def pin_lead_leibniz(lead):
+    rng = _rng(92)
+    for n in (1, 2, 3, 5):
+        A = rng.standard_normal((n, n))
+        out = lead(A)
+        for k in range(1, n + 1):
+            ref = leibniz_det(A[:k, :k])
+            assert abs(out[k - 1] - ref) <= 1e-12 * max(1.0, abs(ref)), (n, k)
+
+
+def pin_lead_ratio(lead):
+    """det A[:k,:k] / det A[:k-1,:k-1] is the last pivot of elimination without row
+    exchanges, i.e. 1 / (A[:k,:k]^-1)[k-1, k-1] (Cramer's rule)."""
+    rng = _rng(93)
+    n = 9
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 3 * np.eye(n)
+    out = lead(A)
+    for k in range(2, n + 1):
+        piv = 1.0 / np.linalg.inv(A[:k, :k])[k - 1, k - 1]
+        assert abs(out[k - 1] / out[k - 2] - piv) <= 1e-11 * abs(piv), k
+
+
+LEAD_PINS = [pin_lead_triangular, pin_lead_leibniz, pin_lead_ratio]

@@ -25,6 +25,11 @@ def test_perm_pins(oracle_mod, pin):
     pin(oracle_mod.perm_minors)
 
 
+@pytest.mark.parametrize("pin", P.LEAD_PINS, ids=lambda f: f.__name__)
+def test_leading_minor_pins(oracle_mod, pin):
+    pin(oracle_mod.leading_minors)
+
+
 @pytest.mark.parametrize("pin", P.XNOR_PINS, ids=lambda f: f.__name__)
 def test_xnor_minor_pins(oracle_mod, pin):
     pin(oracle_mod.xnor_minors)

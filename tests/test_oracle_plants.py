@@ -18,6 +18,7 @@ PLANTS = {
     7: ("xor", "the other row of every block kept"),
     8: ("xor", "columns taken from the other branch of each block"),
     9: ("xnor", "the first row of a kept block taken twice"),
+    10: ("lead", "entry k holds the leading minor of order k - 1"),
 }
 
 
@@ -32,6 +33,8 @@ def test_planted_mistake_is_caught(oracle_mod, plant):
             fn, pins = (lambda A: oracle_mod.minors(A, lib=lib)), P.MINOR_PINS
         elif kind == "cminors":
             fn, pins = (lambda A: oracle_mod.minors_complex(A, lib=lib)), P.CMINOR_PINS
+        elif kind == "lead":
+            fn, pins = (lambda A: oracle_mod.leading_minors(A, lib=lib)), P.LEAD_PINS
         elif kind == "xnor":
             fn, pins = (lambda A: oracle_mod.xnor_minors(A, lib=lib)), P.XNOR_PINS
         elif kind == "xor":
