@@ -63,6 +63,7 @@ typedef enum {
 #define APM_MAX_N_CS 20       /* largest order accepted by apm_connected_sums             */
 #define APM_MAX_N_PERM 16     /* largest order accepted by apm_all_perm_minors            */
 #define APM_MAX_N_XOR 16      /* most 2 x 2 blocks accepted by apm_xor_minors             */
+#define APM_MAX_N_LEAD 32     /* largest order accepted by apm_leading_minors             */
 
 /* opaque HIP stream (binary compatible with hipStream_t); NULL = the default stream */
 typedef struct ihipStream_t *apm_stream;
@@ -201,6 +202,22 @@ apm_status apm_xor_minors(apm_dtype dt, const void *A, const apm_batch *bd, void
  */
 apm_status apm_xnor_minors(apm_dtype dt, const void *A, const apm_batch *bd, void *out, int32_t *info,
                            apm_stream stream);
+
+/*
+ * apm_leading_minors -- the n leading principal minors det A[:k, :k], k = 1..n.
+ *
+ * Passage: Sec. III, "Leading principal minors" (successive Schur complements give the
+ * minors of the subsets 2^k - 1 in O(n^3); no pivot correction is possible).
+ *
+ *   dt      APM_R64 or APM_C128 (others APM_EUNSUPPORTED).
+ *   A       [B x n x n] row-major input; bd uniform, 1 <= n <= APM_MAX_N_LEAD, no offsets.
+ *   out     [B x n]: out[b][k-1] = det A_b[:k, :k].
+ *   info    [B] int32 or NULL: 0, -2 non-finite input (outputs NaN), -3 non-finite output
+ *           (a zero pivot: elimination runs without row exchanges).
+ * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED or APM_EDEVICE.
+ */
+apm_status apm_leading_minors(apm_dtype dt, const void *A, const apm_batch *bd, void *out, int32_t *info,
+                              apm_stream stream);
 
 /*
  * apm_autotune_minors -- pick the per-order layout of apm_all_minors by measurement.

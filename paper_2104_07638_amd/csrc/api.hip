@@ -636,6 +636,19 @@ apm_status apm_xnor_minors(apm_dtype dt, const void* A, const apm_batch* bd, voi
     return block_minors(true, dt, A, bd, out, info, stream);
 }
 
+apm_status apm_leading_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
+                              apm_stream stream)
+{
+    if ((int)dt < 0 || (int)dt > 3) return APM_EINVAL;
+    if (bad_batch(bd, APM_MAX_N_LEAD)) return APM_EINVAL;
+    if (dt != APM_R64 && dt != APM_C128) return APM_EUNSUPPORTED;
+    if (bd->n_uniform == 0 || bd->in_off || bd->out_off) return APM_EUNSUPPORTED;
+    if (bd->n_uniform > APM_MAX_N_LEAD) return APM_EUNSUPPORTED;
+    if (bd->batch == 0) return APM_OK;
+    if (!A || !out) return APM_EINVAL;
+    return from_hip(apm::lead_launch((int)dt, A, out, info, bd->batch, bd->n_uniform, (hipStream_t)stream));
+}
+
 apm_status apm_plan_create(const apm_plan_desc* d, apm_plan** out)
 {
     if (!out) return APM_EINVAL;

@@ -87,6 +87,9 @@ struct LaunchXor {
 int64_t xor_ws_elems(int n);
 hipError_t xor_launch(const LaunchXor& L, hipStream_t st);
 
+// Leading principal minors: [batch][n] of [batch][n][n] (dtype R64 or C128, n <= 32).
+hipError_t lead_launch(int dtype, const void* A, void* out, int32_t* info, int32_t batch, int n, hipStream_t st);
+
 // ---------------------------------------------------------------- proposal network
 struct MlpNet {
     int dp, op;                // padded input / output sizes

@@ -225,3 +225,12 @@ def test_xnor_validation(apm):
     assert f(0, P, _bd(apm, n=17), P, None, None) == apm.APM_EUNSUPPORTED
     assert f(0, P, _bd(apm, ooff=P), P, None, None) == apm.APM_EUNSUPPORTED
     assert f(0, P, _bd(apm), None, None, None) == apm.APM_EINVAL
+
+
+def test_leading_validation(apm):
+    f = apm.apm_leading_minors
+    assert f(0, P, _bd(apm, batch=0), P, None, None) == apm.APM_OK
+    assert f(5, P, _bd(apm), P, None, None) == apm.APM_EINVAL
+    assert f(3, P, _bd(apm), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(0, P, _bd(apm, n=33), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(0, None, _bd(apm), P, None, None) == apm.APM_EINVAL
