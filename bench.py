@@ -281,6 +281,14 @@ def run_extra(torch, apm, W, np, steps):
     ms = time_fn(torch, lambda: apm.all_perm_minors(P, out=po), steps)
     ex["perm_n12_2048"] = {"ms": round(ms, 4), "matrices_per_s": round(2048 / (ms * 1e-3), 1),
                            "products_per_s": round(2048 * 3 ** 12 / (ms * 1e-3), 1)}
+    # leading principal minors of the headline lattice batch (8192 x n = 16)
+    LA = torch.from_numpy(W.lattice_batch(8192, 16, W.Lattice(32, 1.0, -0.5, 5.0), seed=W.BASE_SEED + 2)).cuda()
+    lo = torch.empty((8192, 16), dtype=torch.float64, device="cuda")
+    li = torch.empty(8192, dtype=torch.int32, device="cuda")
+    ms = time_fn(torch, lambda: apm.leading_minors(LA, out=lo, info=li), steps)
+    ex["leading_n16_8192_r64"] = {"ms": round(ms, 4), "matrices_per_s": round(8192 / (ms * 1e-3), 1),
+                                  "GBs": round((LA.numel() + lo.numel()) * 8 / (ms * 1e-3) / 1e9, 1)}
+    del LA, lo, li
     # XOR minors (Keldysh-index determinants): 4096 Keldysh block matrices of 14 blocks
     # (28 x 28 complex128), every branch assignment and the trailing-block side products
     K2 = torch.from_numpy(W.keldysh_block(4096, 14, seed=W.BASE_SEED + 4)).cuda()
