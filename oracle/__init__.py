@@ -16,6 +16,8 @@ bit k <-> row/column k, out[0] = det of the empty matrix = 1):
                               (-1)^|S| factor the printed Eq. (ryser) drops.
 * ``xnor_minors(A)``       -- Sec. III, XNOR case: det of every whole-block subset.
 * ``leading_minors(A)``    -- Sec. III: det of every leading k x k submatrix.
+* ``nand_minors(A)``       -- Sec. III, NAND case: det of every at-most-one-row-per-block
+                              subset.
 * ``xor_minors(A)``        -- Sec. III, XOR case: det of every one-row-per-block
                               choice of a 2n x 2n block matrix, and of the trailing
                               k blocks for every depth k < n.
@@ -81,7 +83,7 @@ def load_library(path: str):
     lib.apm_oracle_cs_scale.restype = ctypes.c_int
     for name in ("apm_oracle_xor_minors_r64", "apm_oracle_xor_minors_c128", "apm_oracle_xnor_minors_r64",
                  "apm_oracle_xnor_minors_c128", "apm_oracle_leading_minors_r64",
-                 "apm_oracle_leading_minors_c128"):
+                 "apm_oracle_leading_minors_c128", "apm_oracle_nand_minors_r64", "apm_oracle_nand_minors_c128"):
         fn = getattr(lib, name)
         fn.argtypes = [ctypes.c_int, dp, dp]
         fn.restype = ctypes.c_int
@@ -218,6 +220,32 @@ def xnor_minors(A, lib=None) -> np.ndarray:
     out = np.empty((B, 1 << n), dtype=A.dtype)
     L = _load(lib)
     fn = L.apm_oracle_xnor_minors_c128 if cplx else L.apm_oracle_xnor_minors_r64
+    for b in range(B):
+        src = A[b].view(np.float64) if cplx else A[b]
+        dst = out[b].view(np.float64) if cplx else out[b]
+        if fn(n, _dp(src), _dp(dst)) != 0:
+            raise ValueError("oracle: bad matrix order")
+    return out[0] if single else out
+
+
+def nand_minors(A, lib=None) -> np.ndarray:
+    """NAND principal minors of 2n x 2n matrices of 2 x 2 blocks (Sec. III, NAND case):
+    entry sum_i t_i 3^i (t_i = 0: block i left out, 1: row 2i kept, 2: row 2i+1 kept) is the
+    determinant over the kept rows (entry 0 = 1).  Real or complex (B, 2n, 2n) or (2n, 2n);
+    returns (B, 3^n)."""
+    A = np.asarray(A)
+    single = A.ndim == 2
+    if single:
+        A = A[None]
+    cplx = np.iscomplexobj(A)
+    A = np.ascontiguousarray(A, dtype=np.complex128 if cplx else np.float64)
+    B, w, _ = A.shape
+    if w % 2:
+        raise ValueError("nand_minors: the order must be even (2 x 2 blocks)")
+    n = w // 2
+    out = np.empty((B, 3 ** n), dtype=A.dtype)
+    L = _load(lib)
+    fn = L.apm_oracle_nand_minors_c128 if cplx else L.apm_oracle_nand_minors_r64
     for b in range(B):
         src = A[b].view(np.float64) if cplx else A[b]
         dst = out[b].view(np.float64) if cplx else out[b]

@@ -486,6 +486,65 @@ int apm_oracle_leading_minors_c128(int n, const double *A, double *out)
     return 0;
 }
 
+/* NAND principal minors of a 2n x 2n matrix of 2 x 2 blocks (Sec. III, the NAND case): the
+ * principal minors that keep at most one of the rows/columns 2i, 2i+1 of every block i.
+ * The choice of block i is the ternary digit t_i (0: neither row, 1: row 2i, 2: row
+ * 2i+1); out[sum_i t_i 3^i] = det A[R, R] over the kept rows, out[0] = 1 (3^n entries).
+ * Each determinant is a separate partial-pivoting LU of the gathered matrix. */
+static int nand_rows(int n, uint32_t code, int *idx)
+{
+    int k = 0;
+    for (int i = 0; i < n; ++i, code /= 3u) {
+        const uint32_t t = code % 3u;
+#if ORACLE_PLANT == 11
+        if (t) idx[k++] = 2 * i + (int)(2u - t);
+#else
+        if (t) idx[k++] = 2 * i + (int)(t - 1u);
+#endif
+    }
+    return k;
+}
+
+static uint32_t pow3u(int n)
+{
+    uint32_t p = 1;
+    for (int i = 0; i < n; ++i) p *= 3u;
+    return p;
+}
+
+int apm_oracle_nand_minors_r64(int n, const double *A, double *out)
+{
+    if (n < 1 || 2 * n > ORACLE_MAX_W || n > 16) return -1;
+    const int w = 2 * n;
+    double sub[ORACLE_MAX_W * ORACLE_MAX_W];
+    int idx[ORACLE_MAX_W];
+    for (uint32_t code = 0; code < pow3u(n); ++code) {
+        const int k = nand_rows(n, code, idx);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) sub[a * k + b] = A[idx[a] * w + idx[b]];
+        out[code] = det_real_inplace(k, sub);
+    }
+    return 0;
+}
+
+int apm_oracle_nand_minors_c128(int n, const double *A, double *out)
+{
+    if (n < 1 || 2 * n > ORACLE_MAX_W || n > 16) return -1;
+    const int w = 2 * n;
+    double sub[2 * ORACLE_MAX_W * ORACLE_MAX_W];
+    int idx[ORACLE_MAX_W];
+    for (uint32_t code = 0; code < pow3u(n); ++code) {
+        const int k = nand_rows(n, code, idx);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+                sub[2 * (a * k + b)]     = A[2 * (idx[a] * w + idx[b])];
+                sub[2 * (a * k + b) + 1] = A[2 * (idx[a] * w + idx[b]) + 1];
+            }
+        det_cplx_inplace(k, sub, &out[2 * code]);
+    }
+    return 0;
+}
+
 typedef int (*oracle_fn)(int, const double *, double *);
 
 static int run_batch(oracle_fn fn, int width, int B, const int32_t *n, const int64_t *in_off,

@@ -608,3 +608,77 @@ def pin_lead_ratio(lead):
 
 
 LEAD_PINS = [pin_lead_triangular, pin_lead_leibniz, pin_lead_ratio]
+
+
+# ----------------------------------------------------------------------------------
+# NAND minors of 2n x 2n block matrices (Sec. III, NAND case)
+# ----------------------------------------------------------------------------------
+def _nand_rows(n, code):
+    r = []
+    for i in range(n):
+        t = code % 3
+        code //= 3
+        if t:
+            r.append(2 * i + t - 1)
+    return r
+
+
+def pin_nand_leibniz(nand):
+    rng = _rng(101)
+    for n in (1, 2, 3):
+        for cplx in (False, True):
+            A = rng.standard_normal((2 * n, 2 * n))
+            if cplx:
+                A = A + 1j * rng.standard_normal((2 * n, 2 * n))
+            out = nand(A)
+            assert out[0] == 1.0
+            for code in range(1, 3 ** n):
+                r = _nand_rows(n, code)
+                ref = leibniz_det(A[np.ix_(r, r)])
+                assert abs(out[code] - ref) <= 1e-12 * max(1.0, abs(ref)), (n, code)
+
+
+def pin_nand_contains_xor(nand):
+    """The entries with no block left out are the order-n XOR minors (Sec. III): choice
+    word beta maps to code sum_i (beta_i + 1) 3^i; they are the polynomial matrix's top
+    coefficients in the paper's alpha reading, checked here against determinants."""
+    rng = _rng(102)
+    n = 5
+    A = rng.standard_normal((2 * n, 2 * n)) + 1j * rng.standard_normal((2 * n, 2 * n))
+    out = nand(A)
+    for beta in range(1 << n):
+        code = sum(((beta >> i & 1) + 1) * 3 ** i for i in range(n))
+        r = [2 * i + (beta >> i & 1) for i in range(n)]
+        ref = np.linalg.det(A[np.ix_(r, r)])
+        assert abs(out[code] - ref) <= 1e-11 * max(1.0, abs(ref)), beta
+
+
+def pin_nand_block_diagonal(nand):
+    """Zero off-diagonal blocks and diagonal 2 x 2 blocks: each minor is the product of the
+    kept diagonal entries."""
+    rng = _rng(103)
+    n = 6
+    A = np.zeros((2 * n, 2 * n))
+    for i in range(n):
+        A[2 * i:2 * i + 2, 2 * i:2 * i + 2] = rng.standard_normal((2, 2))
+    out = nand(A)
+    d = np.diag(A)
+    ref = np.array([np.prod([d[r] for r in _nand_rows(n, c)]) for c in range(3 ** n)])
+    assert close(out, ref, 1e-13, 1e-15)
+
+
+def pin_nand_sum(nand):
+    """With every off-diagonal block zero, the sum of all NAND minors factorises into
+    prod_i (1 + A[2i, 2i] + A[2i+1, 2i+1]) (each block contributes nothing or one of its
+    two diagonal entries)."""
+    rng = _rng(104)
+    n = 7
+    A = np.zeros((2 * n, 2 * n))
+    for i in range(n):
+        A[2 * i:2 * i + 2, 2 * i:2 * i + 2] = rng.standard_normal((2, 2))
+    out = nand(A)
+    ref = np.prod([1 + A[2 * i, 2 * i] + A[2 * i + 1, 2 * i + 1] for i in range(n)])
+    assert abs(out.sum() - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+NAND_PINS = [pin_nand_leibniz, pin_nand_contains_xor, pin_nand_block_diagonal, pin_nand_sum]

@@ -25,6 +25,11 @@ def test_perm_pins(oracle_mod, pin):
     pin(oracle_mod.perm_minors)
 
 
+@pytest.mark.parametrize("pin", P.NAND_PINS, ids=lambda f: f.__name__)
+def test_nand_minor_pins(oracle_mod, pin):
+    pin(oracle_mod.nand_minors)
+
+
 @pytest.mark.parametrize("pin", P.LEAD_PINS, ids=lambda f: f.__name__)
 def test_leading_minor_pins(oracle_mod, pin):
     pin(oracle_mod.leading_minors)

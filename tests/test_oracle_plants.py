@@ -19,6 +19,7 @@ PLANTS = {
     8: ("xor", "columns taken from the other branch of each block"),
     9: ("xnor", "the first row of a kept block taken twice"),
     10: ("lead", "entry k holds the leading minor of order k - 1"),
+    11: ("nand", "the two kept-row choices of a block swapped"),
 }
 
 
@@ -33,6 +34,8 @@ def test_planted_mistake_is_caught(oracle_mod, plant):
             fn, pins = (lambda A: oracle_mod.minors(A, lib=lib)), P.MINOR_PINS
         elif kind == "cminors":
             fn, pins = (lambda A: oracle_mod.minors_complex(A, lib=lib)), P.CMINOR_PINS
+        elif kind == "nand":
+            fn, pins = (lambda A: oracle_mod.nand_minors(A, lib=lib)), P.NAND_PINS
         elif kind == "lead":
             fn, pins = (lambda A: oracle_mod.leading_minors(A, lib=lib)), P.LEAD_PINS
         elif kind == "xnor":
