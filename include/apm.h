@@ -64,6 +64,7 @@ typedef enum {
 #define APM_MAX_N_PERM 16     /* largest order accepted by apm_all_perm_minors            */
 #define APM_MAX_N_XOR 16      /* most 2 x 2 blocks accepted by apm_xor_minors             */
 #define APM_MAX_N_LEAD 32     /* largest order accepted by apm_leading_minors             */
+#define APM_MAX_N_NAND 13     /* most 2 x 2 blocks accepted by apm_nand_minors (3^n out)  */
 
 /* opaque HIP stream (binary compatible with hipStream_t); NULL = the default stream */
 typedef struct ihipStream_t *apm_stream;
@@ -201,6 +202,24 @@ apm_status apm_xor_minors(apm_dtype dt, const void *A, const apm_batch *bd, void
  * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED, APM_ENOMEM or APM_EDEVICE.
  */
 apm_status apm_xnor_minors(apm_dtype dt, const void *A, const apm_batch *bd, void *out, int32_t *info,
+                           apm_stream stream);
+
+/*
+ * apm_nand_minors -- NAND principal minors of 2n x 2n matrices of 2 x 2 blocks.
+ *
+ * Passage: Sec. III, the NAND case (the principal minors that keep at most one of the
+ * rows/columns 2i, 2i+1 of every block i: the ternary tree whose branches leave the block
+ * out or take the Schur complement over one of its two diagonal entries, O(3^n)).
+ *
+ *   dt, A, info, stream   as for apm_xor_minors (info -3: a zero pivot; no pivot shifts
+ *           are made).
+ *   bd      uniform batch, n_uniform = n blocks, 1 <= n <= APM_MAX_N_NAND, no offsets.
+ *   out     [B x 3^n]: entry sum_i t_i 3^i is the determinant over the kept rows, with
+ *           t_i = 0 (block i left out), 1 (row 2i kept) or 2 (row 2i+1 kept); entry 0 = 1.
+ * Uses the same per-(device, stream) workspace as apm_xor_minors.
+ * Returns APM_OK, APM_EINVAL, APM_EUNSUPPORTED, APM_ENOMEM or APM_EDEVICE.
+ */
+apm_status apm_nand_minors(apm_dtype dt, const void *A, const apm_batch *bd, void *out, int32_t *info,
                            apm_stream stream);
 
 /*

@@ -11,6 +11,7 @@ Operations (Simkovic & Ferrero, arXiv:2104.07638):
   determinants of every Keldysh index assignment of a 2n x 2n block matrix.
 * ``apm_xnor_minors`` / ``xnor_minors``       -- Sec. III (XNOR case): whole-block minors.
 * ``apm_leading_minors`` / ``leading_minors`` -- Sec. III: the n leading principal minors.
+* ``apm_nand_minors`` / ``nand_minors``       -- Sec. III (NAND case): at most one row per block.
 * ``apm_mc_*`` / ``apm_mlp_*`` (``include/apm_mc.h``) -- Metropolis-Hastings steps over
   vertex configurations weighted by |c[V]| (Sec. V.A), with a learned proposal network
   trained by the library's own forward/backward/Adam kernels (``Mlp``, ``mc_step``).
@@ -32,7 +33,7 @@ LIB_PATH = os.path.join(_HERE, "libapm.so")
 
 APM_OK, APM_EINVAL, APM_EUNSUPPORTED, APM_EDEVICE, APM_ENOMEM = 0, 1, 2, 3, 4
 APM_R64, APM_R32S, APM_C128, APM_C64S = 0, 1, 2, 3
-APM_MAX_N, APM_MAX_N_CS, APM_MAX_N_PERM, APM_MAX_N_XOR, APM_MAX_N_LEAD = 20, 20, 16, 16, 32
+APM_MAX_N, APM_MAX_N_CS, APM_MAX_N_PERM, APM_MAX_N_XOR, APM_MAX_N_LEAD, APM_MAX_N_NAND = 20, 20, 16, 16, 32, 13
 APM_OUT_F64, APM_NO_PERTURB = 1, 2
 APM_CS_ROOTED, APM_CS_ALL, APM_CS_WEIGHTS = 0, 1, 2
 APM_PLAN_MINORS, APM_PLAN_CONNECTED_SUMS, APM_PLAN_PERM_MINORS, APM_PLAN_CDET = 0, 1, 2, 3
@@ -48,7 +49,7 @@ EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_s
            "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
            "apm_minors_k0", "apm_plan_create", "apm_plan_launch", "apm_plan_k0", "apm_plan_graphed",
            "apm_plan_destroy", "apm_last_device_error", "apm_xor_minors", "apm_xnor_minors",
-           "apm_leading_minors")
+           "apm_leading_minors", "apm_nand_minors")
 
 APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
@@ -118,7 +119,7 @@ def _load():
     lib.apm_all_perm_minors.argtypes = [vp, ctypes.POINTER(apm_batch), vp, vp]
     lib.apm_all_perm_minors.restype = ctypes.c_int
     for name in ("apm_xor_minors", "apm_xnor_minors",
-           "apm_leading_minors"):
+           "apm_leading_minors", "apm_nand_minors"):
         getattr(lib, name).argtypes = [ctypes.c_int, vp, ctypes.POINTER(apm_batch), vp, vp, vp]
         getattr(lib, name).restype = ctypes.c_int
     lib.apm_status_str.argtypes = [ctypes.c_int]
@@ -191,6 +192,10 @@ def apm_xor_minors(dt, A, bd, out, info, stream):
 
 def apm_xnor_minors(dt, A, bd, out, info, stream):
     return _lib.apm_xnor_minors(int(dt), A, ctypes.byref(bd) if bd is not None else None, out, info, stream)
+
+
+def apm_nand_minors(dt, A, bd, out, info, stream):
+    return _lib.apm_nand_minors(int(dt), A, ctypes.byref(bd) if bd is not None else None, out, info, stream)
 
 
 def apm_leading_minors(dt, A, bd, out, info, stream):
@@ -388,6 +393,24 @@ def xnor_minors(A, *, out=None, info=None, stream=None):
     return out, info
 
 
+def nand_minors(A, *, out=None, info=None, stream=None):
+    """NAND principal minors of a (B, 2n, 2n) float64 or complex128 tensor of 2 x 2 blocks:
+    (B, 3**n), entry sum_i t_i 3**i with t_i = 0 (block i out), 1 (row 2i), 2 (row 2i+1)."""
+    if A.dim() != 3 or A.shape[1] != A.shape[2] or A.shape[1] % 2:
+        raise ValueError("A must be (B, 2n, 2n)")
+    if not A.is_cuda or not A.is_contiguous() or A.dtype not in (torch.float64, torch.complex128):
+        raise TypeError("A must be a contiguous float64 or complex128 CUDA tensor")
+    B, n = A.shape[0], A.shape[1] // 2
+    dt = APM_C128 if A.dtype == torch.complex128 else APM_R64
+    if out is None:
+        out = torch.empty((B, 3 ** n), dtype=A.dtype, device=A.device)
+    if info is None:
+        info = torch.empty(B, dtype=torch.int32, device=A.device)
+    _check(apm_nand_minors(dt, _ptr(A), make_batch(B, n), _ptr(out), _ptr(info), _stream(stream)),
+           "apm_nand_minors")
+    return out, info
+
+
 def leading_minors(A, *, out=None, info=None, stream=None):
     """Leading principal minors det A[:k, :k] (k = 1..n) of a (B, n, n) float64 or
     complex128 tensor: (B, n)."""
@@ -402,7 +425,7 @@ def leading_minors(A, *, out=None, info=None, stream=None):
     if info is None:
         info = torch.empty(B, dtype=torch.int32, device=A.device)
     _check(apm_leading_minors(dt, _ptr(A), make_batch(B, n), _ptr(out), _ptr(info), _stream(stream)),
-           "apm_leading_minors")
+           "apm_leading_minors", "apm_nand_minors")
     return out, info
 
 

@@ -595,14 +595,14 @@ apm_status apm_all_perm_minors(const double* A, const apm_batch* bd, double* per
 
 namespace {
 
-apm_status block_minors(bool xnor, apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
+apm_status block_minors(int mode, apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
                         apm_stream stream)
 {
     if ((int)dt < 0 || (int)dt > 3) return APM_EINVAL;
     if (bad_batch(bd, APM_MAX_N_XOR)) return APM_EINVAL;
     if (dt != APM_R64 && dt != APM_C128) return APM_EUNSUPPORTED;
     if (bd->n_uniform == 0 || bd->in_off || bd->out_off) return APM_EUNSUPPORTED;
-    if (bd->n_uniform > APM_MAX_N_XOR) return APM_EUNSUPPORTED;
+    if (bd->n_uniform > (mode == 2 ? APM_MAX_N_NAND : APM_MAX_N_XOR)) return APM_EUNSUPPORTED;
     if (bd->batch == 0) return APM_OK;
     if (!A || !out) return APM_EINVAL;
     apm::LaunchXor L{};
@@ -612,8 +612,8 @@ apm_status block_minors(bool xnor, apm_dtype dt, const void* A, const apm_batch*
     L.info = info;
     L.batch = bd->batch;
     L.n = bd->n_uniform;
-    L.xnor = xnor ? 1 : 0;
-    L.ws_stride = apm::xor_ws_elems(L.n);
+    L.mode = mode;
+    L.ws_stride = apm::xor_ws_elems(L.n, mode);
     if (L.ws_stride > 0) {
         const size_t bytes = (size_t)L.ws_stride * (size_t)bd->batch * (dt == APM_C128 ? 16 : 8);
         apm_status s = get_xor_ws((hipStream_t)stream, bytes, &L.ws);
@@ -627,13 +627,19 @@ apm_status block_minors(bool xnor, apm_dtype dt, const void* A, const apm_batch*
 apm_status apm_xor_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
                           apm_stream stream)
 {
-    return block_minors(false, dt, A, bd, out, info, stream);
+    return block_minors(0, dt, A, bd, out, info, stream);
 }
 
 apm_status apm_xnor_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
                            apm_stream stream)
 {
-    return block_minors(true, dt, A, bd, out, info, stream);
+    return block_minors(1, dt, A, bd, out, info, stream);
+}
+
+apm_status apm_nand_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,
+                           apm_stream stream)
+{
+    return block_minors(2, dt, A, bd, out, info, stream);
 }
 
 apm_status apm_leading_minors(apm_dtype dt, const void* A, const apm_batch* bd, void* out, int32_t* info,

@@ -80,11 +80,12 @@ struct LaunchXor {
     int n;                     // blocks per matrix
     void* ws;                  // top-level node matrices, ws_stride elements per matrix
     int64_t ws_stride;
-    int xnor;                  // 0: XOR minors [batch][2^(n+1) - 2]; 1: XNOR minors [batch][2^n]
+    int mode;                  // 0: XOR minors [batch][2^(n+1) - 2]; 1: XNOR [batch][2^n];
+                               // 2: NAND [batch][3^n]
 };
 
 // Elements of top-level workspace per matrix with n blocks (0: none needed).
-int64_t xor_ws_elems(int n);
+int64_t xor_ws_elems(int n, int mode);
 hipError_t xor_launch(const LaunchXor& L, hipStream_t st);
 
 // Leading principal minors: [batch][n] of [batch][n][n] (dtype R64 or C128, n <= 32).

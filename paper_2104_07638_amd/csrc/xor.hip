@@ -38,7 +38,12 @@
 namespace apm {
 namespace {
 
-constexpr int kXQ = 6;       // levels expanded breadth first in LDS
+constexpr int kXQ = 6;       // levels expanded breadth first in LDS (XOR, XNOR)
+constexpr int kXQ3 = 4;      // the same for the ternary NAND tree
+// modes: the XOR, XNOR and NAND cases of Sec. III
+constexpr int kXor = 0, kXnor = 1, kNand = 2;
+__host__ __device__ constexpr int xq(int mode) { return mode == kNand ? kXQ3 : kXQ; }
+__host__ __device__ constexpr int64_t pow3(int k) { return k <= 0 ? 1 : 3 * pow3(k - 1); }
 #ifndef APM_XOR_PAD
 #define APM_XOR_PAD 1
 #endif
@@ -63,7 +68,7 @@ __host__ __device__ constexpr int64_t xor_top_off(int n, int d)
 template <class F>
 struct XorLds {
     typename F::E buf[2][kXBuf];
-    typename F::E mn[2][1 << kXQ];   // minors of the nodes of the current and the next level
+    typename F::E mn[2][128];        // minors of the nodes of the current and the next level
     typename F::E wk[64];            // subtree levels: each child's pivot row times 1/pivot
     typename F::E wv[32];            // top levels: pivot row times 1/pivot (XNOR: first row of
     typename F::E wv2[32];           // the pivot block's inverse times the pivot rows, and second)
@@ -73,7 +78,7 @@ struct XorLds {
 
 // Top level D of matrix order 2N: the child of the depth-D node on path s (half a row of
 // the child per lane), from the workspace (or the input at D = 0) to the workspace.
-template <class F, int N, int T, int D, bool XN>
+template <class F, int N, int T, int D, int MODE>
 __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, typename F::E* st,
                                         typename F::E* ob, XorLds<F>& sh, double& chk)
 {
@@ -104,7 +109,9 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             } else {
                 C = st + xor_top_off(N, D + 1);
             }
-            const int a = (s >> (T - 1 - D)) & 1;
+            // this level's choice: a bit (XOR, XNOR) or a ternary digit (NAND: 0 leaves the
+            // block out, 1 and 2 keep its first or second row)
+            const int a = MODE == kNand ? (int)((s / pow3(T - 1 - D)) % 3) : (s >> (T - 1 - D)) & 1;
             // every load of the node first, then the arithmetic: one round trip per node.
             // Lanes 2i and 2i+1 take the two halves of row i of the child.
             constexpr int hm = (mc + 1) / 2;
@@ -115,9 +122,9 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                 for (int j = 0; j < hm; ++j)
                     if (h0 + j < mc) row[j] = P[i * ps + h0 + j];
             }
-            if constexpr (!XN) {
+            if (MODE == kXor || (MODE == kNand && a != 0)) {
                 // child keeps row p of the last block: 1 x 1 pivot
-                const int p = mc + a;
+                const int p = MODE == kNand ? mc + a - 1 : mc + a;
                 const E pv = P[p * ps + p];
                 E pc = F::zero(), pr = F::zero();
                 if (i < mc) pc = P[i * ps + p];
@@ -127,7 +134,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                 if (lane == 0) {
                     const E mk = F::bmul(sh.topm[D], pv, 0);
                     sh.topm[D + 1] = mk;
-                    ob[(int64_t(2) << D) - 2 + (s >> (T - 1 - D))] = mk;
+                    if constexpr (MODE == kXor) ob[(int64_t(2) << D) - 2 + (s >> (T - 1 - D))] = mk;
                     chk += F::fincheck(mk);
                 }
                 wave_sync();
@@ -137,7 +144,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                         if (h0 + j < mc) C[i * cs + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
                 }
             } else if (a == 0) {
-                // XNOR, the block dropped: the leading part of the node, minor unchanged
+                // XNOR or NAND, the block left out: the leading part of the node, minor unchanged
                 if (lane == 0) sh.topm[D + 1] = sh.topm[D];
                 if (i < mc) {
 #pragma unroll
@@ -182,7 +189,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                 wave_mem_fence();   // the child is the next level's node (and wv is rewritten)
             }
         }
-        xor_top<F, N, T, D + 1, XN>(d0, s, A0, st, ob, sh, chk);
+        xor_top<F, N, T, D + 1, MODE>(d0, s, A0, st, ob, sh, chk);
     }
 }
 
@@ -190,16 +197,17 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
 // (order 2(Q - J)) into buf[(J + 1) & 1], one row of a child per lane.  base is where the
 // children's depth T+J+1 starts in the output (2^(T+J+1) - 2; XOR only: the XNOR minors
 // are the 2^N leaves, written at the last level in block-mask order).
-template <class F, int Q, int J, bool XN>
+template <class F, int Q, int J, int MODE>
 __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, XorLds<F>& sh, double& chk)
 {
     if constexpr (J < Q) {
         using E = typename F::E;
         constexpr int cur = J & 1, nxt = cur ^ 1;
-        constexpr int m = 2 * (Q - J), mc = m - 2, kids = 2 << J;
-        static_assert(kids <= 64 && kids * mc <= 64, "one pass per level");
+        constexpr int m = 2 * (Q - J), mc = m - 2;
+        constexpr int kids = MODE == kNand ? (int)pow3(J + 1) : 2 << J;
+        static_assert(kids * mc <= 64 && (MODE == kNand || kids <= 64), "one pass per level");
         const int lane = threadIdx.x;
-        if constexpr (!XN) {
+        if constexpr (MODE == kXor) {
             // child k of node k/2 keeps row mc + (k & 1) of the node's last block: its minor,
             // and the pivot row times 1/pivot (lane k mc + j holds entry j)
             if (lane < kids) {
@@ -217,7 +225,7 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
                     sh.wk[lane] = F::rowscale(P[p * xs(m) + j], F::recip(P[p * xs(m) + p]));
                 }
             }
-        } else {
+        } else if constexpr (MODE == kXnor) {
             // child 2v drops node v's last block (minor unchanged), child 2v+1 keeps it (minor
             // times the pivot block's determinant; the inverse times the two pivot rows go to
             // wk[v][0..1][...], lane 2 v mc + r mc + j holding entry j of row r)
@@ -243,6 +251,29 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
                                          : F::rowscale(F::upd(F::bmul(p1, a00, 0), a10, p0), rd);
                 }
             }
+        } else {
+            // NAND: child 3v + c of node v leaves the last block out (c = 0, minor unchanged)
+            // or keeps its row mc + c - 1; the kept rows' pivot rows times 1/pivot go to
+            // wk[v][c - 1][...] (lane 2 v mc + r mc + j holds entry j of row mc + r)
+            for (int t = lane; t < kids; t += 64) {
+                const int v = t / 3, c = t - 3 * v;
+                E mk = sh.mn[cur][v];
+                if (c) {
+                    const int p = mc + c - 1;
+                    mk = F::bmul(mk, sh.buf[cur][v * m * xs(m) + p * xs(m) + p], 0);
+                }
+                sh.mn[nxt][t] = mk;
+                if constexpr (J == Q - 1) ob[(int64_t)s * pow3(Q) + t] = mk;
+                chk += F::fincheck(mk);
+            }
+            if constexpr (mc > 0) {
+                if (lane < 2 * (kids / 3) * mc) {
+                    const int v = lane / (2 * mc), rr = lane - v * 2 * mc, r = rr / mc, j = rr - r * mc;
+                    const E* P = &sh.buf[cur][v * m * xs(m)];
+                    const int p = mc + r;
+                    sh.wk[lane] = F::rowscale(P[p * xs(m) + j], F::recip(P[p * xs(m) + p]));
+                }
+            }
         }
         wave_sync();
         if constexpr (mc > 0) {
@@ -250,7 +281,20 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
                 const int k = lane / mc, i = lane - k * mc;
                 const E* P = &sh.buf[cur][(k >> 1) * m * xs(m)];
                 E* Cr = &sh.buf[nxt][k * mc * xs(mc) + i * xs(mc)];
-                if constexpr (!XN) {
+                if constexpr (MODE == kNand) {
+                    // (P, Cr above assume two children per node: recomputed for three)
+                    const int v = k / 3, c = k - 3 * v;
+                    const E* Pn = &sh.buf[cur][v * m * xs(m)];
+                    if (c == 0) {
+#pragma unroll
+                        for (int j = 0; j < mc; ++j) Cr[j] = Pn[i * xs(m) + j];
+                    } else {
+                        const E ci = Pn[i * xs(m) + mc + c - 1];
+                        const E* wr = &sh.wk[(2 * v + c - 1) * mc];
+#pragma unroll
+                        for (int j = 0; j < mc; ++j) Cr[j] = F::upd(Pn[i * xs(m) + j], ci, wr[j]);
+                    }
+                } else if constexpr (MODE == kXor) {
                     const E ci = P[i * xs(m) + mc + (k & 1)];
                     const E* wr = &sh.wk[k * mc];
 #pragma unroll
@@ -267,17 +311,17 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
             }
             wave_sync();
         }
-        xor_sub<F, Q, J + 1, XN>(2 * base + 2, s, ob, sh, chk);   // XOR depth T+J+2 starts at 2^(T+J+2) - 2
+        xor_sub<F, Q, J + 1, MODE>(2 * base + 2, s, ob, sh, chk);   // XOR depth T+J+2 starts at 2^(T+J+2) - 2
     }
 }
 
-template <class F, int N, bool XN>
+template <class F, int N, int MODE>
 __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict__ A, typename F::E* __restrict__ out,
                                                  int32_t* __restrict__ info, int32_t batch,
                                                  typename F::E* __restrict__ ws, int64_t ws_stride)
 {
     using E = typename F::E;
-    constexpr int Q = N < kXQ ? N : kXQ;
+    constexpr int Q = N < xq(MODE) ? N : xq(MODE);
     constexpr int T = N - Q;
     constexpr int w = 2 * N;
     __shared__ XorLds<F> sh;
@@ -285,7 +329,7 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
     if (b >= batch) return;
     const int lane = threadIdx.x;
     const E* A0 = A + (int64_t)b * w * w;
-    constexpr int64_t nout = XN ? (int64_t(1) << N) : (int64_t(2) << N) - 2;   // outputs per matrix
+    constexpr int64_t nout = MODE == kNand ? pow3(N) : MODE == kXnor ? (int64_t(1) << N) : (int64_t(2) << N) - 2;
     E* ob = out + (int64_t)b * nout;
 
     bool fin = true;
@@ -298,17 +342,28 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
     E* st = ws + (int64_t)b * ws_stride;
     double chk = 0.0;
     if (lane == 0) sh.topm[0] = F::one();
-    for (int s = 0; s < (1 << T); ++s) {
-        // top levels: redo the path below the first choice that changed from s - 1
-        const int d0 = s ? T - 1 - (31 - __clz((unsigned)(s ^ (s - 1)))) : 0;
-        xor_top<F, N, T, 0, XN>(d0, s, A0, st, ob, sh, chk);
+    constexpr int ntop = MODE == kNand ? (int)pow3(T) : 1 << T;
+    for (int s = 0; s < ntop; ++s) {
+        // top levels: redo the path below the first choice that changed from s - 1 (the
+        // number of trailing zero digits of s, binary or ternary)
+        int d0 = 0;
+        if (s) {
+            if constexpr (MODE == kNand) {
+                int tz = 0;
+                for (int t = s; t % 3 == 0; t /= 3) ++tz;
+                d0 = T - 1 - tz;
+            } else {
+                d0 = T - 1 - (31 - __clz((unsigned)(s ^ (s - 1))));
+            }
+        }
+        xor_top<F, N, T, 0, MODE>(d0, s, A0, st, ob, sh, chk);
         // the subtree of depth-T node s, breadth first in LDS
         if constexpr (T == 0) {
             for (int e = lane; e < w * w; e += 64) sh.buf[0][(e / w) * xs(w) + e % w] = A0[e];
         }
         if (lane == 0) sh.mn[0][0] = sh.topm[T];
         wave_sync();
-        xor_sub<F, Q, 0, XN>((int64_t(2) << T) - 2, s, ob, sh, chk);
+        xor_sub<F, Q, 0, MODE>((int64_t(2) << T) - 2, s, ob, sh, chk);
     }
     const bool bad = __any(chk == 0.0 ? 0 : 1);
     if (info && lane == 0) info[b] = bad ? -3 : 0;
@@ -321,14 +376,18 @@ hipError_t xor_launch_n(const LaunchXor& L, hipStream_t st)
         return hipErrorInvalidValue;
     } else {
         if (L.n != N) return xor_launch_n<F, N + 1>(L, st);
-        if (L.xnor) {
-            hipLaunchKernelGGL((xor_kernel<F, N, true>), dim3((unsigned)L.batch), dim3(64), 0, st,
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)L.batch), dim3(64), 0, st,
                                static_cast<const typename F::E*>(L.A), static_cast<typename F::E*>(L.out), L.info,
                                L.batch, static_cast<typename F::E*>(L.ws), L.ws_stride);
+        };
+        if (L.mode == kXnor) {
+            go(xor_kernel<F, N, kXnor>);
+        } else if (L.mode == kNand) {
+            if constexpr (N <= 13) go(xor_kernel<F, N, kNand>);
+            else return hipErrorInvalidValue;
         } else {
-            hipLaunchKernelGGL((xor_kernel<F, N, false>), dim3((unsigned)L.batch), dim3(64), 0, st,
-                               static_cast<const typename F::E*>(L.A), static_cast<typename F::E*>(L.out), L.info,
-                               L.batch, static_cast<typename F::E*>(L.ws), L.ws_stride);
+            go(xor_kernel<F, N, kXor>);
         }
         return hipGetLastError();
     }
@@ -336,10 +395,10 @@ hipError_t xor_launch_n(const LaunchXor& L, hipStream_t st)
 
 }  // namespace
 
-int64_t xor_ws_elems(int n)
+int64_t xor_ws_elems(int n, int mode)
 {
     // depths 1 .. G live in the workspace, the deeper top nodes in LDS
-    const int T = n > kXQ ? n - kXQ : 0;
+    const int T = n > xq(mode) ? n - xq(mode) : 0;
     const int G = (APM_XOR_PRE && T >= 2) ? T - 2 : T - 1;
     return G >= 1 ? xor_top_off(n, G + 1) : 0;
 }

@@ -234,3 +234,11 @@ def test_leading_validation(apm):
     assert f(3, P, _bd(apm), P, None, None) == apm.APM_EUNSUPPORTED
     assert f(0, P, _bd(apm, n=33), P, None, None) == apm.APM_EUNSUPPORTED
     assert f(0, None, _bd(apm), P, None, None) == apm.APM_EINVAL
+
+
+def test_nand_validation(apm):
+    f = apm.apm_nand_minors
+    assert f(2, P, _bd(apm, batch=0), P, None, None) == apm.APM_OK
+    assert f(2, P, _bd(apm, n=14), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(1, P, _bd(apm), P, None, None) == apm.APM_EUNSUPPORTED
+    assert f(2, None, _bd(apm), P, None, None) == apm.APM_EINVAL

@@ -170,3 +170,61 @@ def test_xnor_keldysh_full_size_sampled(apm, oracle_mod):
                 H[t] = np.prod(np.linalg.norm(A[sel[i]][np.ix_(r, r)], axis=1))
         e = metrics.mixed_err(got[i][masks], ref[i][masks], H)
         assert e.max() <= 1e-10, (int(sel[i]), float(e.max()))
+
+
+def nand_rows(n, code):
+    r = []
+    for i in range(n):
+        t = code % 3
+        code //= 3
+        if t:
+            r.append(2 * i + t - 1)
+    return r
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_nand_parity(apm, oracle_mod, n):
+    import torch
+    rng = np.random.default_rng(700 + n)
+    for cplx in (False, True):
+        A = rng.standard_normal((3, 2 * n, 2 * n)) + 3.0 * np.eye(2 * n)
+        if cplx:
+            A = A + 1j * rng.standard_normal((3, 2 * n, 2 * n))
+        out, info = apm.nand_minors(torch.from_numpy(A).cuda())
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0)
+        got = out.cpu().numpy()
+        ref = oracle_mod.nand_minors(A)
+        for b in range(3):
+            H = np.array([np.prod(np.linalg.norm(A[b][np.ix_(r, r)], axis=1)) if r else 1.0
+                          for r in (nand_rows(n, c) for c in range(3 ** n))])
+            e = metrics.mixed_err(got[b], ref[b], H)
+            assert e.max() <= 1e-10, (n, cplx, b, float(e.max()))
+
+
+def test_nand_keldysh_sampled(apm, oracle_mod):
+    """512 Keldysh block matrices of 10 blocks; sampled matrices and codes against the oracle,
+    and the full-order entries against the XOR minors of the same matrices."""
+    import torch
+    n = 10
+    A = W.keldysh_block(512, n, seed=W.BASE_SEED + 5)
+    dA = torch.from_numpy(A).cuda()
+    out, info = apm.nand_minors(dA)
+    xo, _ = apm.xor_minors(dA)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    sel = np.random.default_rng(513).choice(512, 2, replace=False)
+    got = out[torch.from_numpy(sel).cuda()].cpu().numpy()
+    ref = oracle_mod.nand_minors(A[sel])
+    codes = np.random.default_rng(2).integers(0, 3 ** n, 600)
+    for i in range(len(sel)):
+        H = np.array([np.prod(np.linalg.norm(A[sel[i]][np.ix_(r, r)], axis=1)) if r else 1.0
+                      for r in (nand_rows(n, int(c)) for c in codes)])
+        e = metrics.mixed_err(got[i][codes], ref[i][codes], H)
+        assert e.max() <= 1e-10, (int(sel[i]), float(e.max()))
+    # every block present: the order-n XOR minors (choice beta -> code sum (beta_i + 1) 3^i)
+    beta = np.arange(1 << n)
+    code = sum(((beta >> i) & 1) * 3 ** i for i in range(n)) + sum(3 ** i for i in range(n))
+    full = out[:, torch.from_numpy(code).cuda()]
+    xfull = xo[:, (1 << n) - 2:]
+    assert bool(torch.allclose(full, xfull, rtol=1e-10, atol=1e-12 * float(xfull.abs().max())))
