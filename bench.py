@@ -312,6 +312,15 @@ def run_extra(torch, apm, W, np, steps):
     ex["xnor_keldysh_n14_4096_c128"] = {"ms": round(ms, 4), "matrices_per_s": round(4096 / (ms * 1e-3), 1),
                                         "GBs": round(by / (ms * 1e-3) / 1e9, 1)}
     del K2, xo, K2r, xr, xn
+    # NAND minors (at most one row per block, 3^n): 1024 Keldysh block matrices of 10 blocks
+    K3 = torch.from_numpy(W.keldysh_block(1024, 10, seed=W.BASE_SEED + 5)).cuda()
+    na = torch.empty((1024, 3 ** 10), dtype=torch.complex128, device="cuda")
+    ni = torch.empty(1024, dtype=torch.int32, device="cuda")
+    ms = time_fn(torch, lambda: apm.nand_minors(K3, out=na, info=ni), steps)
+    by = K3.numel() * 16 + na.numel() * 16
+    ex["nand_keldysh_n10_1024_c128"] = {"ms": round(ms, 4), "matrices_per_s": round(1024 / (ms * 1e-3), 1),
+                                        "GBs": round(by / (ms * 1e-3) / 1e9, 1)}
+    del K3, na, ni
     for k, v in ex.items():
         log(f"{k}: {v}")
     return ex
