@@ -425,7 +425,7 @@ def leading_minors(A, *, out=None, info=None, stream=None):
     if info is None:
         info = torch.empty(B, dtype=torch.int32, device=A.device)
     _check(apm_leading_minors(dt, _ptr(A), make_batch(B, n), _ptr(out), _ptr(info), _stream(stream)),
-           "apm_leading_minors", "apm_nand_minors")
+           "apm_leading_minors")
     return out, info
 
 
