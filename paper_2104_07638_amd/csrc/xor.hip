@@ -50,8 +50,26 @@ __host__ __device__ constexpr int64_t pow3(int k) { return k <= 0 ? 1 : 3 * pow3
 // Row stride of an order-m node matrix in LDS: one element of padding, so that lanes
 // reading the same column of different rows fall on different banks.
 __host__ __device__ constexpr int xs(int m) { return m + APM_XOR_PAD; }
-// largest level of the six-level subtree: 8 nodes of order 6 (6 rows of stride xs(6))
-constexpr int kXBuf = 8 * 6 * xs(6);
+// Entries of the largest subtree level in LDS, over the binary (six-level) and ternary
+// (four-level) subtrees: the root, and every level's children with padded rows.
+__host__ __device__ constexpr int xbuf_need()
+{
+    int need = 0;
+    for (int mode = 0; mode < 3; ++mode) {
+        const int Q = mode == 2 ? kXQ3 : kXQ;
+        int kids = 1;
+        const int root = 2 * Q * xs(2 * Q);
+        need = root > need ? root : need;
+        for (int J = 0; J < Q; ++J) {
+            kids *= mode == 2 ? 3 : 2;
+            const int mc = 2 * (Q - J) - 2;
+            const int lvl = kids * mc * xs(mc);
+            need = lvl > need ? lvl : need;
+        }
+    }
+    return need;
+}
+constexpr int kXBuf = xbuf_need();
 #ifndef APM_XOR_PRE
 #define APM_XOR_PRE 1     // keep the depth T-1 node (order 14) in LDS as well
 #endif
@@ -93,6 +111,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             constexpr bool kPinP = kPin && D == T - 1, kLdsC = D == T - 1 || (kPin && D == T - 2);
             constexpr int ps = kPinP ? xs(m) : m;
             constexpr int cs = kLdsC ? xs(mc) : mc;
+            static_assert(!kLdsC || mc * xs(mc) <= (D == T - 1 ? kXBuf : kXPre), "LDS node fits its buffer");
             const E* P;
             if constexpr (D == 0) {
                 P = A0;
@@ -206,6 +225,8 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         constexpr int m = 2 * (Q - J), mc = m - 2;
         constexpr int kids = MODE == kNand ? (int)pow3(J + 1) : 2 << J;
         static_assert(kids * mc <= 64 && (MODE == kNand || kids <= 64), "one pass per level");
+        static_assert(kids * mc * xs(mc) <= kXBuf && m * xs(m) * (kids / (MODE == kNand ? 3 : 2)) <= kXBuf,
+                      "a subtree level fits its LDS buffer");
         const int lane = threadIdx.x;
         if constexpr (MODE == kXor) {
             // child k of node k/2 keeps row mc + (k & 1) of the node's last block: its minor,
