@@ -38,7 +38,10 @@
 namespace apm {
 namespace {
 
-constexpr int kXQ = 6;       // levels expanded breadth first in LDS (XOR, XNOR)
+#ifndef APM_XOR_Q
+#define APM_XOR_Q 6
+#endif
+constexpr int kXQ = APM_XOR_Q;   // levels expanded breadth first in LDS (XOR, XNOR)
 constexpr int kXQ3 = 4;      // the same for the ternary NAND tree
 // modes: the XOR, XNOR and NAND cases of Sec. III
 constexpr int kXor = 0, kXnor = 1, kNand = 2;
