@@ -77,6 +77,8 @@ constexpr int kXBuf = xbuf_need();
 #define APM_XOR_PRE 1     // keep the depth T-1 node (order 14) in LDS as well
 #endif
 constexpr int kXPre = APM_XOR_PRE ? 14 * xs(14) : 1;
+// Zero pivot rows of the widest subtree level (two rows of order 2Q - 2).
+constexpr int kXZero = 4 * (kXQ > kXQ3 ? kXQ : kXQ3) - 4;
 
 // Start of the depth-d node matrix (d >= 1) in a matrix's workspace, in elements.
 __host__ __device__ constexpr int64_t xor_top_off(int n, int d)
@@ -95,6 +97,8 @@ struct XorLds {
     typename F::E wv2[32];           // the pivot block's inverse times the pivot rows, and second)
     typename F::E topm[17];          // minors along the top path
     typename F::E pre[kXPre];        // the depth T-1 node
+    typename F::E wz[kXZero];        // zeros: the pivot column and rows of a child that leaves
+                                     // its block out, so that it runs the keeping children's code
 };
 
 // Top level D of matrix order 2N: the child of the depth-D node on path s (half a row of
@@ -230,6 +234,7 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         static_assert(kids * mc <= 64 && (MODE == kNand || kids <= 64), "one pass per level");
         static_assert(kids * mc * xs(mc) <= kXBuf && m * xs(m) * (kids / (MODE == kNand ? 3 : 2)) <= kXBuf,
                       "a subtree level fits its LDS buffer");
+        static_assert(2 * mc <= kXZero, "zero pivot rows cover a level");
         const int lane = threadIdx.x;
         if constexpr (MODE == kXor) {
             // child k of node k/2 keeps row mc + (k & 1) of the node's last block: its minor,
@@ -309,26 +314,24 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
                     // (P, Cr above assume two children per node: recomputed for three)
                     const int v = k / 3, c = k - 3 * v;
                     const E* Pn = &sh.buf[cur][v * m * xs(m)];
-                    if (c == 0) {
+                    // one instruction stream for all three children (a copy branch beside the
+                    // update would issue both): the one that leaves the block out subtracts
+                    // zero times a zero row
+                    const E ci = c ? Pn[i * xs(m) + mc + c - 1] : F::zero();
+                    const E* wr = c ? &sh.wk[(2 * v + c - 1) * mc] : sh.wz;
 #pragma unroll
-                        for (int j = 0; j < mc; ++j) Cr[j] = Pn[i * xs(m) + j];
-                    } else {
-                        const E ci = Pn[i * xs(m) + mc + c - 1];
-                        const E* wr = &sh.wk[(2 * v + c - 1) * mc];
-#pragma unroll
-                        for (int j = 0; j < mc; ++j) Cr[j] = F::upd(Pn[i * xs(m) + j], ci, wr[j]);
-                    }
+                    for (int j = 0; j < mc; ++j) Cr[j] = F::upd(Pn[i * xs(m) + j], ci, wr[j]);
                 } else if constexpr (MODE == kXor) {
                     const E ci = P[i * xs(m) + mc + (k & 1)];
                     const E* wr = &sh.wk[k * mc];
 #pragma unroll
                     for (int j = 0; j < mc; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
-                } else if ((k & 1) == 0) {
-#pragma unroll
-                    for (int j = 0; j < mc; ++j) Cr[j] = P[i * xs(m) + j];
                 } else {
-                    const E c0 = P[i * xs(m) + mc], c1 = P[i * xs(m) + mc + 1];
-                    const E* w0 = &sh.wk[(k >> 1) * 2 * mc];
+                    // both children in one instruction stream: the one that drops the block
+                    // subtracts zero times zero rows
+                    const bool keep = k & 1;
+                    const E c0 = keep ? P[i * xs(m) + mc] : F::zero(), c1 = keep ? P[i * xs(m) + mc + 1] : F::zero();
+                    const E* w0 = keep ? &sh.wk[(k >> 1) * 2 * mc] : sh.wz;
 #pragma unroll
                     for (int j = 0; j < mc; ++j) Cr[j] = F::upd(F::upd(P[i * xs(m) + j], c0, w0[j]), c1, w0[mc + j]);
                 }
@@ -366,6 +369,7 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
     E* st = ws + (int64_t)b * ws_stride;
     double chk = 0.0;
     if (lane == 0) sh.topm[0] = F::one();
+    for (int e = lane; e < kXZero; e += 64) sh.wz[e] = F::zero();
     constexpr int ntop = MODE == kNand ? (int)pow3(T) : 1 << T;
     for (int s = 0; s < ntop; ++s) {
         // top levels: redo the path below the first choice that changed from s - 1 (the
