@@ -77,6 +77,15 @@ constexpr int kXBuf = xbuf_need();
 #define APM_XOR_PRE 1     // keep the depth T-1 node (order 14) in LDS as well
 #endif
 constexpr int kXPre = APM_XOR_PRE ? 14 * xs(14) : 1;
+// Lanes per row in a subtree pass of `rows` rows of mc entries: the largest divisor of mc
+// that keeps rows x H within the wavefront (1 when the rows fill it).
+__host__ __device__ constexpr int col_groups(int rows, int mc)
+{
+    int h = 1;
+    for (int c = 2; c <= mc && rows * c <= 64; ++c)
+        if (mc % c == 0) h = c;
+    return h;
+}
 // Zero pivot rows of the widest subtree level (two rows of order 2Q - 2).
 constexpr int kXZero = 4 * (kXQ > kXQ3 ? kXQ : kXQ3) - 4;
 
@@ -306,34 +315,38 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         }
         wave_sync();
         if constexpr (mc > 0) {
-            if (lane < kids * mc) {
-                const int k = lane / mc, i = lane - k * mc;
-                const E* P = &sh.buf[cur][(k >> 1) * m * xs(m)];
-                E* Cr = &sh.buf[nxt][k * mc * xs(mc) + i * xs(mc)];
+            // lane (h, k, i) writes columns [h cw, (h + 1) cw) of row i of child k: where the
+            // rows do not fill the wavefront, each row is split over H lanes
+            constexpr int rows = kids * mc, H = col_groups(rows, mc), cw = mc / H;
+            if (lane < rows * H) {
+                const int r = lane % rows, h = lane / rows;
+                const int k = r / mc, i = r - k * mc, j0 = h * cw;
+                E* Cr = &sh.buf[nxt][k * mc * xs(mc) + i * xs(mc)] + j0;
+                // the node's entries from column j0 on (two children per node, three for NAND)
+                const E* P = &sh.buf[cur][(MODE == kNand ? k / 3 : k >> 1) * m * xs(m)] + j0;
                 if constexpr (MODE == kNand) {
-                    // (P, Cr above assume two children per node: recomputed for three)
-                    const int v = k / 3, c = k - 3 * v;
-                    const E* Pn = &sh.buf[cur][v * m * xs(m)];
+                    const int c = k % 3;
                     // one instruction stream for all three children (a copy branch beside the
                     // update would issue both): the one that leaves the block out subtracts
                     // zero times a zero row
-                    const E ci = c ? Pn[i * xs(m) + mc + c - 1] : F::zero();
-                    const E* wr = c ? &sh.wk[(2 * v + c - 1) * mc] : sh.wz;
+                    const E ci = c ? P[i * xs(m) + mc - j0 + c - 1] : F::zero();
+                    const E* wr = (c ? &sh.wk[(2 * (k / 3) + c - 1) * mc] : sh.wz) + j0;
 #pragma unroll
-                    for (int j = 0; j < mc; ++j) Cr[j] = F::upd(Pn[i * xs(m) + j], ci, wr[j]);
+                    for (int j = 0; j < cw; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
                 } else if constexpr (MODE == kXor) {
-                    const E ci = P[i * xs(m) + mc + (k & 1)];
-                    const E* wr = &sh.wk[k * mc];
+                    const E ci = P[i * xs(m) + mc - j0 + (k & 1)];
+                    const E* wr = &sh.wk[k * mc] + j0;
 #pragma unroll
-                    for (int j = 0; j < mc; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
+                    for (int j = 0; j < cw; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
                 } else {
                     // both children in one instruction stream: the one that drops the block
                     // subtracts zero times zero rows
                     const bool keep = k & 1;
-                    const E c0 = keep ? P[i * xs(m) + mc] : F::zero(), c1 = keep ? P[i * xs(m) + mc + 1] : F::zero();
-                    const E* w0 = keep ? &sh.wk[(k >> 1) * 2 * mc] : sh.wz;
+                    const E c0 = keep ? P[i * xs(m) + mc - j0] : F::zero();
+                    const E c1 = keep ? P[i * xs(m) + mc - j0 + 1] : F::zero();
+                    const E* w0 = (keep ? &sh.wk[(k >> 1) * 2 * mc] : sh.wz) + j0;
 #pragma unroll
-                    for (int j = 0; j < mc; ++j) Cr[j] = F::upd(F::upd(P[i * xs(m) + j], c0, w0[j]), c1, w0[mc + j]);
+                    for (int j = 0; j < cw; ++j) Cr[j] = F::upd(F::upd(P[i * xs(m) + j], c0, w0[j]), c1, w0[mc + j]);
                 }
             }
             wave_sync();
