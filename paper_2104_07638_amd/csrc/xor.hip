@@ -86,6 +86,13 @@ __host__ __device__ constexpr int col_groups(int rows, int mc)
         if (mc % c == 0) h = c;
     return h;
 }
+// Columns per lane in a top-level pass over a child of order mc (mc rows): as few as the
+// wavefront allows, with the column groups as even as that count permits.
+__host__ __device__ constexpr int top_cols(int mc)
+{
+    const int hmax = 64 / mc < mc ? 64 / mc : mc;
+    return (mc + hmax - 1) / hmax;
+}
 // Zero pivot rows of the widest subtree level (two rows of order 2Q - 2).
 constexpr int kXZero = 4 * (kXQ > kXQ3 ? kXQ : kXQ3) - 4;
 
@@ -148,21 +155,23 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             // block out, 1 and 2 keep its first or second row)
             const int a = MODE == kNand ? (int)((s / pow3(T - 1 - D)) % 3) : (s >> (T - 1 - D)) & 1;
             // every load of the node first, then the arithmetic: one round trip per node.
-            // Lanes 2i and 2i+1 take the two halves of row i of the child.
-            constexpr int hm = (mc + 1) / 2;
-            const int i = lane >> 1, h0 = (lane & 1) * hm;
-            E row[hm];
-            if (i < mc) {
+            // Lane h mc + i takes columns [h cw, (h + 1) cw) of row i of the child.
+            constexpr int cw = top_cols(mc), H = (mc + cw - 1) / cw;
+            constexpr bool kEven = mc % cw == 0;
+            const int i = lane % mc, h = lane / mc, h0 = h * cw;
+            const bool act = h < H;
+            E row[cw];
+            if (act) {
 #pragma unroll
-                for (int j = 0; j < hm; ++j)
-                    if (h0 + j < mc) row[j] = P[i * ps + h0 + j];
+                for (int j = 0; j < cw; ++j)
+                    if (kEven || h0 + j < mc) row[j] = P[i * ps + h0 + j];
             }
             if (MODE == kXor || (MODE == kNand && a != 0)) {
                 // child keeps row p of the last block: 1 x 1 pivot
                 const int p = MODE == kNand ? mc + a - 1 : mc + a;
                 const E pv = P[p * ps + p];
                 E pc = F::zero(), pr = F::zero();
-                if (i < mc) pc = P[i * ps + p];
+                if (act) pc = P[i * ps + p];
                 if (lane < mc) pr = P[p * ps + lane];
                 const typename F::R r = F::recip(pv);
                 if (lane < mc) sh.wv[lane] = F::rowscale(pr, r);
@@ -173,25 +182,25 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                     chk += F::fincheck(mk);
                 }
                 wave_sync();
-                if (i < mc) {
+                if (act) {
 #pragma unroll
-                    for (int j = 0; j < hm; ++j)
-                        if (h0 + j < mc) C[i * cs + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
+                    for (int j = 0; j < cw; ++j)
+                        if (kEven || h0 + j < mc) C[i * cs + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
                 }
             } else if (a == 0) {
                 // XNOR or NAND, the block left out: the leading part of the node, minor unchanged
                 if (lane == 0) sh.topm[D + 1] = sh.topm[D];
-                if (i < mc) {
+                if (act) {
 #pragma unroll
-                    for (int j = 0; j < hm; ++j)
-                        if (h0 + j < mc) C[i * cs + h0 + j] = row[j];
+                    for (int j = 0; j < cw; ++j)
+                        if (kEven || h0 + j < mc) C[i * cs + h0 + j] = row[j];
                 }
             } else {
                 // XNOR, the block kept: 2 x 2 pivot block, its inverse applied to the pivot rows
                 const E a00 = P[mc * ps + mc], a01 = P[mc * ps + mc + 1];
                 const E a10 = P[(mc + 1) * ps + mc], a11 = P[(mc + 1) * ps + mc + 1];
                 E pc0 = F::zero(), pc1 = F::zero(), pr0 = F::zero(), pr1 = F::zero();
-                if (i < mc) {
+                if (act) {
                     pc0 = P[i * ps + mc];
                     pc1 = P[i * ps + mc + 1];
                 }
@@ -211,10 +220,10 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                     chk += F::fincheck(mk);
                 }
                 wave_sync();
-                if (i < mc) {
+                if (act) {
 #pragma unroll
-                    for (int j = 0; j < hm; ++j)
-                        if (h0 + j < mc)
+                    for (int j = 0; j < cw; ++j)
+                        if (kEven || h0 + j < mc)
                             C[i * cs + h0 + j] = F::upd(F::upd(row[j], pc0, sh.wv[h0 + j]), pc1, sh.wv2[h0 + j]);
                 }
             }
