@@ -286,10 +286,18 @@ __device__ __forceinline__ void inlane_step(const typename F::E (&M)[SZ * SZ], t
         for (int b = 0; b < m; ++b) Q[a * m + b] = F::upd(M[(1 + a) * SZ + 1 + b], M[(1 + a) * SZ], w[b]);
 }
 
+// Columns per lane of a breadth-first level of `rows` rows of m entries: as few as the
+// wavefront allows, the column groups as even as that count permits.
+constexpr int bf_cols(int rows, int m)
+{
+    const int hmax = kWave / rows < m ? kWave / rows : m;
+    return (m + hmax - 1) / hmax;
+}
+
 // Breadth-first mid level J (and, recursively, the following ones) of a chunk: lane
 // (t, a) writes row a of both children of node (J, t) -- the left child (the trailing
-// block) and the right child (the Schur complement).  Every lane of a node repeats the
-// node's pivot analysis; lane a == 0 publishes it.
+// block) and the right child (the Schur complement), or a group of its columns.  Every
+// lane of a node repeats the node's pivot analysis; one lane publishes it.
 template <class F, int N, int K0MAX, int J>
 __device__ __forceinline__ void bf_levels(typename F::E* lds, typename F::E* pt_a, typename F::E* pu_a,
                                           typename F::R* ri_a, int8_t* midc, int x0o, int x0l, int lane,
@@ -303,30 +311,42 @@ __device__ __forceinline__ void bf_levels(typename F::E* lds, typename F::E* pt_
         constexpr int sz = P::K - J;
         constexpr int m = sz - 1;
         static_assert(nodes * m <= kWave, "one row per lane");
+        // where the rows do not fill the wavefront, each is split over H lanes: lane
+        // (h, t, a) writes columns [h cw, (h + 1) cw) of row a of node t's children
+        constexpr int rows = nodes * m, cw = bf_cols(rows, m), H = (m + cw - 1) / cw;
+        constexpr bool kEven = m % cw == 0;
         bool pert = false;
-        if (lane < nodes * m) {
-            const int t = lane / m, a = lane - (lane / m) * m;
+        if (lane < rows * H) {
+            const int r = lane % rows, h = lane / rows;
+            const int t = r / m, a = r - t * m, j0 = h * cw;
             const E* Pm = (J == 0) ? lds + x0o : lds + L::lvl_base(J) + t * L::ns(sz);
             const int pl = (J == 0) ? x0l : L::rs(sz);
-            E row[m], mine[m];
+            E row[cw], mine[cw];
             double rv[m], cv[m];
 #pragma unroll
             for (int b = 0; b < m; ++b) {
-                row[b] = Pm[b + 1];
-                mine[b] = Pm[(a + 1) * pl + b + 1];
-                rv[b] = F::mag(row[b]);
+                rv[b] = F::mag(Pm[b + 1]);
                 cv[b] = F::mag(Pm[(b + 1) * pl]);
+            }
+#pragma unroll
+            for (int b = 0; b < cw; ++b) {
+                if (kEven || j0 + b < m) {
+                    row[b] = Pm[j0 + b + 1];
+                    mine[b] = Pm[(a + 1) * pl + j0 + b + 1];
+                }
             }
             const E c = Pm[(a + 1) * pl];
             const PivInfo<F> pv = analyse<F>(Pm[0], tree_max(rv), tree_max(cv), sz, pc);
-            E* Lr = lds + L::lvl_base(J + 1) + t * L::ns(m) + a * L::rs(m);
+            E* Lr = lds + L::lvl_base(J + 1) + t * L::ns(m) + a * L::rs(m) + j0;
             E* Rr = Lr + nodes * L::ns(m);
 #pragma unroll
-            for (int b = 0; b < m; ++b) {
-                Lr[b] = mine[b];
-                Rr[b] = F::upd(mine[b], c, F::rowscale(row[b], pv.ri));
+            for (int b = 0; b < cw; ++b) {
+                if (kEven || j0 + b < m) {
+                    Lr[b] = mine[b];
+                    Rr[b] = F::upd(mine[b], c, F::rowscale(row[b], pv.ri));
+                }
             }
-            if (a == 0) {
+            if (a == 0 && h == 0) {
                 pt_a[nodes - 1 + t] = pv.pt;
                 pu_a[nodes - 1 + t] = pv.pu;
                 ri_a[nodes - 1 + t] = pv.ri;
