@@ -361,7 +361,8 @@ __device__ __forceinline__ void bf_levels(typename F::E* lds, typename F::E* pt_
 }
 
 // Top level D: take the right branch of the depth-D node (Schur complement of order
-// N-D-1 into top storage D+1); lane a writes row a.  Returns the pivot analysis.
+// N-D-1 into top storage D+1), a column per lane over groups of rows.  Returns the pivot
+// analysis.
 template <class F, int N, int K0MAX, int D>
 __device__ __forceinline__ PivInfo<F> top_right(typename F::E* lds, int xo, int xl, int lane, const PivCtl& pc)
 {
