@@ -104,10 +104,11 @@ __host__ __device__ constexpr int64_t xor_top_off(int n, int d)
     return s;
 }
 
-template <class F>
+template <class F, int MODE>
 struct XorLds {
     typename F::E buf[2][kXBuf];
-    typename F::E mn[2][128];        // minors of the nodes of the current and the next level
+    // minors of the nodes of the current and the next level (at most 2^Q, or 3^Q for NAND)
+    typename F::E mn[2][MODE == kNand ? pow3(kXQ3) : (1 << kXQ)];
     typename F::E wk[64];            // subtree levels: each child's pivot row times 1/pivot
     typename F::E wv[32];            // top levels: pivot row times 1/pivot (XNOR: first row of
     typename F::E wv2[32];           // the pivot block's inverse times the pivot rows, and second)
@@ -121,7 +122,7 @@ struct XorLds {
 // the child per lane), from the workspace (or the input at D = 0) to the workspace.
 template <class F, int N, int T, int D, int MODE>
 __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, typename F::E* st,
-                                        typename F::E* ob, XorLds<F>& sh, double& chk)
+                                        typename F::E* ob, XorLds<F, MODE>& sh, double& chk)
 {
     if constexpr (D < T) {
         using E = typename F::E;
@@ -242,7 +243,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
 // children's depth T+J+1 starts in the output (2^(T+J+1) - 2; XOR only: the XNOR minors
 // are the 2^N leaves, written at the last level in block-mask order).
 template <class F, int Q, int J, int MODE>
-__device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, XorLds<F>& sh, double& chk)
+__device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, XorLds<F, MODE>& sh, double& chk)
 {
     if constexpr (J < Q) {
         using E = typename F::E;
@@ -253,6 +254,7 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         static_assert(kids * mc * xs(mc) <= kXBuf && m * xs(m) * (kids / (MODE == kNand ? 3 : 2)) <= kXBuf,
                       "a subtree level fits its LDS buffer");
         static_assert(2 * mc <= kXZero, "zero pivot rows cover a level");
+        static_assert(kids * sizeof(E) <= sizeof(XorLds<F, MODE>::mn[0]), "a level's minors fit");
         const int lane = threadIdx.x;
         if constexpr (MODE == kXor) {
             // child k of node k/2 keeps row mc + (k & 1) of the node's last block: its minor,
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
     constexpr int Q = N < xq(MODE) ? N : xq(MODE);
     constexpr int T = N - Q;
     constexpr int w = 2 * N;
-    __shared__ XorLds<F> sh;
+    __shared__ XorLds<F, MODE> sh;
     const int b = blockIdx.x;
     if (b >= batch) return;
     const int lane = threadIdx.x;
