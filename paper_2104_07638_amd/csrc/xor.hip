@@ -22,11 +22,15 @@
 //     and the pivot rows are the last two rows of its matrix; depth k of the output holds
 //     the minors of the k trailing blocks, and every subtree's outputs are contiguous;
 //   * top levels (d < T = n - Q): depth first over the 2^T depth-T nodes, the stack of
-//     node matrices (orders 2(n-1) ... 2(n-T+1)) in a workspace in global memory, half a
-//     row of the child per lane, with the pivot row (scaled by 1/pivot) staged in LDS; the
-//     depth-T node is written straight into LDS;
+//     node matrices (orders 2(n-1) ... 2(n-T+1)) in a workspace in global memory (the
+//     depth T-1 node in LDS), each row of the child split over as many lanes as the
+//     wavefront allows, with the pivot row (scaled by 1/pivot) staged in LDS; the depth-T
+//     node is written straight into LDS;
 //   * the last Q = min(n, 6) levels of each depth-T node: breadth first in LDS, one row of
-//     a child per lane, so each level is one pass (at most 64 rows, 288 entries);
+//     a child per lane (split over column groups where the rows leave lanes idle), so
+//     each level is one pass (at most 64 rows);
+//   * the LDS arrays are sized for the one tree a kernel runs (binary or ternary), which
+//     sets how many wavefronts a compute unit holds;
 //   * every size is a compile-time constant (one kernel per number of blocks), so no index
 //     arithmetic divides at run time.
 #include <hip/hip_runtime.h>
@@ -53,30 +57,27 @@ __host__ __device__ constexpr int64_t pow3(int k) { return k <= 0 ? 1 : 3 * pow3
 // Row stride of an order-m node matrix in LDS: one element of padding, so that lanes
 // reading the same column of different rows fall on different banks.
 __host__ __device__ constexpr int xs(int m) { return m + APM_XOR_PAD; }
-// Entries of the largest subtree level in LDS, over the binary (six-level) and ternary
-// (four-level) subtrees: the root, and every level's children with padded rows.
-__host__ __device__ constexpr int xbuf_need()
+// Entries of the largest subtree level of one tree (mode) in LDS: the root, and every
+// level's children with padded rows.
+__host__ __device__ constexpr int xbuf_need(int mode)
 {
-    int need = 0;
-    for (int mode = 0; mode < 3; ++mode) {
-        const int Q = mode == 2 ? kXQ3 : kXQ;
-        int kids = 1;
-        const int root = 2 * Q * xs(2 * Q);
-        need = root > need ? root : need;
-        for (int J = 0; J < Q; ++J) {
-            kids *= mode == 2 ? 3 : 2;
-            const int mc = 2 * (Q - J) - 2;
-            const int lvl = kids * mc * xs(mc);
-            need = lvl > need ? lvl : need;
-        }
+    const int Q = xq(mode);
+    int kids = 1, need = 2 * Q * xs(2 * Q);
+    for (int J = 0; J < Q; ++J) {
+        kids *= mode == kNand ? 3 : 2;
+        const int mc = 2 * (Q - J) - 2;
+        const int lvl = kids * mc * xs(mc);
+        need = lvl > need ? lvl : need;
     }
     return need;
 }
-constexpr int kXBuf = xbuf_need();
 #ifndef APM_XOR_PRE
-#define APM_XOR_PRE 1     // keep the depth T-1 node (order 14) in LDS as well
+#define APM_XOR_PRE 1     // keep the depth T-1 node (order 2(Q + 1)) in LDS as well
 #endif
-constexpr int kXPre = APM_XOR_PRE ? 14 * xs(14) : 1;
+__host__ __device__ constexpr int xpre_need(int mode)
+{
+    return APM_XOR_PRE ? 2 * (xq(mode) + 1) * xs(2 * (xq(mode) + 1)) : 1;
+}
 // Lanes per row in a subtree pass of `rows` rows of mc entries: the largest divisor of mc
 // that keeps rows x H within the wavefront (1 when the rows fill it).
 __host__ __device__ constexpr int col_groups(int rows, int mc)
@@ -94,7 +95,7 @@ __host__ __device__ constexpr int top_cols(int mc)
     return (mc + hmax - 1) / hmax;
 }
 // Zero pivot rows of the widest subtree level (two rows of order 2Q - 2).
-constexpr int kXZero = 4 * (kXQ > kXQ3 ? kXQ : kXQ3) - 4;
+__host__ __device__ constexpr int xzero_need(int mode) { return xq(mode) > 1 ? 4 * xq(mode) - 4 : 1; }
 
 // Start of the depth-d node matrix (d >= 1) in a matrix's workspace, in elements.
 __host__ __device__ constexpr int64_t xor_top_off(int n, int d)
@@ -106,20 +107,22 @@ __host__ __device__ constexpr int64_t xor_top_off(int n, int d)
 
 template <class F, int MODE>
 struct XorLds {
-    typename F::E buf[2][kXBuf];
+    typename F::E buf[2][xbuf_need(MODE)];
     // minors of the nodes of the current and the next level (at most 2^Q, or 3^Q for NAND)
-    typename F::E mn[2][MODE == kNand ? pow3(kXQ3) : (1 << kXQ)];
+    typename F::E mn[2][MODE == kNand ? pow3(xq(MODE)) : (1 << xq(MODE))];
     typename F::E wk[64];            // subtree levels: each child's pivot row times 1/pivot
     typename F::E wv[32];            // top levels: pivot row times 1/pivot (XNOR: first row of
     typename F::E wv2[32];           // the pivot block's inverse times the pivot rows, and second)
     typename F::E topm[17];          // minors along the top path
-    typename F::E pre[kXPre];        // the depth T-1 node
-    typename F::E wz[kXZero];        // zeros: the pivot column and rows of a child that leaves
-                                     // its block out, so that it runs the keeping children's code
+    typename F::E pre[xpre_need(MODE)];     // the depth T-1 node
+    // zeros: the pivot column and rows of a child that leaves its block out, so that it
+    // runs the keeping children's code
+    typename F::E wz[xzero_need(MODE)];
 };
 
-// Top level D of matrix order 2N: the child of the depth-D node on path s (half a row of
-// the child per lane), from the workspace (or the input at D = 0) to the workspace.
+// Top level D of matrix order 2N: the child of the depth-D node on path s (a group of
+// columns of a row of the child per lane), from the workspace (or the input at D = 0) to
+// the workspace.
 template <class F, int N, int T, int D, int MODE>
 __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, typename F::E* st,
                                         typename F::E* ob, XorLds<F, MODE>& sh, double& chk)
@@ -135,7 +138,8 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             constexpr bool kPinP = kPin && D == T - 1, kLdsC = D == T - 1 || (kPin && D == T - 2);
             constexpr int ps = kPinP ? xs(m) : m;
             constexpr int cs = kLdsC ? xs(mc) : mc;
-            static_assert(!kLdsC || mc * xs(mc) <= (D == T - 1 ? kXBuf : kXPre), "LDS node fits its buffer");
+            static_assert(!kLdsC || mc * xs(mc) <= (D == T - 1 ? xbuf_need(MODE) : xpre_need(MODE)),
+                          "LDS node fits its buffer");
             const E* P;
             if constexpr (D == 0) {
                 P = A0;
@@ -251,9 +255,10 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         constexpr int m = 2 * (Q - J), mc = m - 2;
         constexpr int kids = MODE == kNand ? (int)pow3(J + 1) : 2 << J;
         static_assert(kids * mc <= 64 && (MODE == kNand || kids <= 64), "one pass per level");
-        static_assert(kids * mc * xs(mc) <= kXBuf && m * xs(m) * (kids / (MODE == kNand ? 3 : 2)) <= kXBuf,
+        static_assert(kids * mc * xs(mc) <= xbuf_need(MODE) &&
+                          m * xs(m) * (kids / (MODE == kNand ? 3 : 2)) <= xbuf_need(MODE),
                       "a subtree level fits its LDS buffer");
-        static_assert(2 * mc <= kXZero, "zero pivot rows cover a level");
+        static_assert(2 * mc <= xzero_need(MODE), "zero pivot rows cover a level");
         static_assert(kids * sizeof(E) <= sizeof(XorLds<F, MODE>::mn[0]), "a level's minors fit");
         const int lane = threadIdx.x;
         if constexpr (MODE == kXor) {
@@ -393,7 +398,7 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
     E* st = ws + (int64_t)b * ws_stride;
     double chk = 0.0;
     if (lane == 0) sh.topm[0] = F::one();
-    for (int e = lane; e < kXZero; e += 64) sh.wz[e] = F::zero();
+    for (int e = lane; e < xzero_need(MODE); e += 64) sh.wz[e] = F::zero();
     constexpr int ntop = MODE == kNand ? (int)pow3(T) : 1 << T;
     for (int s = 0; s < ntop; ++s) {
         // top levels: redo the path below the first choice that changed from s - 1 (the
