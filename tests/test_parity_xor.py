@@ -228,3 +228,55 @@ def test_nand_keldysh_sampled(apm, oracle_mod):
     full = out[:, torch.from_numpy(code).cuda()]
     xfull = xo[:, (1 << n) - 2:]
     assert bool(torch.allclose(full, xfull, rtol=1e-10, atol=1e-12 * float(xfull.abs().max())))
+
+
+def _row_log_norms(A):
+    return np.log(np.maximum(np.linalg.norm(A, axis=1), 1e-300))
+
+
+def _bound_xor(A):
+    """Hadamard bound of every XOR entry from the full rows' norms (a valid, looser bound:
+    ||A[i, R]|| <= ||A[i, :]||), in output order."""
+    n = A.shape[0] // 2
+    ln = _row_log_norms(A)
+    out = []
+    for k in range(1, n + 1):
+        bits = (np.arange(1 << k)[:, None] >> np.arange(k)[None, :]) & 1
+        rows = 2 * (n - k + np.arange(k))[None, :] + bits
+        out.append(np.exp(ln[rows].sum(axis=1)))
+    return np.concatenate(out)
+
+
+def _bound_xnor(A):
+    n = A.shape[0] // 2
+    ln = _row_log_norms(A)
+    bits = (np.arange(1 << n)[:, None] >> np.arange(n)[None, :]) & 1
+    return np.exp(bits @ (ln[0::2] + ln[1::2]))
+
+
+def _bound_nand(A):
+    n = A.shape[0] // 2
+    ln = _row_log_norms(A)
+    codes = np.arange(3 ** n)
+    digits = (codes[:, None] // 3 ** np.arange(n)[None, :]) % 3
+    lt = np.stack([np.zeros(n), ln[0::2], ln[1::2]], axis=1)    # [block][digit]
+    return np.exp(lt[np.arange(n)[None, :], digits].sum(axis=1))
+
+
+@pytest.mark.parametrize("mode,n", [("xor", 15), ("xor", 16), ("xnor", 15), ("xnor", 16), ("nand", 12), ("nand", 13)])
+def test_largest_block_counts(apm, oracle_mod, mode, n):
+    """Every entry at the largest block counts (the widest top-level passes: child orders
+    up to 30, split over two lanes per row), complex Keldysh and real random matrices."""
+    import torch
+    fn = {"xor": (apm.xor_minors, oracle_mod.xor_minors, _bound_xor),
+          "xnor": (apm.xnor_minors, oracle_mod.xnor_minors, _bound_xnor),
+          "nand": (apm.nand_minors, oracle_mod.nand_minors, _bound_nand)}[mode]
+    rng = np.random.default_rng(900 + n)
+    for A in (W.keldysh_block(1, n, seed=910 + n), rng.standard_normal((1, 2 * n, 2 * n)) + 3.0 * np.eye(2 * n)):
+        out, info = fn[0](torch.from_numpy(A).cuda())
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0)
+        got = out.cpu().numpy()[0]
+        ref = fn[1](A)[0]
+        e = metrics.mixed_err(got, ref, fn[2](A[0]))
+        assert e.max() <= 1e-10, (mode, n, A.dtype, float(e.max()), int(np.argmax(e)))
