@@ -52,8 +52,11 @@ __device__ __forceinline__ double rcp64(double x)
     return fma(r, e, r);
 }
 
-struct cd { double x, y; };
-struct cf { float x, y; };
+// Complex values aligned to their size, so that one 16-byte (8-byte) LDS or global access
+// moves a whole value: paired half-size LDS accesses of a padded row fall on the same
+// banks every eight rows.
+struct alignas(16) cd { double x, y; };
+struct alignas(8) cf { float x, y; };
 
 __device__ __forceinline__ cd operator*(cd a, cd b) { return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)}; }
 __device__ __forceinline__ cd operator-(cd a, cd b) { return {a.x - b.x, a.y - b.y}; }
