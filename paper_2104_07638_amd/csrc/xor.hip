@@ -35,6 +35,7 @@
 //     arithmetic divides at run time.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "apm_device.h"
 #include "apm_kernels.h"
@@ -371,10 +372,11 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
     }
 }
 
+// The block minors of matrix blockIdx.x (one wavefront).
 template <class F, int N, int MODE>
-__global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict__ A, typename F::E* __restrict__ out,
-                                                 int32_t* __restrict__ info, int32_t batch,
-                                                 typename F::E* __restrict__ ws, int64_t ws_stride)
+__device__ __forceinline__ void xor_matrix(const typename F::E* __restrict__ A, typename F::E* __restrict__ out,
+                                           int32_t* __restrict__ info, int32_t batch,
+                                           typename F::E* __restrict__ ws, int64_t ws_stride)
 {
     using E = typename F::E;
     constexpr int Q = N < xq(MODE) ? N : xq(MODE);
@@ -426,6 +428,33 @@ __global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict
     if (info && lane == 0) info[b] = bad ? -3 : 0;
 }
 
+template <class F, int N, int MODE>
+__global__ __launch_bounds__(64) void xor_kernel(const typename F::E* __restrict__ A, typename F::E* __restrict__ out,
+                                                 int32_t* __restrict__ info, int32_t batch,
+                                                 typename F::E* __restrict__ ws, int64_t ws_stride)
+{
+    xor_matrix<F, N, MODE>(A, out, info, batch, ws, ws_stride);
+}
+
+// fp64: registers capped for four wavefronts per SIMD (the compiler's choice at 14 blocks,
+// 140 registers, holds three); a few spilled registers cost less than the residency gains.
+template <int N, int MODE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void xor_kernel_r64(
+    const double* __restrict__ A, double* __restrict__ out, int32_t* __restrict__ info, int32_t batch,
+    double* __restrict__ ws, int64_t ws_stride)
+{
+    xor_matrix<FR64, N, MODE>(A, out, info, batch, ws, ws_stride);
+}
+
+template <class F, int N, int MODE>
+constexpr auto xor_kernel_for()
+{
+    if constexpr (std::is_same_v<F, FR64>)
+        return xor_kernel_r64<N, MODE>;
+    else
+        return xor_kernel<F, N, MODE>;
+}
+
 template <class F, int N>
 hipError_t xor_launch_n(const LaunchXor& L, hipStream_t st)
 {
@@ -439,12 +468,12 @@ hipError_t xor_launch_n(const LaunchXor& L, hipStream_t st)
                                L.batch, static_cast<typename F::E*>(L.ws), L.ws_stride);
         };
         if (L.mode == kXnor) {
-            go(xor_kernel<F, N, kXnor>);
+            go(xor_kernel_for<F, N, kXnor>());
         } else if (L.mode == kNand) {
-            if constexpr (N <= 13) go(xor_kernel<F, N, kNand>);
+            if constexpr (N <= 13) go(xor_kernel_for<F, N, kNand>());
             else return hipErrorInvalidValue;
         } else {
-            go(xor_kernel<F, N, kXor>);
+            go(xor_kernel_for<F, N, kXor>());
         }
         return hipGetLastError();
     }
