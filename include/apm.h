@@ -10,7 +10,9 @@
  *     (the paper's Sec. II convention S_13 = {1,3,4}, shifted to 0-based rows).
  *     Every output array of a matrix of order n has 2^n entries in mask order.
  *   - Matrices are dense row-major; complex values are interleaved (re, im) pairs
- *     (the layout of torch.complex128 / complex64 and C99 _Complex double).
+ *     (the layout of torch.complex128 / complex64 and C99 _Complex double), each value
+ *     aligned to its size (16 bytes for complex128, 8 for complex64), as every
+ *     allocation of those types is: the kernels move a whole value per access.
  *   - Pointers inside apm_batch and every data pointer are DEVICE pointers unless
  *     stated otherwise; the caller owns all of them.  The library owns only its
  *     small internal workspace (queue counters and packed offsets of mixed-order
