@@ -244,9 +244,9 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
 }
 
 // Subtree level J of a Q-level subtree: the children of the 2^J nodes in buf[J & 1]
-// (order 2(Q - J)) into buf[(J + 1) & 1], one row of a child per lane.  base is where the
-// children's depth T+J+1 starts in the output (2^(T+J+1) - 2; XOR only: the XNOR minors
-// are the 2^N leaves, written at the last level in block-mask order).
+// (order 2(Q - J)) into buf[(J + 1) & 1], one row (or column group) of a child per lane.
+// base is where the children's depth T+J+1 starts in the output (2^(T+J+1) - 2; XOR
+// only: the XNOR minors are the 2^N leaves, written at the last level in block-mask order).
 template <class F, int Q, int J, int MODE>
 __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, XorLds<F, MODE>& sh, double& chk)
 {
