@@ -150,9 +150,20 @@ int apm_oracle_minors_r64_masks(int n, const double *A, int count, const uint32_
     for (int t = 0; t < count; ++t) {
         uint32_t m = masks[t];
         int k = 0;
+#if ORACLE_PLANT == 12
+        for (int i = 0; i < n; ++i) if (m >> (n - 1 - i) & 1u) idx[k++] = i;
+#else
         for (int i = 0; i < n; ++i) if (m >> i & 1u) idx[k++] = i;
+#endif
         for (int a = 0; a < k; ++a)
-            for (int b = 0; b < k; ++b) sub[a * k + b] = A[idx[a] * n + idx[b]];
+            for (int b = 0; b < k; ++b) {
+#if ORACLE_PLANT == 13
+                const int ra = (a == k - 1 && k > 1) ? a - 1 : a;
+#else
+                const int ra = a;
+#endif
+                sub[a * k + b] = A[idx[ra] * n + idx[b]];
+            }
         out[t] = det_real_inplace(k, sub);
     }
     return 0;

@@ -88,6 +88,17 @@ def close(a, b, rtol, atol=0.0):
 # ----------------------------------------------------------------------------------
 # principal minors (Sec. II)
 # ----------------------------------------------------------------------------------
+def minors_via_masks(oracle_mod, A, lib=None):
+    """All principal minors through the mask-list entry point ``minors_at`` (every mask
+    listed), for single matrices or batches, so that the same pins check it."""
+    A = np.asarray(A, dtype=np.float64)
+    single = A.ndim == 2
+    Ab = A[None] if single else A
+    masks = np.arange(1 << Ab.shape[-1], dtype=np.uint32)
+    out = np.stack([oracle_mod.minors_at(a, masks, lib=lib) for a in Ab])
+    return out[0] if single else out
+
+
 def pin_minors_golden_mask(minors):
     """Sec. II bit-mask example: mask 13 <-> rows {1,3,4} (1-based)."""
     g = json.load(open(os.path.join(GOLDEN, "mask_convention.json")))

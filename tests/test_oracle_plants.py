@@ -20,6 +20,8 @@ PLANTS = {
     9: ("xnor", "the first row of a kept block taken twice"),
     10: ("lead", "entry k holds the leading minor of order k - 1"),
     11: ("nand", "the two kept-row choices of a block swapped"),
+    12: ("minors_at", "mask bits read in reversed order by the mask-list gather"),
+    13: ("minors_at", "the last kept row gathered twice by the mask-list gather"),
 }
 
 
@@ -32,6 +34,8 @@ def test_planted_mistake_is_caught(oracle_mod, plant):
         lib = oracle_mod.load_library(path)
         if kind == "minors":
             fn, pins = (lambda A: oracle_mod.minors(A, lib=lib)), P.MINOR_PINS
+        elif kind == "minors_at":
+            fn, pins = (lambda A: P.minors_via_masks(oracle_mod, A, lib=lib)), P.MINOR_PINS
         elif kind == "cminors":
             fn, pins = (lambda A: oracle_mod.minors_complex(A, lib=lib)), P.CMINOR_PINS
         elif kind == "nand":
