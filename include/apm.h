@@ -19,7 +19,9 @@
  *     batches), allocated on first use per device and grown when a larger mixed-order
  *     batch arrives.  Mixed-order calls (n_uniform == 0) share that workspace: they
  *     must not overlap in time on one device (order them on one stream).  A call that
- *     would grow it must not be the first such call inside a graph capture.
+ *     would grow it must not be the first such call inside a graph capture.  A grown
+ *     workspace replaces the old one, which is kept (not freed) until the process ends,
+ *     so a graph captured earlier stays valid; its replays keep using the old buffer.
  *     Uniform-order calls of apm_all_minors keep one more small buffer per (device,
  *     stream): the queue of matrices whose pivot corrections in the top tree levels are
  *     applied by a follow-up launch.  Calls on one stream are ordered by the stream.
@@ -27,7 +29,8 @@
  *     whose stream has no queue of the batch's size applies those corrections inside
  *     the minors kernel (same results, bit for bit).  A graph that did capture a queue
  *     uses the capturing stream's buffer: its replays must not overlap direct calls on
- *     that stream.
+ *     that stream.  Like the workspace, a queue (and the XOR minors' per-stream node
+ *     workspace) is never freed when a larger one replaces it.
  *   - Calls are asynchronous: arguments are validated on the host, work is
  *     enqueued on `stream`, and the call returns.  Results are valid once the
  *     stream has been synchronised.  Argument errors return before anything is
@@ -87,11 +90,14 @@ typedef struct {
  * Pivot shift (Sec. II, pivot correction; the paper leaves the test and C open):
  * at a tree node with pivot p, largest row entry r = max_j |M_0j| and largest column
  * entry c = max_i |M_i0| of the node's matrix (|z| = max(|Re z|, |Im z|) for complex),
- * p is shifted to p + C when |p|^2 < piv_tol^2 * r * c or p == 0, with C the power of
- * two just below sqrt(r c) (s = max_ij |A_ij| when r c == 0).  The test is invariant
- * under diagonal similarity, as the minors are. */
+ * p is shifted to p + C when |p|^2 < piv_tol^2 * r * c or p == 0.  C is the power of
+ * two 2^(floor(log2(r min(r, c)) / 2) - 4), about min(sqrt(r c), r) / 16 (s / 16 when
+ * r c == 0, with s = max_ij |A_ij|), with the sign of Re p, so that |p + C| >= |C|.  The test is
+ * invariant under diagonal similarity, as the minors are.  The minors are corrected
+ * exactly for every shift (det A[S] = det A~[S] - C det A[S \ {l}]), so piv_tol trades
+ * the number of corrections against the growth of the unshifted Schur complements. */
 typedef struct {
-    double piv_tol;           /* <= 0: default 1e-4 (R64, C128) or 1e-3 (R32S, C64S)      */
+    double piv_tol;           /* <= 0: default 1e-3 (every element type)                  */
     uint32_t flags;           /* APM_OUT_F64 | APM_NO_PERTURB                             */
 } apm_opts;
 

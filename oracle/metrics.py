@@ -6,11 +6,20 @@ H_S = prod_{i in S} ||A[i, S]||_2 >= |det A[S]|  (e_S = 0 when x_S == ref_S)."""
 import numpy as np
 
 
+def _row_scaled_squares(A):
+    """|A_ij|^2 / m_i^2 and log m_i with m_i = max_j |A_ij| (1 for a zero row), so that the
+    squares neither overflow nor underflow for any finite entries."""
+    mag = np.abs(A)
+    m = mag.max(axis=-1, keepdims=True)
+    m = np.where(m > 0, m, 1.0)
+    return (mag / m) ** 2, np.log(m[..., 0])
+
+
 def hadamard_bounds(A):
     """H[m] = prod_{i in S_m} ||A[i, S_m]||_2 for every mask m, for one (n, n) matrix."""
     A = np.asarray(A)
     n = A.shape[0]
-    sq = np.abs(A) ** 2
+    sq, logm = _row_scaled_squares(A)
     nm = 1 << n
     logH = np.zeros(nm)
     masks = np.arange(nm)
@@ -19,19 +28,27 @@ def hadamard_bounds(A):
         for j in range(n):
             rows = np.concatenate([rows, rows + sq[i, j]])
         with np.errstate(divide="ignore"):
-            lr = 0.5 * np.log(rows)
+            lr = 0.5 * np.log(rows) + logm[i]
         inS = (masks >> i) & 1
         logH = logH + np.where(inS == 1, lr, 0.0)
     return np.exp(logH)
 
 
+def _norm2(x):
+    """||x||_2 computed as m ||x / m||_2, m = max |x_j|, free of overflow and underflow."""
+    m = np.max(np.abs(x)) if x.size else 0.0
+    return 0.0 if m == 0 else m * np.sqrt(np.sum((np.abs(x) / m) ** 2))
+
+
 def hadamard_at(A, masks):
+    """H_S for the listed masks only, by explicit products of row norms (log-summed)."""
     A = np.asarray(A)
     n = A.shape[0]
     out = np.empty(len(masks))
     for t, m in enumerate(masks):
         r = [k for k in range(n) if m >> k & 1]
-        out[t] = np.prod([np.linalg.norm(A[i, r]) for i in r]) if r else 1.0
+        with np.errstate(divide="ignore"):
+            out[t] = np.exp(np.sum([np.log(_norm2(A[i, r])) for i in r])) if r else 1.0
     return out
 
 
@@ -59,7 +76,7 @@ def hadamard_bounds_batch(A):
     """hadamard_bounds for a (B, n, n) batch."""
     A = np.asarray(A)
     B, n, _ = A.shape
-    sq = np.abs(A) ** 2
+    sq, logm = _row_scaled_squares(A)
     nm = 1 << n
     masks = np.arange(nm)
     logH = np.zeros((B, nm))
@@ -68,7 +85,7 @@ def hadamard_bounds_batch(A):
         for j in range(n):
             rows = np.concatenate([rows, rows + sq[:, i, j:j + 1]], axis=1)
         with np.errstate(divide="ignore"):
-            lr = 0.5 * np.log(rows)
+            lr = 0.5 * np.log(rows) + logm[:, i:i + 1]
         logH = logH + np.where(((masks >> i) & 1) == 1, lr, 0.0)
     return np.exp(logH)
 

@@ -34,6 +34,23 @@ struct Workspace {
 std::mutex g_ws_mu;
 std::vector<Workspace> g_ws;
 
+// Buffers replaced by larger ones.  A graph captured from an earlier call may still hold
+// their addresses, so they are kept (never freed) until the process ends; capacities grow
+// at least geometrically, so the retired ones together never exceed the live one.
+std::vector<void*> g_retired;
+
+void retire(void* p)
+{
+    if (p) g_retired.push_back(p);
+}
+
+int64_t grown(int64_t cur, int64_t need, int64_t floor_cap)
+{
+    int64_t cap = cur * 2;
+    if (cap < need) cap = need;
+    return cap < floor_cap ? floor_cap : cap;
+}
+
 apm_status get_workspace(int64_t batch, int32_t** counter, int32_t** order, int64_t** ioff, int64_t** ooff,
                          int* cus)
 {
@@ -50,11 +67,12 @@ apm_status get_workspace(int64_t batch, int32_t** counter, int32_t** order, int6
         w.cus = v;
     }
     if (w.cap < batch) {
-        if (w.buf) (void)hipFree(w.buf);
-        w.buf = nullptr;
-        int64_t cap = batch < 4096 ? 4096 : batch;
-        e = hipMalloc(&w.buf, 256 + (size_t)cap * (4 + 8 + 8));
-        if (e != hipSuccess) { w.cap = 0; return from_hip(e); }
+        const int64_t cap = grown(w.cap, batch, 4096);
+        void* nb = nullptr;
+        e = hipMalloc(&nb, 256 + (size_t)cap * (4 + 8 + 8));
+        if (e != hipSuccess) return from_hip(e);
+        retire(w.buf);
+        w.buf = nb;
         w.cap = cap;
     }
     char* p = static_cast<char*>(w.buf);
@@ -87,14 +105,11 @@ int32_t* get_topq(hipStream_t st, int64_t batch, int32_t* cap_out, TopQueue** q_
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
         if (q.cap < batch) {
-            if (q.buf) (void)hipFree(q.buf);
-            q.buf = nullptr;
-            q.cap = 0;
-            const int64_t cap = batch < 4096 ? 4096 : batch;
-            if (hipMalloc(&q.buf, (size_t)apm::fpm_topq_bytes(cap)) != hipSuccess) {
-                q.buf = nullptr;
-                return nullptr;
-            }
+            const int64_t cap = grown(q.cap, batch, 4096);
+            void* nb = nullptr;
+            if (hipMalloc(&nb, (size_t)apm::fpm_topq_bytes(cap)) != hipSuccess) return nullptr;
+            retire(q.buf);
+            q.buf = nb;
             q.cap = cap;
         }
         if (hipMemsetAsync(q.buf, 0, (size_t)apm::fpm_topq_bytes(q.cap), st) != hipSuccess) return nullptr;
@@ -125,19 +140,13 @@ apm_status get_xor_ws(hipStream_t st, size_t bytes, void** out)
         e = hipStreamIsCapturing(st, &cs);
         if (e != hipSuccess) return from_hip(e);
         if (cs != hipStreamCaptureStatusNone) return APM_EUNSUPPORTED;
-        if (w.buf) {
-            e = hipStreamSynchronize(st);   // earlier work on this stream may still use it
-            if (e != hipSuccess) return from_hip(e);
-            (void)hipFree(w.buf);
-        }
-        w.buf = nullptr;
-        w.cap = 0;
-        e = hipMalloc(&w.buf, bytes);
-        if (e != hipSuccess) {
-            w.buf = nullptr;
-            return from_hip(e);
-        }
-        w.cap = bytes;
+        const size_t cap = bytes > 2 * w.cap ? bytes : 2 * w.cap;
+        void* nb = nullptr;
+        e = hipMalloc(&nb, cap);
+        if (e != hipSuccess) return from_hip(e);
+        retire(w.buf);
+        w.buf = nb;
+        w.cap = cap;
     }
     *out = w.buf;
     return APM_OK;
@@ -186,8 +195,7 @@ apm_status minors_args(apm_dtype dt, const void* A, const apm_batch* bd, void* m
     L->n_max = bd->n_max > 0 ? bd->n_max : APM_MAX_N;
     L->in_off = bd->in_off;
     L->out_off = bd->out_off;
-    const double tau_def = scaled ? 1e-3 : 1e-4;
-    L->tau = (opt && opt->piv_tol > 0) ? opt->piv_tol : tau_def;
+    L->tau = (opt && opt->piv_tol > 0) ? opt->piv_tol : apm::kDefaultPivTol;
     L->perturb = !(flags & APM_NO_PERTURB);
     L->out_f64 = out_f64;
     return APM_OK;
@@ -534,7 +542,7 @@ apm_status apm_autotune_minors(apm_dtype dt, int32_t n, int32_t batch, int32_t* 
             L.batch = batch;
             L.n_uniform = n;
             L.n_max = n;
-            L.tau = scaled ? 1e-3 : 1e-4;
+            L.tau = apm::kDefaultPivTol;
             L.perturb = true;
             L.force_k0 = k;
             e = apm::fpm_launch(L, st);                       // warm-up

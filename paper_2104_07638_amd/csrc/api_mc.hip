@@ -140,7 +140,7 @@ hipError_t weights(const apm::McArgs& a, const McWork& wk, hipStream_t st)
     L.batch = a.W;
     L.n_uniform = a.n;
     L.n_max = a.n;
-    L.tau = 1e-4;
+    L.tau = apm::kDefaultPivTol;
     L.perturb = true;
     hipError_t e = apm::fpm_launch(L, st);
     if (e != hipSuccess) return e;

@@ -80,6 +80,7 @@ struct FR64 {
     __device__ static bool in_finite(In v) { return isfinite(v); }
     __device__ static E conv(In v, double sc) { return v; }
     __device__ static double mag(E p) { return fabs(p); }
+    __device__ static double re(E p) { return p; }
     __device__ static E shift(E p, double C) { return p + C; }
     __device__ static R recip(E p) { return rcp64(p); }
     __device__ static E rowscale(E v, R r) { return v * r; }
@@ -125,6 +126,7 @@ struct FR32S {
     __device__ static bool in_finite(In v) { return isfinite(v); }
     __device__ static E conv(In v, double sc) { return (float)(v * sc); }
     __device__ static double mag(E p) { return fabs((double)p); }
+    __device__ static double re(E p) { return (double)p; }
     __device__ static E shift(E p, double C) { return (float)((double)p + C); }
     __device__ static R recip(E p) { return rcp64((double)p); }
     __device__ static E rowscale(E v, R r) { return (float)((double)v * r); }
@@ -209,11 +211,18 @@ struct FC128 {
     __device__ static bool in_finite(In v) { return isfinite(v.x) && isfinite(v.y); }
     __device__ static E conv(In v, double) { return v; }
     __device__ static double mag(E p) { return fmax(fabs(p.x), fabs(p.y)); }
+    __device__ static double re(E p) { return p.x; }
     __device__ static E shift(E p, double C) { return {p.x + C, p.y}; }
+    // 1/p = conj(p) / |p|^2, with p scaled by the power of two 2^-k nearest its larger
+    // component before squaring, so that |p|^2 neither overflows nor underflows for any
+    // representable pivot: 1/p = 2^-k conj(q) / |q|^2, q = 2^-k p.
     __device__ static R recip(E p)
     {
-        double d = rcp64(fma(p.x, p.x, p.y * p.y));
-        return {p.x * d, -p.y * d};
+        int k = 0;
+        (void)frexp(fmax(fabs(p.x), fabs(p.y)), &k);
+        const double qx = ldexp(p.x, -k), qy = ldexp(p.y, -k);
+        const double d = ldexp(rcp64(fma(qx, qx, qy * qy)), -k);
+        return {qx * d, -qy * d};
     }
     __device__ static E rowscale(E v, R r) { return v * r; }
     __device__ static E det2(E p, E r, E c, E d)
@@ -267,6 +276,7 @@ struct FC64S {
     __device__ static bool in_finite(In v) { return isfinite(v.x) && isfinite(v.y); }
     __device__ static E conv(In v, double sc) { return {(float)(v.x * sc), (float)(v.y * sc)}; }
     __device__ static double mag(E p) { return (double)fmaxf(fabsf(p.x), fabsf(p.y)); }
+    __device__ static double re(E p) { return (double)p.x; }
     __device__ static E shift(E p, double C) { return {(float)((double)p.x + C), p.y}; }
     __device__ static R recip(E p)
     {

@@ -5,6 +5,9 @@
 
 namespace apm {
 
+// Default relative pivot-shift threshold of the minors tree, every element type.
+constexpr double kDefaultPivTol = 1e-3;
+
 struct LaunchMinors {
     int dtype;                 // apm_dtype
     const void* A;

@@ -23,8 +23,8 @@
 //   * every mask is written exactly once, by the lane whose subtree contains it;
 //     the node's recorded minor uses the true pivot (Algorithm 1 records before
 //     it shifts), its right subtree uses the shifted one.
-//   * shifted pivots (see analyse() for the test and the shift) are recorded with the
-//     exponent of their power-of-two shift (top: one byte per chunk transition; mid:
+//   * shifted pivots (see analyse() for the test and the shift) are recorded as one byte
+//     holding the signed power-of-two shift (top: one byte per chunk transition; mid:
 //     one byte per node; lane: one byte per node packed in a 64-bit register) and
 //     corrected after the stores, deepest level first, by read-modify-write passes
 //     over the already written minors (rare path).
@@ -41,7 +41,7 @@ namespace apm {
 #endif
 
 constexpr int kMid = 6;
-constexpr int8_t kNoEv = -128;   // "no shifted pivot" marker in the int8 shift-exponent tables
+constexpr int8_t kNoEv = 0;      // "no shifted pivot" marker in the one-byte shift-code tables
 
 template <int N, int K0MAX>
 struct Plan {
@@ -149,35 +149,61 @@ struct PivInfo {
     typename F::E pt, pu;
     typename F::R ri;
     bool pert;
-    int de;          // the shift is C = 2^(es + de) (stored units)
+    int8_t code;     // shift code (see shift_value), kNoEv if not shifted
 };
+
+// Magnitude of the pivot shift: the power of two 2^(floor(log2(rmax * min(rmax, cmax)) / 2)
+// + kShiftLog2), about min(sqrt(rmax cmax), rmax) / 16.  The correction
+// det A[S] = det A~[S] - C det A[S \ {l}] loses about eps C / |row l| of the Hadamard bound
+// of A[S] to cancellation, so C stays at or below the pivot row's scale; the sign alignment
+// below keeps |p + C| >= |C|, so the right child's elements change by at most
+// rmax cmax / |C| (at most 16 times the larger of the column scale and sqrt(rmax cmax)).
+constexpr int kShiftLog2 = -4;
+
+// A shift is recorded as one byte: code = 2 (de + kShiftBias) + (C < 0), with
+// C = +-2^(es + de) in stored units (es: exponent of s = max |A_ij|) and de clamped to
+// [1 - kShiftBias, 127 - kShiftBias] = [-119, 7]: shifts far below the matrix's largest
+// entry (rows of a near-singular or strongly graded part) are more common than shifts
+// above it, which need growth of the Schur complements beyond 2^11 s.  kNoEv (0) marks
+// "no shift".
+constexpr int kShiftBias = 120;
+
+__device__ __forceinline__ double shift_value(int es, int code)
+{
+    const int u = code & 0xFF;
+    const double C = ldexp(1.0, es + (u >> 1) - kShiftBias);
+    return (u & 1) ? -C : C;
+}
 
 // Pivot analysis of a node (Sec. II, pivot correction).  A pivot p is shifted when
 // |p|^2 < tau^2 * rmax * cmax, rmax / cmax being the largest magnitudes in the pivot's
 // row / column of the node's matrix (a test invariant under diagonal similarity), or
-// when p == 0; the shift is the power of two nearest below sqrt(rmax * cmax) (s when the
-// row or column vanishes).
+// when p == 0.  The shift C takes the sign of Re p, so that it never cancels the pivot;
+// its magnitude is given above (s / 16 when the row or column vanishes: the right child
+// then equals the left one exactly, times C).
 template <class F>
 __device__ __forceinline__ PivInfo<F> analyse(typename F::E p, double rmax, double cmax, int size,
                                               const PivCtl& pc)
 {
     PivInfo<F> v;
     v.pt = p;
-    v.de = 0;
+    v.code = kNoEv;
     const double prod = rmax * cmax;
     const double pm = F::mag(p);
     v.pert = pc.perturb && size >= 2 && (pm == 0.0 || pm * pm < pc.tau2 * prod);
     v.pu = p;
     if (v.pert) {
-        int de = 0;
-        if (prod > 0.0) {
+        int de = kShiftLog2;
+        const double pr = rmax * fmin(rmax, cmax);
+        if (pr > 0.0) {
             int ep;
-            (void)frexp(prod, &ep);
-            de = (ep >> 1) - pc.es;
-            de = de < -127 ? -127 : (de > 127 ? 127 : de);
+            (void)frexp(pr, &ep);
+            de = (ep >> 1) + kShiftLog2 - pc.es;
         }
-        v.de = de;
-        v.pu = F::shift(p, ldexp(1.0, pc.es + de));
+        de = de < 1 - kShiftBias ? 1 - kShiftBias : (de > 127 - kShiftBias ? 127 - kShiftBias : de);
+        const bool neg = F::re(p) < 0.0;
+        v.code = (int8_t)(uint8_t)(2 * (de + kShiftBias) + (neg ? 1 : 0));
+        v.pu = F::shift(p, shift_value(pc.es, v.code));
     }
     v.ri = F::recip(v.pu);
     return v;
@@ -236,7 +262,7 @@ __device__ __forceinline__ void lane_node(const typename F::E (&M)[KP * KP], typ
         if (pv.pert) {
             cx.ev |= 1u << id;
             constexpr int sh = 8 * (id & 7);
-            const uint64_t byte = (uint64_t)(uint8_t)(int8_t)pv.de << sh;
+            const uint64_t byte = (uint64_t)(uint8_t)pv.code << sh;
             if constexpr (id < 8)
                 cx.lc0 = (cx.lc0 & ~(0xFFull << sh)) | byte;
             else
@@ -350,7 +376,7 @@ __device__ __forceinline__ void bf_levels(typename F::E* lds, typename F::E* pt_
                 pt_a[nodes - 1 + t] = pv.pt;
                 pu_a[nodes - 1 + t] = pv.pu;
                 ri_a[nodes - 1 + t] = pv.ri;
-                midc[nodes - 1 + t] = pv.pert ? (int8_t)pv.de : kNoEv;
+                midc[nodes - 1 + t] = pv.code;
                 pert = pv.pert;
             }
         }
@@ -420,7 +446,7 @@ __device__ __noinline__ void chunk_fixup(void* out, int16_t* ex, int64_t base, i
                 const int id = (1 << dep) - 1 + q;
                 if (active && (ev >> id & 1u)) {
                     const uint64_t lw = id < 8 ? lc0 : lc1;
-                    const double Ct = ldexp(1.0, es_true + (int)(int8_t)(uint8_t)(lw >> (8 * (id & 7))));
+                    const double Ct = shift_value(es_true, (int)(uint8_t)(lw >> (8 * (id & 7))));
                     const int nu = 1 << (k0 - 1 - dep);
                     const int64_t pstep = (int64_t)(1 << dep) << kMid;
                     for (int u0 = 1; u0 < nu; u0 += 4) {
@@ -454,7 +480,7 @@ __device__ __noinline__ void chunk_fixup(void* out, int16_t* ex, int64_t base, i
         const bool mine = active && ((lane >> b) & 1) && de != kNoEv;
         if (ballot(mine) == 0) continue;
         if (mine) {
-            const double Ct = ldexp(1.0, es_true + de);
+            const double Ct = shift_value(es_true, de);
             const int j0 = ((lane >> (b + 1)) == 0) ? 1 : 0;   // skip the node's own recorded minor
             for (int jb = j0; jb < (1 << k0); jb += 4) {
                 typename F::V va[4], vb[4];
@@ -552,7 +578,7 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
             if (pv.pert) {
                 nev += 1;
                 any_top = true;
-                if (lane == 0) tevc[c] = (int8_t)pv.de;
+                if (lane == 0) tevc[c] = pv.code;
             }
             const Bs bnew = F::bmul(bud, pv.pu, e0);
             const Bs rnew = F::bmul(bud, pv.pt, e0);
@@ -592,7 +618,7 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
         const double rm = szb > 1 ? tree_max(rvm) : 0.0, cm = szb > 1 ? tree_max(cvm) : 0.0;
         const PivInfo<F> v0 = analyse<F>(Pb[0], rm, cm, szb, pc);
         mid_any |= ballot(lane < (1 << bf) && v0.pert) != 0;
-        if (lane < (1 << bf)) midc[(1 << bf) - 1 + lane] = v0.pert ? (int8_t)v0.de : kNoEv;
+        if (lane < (1 << bf)) midc[(1 << bf) - 1 + lane] = v0.code;
         const bool rb0 = (lane >> bf) & 1;
         E M1[nz(sq(szb - 1))];
 #pragma unroll
@@ -625,8 +651,8 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
         cx.active = lane < P::active;
         cx.f64 = o.out_f64;
         cx.ev = 0;
-        cx.lc0 = 0x8080808080808080ull;
-        cx.lc1 = 0x8080808080808080ull;
+        cx.lc0 = 0;
+        cx.lc1 = 0;
         cx.chk = 0.0;
 
         if constexpr (P::inl == 2) {
@@ -635,7 +661,7 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
             rc_max<F, sz1>(M1, rm1, cm1);
             const PivInfo<F> v1 = analyse<F>(M1[0], rm1, cm1, sz1, pc);
             mid_any |= ballot(lane < (2 << bf) && v1.pert) != 0;
-            if (lane < (2 << bf)) midc[(2 << bf) - 1 + lane] = v1.pert ? (int8_t)v1.de : kNoEv;
+            if (lane < (2 << bf)) midc[(2 << bf) - 1 + lane] = v1.code;
             if ((lane >> (bf + 1)) & 1) {
                 if (bf + 1 == h) rec = F::bmul(acc, v1.pt, e0);
                 acc = F::bmul(acc, v1.pu, e0);
@@ -697,7 +723,7 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
                     const int de = tevc[c];
                     if (de == kNoEv) continue;
                     did = true;
-                    const double Ct = ldexp(1.0, pc.es_true + de);
+                    const double Ct = shift_value(pc.es_true, de);
                     const int64_t start = (int64_t)c << K, end = start + half;
                     constexpr int kU = 8;
                     for (int64_t i0 = start + 1; i0 < end; i0 += kWave * kU) {
@@ -779,7 +805,7 @@ __global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int
             if (de == kNoEv) continue;
             void* out = reinterpret_cast<void*>((uint64_t)(uint32_t)ent[0] | ((uint64_t)(uint32_t)ent[1] << 32));
             int16_t* ex = reinterpret_cast<int16_t*>((uint64_t)(uint32_t)ent[2] | ((uint64_t)(uint32_t)ent[3] << 32));
-            const double Ct = ldexp(1.0, ent[4] + de);
+            const double Ct = shift_value(ent[4], de);
             const int64_t start = (int64_t)c << K, end = start + half;
             const int64_t i0 = start + 1 + t * kTopTile;
             constexpr int kU = kTopTile / 256;

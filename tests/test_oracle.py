@@ -123,6 +123,12 @@ def test_hadamard_at_matches_hadamard_bounds():
         masks = np.arange(1 << n)
         np.testing.assert_allclose(metrics.hadamard_at(A, masks), H, rtol=1e-13)
         assert H[0] == 1.0
+    # entries whose squares overflow or underflow fp64 (numpy's norm rescales internally)
+    A = rng.standard_normal((6, 6)) * np.array([2.0 ** 600, 1.0, 2.0 ** -560, 1.0, 1.0, 1.0])[:, None]
+    H = metrics.hadamard_bounds(A)
+    assert np.all(np.isfinite(H[1:])) and np.all(H[1:] > 0)
+    np.testing.assert_allclose(metrics.hadamard_at(A, np.arange(64)), H, rtol=1e-13)
+    np.testing.assert_allclose(metrics.hadamard_bounds_batch(A[None])[0], H, rtol=1e-14)
 
 
 def test_hadamard_inequality_and_equality():

@@ -202,3 +202,47 @@ def test_ragged_default_offsets_csum_perm(apm, oracle_mod):
         seg = got[ooff[k]:ooff[k] + (1 << M.shape[0])]
         ref = oracle_mod.perm_minors(M)
         assert np.allclose(seg, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+
+
+def test_capture_survives_workspace_growth(apm, oracle_mod):
+    """A graph captured from a direct mixed-order call keeps the library workspace it
+    recorded: a later direct call that needs a larger workspace replaces it without
+    freeing it, so the next replay reads and writes live memory and gives the same bits."""
+    import torch
+    mats, _ = W.lattice_ragged(48, 6, 11, W.Lattice(16, 1.0, 0.0, 4.0), seed=95)
+    ns, flat, ooff, tot = pack(mats)
+    A = torch.from_numpy(flat).cuda()
+    n_t = torch.from_numpy(ns).cuda()
+    m = torch.empty(tot, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        apm.all_minors_ragged(A, n_t, 11, "r64", out=m)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    m_ref = m.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        apm.all_minors_ragged(A, n_t, 11, "r64", out=m)
+    # more matrices than any earlier call of this process used: the workspace must grow
+    big = 1 << 17
+    rng = np.random.default_rng(96)
+    bns = rng.integers(2, 5, big).astype(np.int32)
+    bflat = np.concatenate([np.eye(k).ravel() * 2.0 for k in bns])
+    btot = int(np.sum(np.left_shift(1, bns.astype(np.int64))))
+    bm = torch.empty(btot, dtype=torch.float64, device="cuda")
+    _, _, binfo = apm.all_minors_ragged(torch.from_numpy(bflat).cuda(), torch.from_numpy(bns).cuda(), 4, "r64",
+                                        out=bm)
+    torch.cuda.synchronize()
+    assert int(binfo.min()) == 0
+    # minors of 2 I: 2^|S|
+    bo = np.concatenate([[0], np.cumsum(np.left_shift(1, bns.astype(np.int64)))[:-1]])
+    got = bm.cpu().numpy()
+    for k in range(0, big, 4099):
+        seg = got[bo[k]:bo[k] + (1 << bns[k])]
+        assert np.array_equal(seg, 2.0 ** np.array([bin(s).count("1") for s in range(1 << bns[k])]))
+    for i in range(2):
+        m.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(m, m_ref), i
