@@ -364,7 +364,9 @@ def test_complex_extreme_pivots(apm, oracle_mod):
     out, info = run(apm, A, "c128")
     assert np.all(info == 0), info
     assert np.all(np.isfinite(out))
-    assert metrics.max_mixed_err(out, ref, A) <= TOL64
+    # the Hadamard bound of A itself overflows here (every row holds a 2^265 entry), and
+    # the minors of a diagonally dominant matrix are well conditioned: plain relative error
+    assert np.max(np.abs(out - ref) / np.abs(ref)) <= 1e-12
     import torch
     lo, li = apm.leading_minors(torch.from_numpy(A).cuda())
     torch.cuda.synchronize()
