@@ -139,6 +139,28 @@ apm_status apm_all_minors(apm_dtype dt, const void *A, const apm_batch *bd, void
 #define APM_CS_ALL 1u         /* j = lowest vertex of S; c[S] for every nonempty S           */
 
 /*
+ * apm_all_minors_noalloc -- apm_all_minors that allocates nothing.
+ *
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, results (bit for bit)
+ * and errors as apm_all_minors, with these differences:
+ *   - batch must be at most APM_NOALLOC_MAX_BATCH; a larger batch returns
+ *     APM_EUNSUPPORTED before anything is enqueued;
+ *   - the call's scratch (the deferred pivot-correction queue of a uniform batch; the
+ *     queue head, queue order and packed offsets of a mixed-order batch) is one static
+ *     device array of 1 MiB + 4.25 KiB per GPU, loaded with the library and held until the
+ *     process ends; its device address is looked up on the first call on each GPU.  No
+ *     call allocates or frees device memory;
+ *   - every call on a GPU uses that GPU's array and leaves its contents to the next
+ *     call: calls that overlap in time on one GPU (other streams, concurrent graph
+ *     replays) race, and the caller must order them.  Each call clears what must start
+ *     at zero with a small kernel on `stream` (no memset), so it can be captured.
+ */
+#define APM_NOALLOC_MAX_BATCH 16384
+apm_status apm_all_minors_noalloc(apm_dtype dt, const void *A, const apm_batch *bd, void *minors,
+                                  int16_t *exp, int32_t *info, const apm_opts *opt, apm_stream stream);
+
+/*
  * apm_connected_sums -- CDet connected sums from subset weights.
  *
  * Passage: Sec. V.A, the weights a[S] = det M_up[S] det M_dn[S] and Eq. (recursion)

@@ -38,6 +38,7 @@ APM_OUT_F64, APM_NO_PERTURB = 1, 2
 APM_CS_ROOTED, APM_CS_ALL, APM_CS_WEIGHTS = 0, 1, 2
 APM_PLAN_MINORS, APM_PLAN_CONNECTED_SUMS, APM_PLAN_PERM_MINORS, APM_PLAN_CDET = 0, 1, 2, 3
 APM_PLAN_AUTOTUNE, APM_PLAN_EAGER = 1, 2
+APM_NOALLOC_MAX_BATCH = 16384
 
 DTYPES = {"r64": APM_R64, "r32s": APM_R32S, "c128": APM_C128, "c64s": APM_C64S}
 
@@ -49,7 +50,7 @@ EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_s
            "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
            "apm_minors_k0", "apm_plan_create", "apm_plan_launch", "apm_plan_k0", "apm_plan_graphed",
            "apm_plan_destroy", "apm_last_device_error", "apm_xor_minors", "apm_xnor_minors",
-           "apm_leading_minors", "apm_nand_minors")
+           "apm_leading_minors", "apm_nand_minors", "apm_all_minors_noalloc")
 
 APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
@@ -118,8 +119,9 @@ def _load():
     lib.apm_connected_sums.restype = ctypes.c_int
     lib.apm_all_perm_minors.argtypes = [vp, ctypes.POINTER(apm_batch), vp, vp]
     lib.apm_all_perm_minors.restype = ctypes.c_int
-    for name in ("apm_xor_minors", "apm_xnor_minors",
-           "apm_leading_minors", "apm_nand_minors"):
+    lib.apm_all_minors_noalloc.argtypes = lib.apm_all_minors.argtypes
+    lib.apm_all_minors_noalloc.restype = ctypes.c_int
+    for name in ("apm_xor_minors", "apm_xnor_minors", "apm_leading_minors", "apm_nand_minors"):
         getattr(lib, name).argtypes = [ctypes.c_int, vp, ctypes.POINTER(apm_batch), vp, vp, vp]
         getattr(lib, name).restype = ctypes.c_int
     lib.apm_status_str.argtypes = [ctypes.c_int]
@@ -175,6 +177,11 @@ _lib = _load()
 def apm_all_minors(dt, A, bd, minors, exp, info, opt, stream):
     return _lib.apm_all_minors(int(dt), A, ctypes.byref(bd) if bd is not None else None, minors, exp, info,
                                ctypes.byref(opt) if opt is not None else None, stream)
+
+
+def apm_all_minors_noalloc(dt, A, bd, minors, exp, info, opt, stream):
+    return _lib.apm_all_minors_noalloc(int(dt), A, ctypes.byref(bd) if bd is not None else None, minors, exp,
+                                       info, ctypes.byref(opt) if opt is not None else None, stream)
 
 
 def apm_connected_sums(m_up, m_dn, bd, c, mode, stream):

@@ -267,6 +267,55 @@ apm_status packed_offsets(const apm_batch* bd, hipStream_t st, const int64_t** i
     return APM_OK;
 }
 
+// ---- scratch of apm_all_minors_noalloc ------------------------------------------------------
+// One static device array per GPU (loaded with the code object, held until the process ends):
+// the deferred pivot-correction queue of a uniform batch, or the queue head, queue order and
+// packed offsets of a mixed-order batch, of at most APM_NOALLOC_MAX_BATCH matrices.
+constexpr int64_t kScratchBytes = 256 + 64 * (int64_t)APM_NOALLOC_MAX_BATCH + 4096;
+constexpr int64_t kScrOrder = 256;                                             // int32 [max]
+constexpr int64_t kScrIoff = kScrOrder + 4 * (int64_t)APM_NOALLOC_MAX_BATCH;    // int64 [max]
+constexpr int64_t kScrOoff = kScrIoff + 8 * (int64_t)APM_NOALLOC_MAX_BATCH;     // int64 [max]
+static_assert(kScrOoff + 8 * (int64_t)APM_NOALLOC_MAX_BATCH <= kScratchBytes, "mixed-order layout fits");
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, looked up once
+int g_scratch_cus[kMaxDevices];
+
+// The device address of this device's copy of `scratch` (its host-side name is only a
+// stand-in) and the device's compute-unit count, looked up on the first call per device.
+apm_status scratch_address(char** base, int* cus)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e);
+    if (dev < 0 || dev >= kMaxDevices) return APM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return from_hip(e);
+        if (!p) return APM_EDEVICE;
+        int v = 0;
+        e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return from_hip(e);
+        g_scratch_cus[dev] = v;
+        g_scratch_ptr[dev] = p;
+    }
+    *base = static_cast<char*>(g_scratch_ptr[dev]);
+    *cus = g_scratch_cus[dev];
+    return APM_OK;
+}
+
+// Clears the deferred-correction queue's two counters (entries queued, workgroups done); the
+// entries themselves are written before they are read.  A kernel, not a memset, so that the
+// call can be captured into a graph.
+__global__ void scratch_head_clear_kernel(int32_t* q)
+{
+    if (threadIdx.x < 2) q[threadIdx.x] = 0;
+}
+
 }  // namespace
 
 // A plan: the launch descriptions of one operation (or of the CDet pipeline) bound to the
@@ -491,6 +540,36 @@ apm_status apm_all_minors(apm_dtype dt, const void* A, const apm_batch* bd, void
         tq->dirty = true;
     }
     return from_hip(e);
+}
+
+apm_status apm_all_minors_noalloc(apm_dtype dt, const void* A, const apm_batch* bd, void* minors, int16_t* exp,
+                                  int32_t* info, const apm_opts* opt, apm_stream stream)
+{
+    apm::LaunchMinors L{};
+    bool noop = false;
+    apm_status s = minors_args(dt, A, bd, minors, exp, info, opt, &L, &noop);
+    if (s != APM_OK || noop) return s;
+    if (bd->batch > APM_NOALLOC_MAX_BATCH) return APM_EUNSUPPORTED;
+    char* base = nullptr;
+    int cus = 0;
+    s = scratch_address(&base, &cus);
+    if (s != APM_OK) return s;
+    const hipStream_t st = (hipStream_t)stream;
+    if (bd->n_uniform == 0) {
+        // the queue-preparation kernel of the launch resets the queue head itself
+        L.counter = reinterpret_cast<int32_t*>(base);
+        L.order = reinterpret_cast<int32_t*>(base + kScrOrder);
+        L.ioff_ws = reinterpret_cast<int64_t*>(base + kScrIoff);
+        L.ooff_ws = reinterpret_cast<int64_t*>(base + kScrOoff);
+        L.n_workers = cus;
+    } else {
+        L.topq = reinterpret_cast<int32_t*>(base);
+        L.topq_cap = bd->batch;
+        hipLaunchKernelGGL(scratch_head_clear_kernel, dim3(1), dim3(64), 0, st, L.topq);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return from_hip(e);
+    }
+    return from_hip(apm::fpm_launch(L, st));
 }
 
 int32_t apm_minors_k0(apm_dtype dt, int32_t n)
