@@ -427,6 +427,61 @@ __device__ __forceinline__ PivInfo<F> top_right_at(int d, typename F::E* lds, in
     return top_right<F, N, K0MAX, D>(lds, xo, xl, lane, pc);
 }
 
+// Lane-level corrections of depth DEP (Sec. II, pivot correction): lane node (DEP, q) with a
+// shifted pivot corrects the lane's own minors j = q | 2^DEP | u 2^(DEP+1), u >= 1, as
+// m[j] -= C m[j - 2^DEP].  Every value involved was stored by this lane, so the thread's
+// program order orders the reads after the writes (no fence); all loads of one depth are
+// in flight together.
+template <class F, int K0, int DEP>
+__device__ __forceinline__ void lane_fix(void* out, int16_t* ex, int64_t base, int lane, bool f64, uint32_t ev,
+                                         uint64_t lc0, uint64_t lc1, int es_true)
+{
+    constexpr int nq = 1 << DEP, nu = 1 << (K0 - 1 - DEP), per = nu - 1, tot = nq * per;
+    constexpr int kB = 6;                     // (value, partner) pairs in flight per batch
+    constexpr uint32_t dmask = ((1u << nq) - 1) << (nq - 1);
+    if ((ev & dmask) == 0) return;
+#pragma unroll
+    for (int t0 = 0; t0 < tot; t0 += kB) {
+        typename F::V va[kB], vb[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int t = t0 + k;
+            if (t < tot) {
+                const int q = t / per, u = t % per + 1;
+                const int64_t i = base + ((int64_t)(q | nq | (u << (DEP + 1))) << kMid) + lane;
+                if ((ev >> (nq - 1 + q)) & 1u) {
+                    va[k] = F::load_v(out, ex, i, f64);
+                    vb[k] = F::load_v(out, ex, i - ((int64_t)nq << kMid), f64);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int t = t0 + k;
+            if (t < tot) {
+                const int q = t / per, u = t % per + 1;
+                const int id = nq - 1 + q;
+                if ((ev >> id) & 1u) {
+                    const uint64_t lw = id < 8 ? lc0 : lc1;
+                    const double Ct = shift_value(es_true, (int)(uint8_t)(lw >> (8 * (id & 7))));
+                    const int64_t i = base + ((int64_t)(q | nq | (u << (DEP + 1))) << kMid) + lane;
+                    F::store_v(out, ex, i, F::sub_scaled(va[k], Ct, vb[k]), f64);
+                }
+            }
+        }
+    }
+}
+
+template <class F, int K0, int DEP>
+__device__ __forceinline__ void lane_fix_all(void* out, int16_t* ex, int64_t base, int lane, bool f64, uint32_t ev,
+                                             uint64_t lc0, uint64_t lc1, int es_true)
+{
+    if constexpr (DEP >= 0) {
+        lane_fix<F, K0, DEP>(out, ex, base, lane, f64, ev, lc0, lc1, es_true);
+        lane_fix_all<F, K0, DEP - 1>(out, ex, base, lane, f64, ev, lc0, lc1, es_true);
+    }
+}
+
 // Correct the minors of one chunk for its lane- and mid-level shifted pivots, deepest
 // level first: det A[S] = det A~[S] - C det A[S \ {l}] over each shifted node's strict
 // right subtree (Sec. II, pivot correction).  Reads back what the chunk stored.
@@ -437,48 +492,21 @@ __device__ __noinline__ void chunk_fixup(void* out, int16_t* ex, int64_t base, i
     using P = Plan<N, K0MAX>;
     constexpr int k0 = P::k0;
     const bool active = lane < P::active;
-    wave_mem_fence();
-    if constexpr (k0 >= 2) {
-        for (int dep = k0 - 2; dep >= 0; --dep) {
-            const uint32_t lvl_mask = ((1u << (1 << dep)) - 1) << ((1 << dep) - 1);
-            if (ballot(active && (ev & lvl_mask)) == 0) continue;
-            for (int q = 0; q < (1 << dep); ++q) {
-                const int id = (1 << dep) - 1 + q;
-                if (active && (ev >> id & 1u)) {
-                    const uint64_t lw = id < 8 ? lc0 : lc1;
-                    const double Ct = shift_value(es_true, (int)(uint8_t)(lw >> (8 * (id & 7))));
-                    const int nu = 1 << (k0 - 1 - dep);
-                    const int64_t pstep = (int64_t)(1 << dep) << kMid;
-                    for (int u0 = 1; u0 < nu; u0 += 4) {
-                        typename F::V va[4], vb[4];
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const int u = u0 + k;
-                            if (u < nu) {
-                                const int64_t i = base + ((int64_t)(q | (1 << dep) | (u << (dep + 1))) << kMid) + lane;
-                                va[k] = F::load_v(out, ex, i, f64);
-                                vb[k] = F::load_v(out, ex, i - pstep, f64);
-                            }
-                        }
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const int u = u0 + k;
-                            if (u < nu) {
-                                const int64_t i = base + ((int64_t)(q | (1 << dep) | (u << (dep + 1))) << kMid) + lane;
-                                F::store_v(out, ex, i, F::sub_scaled(va[k], Ct, vb[k]), f64);
-                            }
-                        }
-                    }
-                }
-            }
-            wave_mem_fence();
-        }
+    // lane subtree nodes of order >= 3 (depth <= k0 - 3) can be shifted; 2 x 2 nodes are not
+    if constexpr (k0 >= 3) {
+        if (active) lane_fix_all<F, k0, k0 - 3>(out, ex, base, lane, f64, ev, lc0, lc1, es_true);
     }
+    // mid levels: a lane corrects its minors from those of lane - 2^b, stored by another lane
+    bool fenced = false;
     for (int b = P::mid - 1; b >= 0; --b) {
         const int q = lane & ((1 << b) - 1);
         const int de = midc[(1 << b) - 1 + q];
         const bool mine = active && ((lane >> b) & 1) && de != kNoEv;
         if (ballot(mine) == 0) continue;
+        if (!fenced) {
+            wave_mem_fence();
+            fenced = true;
+        }
         if (mine) {
             const double Ct = shift_value(es_true, de);
             const int j0 = ((lane >> (b + 1)) == 0) ? 1 : 0;   // skip the node's own recorded minor
