@@ -386,6 +386,15 @@ apm_status apm_last_device_error(void);
 /* Library version, major * 10000 + minor * 100 + patch. */
 int apm_version(void);
 
+/*
+ * apm_probe_fma64 -- measurement probe (not part of the method): `blocks` workgroups of
+ * 256 threads each run 8 independent fp64 FMA chains of `iters` steps, so that the
+ * achieved fp64 vector FMA rate of the device can be timed by the caller around the
+ * launch.  sink: device array of blocks * 256 doubles (written); *fmas (host, may be
+ * NULL) receives the number of FMAs launched.  Asynchronous on `stream`.
+ */
+apm_status apm_probe_fma64(double *sink, int32_t blocks, int32_t iters, int64_t *fmas, apm_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,7 +50,7 @@ EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_s
            "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
            "apm_minors_k0", "apm_plan_create", "apm_plan_launch", "apm_plan_k0", "apm_plan_graphed",
            "apm_plan_destroy", "apm_last_device_error", "apm_xor_minors", "apm_xnor_minors",
-           "apm_leading_minors", "apm_nand_minors", "apm_all_minors_noalloc")
+           "apm_leading_minors", "apm_nand_minors", "apm_all_minors_noalloc", "apm_probe_fma64")
 
 APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
@@ -119,6 +119,8 @@ def _load():
     lib.apm_connected_sums.restype = ctypes.c_int
     lib.apm_all_perm_minors.argtypes = [vp, ctypes.POINTER(apm_batch), vp, vp]
     lib.apm_all_perm_minors.restype = ctypes.c_int
+    lib.apm_probe_fma64.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), vp]
+    lib.apm_probe_fma64.restype = ctypes.c_int
     lib.apm_all_minors_noalloc.argtypes = lib.apm_all_minors.argtypes
     lib.apm_all_minors_noalloc.restype = ctypes.c_int
     for name in ("apm_xor_minors", "apm_xnor_minors", "apm_leading_minors", "apm_nand_minors"):
@@ -182,6 +184,15 @@ def apm_all_minors(dt, A, bd, minors, exp, info, opt, stream):
 def apm_all_minors_noalloc(dt, A, bd, minors, exp, info, opt, stream):
     return _lib.apm_all_minors_noalloc(int(dt), A, ctypes.byref(bd) if bd is not None else None, minors, exp,
                                        info, ctypes.byref(opt) if opt is not None else None, stream)
+
+
+def probe_fma64(blocks, iters, stream=None):
+    """Launch the fp64 FMA-rate probe; returns (sink tensor, FMAs launched)."""
+    sink = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    f = ctypes.c_int64(0)
+    _check(_lib.apm_probe_fma64(_ptr(sink), int(blocks), int(iters), ctypes.byref(f), _stream(stream)),
+           "apm_probe_fma64")
+    return sink, f.value
 
 
 def apm_connected_sums(m_up, m_dn, bd, c, mode, stream):
