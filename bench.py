@@ -240,14 +240,20 @@ def main():
 
 
 def measured_peaks(torch, apm):
-    """Measured ceilings beside the datasheet ones: a plain 2 GiB device copy (read + write
-    bytes per second) and the library's fp64 FMA-loop probe (8 independent chains per
-    thread, 4096 workgroups of 256 threads)."""
+    """Measured ceilings beside the datasheet ones: a 2 GiB device copy by the library's copy
+    probe (16-byte accesses, best of three grid sizes; read + write bytes per second; torch's
+    copy beside it) and the library's fp64 FMA-loop probe (8 independent chains per thread,
+    4096 workgroups of 256 threads)."""
     nb = (2 << 30) // 8
     x = torch.ones(nb, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
-    ms = time_fn(torch, lambda: y.copy_(x), 5)
-    copy_gbs = 2 * nb * 8 / (ms * 1e-3) / 1e9
+    ms_t = time_fn(torch, lambda: y.copy_(x), 5)
+    best = None
+    for blocks in (2048, 4096, 8192):
+        msb = time_fn(torch, lambda: apm.probe_copy(y, x, blocks), 5)
+        best = msb if best is None else min(best, msb)
+    copy_gbs = 2 * nb * 8 / (best * 1e-3) / 1e9
+    torch_gbs = 2 * nb * 8 / (ms_t * 1e-3) / 1e9
     del x, y
     fmas = [0]
 
@@ -257,6 +263,7 @@ def measured_peaks(torch, apm):
     msf = time_fn(torch, fma, 5)
     tf = 2 * fmas[0] / (msf * 1e-3) / 1e12
     res = {"copy_GBs": round(copy_gbs, 1), "copy_frac_datasheet": round(copy_gbs / PEAK_HBM_GBS, 4),
+           "torch_copy_GBs": round(torch_gbs, 1),
            "fma64_TFLOPs": round(tf, 2), "fma64_frac_datasheet": round(tf / 78.6, 4)}
     log(f"measured peaks: {res}")
     return res

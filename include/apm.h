@@ -395,6 +395,14 @@ int apm_version(void);
  */
 apm_status apm_probe_fma64(double *sink, int32_t blocks, int32_t iters, int64_t *fmas, apm_stream stream);
 
+/*
+ * apm_probe_copy -- measurement probe (not part of the method): copies `bytes` (a multiple
+ * of 16; both pointers 16-byte aligned, device memory, not overlapping) with `blocks`
+ * workgroups of 256 threads moving 16 bytes per access, so that the achievable HBM
+ * bandwidth can be timed by the caller.  APM_EINVAL for a bad size or alignment.
+ */
+apm_status apm_probe_copy(void *dst, const void *src, int64_t bytes, int32_t blocks, apm_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -253,7 +253,8 @@ apm_status perm_args(const double* A, const apm_batch* bd, double* perm, apm::La
 
 // Packed default offsets of a ragged batch given without offset arrays: the queue
 // preparation kernel writes the prefix sums of n_b^2 and 2^n_b into the workspace.
-apm_status packed_offsets(const apm_batch* bd, hipStream_t st, const int64_t** ioff, const int64_t** ooff)
+apm_status packed_offsets(const apm_batch* bd, hipStream_t st, const int64_t** ioff, const int64_t** ooff,
+                          const int32_t** order = nullptr)
 {
     apm::LaunchMinors L{};
     L.batch = bd->batch;
@@ -264,6 +265,7 @@ apm_status packed_offsets(const apm_batch* bd, hipStream_t st, const int64_t** i
     if (e != hipSuccess) return from_hip(e);
     *ioff = L.ioff_ws;
     *ooff = L.ooff_ws;
+    if (order) *order = L.order;
     return APM_OK;
 }
 
@@ -425,7 +427,7 @@ apm_status plan_workspace(const apm_plan_desc* d, apm_plan* p)
     const int64_t B = bd->batch;
     const bool ragged = bd->n_uniform == 0;
     const bool minors = d->kind == APM_PLAN_MINORS || d->kind == APM_PLAN_CDET;
-    p->prep = ragged && ((d->kind == APM_PLAN_CONNECTED_SUMS && !bd->out_off) ||
+    p->prep = ragged && (d->kind == APM_PLAN_CONNECTED_SUMS ||
                          (d->kind == APM_PLAN_PERM_MINORS && (!bd->in_off || !bd->out_off)));
     const bool need_ragged = ragged && (minors || p->prep);
     const bool need_topq = !ragged && minors && B <= INT32_MAX / 2;
@@ -464,13 +466,15 @@ apm_status plan_workspace(const apm_plan_desc* d, apm_plan* p)
         bind(p->Lm);
         if (p->has_dn) bind(p->Lm_dn);
         if (d->kind == APM_PLAN_CDET && ragged && !bd->out_off) p->Lc.off = p->Lm.ooff_ws;
+        if (d->kind == APM_PLAN_CDET && ragged) p->Lc.order = p->Lm.order;
     }
     if (p->prep) {
         p->Lprep.batch = bd->batch;
         p->Lprep.n = bd->n;
         bind(p->Lprep);
         if (d->kind == APM_PLAN_CONNECTED_SUMS) {
-            p->Lc.off = p->Lprep.ooff_ws;
+            if (!bd->out_off) p->Lc.off = p->Lprep.ooff_ws;
+            p->Lc.order = p->Lprep.order;
         } else {
             if (!p->Lp.in_off) p->Lp.in_off = p->Lprep.ioff_ws;
             if (!p->Lp.out_off) p->Lp.out_off = p->Lprep.ooff_ws;
@@ -656,10 +660,12 @@ apm_status apm_connected_sums(const double* m_up, const double* m_dn, const apm_
     bool noop = false;
     apm_status s = cs_args(m_up, m_dn, bd, c, mode, &L, &noop);
     if (s != APM_OK || noop) return s;
-    if (bd->n_uniform == 0 && !L.off) {
-        const int64_t* ioff = nullptr;
-        s = packed_offsets(bd, (hipStream_t)stream, &ioff, &L.off);
+    if (bd->n_uniform == 0) {
+        // the queue preparation sorts the matrices by order (and packs default offsets)
+        const int64_t *ioff = nullptr, *ooff = nullptr;
+        s = packed_offsets(bd, (hipStream_t)stream, &ioff, &ooff, &L.order);
         if (s != APM_OK) return s;
+        if (!L.off) L.off = ooff;
     }
     return from_hip(apm::cs_launch(L, (hipStream_t)stream));
 }

@@ -57,6 +57,7 @@ struct LaunchCS {
     const int64_t* off;        // element offsets (shared by inputs and output), may be NULL
     uint32_t mode;
     double* summ;              // rooted, orders <= 12 only: (c[V], d[V]) per matrix instead of c[]
+    const int32_t* order;      // mixed orders: matrix indices by decreasing order (queue preparation), or NULL
 };
 
 hipError_t cs_launch(const LaunchCS& L, hipStream_t st);

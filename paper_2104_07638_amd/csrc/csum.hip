@@ -353,17 +353,18 @@ __device__ __forceinline__ void row_group(bool valid, uint32_t xh, int items, in
 
 // One rank pass over the rows Xh of rank r of a block, G lanes per row (G the largest power
 // of two with nout G GMUL <= threads, G <= 64 and G <= the pairs of a row).
-template <int M, bool TRI, bool RPAD = false>
-__device__ __forceinline__ void rank_pass(int r, const uint16_t* rk_tab, const int* rk_off, const double* cb,
+template <int M, int NT, bool TRI, bool RPAD = false>
+__device__ __forceinline__ void rank_pass(int tid, int r, const uint16_t* rk_tab, const int* rk_off, const double* cb,
                                           const double* bb, double* rb, double* cb_out)
 {
-    constexpr int NT = cs_threads<M>();
-    const int tid = threadIdx.x;
     const int nout = rk_off[r + 1] - rk_off[r];
     const int items = TRI ? (1 << r) - 1 : (1 << r);
     int G = 1;
-    constexpr int GMUL = NT == kWave ? APM_CS_GMUL_SMALL : (TRI ? APM_CS_GMUL_TRI : APM_CS_GMUL);
-    while (G * 2 <= kWave && nout * G * GMUL <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
+    // lanes per problem: a whole wavefront (GMUL 2: at most half of it per pass, measured
+    // faster than the whole one), or four wavefronts
+    constexpr int GMUL = NT < kWave ? 1 : (NT == kWave ? APM_CS_GMUL_SMALL : (TRI ? APM_CS_GMUL_TRI : APM_CS_GMUL));
+    constexpr int GMAX = NT < kWave ? NT : kWave;
+    while (G * 2 <= GMAX && nout * G * GMUL <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
     const int per_pass = NT / G;
     for (int ob = 0; ob < nout; ob += per_pass) {
         const int o = ob + tid / G;
@@ -395,14 +396,14 @@ __device__ __forceinline__ void conv_task(int lane, int r1, int k1, int r2, int 
     row_group<M, false, G>(valid, xh, 1 << r, G, lane % G, cb, bb, rb, nullptr);
 }
 
-template <int M>
-__device__ __forceinline__ void conv_block(const uint16_t* rk_tab, const int* rk_off, const double* cb,
+template <int M, int NT>
+__device__ __forceinline__ void conv_block(int tid, const uint16_t* rk_tab, const int* rk_off, const double* cb,
                                            const double* bb, double* rb)
 {
     constexpr int H = CsPlan<M>::H;
-    if constexpr (H == 7 && cs_threads<M>() == 4 * kWave && APM_CS_SCHED) {
-        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-        const int lane = (int)(threadIdx.x % kWave);
+    if constexpr (H == 7 && NT == 4 * kWave && APM_CS_SCHED) {
+        const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+        const int lane = tid % kWave;
         if (wave == 0) {
             conv_task<M, 2>(lane, 5, 21, 0, 0, rk_tab, rk_off, cb, bb, rb);
         } else if (wave == 1) {
@@ -415,7 +416,7 @@ __device__ __forceinline__ void conv_block(const uint16_t* rk_tab, const int* rk
             conv_task<M, 64>(lane, 7, 1, 0, 0, rk_tab, rk_off, cb, bb, rb);
         }
     } else {
-        for (int r = 0; r <= H; ++r) rank_pass<M, false>(r, rk_tab, rk_off, cb, bb, rb, nullptr);
+        for (int r = 0; r <= H; ++r) rank_pass<M, NT, false>(tid, r, rk_tab, rk_off, cb, bb, rb, nullptr);
     }
 }
 
@@ -447,15 +448,14 @@ constexpr RankTables make_rank_tables()
 __constant__ RankTables kRank = make_rank_tables();
 
 
-// Problem (matrix b, root j): solve (*) for the m = n-1-j vertices above j.
-template <int M>
-__device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even, double* lds_c, double* lds_b,
-                           double* lds_r, uint16_t* rk_tab, int* rk_off)
+// Problem (matrix b, root j): solve (*) for the m = n-1-j vertices above j, with NT lanes
+// (tid in [0, NT)).  act = false runs the same passes and barriers without touching memory.
+template <int M, int NT>
+__device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even, int tid, bool act, double* lds_c,
+                           double* lds_b, double* lds_r, uint16_t* rk_tab, int* rk_off)
 {
     using CP = CsPlan<M>;
     constexpr int P = CP::P, LB = CP::LB, H = CP::H;
-    constexpr int NT = cs_threads<M>();
-    const int tid = threadIdx.x;
     const int jsh = j + 1;                          // X -> S = (1 << j) | (X << (j+1))
     const int64_t sroot = base + (int64_t(1) << j);  // element index of S = {j}
     double* c = g.c;
@@ -474,7 +474,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
     constexpr bool kOneBlock = CP::TB == 0;
     const bool pair_stage = kOneBlock && j == 0 && !(base & 1);
     if (pair_stage) {
-        for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+        for (int x1 = act ? tid : (1 << P); x1 < (1 << P); x1 += NT) {
             const double2 u = *reinterpret_cast<const double2*>(g.up + base + 2 * x1);
             double w0, w1;
             if (g.weights) {
@@ -495,7 +495,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
     for (int x2 = 0; x2 < (1 << CP::TB); ++x2) {
         // right-hand side a0 of the block
         if (!pair_stage) {
-            for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+            for (int x1 = act ? tid : (1 << P); x1 < (1 << P); x1 += NT) {
                 const int64_t x = ((int64_t)x2 << P) | x1;
                 rhs[sw<LB, kRPad>(x1)] = weight(g, base, (int64_t(1) << j) | (x << jsh));
             }
@@ -505,24 +505,24 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
             if (y2 & ~(uint32_t)x2) continue;
             const uint32_t d2 = (uint32_t)x2 ^ y2;
             __syncthreads();
-            for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+            for (int x1 = act ? tid : (1 << P); x1 < (1 << P); x1 += NT) {
                 lds_c[sw<LB, kPad>(x1)] = c[sroot + ((((int64_t)y2 << P) | x1) << jsh)];
                 lds_b[sw<LB, kPad>(x1)] = weight(g, base, (((int64_t)d2 << P) | x1) << jsh);
             }
             __syncthreads();
-            conv_block<M>(rk_tab, rk_off, lds_c, lds_b, rhs);
+            conv_block<M, NT>(tid, rk_tab, rk_off, lds_c, lds_b, rhs);
         }
         // the block's own triangular solve, with b of block 0
         __syncthreads();
         if (!pair_stage) {
-            for (int x1 = tid; x1 < (1 << P); x1 += NT)
+            for (int x1 = act ? tid : (1 << P); x1 < (1 << P); x1 += NT)
                 lds_b[sw<LB, kPad>(x1)] = x1 ? weight(g, base, (int64_t)x1 << jsh) : 0.0;
             __syncthreads();
         }
         // a[V] for the summary (the in-place solve overwrites it)
         const double a_full = (CP::TB == 0 && g.summ) ? rhs[sw<LB, kRPad>((1 << P) - 1)] : 0.0;
         for (int r = 0; r <= H; ++r) {
-            rank_pass<M, true, kRPad>(r, rk_tab, rk_off, lds_c, lds_b, rhs, lds_c);
+            rank_pass<M, NT, true, kRPad>(tid, r, rk_tab, rk_off, lds_c, lds_b, rhs, lds_c);
             __syncthreads();
         }
         if constexpr (CP::TB == 0) {
@@ -532,7 +532,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                 constexpr int full = (1 << P) - 1;
                 double part = 0.0;
                 for (int x1 = tid; x1 < full; x1 += NT) part += fabs(lds_c[sw<LB, kPad>(x1)]) * fabs(lds_b[sw<LB, kPad>(full ^ x1)]);
-                for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+                for (int o = (NT < kWave ? NT : kWave) / 2; o > 0; o >>= 1) part += __shfl_xor(part, o);
                 if constexpr (NT > kWave) {
                     __syncthreads();
                     if ((tid & (kWave - 1)) == 0) lds_b[tid / kWave] = part;   // b block no longer needed
@@ -540,7 +540,7 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
                     part = 0.0;
                     for (int w = 0; w < NT / kWave; ++w) part += lds_b[w];
                 }
-                if (tid == 0) {
+                if (tid == 0 && act) {
                     g.summ[0] = lds_c[sw<LB, kPad>(full)];
                     g.summ[1] = fabs(a_full) + part;
                 }
@@ -549,25 +549,50 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
         }
         if (zero_even && !(base & 1)) {
             // rooted problem: write (c[2x] = 0, c[2x+1] = c'[x]) as one 16-byte store
-            for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+            for (int x1 = act ? tid : (1 << P); x1 < (1 << P); x1 += NT) {
                 const int64_t x = ((int64_t)x2 << P) | x1;
                 *reinterpret_cast<double2*>(c + base + 2 * x) = make_double2(0.0,
                                                                              lds_c[sw<LB, kPad>(x1)]);
             }
         } else {
-            for (int x1 = tid; x1 < (1 << P); x1 += NT) {
+            for (int x1 = act ? tid : (1 << P); x1 < (1 << P); x1 += NT) {
                 const int64_t x = ((int64_t)x2 << P) | x1;
                 c[sroot + (x << jsh)] = lds_c[sw<LB, kPad>(x1)];
                 if (zero_even) c[base + 2 * x] = 0.0;
             }
         }
     }
-    if (j == 0 && tid == 0) c[base] = 0.0;   // c[empty] = 0
+    if (j == 0 && tid == 0 && act) c[base] = 0.0;   // c[empty] = 0
 }
 
+// Problem p of a launch: matrix b (through the size-sorted queue order when given) and root j.
+struct CsMap {
+    int32_t batch;
+    int n_uniform;
+    const int32_t* nv;
+    const int64_t* off;
+    const int32_t* order;   // mixed-order rooted batches: matrix indices by decreasing order, else NULL
+    int roots;
+};
+
+__device__ __forceinline__ bool cs_locate(const CsMap& mp, int64_t p, int m_want, int* b_out, int* j_out,
+                                          int64_t* base_out)
+{
+    if (p >= (int64_t)mp.batch * mp.roots) return false;
+    int b = (int)(p / mp.roots);
+    const int j = (int)(p % mp.roots);
+    if (mp.order) b = mp.order[b];
+    const int n = mp.n_uniform > 0 ? mp.n_uniform : mp.nv[b];
+    if (n - 1 - j != m_want) return false;   // problems with exactly m_want bits
+    *b_out = b;
+    *j_out = j;
+    *base_out = mp.off ? mp.off[b] : ((int64_t)b << n);
+    return true;
+}
+
+// One problem per workgroup (cs_threads<M>() threads).
 template <int M>
-__global__ __launch_bounds__(cs_threads<M>()) void cs_kernel(CsArgs g, int32_t batch, int n_uniform,
-                                                             const int32_t* nv, const int64_t* off, int roots)
+__global__ __launch_bounds__(cs_threads<M>()) void cs_kernel(CsArgs g, CsMap mp)
 {
     using CP = CsPlan<M>;
     __shared__ __align__(16) double lds_c[block_len<CP::P, CP::LB, kPad>()];
@@ -576,37 +601,73 @@ __global__ __launch_bounds__(cs_threads<M>()) void cs_kernel(CsArgs g, int32_t b
     __shared__ __align__(16) double lds_r[CP::TB == 0 ? 2 : block_len<CP::P, CP::LB, false>()];
     __shared__ uint16_t rk_tab[1 << CsPlan<M>::H];
     __shared__ int rk_off[CsPlan<M>::H + 2];
-    const int b = blockIdx.x / roots;
-    const int j = blockIdx.x % roots;
-    if (b >= batch) return;
-    const int n = n_uniform > 0 ? n_uniform : nv[b];
-    if (n - 1 - j != M) return;   // launched for problems with exactly M bits
-    const int64_t base = off ? off[b] : ((int64_t)b << n);
+    int b = 0, j = 0;
+    int64_t base = 0;
+    if (!cs_locate(mp, blockIdx.x, M, &b, &j, &base)) return;
     // the rooted problem also writes c[S] = 0 for the sets without vertex 0
     CsArgs gb = g;
     if (gb.summ) gb.summ += 2 * (int64_t)b;
-    cs_problem<M>(gb, base, j, roots == 1, lds_c, lds_b, lds_r, rk_tab, rk_off);
+    cs_problem<M, cs_threads<M>()>(gb, base, j, mp.roots == 1, (int)threadIdx.x, true, lds_c, lds_b, lds_r, rk_tab,
+                                   rk_off);
+}
+
+// Mixed-order rooted batches: every problem of 11 bits or more in one launch, taken from the
+// queue order (largest first, so that the shorter problems fill the end of the launch); each
+// workgroup runs the code for its problem's size.  All these sizes share the 11-bit blocks.
+constexpr int kLargeMin = 11;
+
+template <int M>
+__device__ __forceinline__ void cs_large_dispatch(int m, const CsArgs& g, int64_t base, double* lds_c, double* lds_b,
+                                                  double* lds_r, uint16_t* rk_tab, int* rk_off)
+{
+    if constexpr (M >= kLargeMin) {
+        if (m == M) {
+            cs_problem<M, cs_threads<M>()>(g, base, 0, true, (int)threadIdx.x, true, lds_c, lds_b, lds_r, rk_tab,
+                                           rk_off);
+            return;
+        }
+        cs_large_dispatch<M - 1>(m, g, base, lds_c, lds_b, lds_r, rk_tab, rk_off);
+    }
+}
+
+__global__ __launch_bounds__(APM_CS_NT_LARGE) __attribute__((amdgpu_waves_per_eu(3))) void cs_kernel_large(CsArgs g, CsMap mp,
+                                                                                                  int m_max)
+{
+    using CP = CsPlan<kLargeMin + 1>;   // the block layout of every size from 11 bits up
+    static_assert(CsPlan<19>::P == CP::P && CsPlan<kLargeMin>::P == CP::P && CsPlan<19>::H == CP::H, "one layout");
+    __shared__ __align__(16) double lds_c[block_len<CP::P, CP::LB, kPad>()];
+    __shared__ __align__(16) double lds_b[block_len<CP::P, CP::LB, kPad>()];
+    __shared__ __align__(16) double lds_r[block_len<CP::P, CP::LB, false>()];
+    __shared__ uint16_t rk_tab[1 << CP::H];
+    __shared__ int rk_off[CP::H + 2];
+    if (blockIdx.x >= (unsigned)mp.batch) return;
+    const int b = mp.order[blockIdx.x];
+    const int n = mp.nv[b];
+    const int m = n - 1;
+    if (m < kLargeMin || m > m_max) return;
+    const int64_t base = mp.off ? mp.off[b] : ((int64_t)b << n);
+    cs_large_dispatch<19>(m, g, base, lds_c, lds_b, lds_r, rk_tab, rk_off);
 }
 
 template <int M>
-hipError_t launch_m(const LaunchCS& L, CsArgs g, int roots, hipStream_t st)
+hipError_t launch_m(CsArgs g, const CsMap& mp, hipStream_t st)
 {
-    hipLaunchKernelGGL(cs_kernel<M>, dim3((unsigned)(L.batch * roots)), dim3(cs_threads<M>()), 0, st, g, L.batch,
-                       L.n_uniform, L.n, L.off, roots);
+    const int64_t problems = (int64_t)mp.batch * mp.roots;
+    hipLaunchKernelGGL(cs_kernel<M>, dim3((unsigned)problems), dim3(cs_threads<M>()), 0, st, g, mp);
     return hipGetLastError();
 }
 
 template <int M>
-hipError_t launch_all_m(int mlo, int mhi, const LaunchCS& L, CsArgs g, int roots, hipStream_t st)
+hipError_t launch_all_m(int mlo, int mhi, CsArgs g, const CsMap& mp, hipStream_t st)
 {
     if constexpr (M < 0) {
         return hipSuccess;
     } else {
         if (M >= mlo && M <= mhi) {
-            hipError_t e = launch_m<M>(L, g, roots, st);
+            hipError_t e = launch_m<M>(g, mp, st);
             if (e != hipSuccess) return e;
         }
-        return launch_all_m<M - 1>(mlo, mhi, L, g, roots, st);
+        return launch_all_m<M - 1>(mlo, mhi, g, mp, st);
     }
 }
 
@@ -619,11 +680,22 @@ hipError_t cs_launch(const LaunchCS& L, hipStream_t st)
     const int nmax = L.n_uniform > 0 ? L.n_uniform : L.n_max;
     const int nmin = L.n_uniform > 0 ? L.n_uniform : 1;
     const int roots = all ? nmax : 1;
-    // one launch per problem size m = n-1-j (largest first); each block exits unless its
+    CsMap mp{L.batch, L.n_uniform, L.n, L.off, nullptr, roots};
+    // one launch per problem size m = n-1-j (largest first); each workgroup exits unless its
     // problem has exactly that size
-    const int mhi = nmax - 1;
+    int mhi = nmax - 1;
     const int mlo = all ? 0 : nmin - 1;
-    return launch_all_m<19>(mlo, mhi, L, g, roots, st);
+    if (!all && L.n_uniform <= 0 && L.order) {
+        // mixed orders, rooted: the large problems in one size-sorted launch, then the rest
+        mp.order = L.order;
+        if (mhi >= kLargeMin) {
+            hipLaunchKernelGGL(cs_kernel_large, dim3((unsigned)L.batch), dim3(APM_CS_NT_LARGE), 0, st, g, mp, mhi);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            mhi = kLargeMin - 1;
+        }
+    }
+    return launch_all_m<19>(mlo, mhi, g, mp, st);
 }
 
 }  // namespace apm
