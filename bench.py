@@ -85,6 +85,17 @@ class Timer:
         return sum(v) / len(v)
 
 
+def settle(torch, fn, seconds=0.2):
+    """Run fn back to back for a fixed wall time before any timing: the GPU raises its clocks
+    over the first tens of milliseconds of load, and a launch measured before that runs up
+    to 20% slower than in steady state."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
 def time_fn(torch, fn, reps):
     fn()
     torch.cuda.synchronize()
@@ -147,6 +158,7 @@ def main():
     def step():
         apm.all_minors(dA, "r64", out=out, info=info)
 
+    settle(torch, step)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

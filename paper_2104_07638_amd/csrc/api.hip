@@ -569,6 +569,7 @@ apm_status apm_all_minors_noalloc(apm_dtype dt, const void* A, const apm_batch* 
     } else {
         L.topq = reinterpret_cast<int32_t*>(base);
         L.topq_cap = bd->batch;
+        L.no_split = true;   // one work item per matrix: the static queue holds one entry each
         hipLaunchKernelGGL(scratch_head_clear_kernel, dim3(1), dim3(64), 0, st, L.topq);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return from_hip(e);

@@ -29,11 +29,13 @@ struct LaunchMinors {
     int n_workers;             // ragged: number of compute units (persistent grid sizing)
     int force_k0;              // > 0: lane-subtree order to use (autotuning); 0: the table
     int32_t* topq;             // uniform batches: deferred top-level correction queue (NULL: none)
-    int32_t topq_cap;          // its capacity in entries
+    int32_t topq_cap;          // its capacity in matrices (fpm_topq_bytes of that many)
+    bool no_split;             // one work item per matrix (bit-identical results either way)
 };
 
-// Bytes of a deferred-correction queue for `batch` matrices (zeroed once at allocation;
-// each use leaves it zeroed).
+// Bytes of a deferred-correction queue for `batch` matrices: entries for every work item
+// of a split launch and one info code per item (zeroed once at allocation; each use leaves
+// its counters zeroed).
 int64_t fpm_topq_bytes(int64_t batch);
 
 hipError_t fpm_launch(const LaunchMinors& L, hipStream_t st);

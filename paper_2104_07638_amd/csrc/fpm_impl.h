@@ -102,8 +102,8 @@ struct Lay {
     static constexpr size_t oBu = al(oLd + sizeof(int) * (P::T + 1));
     static constexpr size_t oRec = al(oBu + sizeof(Bs) * (P::T + 1));
     static constexpr size_t oTev = al(oRec + sizeof(Bs) * (P::T + 1));     // int8 [2^T]
-    static constexpr size_t oMid = al(oTev + (size_t(1) << P::T));        // int8 [64]
-    static constexpr size_t bytes = al(oMid + 64);
+    static constexpr size_t oMid = al(oTev + (size_t(1) << P::T));        // int8 [2][64]: two chunks
+    static constexpr size_t bytes = al(oMid + 128);
     // element offset of BF level j (j >= 1); node q of that level starts at q ns(K-j)
     static constexpr int lvl_base(int j) { return top_off(P::T + 1) + ((j & 1) ? 0 : bufA()); }
 };
@@ -114,7 +114,14 @@ struct Opts {
     bool out_f64;
     int* topq;       // deferred top-level corrections (NULL: applied by the wavefront itself)
     int topq_cap;    // entries the queue holds
+    int split;       // work items per matrix (a power of two dividing the chunk count); > 1 needs topq
+    int* part;       // split > 1: per-item info codes, combined by the last deferred-correction launch
 };
+
+// Work items per matrix of a uniform launch with deferred top-level corrections: each item
+// takes 2^T / kSplit consecutive chunks, so that one matrix with many shifted pivots (whose
+// corrections reread its minors) spreads over several wavefronts instead of holding one.
+constexpr int kSplit = 4;
 
 // Deferred top-level corrections.  A wavefront whose matrix has shifted pivots in the top
 // levels records (output pointers, exponent of s, per-chunk shift exponents) in a queue
@@ -427,114 +434,103 @@ __device__ __forceinline__ PivInfo<F> top_right_at(int d, typename F::E* lds, in
     return top_right<F, N, K0MAX, D>(lds, xo, xl, lane, pc);
 }
 
-// Lane-level corrections of depth DEP (Sec. II, pivot correction): lane node (DEP, q) with a
-// shifted pivot corrects the lane's own minors j = q | 2^DEP | u 2^(DEP+1), u >= 1, as
-// m[j] -= C m[j - 2^DEP].  Every value involved was stored by this lane, so the thread's
-// program order orders the reads after the writes (no fence); all loads of one depth are
-// in flight together.
-template <class F, int K0, int DEP>
-__device__ __forceinline__ void lane_fix(void* out, int16_t* ex, int64_t base, int lane, bool f64, uint32_t ev,
-                                         uint64_t lc0, uint64_t lc1, int es_true)
-{
-    constexpr int nq = 1 << DEP, nu = 1 << (K0 - 1 - DEP), per = nu - 1, tot = nq * per;
-    constexpr int kB = 6;                     // (value, partner) pairs in flight per batch
-    constexpr uint32_t dmask = ((1u << nq) - 1) << (nq - 1);
-    if ((ev & dmask) == 0) return;
-#pragma unroll
-    for (int t0 = 0; t0 < tot; t0 += kB) {
-        typename F::V va[kB], vb[kB];
-#pragma unroll
-        for (int k = 0; k < kB; ++k) {
-            const int t = t0 + k;
-            if (t < tot) {
-                const int q = t / per, u = t % per + 1;
-                const int64_t i = base + ((int64_t)(q | nq | (u << (DEP + 1))) << kMid) + lane;
-                if ((ev >> (nq - 1 + q)) & 1u) {
-                    va[k] = F::load_v(out, ex, i, f64);
-                    vb[k] = F::load_v(out, ex, i - ((int64_t)nq << kMid), f64);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kB; ++k) {
-            const int t = t0 + k;
-            if (t < tot) {
-                const int q = t / per, u = t % per + 1;
-                const int id = nq - 1 + q;
-                if ((ev >> id) & 1u) {
-                    const uint64_t lw = id < 8 ? lc0 : lc1;
-                    const double Ct = shift_value(es_true, (int)(uint8_t)(lw >> (8 * (id & 7))));
-                    const int64_t i = base + ((int64_t)(q | nq | (u << (DEP + 1))) << kMid) + lane;
-                    F::store_v(out, ex, i, F::sub_scaled(va[k], Ct, vb[k]), f64);
-                }
-            }
-        }
-    }
-}
+// Cross-lane exchange of a correction value (fp64, or the two halves of a complex value).
+__device__ __forceinline__ double shfl_xor_v(double v, int m) { return __shfl_xor(v, m); }
+__device__ __forceinline__ cd shfl_xor_v(cd v, int m) { return {__shfl_xor(v.x, m), __shfl_xor(v.y, m)}; }
 
+// Lane-level corrections of depth DEP and above (deepest first), on a lane's minors held in
+// registers: lane node (DEP, q) with a shifted pivot corrects the minors of its strict right
+// subtree, j = q | 2^DEP | u 2^(DEP+1) with u >= 1, as m[j] -= C m[j - 2^DEP] (Sec. II, pivot
+// correction).
 template <class F, int K0, int DEP>
-__device__ __forceinline__ void lane_fix_all(void* out, int16_t* ex, int64_t base, int lane, bool f64, uint32_t ev,
+__device__ __forceinline__ void lane_fix_reg(typename F::V (&v)[1 << K0], uint32_t& touched, uint32_t ev,
                                              uint64_t lc0, uint64_t lc1, int es_true)
 {
     if constexpr (DEP >= 0) {
-        lane_fix<F, K0, DEP>(out, ex, base, lane, f64, ev, lc0, lc1, es_true);
-        lane_fix_all<F, K0, DEP - 1>(out, ex, base, lane, f64, ev, lc0, lc1, es_true);
+        constexpr int nq = 1 << DEP, nu = 1 << (K0 - 1 - DEP);
+#pragma unroll
+        for (int q = 0; q < nq; ++q) {
+            const int id = nq - 1 + q;
+            if ((ev >> id) & 1u) {
+                const uint64_t lw = id < 8 ? lc0 : lc1;
+                const double Ct = shift_value(es_true, (int)(uint8_t)(lw >> (8 * (id & 7))));
+#pragma unroll
+                for (int u = 1; u < nu; ++u) {
+                    const int j = q | nq | (u << (DEP + 1));
+                    v[j] = F::sub_scaled(v[j], Ct, v[j - nq]);
+                    touched |= 1u << j;
+                }
+            }
+        }
+        lane_fix_reg<F, K0, DEP - 1>(v, touched, ev, lc0, lc1, es_true);
     }
 }
 
-// Correct the minors of one chunk for its lane- and mid-level shifted pivots, deepest
-// level first: det A[S] = det A~[S] - C det A[S \ {l}] over each shifted node's strict
-// right subtree (Sec. II, pivot correction).  Reads back what the chunk stored.
+// Correct the minors of one chunk for its lane- and mid-level shifted pivots, deepest level
+// first: det A[S] = det A~[S] - C det A[S \ {l}] over each shifted node's strict right subtree
+// (Sec. II, pivot correction).  One pass: every lane loads its own 2^k0 minors of the chunk
+// (all loads in flight together; a lane rereads only what it stored itself, so program order
+// suffices), applies the lane-level corrections in registers, then the mid-level ones with the
+// partner lane's values taken by cross-lane exchange (mid node (b, q) corrects lane l with bit
+// b set from lane l - 2^b), and stores what changed.
 template <class F, int N, int K0MAX>
 __device__ __noinline__ void chunk_fixup(void* out, int16_t* ex, int64_t base, int lane, bool f64, uint32_t ev,
                                          uint64_t lc0, uint64_t lc1, const int8_t* midc, int es_true)
 {
     using P = Plan<N, K0MAX>;
-    constexpr int k0 = P::k0;
+    constexpr int k0 = P::k0, J = 1 << k0;
+    using V = typename F::V;
     const bool active = lane < P::active;
+    V v[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (active) v[j] = F::load_v(out, ex, base + ((int64_t)j << kMid) + lane, f64);
+        else v[j] = V{};
+    }
+    uint32_t touched = 0;
     // lane subtree nodes of order >= 3 (depth <= k0 - 3) can be shifted; 2 x 2 nodes are not
     if constexpr (k0 >= 3) {
-        if (active) lane_fix_all<F, k0, k0 - 3>(out, ex, base, lane, f64, ev, lc0, lc1, es_true);
+        if (active) lane_fix_reg<F, k0, k0 - 3>(v, touched, ev, lc0, lc1, es_true);
     }
-    // mid levels: a lane corrects its minors from those of lane - 2^b, stored by another lane
-    bool fenced = false;
     for (int b = P::mid - 1; b >= 0; --b) {
         const int q = lane & ((1 << b) - 1);
-        const int de = midc[(1 << b) - 1 + q];
-        const bool mine = active && ((lane >> b) & 1) && de != kNoEv;
+        const int code = midc[(1 << b) - 1 + q];
+        const bool mine = active && ((lane >> b) & 1) && code != kNoEv;
         if (ballot(mine) == 0) continue;
-        if (!fenced) {
-            wave_mem_fence();
-            fenced = true;
-        }
-        if (mine) {
-            const double Ct = shift_value(es_true, de);
-            const int j0 = ((lane >> (b + 1)) == 0) ? 1 : 0;   // skip the node's own recorded minor
-            for (int jb = j0; jb < (1 << k0); jb += 4) {
-                typename F::V va[4], vb[4];
+        const double Ct = mine ? shift_value(es_true, code) : 0.0;
+        const bool skip0 = (lane >> (b + 1)) == 0;   // the node's own recorded minor (j = 0)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int64_t i = base + ((int64_t)(jb + k) << kMid) + lane;
-                    if (jb + k < (1 << k0)) {
-                        va[k] = F::load_v(out, ex, i, f64);
-                        vb[k] = F::load_v(out, ex, i - (1 << b), f64);
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int64_t i = base + ((int64_t)(jb + k) << kMid) + lane;
-                    if (jb + k < (1 << k0)) F::store_v(out, ex, i, F::sub_scaled(va[k], Ct, vb[k]), f64);
-                }
+        for (int j = 0; j < J; ++j) {
+            const V pv = shfl_xor_v(v[j], 1 << b);
+            if (mine && !(j == 0 && skip0)) {
+                v[j] = F::sub_scaled(v[j], Ct, pv);
+                touched |= 1u << j;
             }
         }
-        wave_mem_fence();
     }
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+        if (active && ((touched >> j) & 1u)) F::store_v(out, ex, base + ((int64_t)j << kMid) + lane, v[j], f64);
+}
+
+// Count and correct the shifted mid- and lane-level pivots of chunk c (whose shift codes are
+// in midc and in the lane registers ev / lc0 / lc1).
+template <class F, int N, int K0MAX>
+__device__ __forceinline__ void fix_chunk(void* out, int16_t* ex, int c, int lane, bool f64, uint32_t ev,
+                                          uint64_t lc0, uint64_t lc1, const int8_t* midc, int es_true, int& nev)
+{
+    using P = Plan<N, K0MAX>;
+    const bool active = lane < P::active;
+    int nm = 0;
+    for (int i = lane; i < (1 << P::mid) - 1; i += kWave) nm += midc[i] != kNoEv;
+    nev += wave_sum(nm + (active ? __builtin_popcount(ev) : 0));
+    chunk_fixup<F, N, K0MAX>(out, ex, (int64_t)c << P::K, lane, f64, ev, lc0, lc1, midc, es_true);
 }
 
 // All principal minors of one N x N matrix by one wavefront.  Returns the info code.
 template <class F, int N, int K0MAX>
 __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, void* out, int16_t* ex,
-                                        unsigned char* lds_raw, const Opts& o)
+                                        unsigned char* lds_raw, const Opts& o, int g = 0)
 {
     using P = Plan<N, K0MAX>;
     using L = Lay<F, N, K0MAX>;
@@ -553,7 +549,7 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
     Bs* bu_a = reinterpret_cast<Bs*>(lds_raw + L::oBu);
     Bs* rec_a = reinterpret_cast<Bs*>(lds_raw + L::oRec);
     int8_t* tevc = reinterpret_cast<int8_t*>(lds_raw + L::oTev);
-    int8_t* midc = reinterpret_cast<int8_t*>(lds_raw + L::oMid);
+    int8_t* const midc_base = reinterpret_cast<int8_t*>(lds_raw + L::oMid);
 
     // ---- load, scale, finiteness ------------------------------------------------------
     double smax = 0.0;
@@ -563,8 +559,11 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
         bad |= !F::in_finite(v);
         smax = fmax(smax, F::in_mag(v));
     }
+    // this item's chunks [c0, c1) (the whole matrix unless it is split)
+    const int nsplit = (T > 0 && o.split > 1) ? o.split : 1;
+    const int c0 = g * ((1 << T) / nsplit), c1 = c0 + (1 << T) / nsplit;
     if (ballot(bad)) {
-        for (int64_t i = lane; i < (int64_t(1) << N); i += kWave) F::store_nan(out, ex, i, o.out_f64);
+        for (int64_t i = ((int64_t)c0 << K) + lane; i < ((int64_t)c1 << K); i += kWave) F::store_nan(out, ex, i, o.out_f64);
         return -2;
     }
     double s = wave_max(smax);
@@ -595,35 +594,58 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
     int nev = 0;
     bool any_top = false;
     double chkf = 0.0;
+    // Corrections of a chunk's shifted mid- and lane-level pivots are applied one chunk late,
+    // after the next chunk's top and breadth-first levels (LDS work): by then the chunk's
+    // stores have drained, and reading them back does not stall the wavefront.
+    bool pend = false;           // the previous chunk has shifted pivots (wavefront-uniform)
+    uint32_t pev = 0;
+    uint64_t plc0 = 0, plc1 = 0;
 
-    for (int c = 0; c < (1 << T); ++c) {
-        // ---- top: take the right branch at the deepest level that changes -----------
-        if constexpr (T > 0) if (c > 0) {
-            const int d = T - 1 - __builtin_ctz((unsigned)c);
-            const int m = N - d - 1;
-            const PivInfo<F> pv = top_right_at<F, N, K0MAX, 0>(d, lds, off_a[d], ld_a[d], lane, pc);
-            const Bs bud = bu_a[d];
-            if (pv.pert) {
-                nev += 1;
-                any_top = true;
-                if (lane == 0) tevc[c] = pv.code;
-            }
-            const Bs bnew = F::bmul(bud, pv.pu, e0);
-            const Bs rnew = F::bmul(bud, pv.pt, e0);
-            for (int dd = d + 1 + lane; dd <= T; dd += kWave) {
-                off_a[dd] = L::top_off(d + 1) + (dd - d - 1) * (m + 1);
-                ld_a[dd] = m;
-                bu_a[dd] = bnew;
-                rec_a[dd] = rnew;
-            }
-            wave_sync();
+    // Top step: take the right branch at top level d (Schur complement into top storage d+1).
+    // A shift is counted and recorded (for the chunk c at which that branch is first taken)
+    // only by the item that owns chunk c.
+    auto top_step = [&](int d, int c, bool own) {
+      if constexpr (T > 0) {
+        const int m = N - d - 1;
+        const PivInfo<F> pv = top_right_at<F, N, K0MAX, 0>(d, lds, off_a[d], ld_a[d], lane, pc);
+        const Bs bud = bu_a[d];
+        if (pv.pert && own) {
+            nev += 1;
+            any_top = true;
+            if (lane == 0) tevc[c] = pv.code;
         }
+        const Bs bnew = F::bmul(bud, pv.pu, e0);
+        const Bs rnew = F::bmul(bud, pv.pt, e0);
+        for (int dd = d + 1 + lane; dd <= T; dd += kWave) {
+            off_a[dd] = L::top_off(d + 1) + (dd - d - 1) * (m + 1);
+            ld_a[dd] = m;
+            bu_a[dd] = bnew;
+            rec_a[dd] = rnew;
+        }
+        wave_sync();
+      }
+    };
+    if constexpr (T > 0) {
+        // the path to the item's first chunk: a right branch for every set bit of c0
+        for (int d = 0; d < T; ++d)
+            if ((c0 >> (T - 1 - d)) & 1) top_step(d, c0, d == T - 1 - __builtin_ctz((unsigned)c0));
+    }
+
+    for (int c = c0; c < c1; ++c) {
+        int8_t* const midc = midc_base + 64 * (c & 1);
+        // ---- top: take the right branch at the deepest level that changes -----------
+        if constexpr (T > 0) if (c > c0) top_step(T - 1 - __builtin_ctz((unsigned)c), c, true);
         const int x0o = off_a[T], x0l = ld_a[T];
         const Bs bu0 = bu_a[T], rec0 = rec_a[T];
 
         // ---- mid levels 0..bf-1: breadth-first in LDS --------------------------------
         bool mid_any = false;
         bf_levels<F, N, K0MAX, 0>(lds, pt_a, pu_a, ri_a, midc, x0o, x0l, lane, pc, mid_any);
+
+        // ---- the previous chunk's pivot corrections -----------------------------------
+        if (pend) fix_chunk<F, N, K0MAX>(out, ex, c - 1, lane, o.out_f64, pev, plc0, plc1,
+                                         midc_base + 64 * ((c - 1) & 1), pc.es_true, nev);
+        pend = false;
 
         // ---- mid levels bf.., per lane, in registers ---------------------------------
         constexpr bool AL = (P::active == kWave);
@@ -704,17 +726,20 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
             put<F, AL>(cx, 0, rec);
         }
 
-        // ---- rare path: shifted pivots inside this chunk --------------------------------
+        // ---- rare path: shifted pivots inside this chunk, corrected after the next one's
+        //      breadth-first levels (or after the loop for the last chunk)
         const bool lane_ev = ballot(cx.active && cx.ev != 0) != 0;
-        if (lane_ev || mid_any) {
-            wave_sync();
-            int nm = 0;
-            for (int i = lane; i < (1 << P::mid) - 1; i += kWave) nm += midc[i] != kNoEv;
-            nev += wave_sum(nm + (cx.active ? __builtin_popcount(cx.ev) : 0));
-            chunk_fixup<F, N, K0MAX>(out, ex, (int64_t)c << K, lane, o.out_f64, cx.ev, cx.lc0, cx.lc1, midc,
-                                         pc.es_true);
-        }
+        pend = lane_ev || mid_any;
+        pev = cx.ev;
+        plc0 = cx.lc0;
+        plc1 = cx.lc1;
         chkf += cx.chk;
+    }
+    if (pend) {
+        const int cl = c1 - 1;
+        wave_sync();
+        fix_chunk<F, N, K0MAX>(out, ex, cl, lane, o.out_f64, pev, plc0, plc1, midc_base + 64 * (cl & 1), pc.es_true,
+                               nev);
     }
 
     // ---- top-level corrections, deepest first ---------------------------------------
@@ -741,6 +766,7 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
                 }
             }
         }
+        if (any_top && !deferred && nsplit > 1) return -3;   // cannot happen: the queue holds every item
         if (any_top && !deferred) {
             wave_mem_fence();
             for (int d = T - 1; d >= 0; --d) {
@@ -787,7 +813,8 @@ __global__ __launch_bounds__(64) APM_FPM_OCC void fpm_uniform_kernel(const typen
                                                          const int64_t* __restrict__ out_off, Opts o)
 {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
-    const int b = blockIdx.x;
+    const int G = o.split > 1 ? o.split : 1;
+    const int b = (int)(blockIdx.x / G), g = (int)(blockIdx.x % G);
     if (b >= batch) return;
     const int64_t io = in_off ? in_off[b] : (int64_t)b * N * N;
     const int64_t oo = out_off ? out_off[b] : ((int64_t)b << N);
@@ -799,8 +826,11 @@ __global__ __launch_bounds__(64) APM_FPM_OCC void fpm_uniform_kernel(const typen
                                         : (void*)(static_cast<float*>(out) + oo);
     }
     int16_t* eb = ex ? ex + oo : nullptr;
-    const int r = fpm_wave<F, N, K0MAX>(A + io, ob, eb, lds_dyn, o);
-    if (info && lane_id() == 0) info[b] = r;
+    const int r = fpm_wave<F, N, K0MAX>(A + io, ob, eb, lds_dyn, o, g);
+    if (lane_id() == 0) {
+        if (G > 1) o.part[blockIdx.x] = r;
+        else if (info) info[b] = r;
+    }
 }
 
 // Deferred top-level corrections (see Opts), one launch per level d, deepest first: the work
@@ -810,7 +840,8 @@ __global__ __launch_bounds__(64) APM_FPM_OCC void fpm_uniform_kernel(const typen
 constexpr int kTopTile = 1024;
 
 template <class F, int N, int K0MAX>
-__global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int f64, int d, int last)
+__global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int f64, int d, int last,
+                                                         const int* part, int split, int32_t* info, int batch)
 {
     using P = Plan<N, K0MAX>;
     constexpr int T = P::T, K = P::K;
@@ -853,6 +884,18 @@ __global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int
             }
         }
     }
+    if (last && split > 1 && info) {
+        // info of a split matrix: the first error code of its items, else their shift counts summed
+        for (int b = blockIdx.x * 256 + tid; b < batch; b += gridDim.x * 256) {
+            int sum = 0, err = 0;
+            for (int k = 0; k < split; ++k) {
+                const int r = part[(int64_t)b * split + k];
+                if (r < 0 && err == 0) err = r;
+                sum += r < 0 ? 0 : r;
+            }
+            info[b] = err ? err : sum;
+        }
+    }
     if (last) {
         __syncthreads();
         if (tid == 0) {
@@ -891,7 +934,7 @@ inline int env_k0()
     return e ? atoi(e) : 0;
 }
 
-constexpr int kTopFixGroups = 256;    // workgroups of each deferred-correction launch
+constexpr int kTopFixGroups = 1024;   // workgroups of each deferred-correction launch (4 per CU: loads in flight)
 
 template <class F, int N, int K0>
 hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
@@ -903,16 +946,24 @@ hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
                                            (int)Ly::bytes);
         if (e != hipSuccess) return e;
     }
-    constexpr bool kDefer = Plan<N, K0>::T > 0 && Plan<N, K0>::T <= kTopDeferMaxT;
+    constexpr int T = Plan<N, K0>::T;
+    constexpr bool kDefer = T > 0 && T <= kTopDeferMaxT;
     int* topq = kDefer ? L.topq : nullptr;
-    Opts o{L.tau, L.perturb, L.out_f64, topq, L.topq_cap};
-    hipLaunchKernelGGL(kern, dim3((unsigned)L.batch), dim3(64), Ly::bytes, st,
+    // split matrices into work items when the queue can take every item's entry (its layout
+    // holds kSplit entries and one info code per matrix of its capacity).  Measured on the
+    // stressed 8192 x 16 batch: fp32-scaled 1.46 -> 1.12 ms (its corrections convert every
+    // value to and from mantissa + exponent, so a few heavily shifted matrices set the end
+    // of the launch); fp64 2-6% slower (its tail is short), so fp64 keeps one item.
+    const int split = (topq && !L.no_split && F::kScaled) ? (kSplit < (1 << T) ? kSplit : (1 << T)) : 1;
+    int* part = topq ? topq + kTopHead + (int64_t)L.topq_cap * kSplit * kTopEntryInts : nullptr;
+    Opts o{L.tau, L.perturb, L.out_f64, topq, topq ? L.topq_cap * kSplit : 0, split, part};
+    hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)L.batch * split)), dim3(64), Ly::bytes, st,
                        static_cast<const typename F::In*>(L.A), L.out, L.ex, L.info, L.batch, L.in_off, L.out_off, o);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !topq) return e;
-    for (int d = Plan<N, K0>::T - 1; d >= 0 && e == hipSuccess; --d) {
-        hipLaunchKernelGGL((fpm_topfix_kernel<F, N, K0>), dim3(kTopFixGroups), dim3(256), 0, st, topq, L.topq_cap,
-                           L.out_f64 ? 1 : 0, d, d == 0 ? 1 : 0);
+    for (int d = T - 1; d >= 0 && e == hipSuccess; --d) {
+        hipLaunchKernelGGL((fpm_topfix_kernel<F, N, K0>), dim3(kTopFixGroups), dim3(256), 0, st, topq, o.topq_cap,
+                           L.out_f64 ? 1 : 0, d, d == 0 ? 1 : 0, part, split, L.info, L.batch);
         e = hipGetLastError();
     }
     return e;
@@ -1053,7 +1104,7 @@ hipError_t fpm_launch_ragged(const LaunchMinors& L, hipStream_t st)
     if (per_cu < 1) per_cu = 1;
     int64_t grid = (int64_t)per_cu * (L.n_workers > 0 ? L.n_workers : 256);
     if (grid > L.batch) grid = L.batch;
-    Opts o{L.tau, L.perturb, L.out_f64, nullptr, 0};   // mixed orders: corrections in the wavefront
+    Opts o{L.tau, L.perturb, L.out_f64, nullptr, 0, 1, nullptr};   // mixed orders: corrections in the wavefront
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), bytes, st, static_cast<const typename F::In*>(L.A),
                        L.out, L.ex, L.info, L.batch, L.n, ioff, ooff, L.order, L.counter, o);
     return hipGetLastError();
