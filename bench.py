@@ -459,12 +459,54 @@ def run_mc(torch, apm, W, np, n_train, n_meas, walkers=8192, n_series=1024):
             out[kind]["final_train_loss"] = round(loss, 3)
         log(f"mc {kind}: {out[kind]}")
         del hs, hl, ha, work
+    # resolution cutoff: the share of proposals given weight 0 (|c[V]| below kappa times the
+    # recursion's rounding scale, or c[V] = 0), counted over untimed steps of the uniform chain
+    # at equilibrium, and the equilibrium mean of log|c| with kappa = 1e-10 against 1e-12
+    out["cutoff"] = mc_cutoff_check(torch, apm, W, np, model, walkers, n_train, min(n_meas, 2000))
     u, l = out["uniform"], out["learned"]
     out["gain_ess_per_s_sign"] = round(l["ess_per_s_sign"] / u["ess_per_s_sign"], 3)
     out["gain_ess_per_s_log_c"] = round(l["ess_per_s_log_c"] / u["ess_per_s_log_c"], 3)
     out["note"] = ("equal-error comparison: the wall time to reach a given standard error of the mean scales as "
                    "1 / (ESS/s), so the gain is the ratio of the learned to the uniform ESS/s")
     return out
+
+
+def mc_cutoff_check(torch, apm, W, np, model, walkers, n_burn, n_meas):
+    """Uniform-proposal chains at resolution cutoffs kappa = 1e-10 (the benchmark's) and
+    1e-12: the share of proposals with weight 0, and the mean of log|c| over the measured
+    steps with its standard error (integrated autocorrelation time of the walker means)."""
+    res = {}
+    for kappa in (1e-10, 1e-12):
+        mdl = W.McModel(n=model.n, L=model.L, t=model.t, mu=model.mu, beta=model.beta, n_tau=model.n_tau,
+                        n_bin=model.n_bin, eps=model.eps, resolve=kappa)
+        g0 = torch.from_numpy(W.mc_g0_table(mdl)).cuda()
+        m = apm.mc_model(mdl.n, mdl.L, mdl.n_tau, mdl.n_bin, mdl.eps, g0, mdl.resolve)
+        chain = apm.McChain(W.mc_cluster_states(walkers, mdl, seed=W.BASE_SEED))
+        work = apm.mc_work(m, walkers, False)
+        apm.mc_evaluate(m, chain, work)
+        rec = apm.McRecord(walkers)
+        for i in range(n_burn):
+            apm.mc_step(m, chain, work, seed=2021, step=i, record=rec)
+        zero = torch.zeros((), dtype=torch.int64, device="cuda")
+        hl = torch.empty((n_meas, walkers), dtype=torch.float32, device="cuda")
+        for i in range(n_meas):
+            apm.mc_step(m, chain, work, seed=2021, step=n_burn + i, record=rec)
+            zero += torch.isinf(rec.logc_prop).sum()
+            hl[i] = rec.obs_logw
+        torch.cuda.synchronize()
+        x = hl.cpu().numpy().astype(np.float64)
+        tau = tau_int(np, x)
+        mean = float(x.mean())
+        se = float(np.sqrt(x.var() * tau / x.size))
+        res[f"kappa_{kappa:g}"] = {"zero_weight_share": round(int(zero.item()) / (walkers * n_meas), 5),
+                                   "mean_log_c": round(mean, 4), "stderr_log_c": round(se, 4),
+                                   "tau_int_log_c": round(tau, 1)}
+        del work, hl
+    a, b = res["kappa_1e-10"], res["kappa_1e-12"]
+    res["mean_log_c_difference_in_stderr"] = round(abs(a["mean_log_c"] - b["mean_log_c"]) /
+                                                   np.hypot(a["stderr_log_c"], b["stderr_log_c"]), 2)
+    log(f"mc cutoff: {res}")
+    return res
 
 
 def cpu_model():

@@ -8,6 +8,11 @@ namespace apm {
 // Default relative pivot-shift threshold of the minors tree, every element type.
 constexpr double kDefaultPivTol = 1e-3;
 
+// Queue-preparation workspace: int32 counter[0] is the mixed-order queue head, counter[1] the
+// head of the large-order queue, counter[kBucketBase + k] (k = 0..22) the start in the queue
+// order of the matrices of order 20 - k (k = 21: invalid orders; k = 22: the end).
+constexpr int kBucketBase = 8;
+
 struct LaunchMinors {
     int dtype;                 // apm_dtype
     const void* A;

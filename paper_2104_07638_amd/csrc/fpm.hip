@@ -77,8 +77,14 @@ __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int
     __syncthreads();
     if (t == 0) {
         int s = 0;
-        for (int k = 0; k < 22; ++k) { pos[k] = s; s += cnt[k]; }
+        for (int k = 0; k < 22; ++k) {
+            pos[k] = s;
+            counter[kBucketBase + k] = s;   // where the matrices of order 20 - k start
+            s += cnt[k];
+        }
+        counter[kBucketBase + 22] = s;
         counter[0] = 0;
+        counter[1] = 0;
     }
     __syncthreads();
     for (int b = t; b < batch; b += 1024) {

@@ -1006,6 +1006,9 @@ constexpr int ragged_k0()
     return K0Set<F>::hi > K0Set<F>::lo ? K0Set<F>::hi - 1 : K0Set<F>::hi;
 }
 
+// Orders run by fpm_ragged_big_kernel (below) when a mixed batch contains them.
+constexpr int kBigLo = 14, kBigHi = 16;
+
 // One order per (non-inlined) function, so that each keeps its own register allocation.
 template <class F, int N>
 __device__ __noinline__ int fpm_wave_n(const typename F::In* A, void* ob, int16_t* eb, unsigned char* lds, Opts o)
@@ -1031,13 +1034,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
                                                         int32_t* info, int32_t batch, const int32_t* __restrict__ nv,
                                                         const int64_t* __restrict__ in_off,
                                                         const int64_t* __restrict__ out_off,
-                                                        const int32_t* __restrict__ order, int32_t* counter, Opts o)
+                                                        const int32_t* __restrict__ order, int32_t* counter, Opts o,
+                                                        int skip_big)
 {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
+    // with skip_big, the matrices of orders kBigLo..kBigHi (a contiguous range of the queue
+    // order) are left to fpm_ragged_big_kernel
+    const int lo = skip_big ? counter[kBucketBase + 20 - kBigHi] : batch;
+    const int gap = skip_big ? counter[kBucketBase + 21 - kBigLo] - lo : 0;
     for (;;) {
         int i = 0;
         if (lane_id() == 0) i = atomicAdd(counter, 1);
         i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
+        if (i >= lo) i += gap;
         if (i >= batch) break;
         const int b = order[i];
         const int n = nv[b];
@@ -1056,6 +1065,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
             int16_t* eb = ex ? ex + oo : nullptr;
             r = fpm_dispatch<F, 1>(n, A + io, ob, eb, lds_dyn, o);
         }
+        if (info && lane_id() == 0) info[b] = r;
+        wave_sync();
+    }
+}
+
+// The large orders of a mixed batch (kBigLo..kBigHi) run in a kernel of their own with the
+// largest lane-subtree order: with only these orders inlined, the merged kernel keeps two
+// wavefronts per SIMD.  The matrices of these orders are a contiguous range of the queue
+// order (sorted by decreasing order), which this kernel walks with its own counter.
+
+template <class F, int N>
+__device__ __forceinline__ int fpm_dispatch_big(int n, const typename F::In* A, void* ob, int16_t* eb,
+                                                unsigned char* lds, const Opts& o)
+{
+    if constexpr (N > kBigHi) {
+        return -1;
+    } else {
+        if (n == N) return fpm_wave<F, N, K0Set<F>::hi>(A, ob, eb, lds, o);
+        return fpm_dispatch_big<F, N + 1>(n, A, ob, eb, lds, o);
+    }
+}
+
+template <class F>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fpm_ragged_big_kernel(
+    const typename F::In* __restrict__ A, void* out, int16_t* ex, int32_t* info, const int32_t* __restrict__ nv,
+    const int64_t* __restrict__ in_off, const int64_t* __restrict__ out_off, const int32_t* __restrict__ order,
+    int32_t* counter, Opts o)
+{
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    const int lo = counter[kBucketBase + 20 - kBigHi], hi = counter[kBucketBase + 21 - kBigLo];
+    for (;;) {
+        int i = 0;
+        if (lane_id() == 0) i = atomicAdd(counter + 1, 1);
+        i = __builtin_amdgcn_readfirstlane(__shfl(i, 0)) + lo;
+        if (i >= hi) break;
+        const int b = order[i];
+        const int n = nv[b];
+        const int64_t oo = out_off[b];
+        void* ob;
+        if constexpr (F::kComplex) {
+            ob = (o.out_f64 || !F::kScaled) ? (void*)(static_cast<cd*>(out) + oo) : (void*)(static_cast<cf*>(out) + oo);
+        } else {
+            ob = (o.out_f64 || !F::kScaled) ? (void*)(static_cast<double*>(out) + oo)
+                                            : (void*)(static_cast<float*>(out) + oo);
+        }
+        const int r = fpm_dispatch_big<F, kBigLo>(n, A + in_off[b], ob, ex ? ex + oo : nullptr, lds_dyn, o);
         if (info && lane_id() == 0) info[b] = r;
         wave_sync();
     }
@@ -1085,6 +1140,17 @@ size_t lay_bytes_upto(int nmax)
     }
 }
 
+template <class F, int N>
+size_t big_lay_bytes(int n)
+{
+    if constexpr (N > kBigHi) {
+        return 0;
+    } else {
+        if (n == N) return Lay<F, N, K0Set<F>::hi>::bytes;
+        return big_lay_bytes<F, N + 1>(n);
+    }
+}
+
 template <class F>
 hipError_t fpm_launch_ragged(const LaunchMinors& L, hipStream_t st)
 {
@@ -1098,15 +1164,40 @@ hipError_t fpm_launch_ragged(const LaunchMinors& L, hipStream_t st)
         e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
+    const int cus = L.n_workers > 0 ? L.n_workers : 256;
+    Opts o{L.tau, L.perturb, L.out_f64, nullptr, 0, 1, nullptr};   // mixed orders: corrections in the wavefront
+    // the large orders first, in their own kernel (largest lane subtrees), then the rest
+    const bool big = L.n_max >= kBigLo;
+    if (big) {
+        size_t bb = 0;
+        for (int nn = kBigLo; nn <= kBigHi && nn <= L.n_max; ++nn) {
+            const size_t x = big_lay_bytes<F, kBigLo>(nn);
+            bb = x > bb ? x : bb;
+        }
+        auto kb = fpm_ragged_big_kernel<F>;
+        if (bb > 65536) {
+            e = hipFuncSetAttribute((const void*)kb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bb);
+            if (e != hipSuccess) return e;
+        }
+        int pcb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pcb, (const void*)kb, 64, bb);
+        if (e != hipSuccess) return e;
+        if (pcb < 1) pcb = 1;
+        int64_t gb = (int64_t)pcb * cus;
+        if (gb > L.batch) gb = L.batch;
+        hipLaunchKernelGGL(kb, dim3((unsigned)gb), dim3(64), bb, st, static_cast<const typename F::In*>(L.A), L.out,
+                           L.ex, L.info, L.n, ioff, ooff, L.order, L.counter, o);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64, bytes);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
-    int64_t grid = (int64_t)per_cu * (L.n_workers > 0 ? L.n_workers : 256);
+    int64_t grid = (int64_t)per_cu * cus;
     if (grid > L.batch) grid = L.batch;
-    Opts o{L.tau, L.perturb, L.out_f64, nullptr, 0, 1, nullptr};   // mixed orders: corrections in the wavefront
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), bytes, st, static_cast<const typename F::In*>(L.A),
-                       L.out, L.ex, L.info, L.batch, L.n, ioff, ooff, L.order, L.counter, o);
+                       L.out, L.ex, L.info, L.batch, L.n, ioff, ooff, L.order, L.counter, o, big ? 1 : 0);
     return hipGetLastError();
 }
 
