@@ -289,6 +289,22 @@ apm_status apm_autotune_minors(apm_dtype dt, int32_t n, int32_t batch, int32_t *
 int32_t apm_minors_k0(apm_dtype dt, int32_t n);
 
 /*
+ * Tuning cache.  apm_autotune_minors also records its choice in a JSON file,
+ *   {"version": 1, "k0": {"<gfx>/<dtype>/<n>": K0, ...}}
+ * keyed by the current device's architecture name (e.g. gfx950), the dtype (r64, r32s,
+ * c128, c64s) and the order; apm_plan_create with APM_PLAN_AUTOTUNE reads it before timing
+ * anything, so that tuned layouts carry over between processes.  The file is the value of
+ * the environment variable APM_TUNE_CACHE, else $HOME/.cache/apm_tune.json (an empty
+ * APM_TUNE_CACHE disables it); missing or malformed files are ignored.
+ *
+ * apm_tune_cache_load installs the entries of the file `path` (NULL: the default path)
+ * for the current device's architecture into this process's table, as if tuned here
+ * (values outside the instantiated range are skipped).  Returns the number installed, or
+ * -1 if the file cannot be read or no device is current.  Host-only, synchronous.
+ */
+int32_t apm_tune_cache_load(const char *path);
+
+/*
  * Plans -- one of the operations above, or the CDet pipeline, bound to fixed buffers and
  * shapes, prepared once and enqueued many times (the Monte Carlo use: the same batch
  * shapes every step, new matrix values in the same buffers).

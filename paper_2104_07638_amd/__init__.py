@@ -50,7 +50,7 @@ EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_s
            "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
            "apm_minors_k0", "apm_plan_create", "apm_plan_launch", "apm_plan_k0", "apm_plan_graphed",
            "apm_plan_destroy", "apm_last_device_error", "apm_xor_minors", "apm_xnor_minors",
-           "apm_leading_minors", "apm_nand_minors", "apm_all_minors_noalloc", "apm_probe_fma64", "apm_probe_copy")
+           "apm_leading_minors", "apm_nand_minors", "apm_all_minors_noalloc", "apm_probe_fma64", "apm_probe_copy", "apm_tune_cache_load")
 
 APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
@@ -121,6 +121,8 @@ def _load():
     lib.apm_all_perm_minors.restype = ctypes.c_int
     lib.apm_probe_fma64.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), vp]
     lib.apm_probe_fma64.restype = ctypes.c_int
+    lib.apm_tune_cache_load.argtypes = [ctypes.c_char_p]
+    lib.apm_tune_cache_load.restype = ctypes.c_int32
     lib.apm_probe_copy.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
     lib.apm_probe_copy.restype = ctypes.c_int
     lib.apm_all_minors_noalloc.argtypes = lib.apm_all_minors.argtypes
@@ -195,6 +197,12 @@ def probe_fma64(blocks, iters, stream=None):
     _check(_lib.apm_probe_fma64(_ptr(sink), int(blocks), int(iters), ctypes.byref(f), _stream(stream)),
            "apm_probe_fma64")
     return sink, f.value
+
+
+def tune_cache_load(path=None):
+    """Install the tuned lane-subtree orders of a cache file (None: the default path) for the
+    current device; returns how many, or -1."""
+    return int(_lib.apm_tune_cache_load(None if path is None else str(path).encode()))
 
 
 def probe_copy(dst, src, blocks, stream=None):

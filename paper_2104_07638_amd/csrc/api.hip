@@ -1,11 +1,16 @@
 // api.hip -- the C ABI of libapm.so: argument validation, workspaces, launches.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 #include <map>
+#include <string>
 #include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "../../include/apm.h"
 #include "apm_kernels.h"
@@ -150,6 +155,126 @@ apm_status get_xor_ws(hipStream_t st, size_t bytes, void** out)
     }
     *out = w.buf;
     return APM_OK;
+}
+
+// ---- persistent cache of autotuned lane-subtree orders -------------------------------------
+// A JSON file {"version": 1, "k0": {"<gfx>/<dtype>/<n>": K0, ...}} (gfx: the device's
+// architecture name up to its first ':'), written by apm_autotune_minors and read by plan
+// creation with APM_PLAN_AUTOTUNE.  Path: APM_TUNE_CACHE, else $HOME/.cache/apm_tune.json;
+// an empty APM_TUNE_CACHE disables the cache.  Unreadable or malformed files are ignored.
+const char* kDtypeName[4] = {"r64", "r32s", "c128", "c64s"};
+
+std::string tune_cache_path()
+{
+    const char* e = getenv("APM_TUNE_CACHE");
+    if (e) return std::string(e);
+    const char* h = getenv("HOME");
+    if (!h || !*h) return std::string();
+    return std::string(h) + "/.cache/apm_tune.json";
+}
+
+bool device_arch(std::string* out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    std::string a(prop.gcnArchName);
+    const size_t c = a.find(':');
+    *out = c == std::string::npos ? a : a.substr(0, c);
+    return !out->empty();
+}
+
+// Reads "key": value pairs of the "k0" object.  Returns false if the file is missing or malformed.
+bool tune_cache_read(const std::string& path, std::map<std::string, int>* kv)
+{
+    FILE* f = path.empty() ? nullptr : fopen(path.c_str(), "rb");
+    if (!f) return false;
+    std::string txt;
+    char buf[4096];
+    size_t r;
+    while ((r = fread(buf, 1, sizeof buf, f)) > 0 && txt.size() < (1u << 20)) txt.append(buf, r);
+    fclose(f);
+    const size_t k = txt.find("\"k0\"");
+    if (k == std::string::npos) return false;
+    size_t i = txt.find('{', k);
+    if (i == std::string::npos) return false;
+    for (++i; i < txt.size();) {
+        const size_t q0 = txt.find_first_of("\"}", i);
+        if (q0 == std::string::npos) return false;
+        if (txt[q0] == '}') return true;
+        const size_t q1 = txt.find('"', q0 + 1);
+        if (q1 == std::string::npos) return false;
+        const std::string key = txt.substr(q0 + 1, q1 - q0 - 1);
+        const size_t colon = txt.find(':', q1);
+        if (colon == std::string::npos) return false;
+        char* end = nullptr;
+        const long v = strtol(txt.c_str() + colon + 1, &end, 10);
+        if (end == txt.c_str() + colon + 1) return false;
+        (*kv)[key] = (int)v;
+        i = (size_t)(end - txt.c_str());
+    }
+    return false;
+}
+
+bool tune_cache_write(const std::string& path, const std::map<std::string, int>& kv)
+{
+    if (path.empty()) return false;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        const std::string dir = path.substr(0, slash);
+        (void)mkdir(dir.c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    fprintf(f, "{\n  \"version\": 1,\n  \"k0\": {");
+    bool first = true;
+    for (const auto& e : kv) {
+        fprintf(f, "%s\n    \"%s\": %d", first ? "" : ",", e.first.c_str(), e.second);
+        first = false;
+    }
+    fprintf(f, "\n  }\n}\n");
+    const bool ok = fclose(f) == 0;
+    return ok && rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+std::mutex g_tune_mu;
+
+// Installs the cached values of this device's architecture; returns how many.
+int tune_cache_install(const std::string& path)
+{
+    std::string arch;
+    if (!device_arch(&arch)) return -1;
+    std::map<std::string, int> kv;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!tune_cache_read(path, &kv)) return -1;
+    int count = 0;
+    for (int dt = 0; dt < 4; ++dt) {
+        for (int n = 1; n <= APM_MAX_N; ++n) {
+            const auto it = kv.find(arch + "/" + kDtypeName[dt] + "/" + std::to_string(n));
+            if (it == kv.end()) continue;
+            int lo, hi;
+            apm::k0_range(dt, &lo, &hi);
+            if (it->second < lo || it->second > hi) continue;
+            apm::set_tuned_k0(dt, n, it->second);
+            ++count;
+        }
+    }
+    return count;
+}
+
+void tune_cache_record(int dt, int n, int k0)
+{
+    std::string arch;
+    if (!device_arch(&arch)) return;
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::map<std::string, int> kv;
+    (void)tune_cache_read(path, &kv);
+    kv[arch + "/" + kDtypeName[dt] + "/" + std::to_string(n)] = k0;
+    (void)tune_cache_write(path, kv);
 }
 
 bool bad_batch(const apm_batch* bd, int nmax)
@@ -650,8 +775,14 @@ apm_status apm_autotune_minors(apm_dtype dt, int32_t n, int32_t batch, int32_t* 
     if (A) (void)hipFree(A);
     if (e != hipSuccess) return from_hip(e);
     apm::set_tuned_k0((int)dt, n, best);
+    tune_cache_record((int)dt, n, best);
     if (k0_out) *k0_out = best;
     return APM_OK;
+}
+
+int32_t apm_tune_cache_load(const char* path)
+{
+    return tune_cache_install(path ? std::string(path) : tune_cache_path());
 }
 
 apm_status apm_connected_sums(const double* m_up, const double* m_dn, const apm_batch* bd, double* c,
@@ -773,6 +904,8 @@ apm_status apm_plan_create(const apm_plan_desc* d, apm_plan** out)
     const bool uniform_minors = (d->kind == APM_PLAN_MINORS || d->kind == APM_PLAN_CDET) && d->batch.n_uniform > 0;
     if (s == APM_OK && !p->noop && uniform_minors) {
         const int n = d->batch.n_uniform;
+        if ((d->flags & APM_PLAN_AUTOTUNE) && apm::tuned_k0((int)d->dtype, n) <= 0 && !getenv("APM_K0"))
+            (void)tune_cache_install(tune_cache_path());
         if ((d->flags & APM_PLAN_AUTOTUNE) && apm::tuned_k0((int)d->dtype, n) <= 0 && !getenv("APM_K0")) {
             // the synthetic tuning batch: the plan's size, at most 8192 matrices and 2 GiB of output
             int32_t tb = d->batch.batch < 8192 ? d->batch.batch : 8192;

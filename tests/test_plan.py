@@ -274,3 +274,34 @@ def test_plan_cdet_ragged_and_r32s(apm):
     cr = apm.connected_sums(r32)
     torch.cuda.synchronize()
     assert same(m32, r32) and same(c32, cr)
+
+
+def test_tune_cache_roundtrip(apm, tmp_path, monkeypatch):
+    """The autotuner records its choice in the JSON tuning cache keyed by (architecture,
+    dtype, order), and a cache file is installed as if tuned in this process."""
+    import json
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("APM_TUNE_CACHE", str(path))
+    k = apm.autotune_minors("r64", 11, batch=256)
+    doc = json.load(open(path))
+    keys = [key for key in doc["k0"] if key.endswith("/r64/11")]
+    assert len(keys) == 1 and keys[0].startswith("gfx") and doc["k0"][keys[0]] == k
+    other = 3 if k != 3 else 4
+    doc["k0"][keys[0]] = other
+    json.dump(doc, open(path, "w"))
+    try:
+        assert apm.tune_cache_load(str(path)) == 1
+        assert apm.apm_minors_k0(apm.APM_R64, 11) == other
+        # a plan created with autotuning now takes the installed value without timing
+        import torch
+        A = torch.from_numpy(W.lattice_batch(64, 11, W.Lattice(32, 1.0, -0.5, 5.0), seed=3)).cuda()
+        out = torch.empty((64, 1 << 11), dtype=torch.float64, device="cuda")
+        p = apm.plan_minors(A, out, autotune=True)
+        assert p.k0 == other
+        p.close()
+    finally:
+        doc["k0"][keys[0]] = k
+        json.dump(doc, open(path, "w"))
+        apm.tune_cache_load(str(path))
+    assert apm.apm_minors_k0(apm.APM_R64, 11) == k
+    assert apm.tune_cache_load(str(tmp_path / "missing.json")) == -1
