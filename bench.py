@@ -383,8 +383,11 @@ def run_extra(torch, apm, W, np, steps):
     ni = torch.empty(1024, dtype=torch.int32, device="cuda")
     ms = time_fn(torch, lambda: apm.nand_minors(K3, out=na, info=ni), steps)
     by = K3.numel() * 16 + na.numel() * 16
+    nic = ni.cpu()
     ex["nand_keldysh_n10_1024_c128"] = {"ms": round(ms, 4), "matrices_per_s": round(1024 / (ms * 1e-3), 1),
-                                        "GBs": round(by / (ms * 1e-3) / 1e9, 1)}
+                                        "GBs": round(by / (ms * 1e-3) / 1e9, 1),
+                                        "matrices_shifted": int((nic > 0).sum()),
+                                        "shifts_total": int(nic[nic > 0].sum()), "errors": int((nic < 0).sum())}
     del K3, na, ni
     for k, v in ex.items():
         log(f"{k}: {v}")

@@ -241,8 +241,15 @@ apm_status apm_xnor_minors(apm_dtype dt, const void *A, const apm_batch *bd, voi
  * rows/columns 2i, 2i+1 of every block i: the ternary tree whose branches leave the block
  * out or take the Schur complement over one of its two diagonal entries, O(3^n)).
  *
- *   dt, A, info, stream   as for apm_xor_minors (info -3: a zero pivot; no pivot shifts
- *           are made).
+ *   dt, A, stream   as for apm_xor_minors.
+ *   info    [B] int32 or NULL: the number of pivot shifts made (>= 0), -2 non-finite
+ *           input (outputs NaN), -3 a non-finite output.  Pivot shift: the test and C of
+ *           apm_opts at the default piv_tol, on each kept row's pivot with the row and
+ *           column entries that enter the child's Schur complement (the other row of the
+ *           block left out); the child's subtree is corrected once it is complete,
+ *           deepest node first (det A[S] = det A~[S] - C det A[S \ {l}], S \ {l} being the
+ *           entry with block l left out), and its own entry is the parent's minor times
+ *           the true pivot.
  *   bd      uniform batch, n_uniform = n blocks, 1 <= n <= APM_MAX_N_NAND, no offsets.
  *   out     [B x 3^n]: entry sum_i t_i 3^i is the determinant over the kept rows, with
  *           t_i = 0 (block i left out), 1 (row 2i kept) or 2 (row 2i+1 kept); entry 0 = 1.

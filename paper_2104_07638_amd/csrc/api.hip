@@ -692,9 +692,10 @@ apm_status apm_all_minors_noalloc(apm_dtype dt, const void* A, const apm_batch* 
         L.ooff_ws = reinterpret_cast<int64_t*>(base + kScrOoff);
         L.n_workers = cus;
     } else {
+        if (apm::fpm_topq_bytes_unsplit(bd->batch) > kScratchBytes) return APM_EUNSUPPORTED;
         L.topq = reinterpret_cast<int32_t*>(base);
         L.topq_cap = bd->batch;
-        L.no_split = true;   // one work item per matrix: the static queue holds one entry each
+        L.no_split = true;   // one work item per matrix: no per-item info codes to hold
         hipLaunchKernelGGL(scratch_head_clear_kernel, dim3(1), dim3(64), 0, st, L.topq);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return from_hip(e);

@@ -36,6 +36,31 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Largest of a non-negative double over the wavefront, by DPP within and across rows of 16
+// lanes (a max-scan that leaves the total in lane 63; lanes with no source read 0), then
+// read from lane 63.  All 64 lanes must be active.
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_max_nonneg(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int slo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xF, true);
+    const int shi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xF, true);
+    return fmax(v, __hiloint2double(shi, slo));
+}
+
+__device__ __forceinline__ double wave_max_nonneg(double v)
+{
+    v = dpp_max_nonneg<0x111>(v);        // row_shr:1
+    v = dpp_max_nonneg<0x112>(v);        // row_shr:2
+    v = dpp_max_nonneg<0x114>(v);        // row_shr:4
+    v = dpp_max_nonneg<0x118>(v);        // row_shr:8
+    v = dpp_max_nonneg<0x142, 0xA>(v);   // row_bcast:15
+    v = dpp_max_nonneg<0x143, 0xC>(v);   // row_bcast:31
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ int wave_sum(int v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -50,6 +75,47 @@ __device__ __forceinline__ double rcp64(double x)
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
+}
+
+// ---- pivot shift (Sec. II, pivot correction), shared by the Schur-complement trees ----------
+constexpr int8_t kNoEv = 0;      // "no shifted pivot" marker in the one-byte shift-code tables
+
+// Magnitude of the pivot shift: the power of two 2^(floor(log2(rmax * min(rmax, cmax)) / 2)
+// + kShiftLog2), about min(sqrt(rmax cmax), rmax) / 16.  The correction
+// det A[S] = det A~[S] - C det A[S \ {l}] loses about eps C / |row l| of the Hadamard bound
+// of A[S] to cancellation, so C stays at or below the pivot row's scale; the sign alignment
+// below keeps |p + C| >= |C|, so the right child's elements change by at most
+// rmax cmax / |C| (at most 16 times the larger of the column scale and sqrt(rmax cmax)).
+constexpr int kShiftLog2 = -4;
+
+// A shift is recorded as one byte: code = 2 (de + kShiftBias) + (C < 0), with
+// C = +-2^(es + de) in stored units (es: exponent of s = max |A_ij|) and de clamped to
+// [1 - kShiftBias, 127 - kShiftBias] = [-119, 7]: shifts far below the matrix's largest
+// entry (rows of a near-singular or strongly graded part) are more common than shifts
+// above it, which need growth of the Schur complements beyond 2^11 s.  kNoEv (0) marks
+// "no shift".
+constexpr int kShiftBias = 120;
+
+__device__ __forceinline__ double shift_value(int es, int code)
+{
+    const int u = code & 0xFF;
+    const double C = ldexp(1.0, es + (u >> 1) - kShiftBias);
+    return (u & 1) ? -C : C;
+}
+
+// Code of the shift of a pivot whose row / column (within the node's matrix, the pivot left
+// out) have largest magnitudes rmax / cmax; neg: Re p < 0.
+__device__ __forceinline__ int8_t shift_code(double rmax, double cmax, int es, bool neg)
+{
+    int de = kShiftLog2;
+    const double pr = rmax * fmin(rmax, cmax);
+    if (pr > 0.0) {
+        int ep;
+        (void)frexp(pr, &ep);
+        de = (ep >> 1) + kShiftLog2 - es;
+    }
+    de = de < 1 - kShiftBias ? 1 - kShiftBias : (de > 127 - kShiftBias ? 127 - kShiftBias : de);
+    return (int8_t)(uint8_t)(2 * (de + kShiftBias) + (neg ? 1 : 0));
 }
 
 // Complex values aligned to their size, so that one 16-byte (8-byte) LDS or global access

@@ -38,10 +38,12 @@ struct LaunchMinors {
     bool no_split;             // one work item per matrix (bit-identical results either way)
 };
 
-// Bytes of a deferred-correction queue for `batch` matrices: entries for every work item
-// of a split launch and one info code per item (zeroed once at allocation; each use leaves
-// its counters zeroed).
+// Bytes of a deferred-correction queue for `batch` matrices: a slot and a list entry per
+// matrix and one info code per work item of a split launch (zeroed once at allocation; each
+// use leaves it zeroed).
 int64_t fpm_topq_bytes(int64_t batch);
+// The part of it that a launch with one work item per matrix (no_split) uses.
+int64_t fpm_topq_bytes_unsplit(int64_t batch);
 
 hipError_t fpm_launch(const LaunchMinors& L, hipStream_t st);
 

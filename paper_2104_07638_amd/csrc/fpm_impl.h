@@ -41,7 +41,6 @@ namespace apm {
 #endif
 
 constexpr int kMid = 6;
-constexpr int8_t kNoEv = 0;      // "no shifted pivot" marker in the one-byte shift-code tables
 
 template <int N, int K0MAX>
 struct Plan {
@@ -113,23 +112,29 @@ struct Opts {
     bool perturb;
     bool out_f64;
     int* topq;       // deferred top-level corrections (NULL: applied by the wavefront itself)
-    int topq_cap;    // entries the queue holds
+    int topq_cap;    // matrices the queue holds (slot index = matrix index)
     int split;       // work items per matrix (a power of two dividing the chunk count); > 1 needs topq
     int* part;       // split > 1: per-item info codes, combined by the last deferred-correction launch
 };
 
-// Work items per matrix of a uniform launch with deferred top-level corrections: each item
-// takes 2^T / kSplit consecutive chunks, so that one matrix with many shifted pivots (whose
-// corrections reread its minors) spreads over several wavefronts instead of holding one.
+// Most work items per matrix of a uniform launch with deferred top-level corrections: each
+// of g items takes 2^T / g consecutive chunks, so that one matrix with many shifted pivots
+// (whose corrections reread its minors) spreads over several wavefronts instead of holding
+// one.
 constexpr int kSplit = 4;
 
 // Deferred top-level corrections.  A wavefront whose matrix has shifted pivots in the top
-// levels records (output pointers, exponent of s, per-chunk shift exponents) in a queue
-// instead of applying the corrections itself; a follow-up launch applies them with a
-// whole workgroup per matrix.  Queue layout (int32): [0] entries, [1] workgroups done,
-// entries of kTopEntryInts from int 64 on: out (2), ex (2), es_true (1), shift bytes.
+// levels records them in the matrix's slot of a queue instead of applying the corrections
+// itself, and lists the matrix once; a follow-up launch applies every level's corrections of
+// the listed matrices in one pass.  Queue layout (int32, cap matrices): [0] listed matrices,
+// [1] workgroups done; from int kTopHead on, one slot of kTopEntryInts per matrix: out (2),
+// ex (2), es_true (1), the shift code of each top node by chunk (8 ints = 32 bytes), the
+// listed flag (1); then the list (cap ints); then, for split launches, the info code of each
+// work item (cap * kSplit ints).  Codes and flags are zero between uses.
 constexpr int kTopDeferMaxT = 5;
-constexpr int kTopEntryInts = 16;
+constexpr int kTopEntryInts = 14;
+constexpr int kTopCodes = 5;     // first int of the shift codes in a slot
+constexpr int kTopFlag = 13;     // the listed flag
 constexpr int kTopHead = 64;
 
 // Matrix-wide parameters of the pivot shift.
@@ -159,29 +164,6 @@ struct PivInfo {
     int8_t code;     // shift code (see shift_value), kNoEv if not shifted
 };
 
-// Magnitude of the pivot shift: the power of two 2^(floor(log2(rmax * min(rmax, cmax)) / 2)
-// + kShiftLog2), about min(sqrt(rmax cmax), rmax) / 16.  The correction
-// det A[S] = det A~[S] - C det A[S \ {l}] loses about eps C / |row l| of the Hadamard bound
-// of A[S] to cancellation, so C stays at or below the pivot row's scale; the sign alignment
-// below keeps |p + C| >= |C|, so the right child's elements change by at most
-// rmax cmax / |C| (at most 16 times the larger of the column scale and sqrt(rmax cmax)).
-constexpr int kShiftLog2 = -4;
-
-// A shift is recorded as one byte: code = 2 (de + kShiftBias) + (C < 0), with
-// C = +-2^(es + de) in stored units (es: exponent of s = max |A_ij|) and de clamped to
-// [1 - kShiftBias, 127 - kShiftBias] = [-119, 7]: shifts far below the matrix's largest
-// entry (rows of a near-singular or strongly graded part) are more common than shifts
-// above it, which need growth of the Schur complements beyond 2^11 s.  kNoEv (0) marks
-// "no shift".
-constexpr int kShiftBias = 120;
-
-__device__ __forceinline__ double shift_value(int es, int code)
-{
-    const int u = code & 0xFF;
-    const double C = ldexp(1.0, es + (u >> 1) - kShiftBias);
-    return (u & 1) ? -C : C;
-}
-
 // Pivot analysis of a node (Sec. II, pivot correction).  A pivot p is shifted when
 // |p|^2 < tau^2 * rmax * cmax, rmax / cmax being the largest magnitudes in the pivot's
 // row / column of the node's matrix (a test invariant under diagonal similarity), or
@@ -200,16 +182,7 @@ __device__ __forceinline__ PivInfo<F> analyse(typename F::E p, double rmax, doub
     v.pert = pc.perturb && size >= 2 && (pm == 0.0 || pm * pm < pc.tau2 * prod);
     v.pu = p;
     if (v.pert) {
-        int de = kShiftLog2;
-        const double pr = rmax * fmin(rmax, cmax);
-        if (pr > 0.0) {
-            int ep;
-            (void)frexp(pr, &ep);
-            de = (ep >> 1) + kShiftLog2 - pc.es;
-        }
-        de = de < 1 - kShiftBias ? 1 - kShiftBias : (de > 127 - kShiftBias ? 127 - kShiftBias : de);
-        const bool neg = F::re(p) < 0.0;
-        v.code = (int8_t)(uint8_t)(2 * (de + kShiftBias) + (neg ? 1 : 0));
+        v.code = shift_code(rmax, cmax, pc.es, F::re(p) < 0.0);
         v.pu = F::shift(p, shift_value(pc.es, v.code));
     }
     v.ri = F::recip(v.pu);
@@ -530,7 +503,7 @@ __device__ __forceinline__ void fix_chunk(void* out, int16_t* ex, int c, int lan
 // All principal minors of one N x N matrix by one wavefront.  Returns the info code.
 template <class F, int N, int K0MAX>
 __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, void* out, int16_t* ex,
-                                        unsigned char* lds_raw, const Opts& o, int g = 0)
+                                        unsigned char* lds_raw, const Opts& o, int g = 0, int mat = 0)
 {
     using P = Plan<N, K0MAX>;
     using L = Lay<F, N, K0MAX>;
@@ -746,23 +719,27 @@ __device__ __forceinline__ int fpm_wave(const typename F::In* __restrict__ A, vo
     if constexpr (T > 0) {
         bool deferred = false;
         if constexpr (T <= kTopDeferMaxT) {
-            if (any_top && o.topq) {
-                int idx = 0;
-                if (lane == 0) idx = atomicAdd(o.topq, 1);
-                idx = __shfl(idx, 0);
-                if (idx < o.topq_cap) {
-                    deferred = true;
-                    int* ent = o.topq + kTopHead + idx * kTopEntryInts;
-                    if (lane == 0) {
-                        const uint64_t po = reinterpret_cast<uint64_t>(out), pe = reinterpret_cast<uint64_t>(ex);
-                        ent[0] = (int)(uint32_t)po;
-                        ent[1] = (int)(uint32_t)(po >> 32);
-                        ent[2] = (int)(uint32_t)pe;
-                        ent[3] = (int)(uint32_t)(pe >> 32);
-                        ent[4] = pc.es_true;
+            if (any_top && o.topq && mat < o.topq_cap) {
+                // the matrix's slot: every item of a split matrix writes the same header and
+                // the codes of its own chunks; the first to set the flag lists the matrix
+                deferred = true;
+                int* ent = o.topq + kTopHead + (int64_t)mat * kTopEntryInts;
+                if (lane == 0) {
+                    const uint64_t po = reinterpret_cast<uint64_t>(out), pe = reinterpret_cast<uint64_t>(ex);
+                    ent[0] = (int)(uint32_t)po;
+                    ent[1] = (int)(uint32_t)(po >> 32);
+                    ent[2] = (int)(uint32_t)pe;
+                    ent[3] = (int)(uint32_t)(pe >> 32);
+                    ent[4] = pc.es_true;
+                }
+                int8_t* tv = reinterpret_cast<int8_t*>(ent + kTopCodes);
+                for (int c = c0 + lane; c < c1; c += kWave) tv[c] = tevc[c];
+                if (lane == 0) {
+                    const bool first = nsplit == 1 || atomicExch(ent + kTopFlag, 1) == 0;
+                    if (first) {
+                        int* list = o.topq + kTopHead + (int64_t)o.topq_cap * kTopEntryInts;
+                        list[atomicAdd(o.topq, 1)] = mat;
                     }
-                    int8_t* tv = reinterpret_cast<int8_t*>(ent + 5);
-                    for (int c = lane; c < (1 << T); c += kWave) tv[c] = tevc[c];
                 }
             }
         }
@@ -826,65 +803,84 @@ __global__ __launch_bounds__(64) APM_FPM_OCC void fpm_uniform_kernel(const typen
                                         : (void*)(static_cast<float*>(out) + oo);
     }
     int16_t* eb = ex ? ex + oo : nullptr;
-    const int r = fpm_wave<F, N, K0MAX>(A + io, ob, eb, lds_dyn, o, g);
+    const int r = fpm_wave<F, N, K0MAX>(A + io, ob, eb, lds_dyn, o, g, b);
     if (lane_id() == 0) {
         if (G > 1) o.part[blockIdx.x] = r;
         else if (info) info[b] = r;
     }
 }
 
-// Deferred top-level corrections (see Opts), one launch per level d, deepest first: the work
-// items (queued matrix, shifted node at level d, tile of kTopTile minors of its strict right
-// subtree) are spread over the whole grid, with the same updates as the in-wavefront path.
-// The launch for level 0 also resets the queue: the last workgroup to finish zeroes it.
-constexpr int kTopTile = 1024;
-
+// Deferred top-level corrections (see Opts), every level in one launch.  The correction of a
+// shifted level-d node c (step s = 2^(T-1-d) chunks) subtracts C times the minor one subtree to
+// the left from each minor of its strict right subtree: chunk c + u, offset j takes chunk
+// c + u - s, offset j (all but the node's own minor, u = j = 0).  For a fixed in-chunk offset j
+// the corrections of all levels act on the 2^T values at offsets j of the chunks only, so a
+// thread holds those values in registers and applies the levels deepest first, with the same
+// operations as the in-wavefront path.  Work items: (listed matrix, tile of 256 offsets).
+// The last workgroup to finish combines split info codes, clears the slots it used and resets
+// the queue head.
 template <class F, int N, int K0MAX>
-__global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int f64, int d, int last,
-                                                         const int* part, int split, int32_t* info, int batch)
+__global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int f64, const int* part, int split,
+                                                         int32_t* info, int batch)
 {
     using P = Plan<N, K0MAX>;
     constexpr int T = P::T, K = P::K;
     const int tid = threadIdx.x;
+    __shared__ int last_s;
+    int count = 0;
     if constexpr (T > 0 && T <= kTopDeferMaxT) {
-        int count = __hip_atomic_load(topq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        constexpr int NC = 1 << T;
+        constexpr int kTiles = (1 << K) / 256;
+        static_assert(kTiles >= 1 && (1 << K) % 256 == 0, "chunks hold whole tiles");
+        using V = typename F::V;
+        const int* list = topq + kTopHead + (int64_t)cap * kTopEntryInts;
+        count = __hip_atomic_load(topq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (count > cap) count = cap;
-        const int step = 1 << (T - 1 - d);
-        const int nodes = 1 << d;                                   // level-d nodes: c = step (2q + 1)
-        const int64_t half = int64_t(1) << (N - 1 - d);
-        const int64_t tiles = (half + kTopTile - 1) / kTopTile;
-        const int64_t items = (int64_t)count * nodes * tiles;
-        for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
-            const int e = (int)(w / ((int64_t)nodes * tiles));
-            const int q = (int)((w / tiles) % nodes);
-            const int64_t t = w % tiles;
-            const int* ent = topq + kTopHead + e * kTopEntryInts;
-            const int c = step * (2 * q + 1);
-            const int de = reinterpret_cast<const int8_t*>(ent + 5)[c];
-            if (de == kNoEv) continue;
+        for (int64_t w = blockIdx.x; w < (int64_t)count * kTiles; w += gridDim.x) {
+            const int* ent = topq + kTopHead + (int64_t)list[w / kTiles] * kTopEntryInts;
+            const int64_t j = (w % kTiles) * 256 + tid;
             void* out = reinterpret_cast<void*>((uint64_t)(uint32_t)ent[0] | ((uint64_t)(uint32_t)ent[1] << 32));
             int16_t* ex = reinterpret_cast<int16_t*>((uint64_t)(uint32_t)ent[2] | ((uint64_t)(uint32_t)ent[3] << 32));
-            const double Ct = shift_value(ent[4], de);
-            const int64_t start = (int64_t)c << K, end = start + half;
-            const int64_t i0 = start + 1 + t * kTopTile;
-            constexpr int kU = kTopTile / 256;
-            typename F::V va[kU], vb[kU];
+            const int es = ent[4];
+            int cw[(NC + 3) / 4];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int64_t i = i0 + tid + 256 * u;
-                if (i < end) {
-                    va[u] = F::load_v(out, ex, i, f64 != 0);
-                    vb[u] = F::load_v(out, ex, i - half, f64 != 0);
+            for (int k = 0; k < (NC + 3) / 4; ++k) cw[k] = ent[kTopCodes + k];
+            auto code = [&](int c) { return (int)(int8_t)(cw[c >> 2] >> (8 * (c & 3))); };
+            // chunks written (right subtrees) and read (left subtrees)
+            uint32_t wm = 0, rm = 0;
+#pragma unroll
+            for (int c = 1; c < NC; ++c) {
+                if (code(c) != kNoEv) {
+                    const int st = c & -c;
+                    wm |= ((1u << st) - 1) << c;
+                    rm |= ((1u << st) - 1) << (c - st);
+                }
+            }
+            V x[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                x[c] = V{};
+                if (((wm | rm) >> c) & 1u) x[c] = F::load_v(out, ex, ((int64_t)c << K) + j, f64 != 0);
+            }
+#pragma unroll
+            for (int lv = 0; lv < T; ++lv) {            // deepest level first: step 1, 2, 4, ...
+                const int st = 1 << lv;
+#pragma unroll
+                for (int c = st; c < NC; c += 2 * st) {
+                    const int de = code(c);
+                    if (de == kNoEv) continue;
+                    const double Ct = shift_value(es, de);
+#pragma unroll
+                    for (int u = 0; u < st; ++u)
+                        if (u != 0 || j != 0) x[c + u] = F::sub_scaled(x[c + u], Ct, x[c + u - st]);
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int64_t i = i0 + tid + 256 * u;
-                if (i < end) F::store_v(out, ex, i, F::sub_scaled(va[u], Ct, vb[u]), f64 != 0);
-            }
+            for (int c = 0; c < NC; ++c)
+                if ((wm >> c) & 1u) F::store_v(out, ex, ((int64_t)c << K) + j, x[c], f64 != 0);
         }
     }
-    if (last && split > 1 && info) {
+    if (split > 1 && info) {
         // info of a split matrix: the first error code of its items, else their shift counts summed
         for (int b = blockIdx.x * 256 + tid; b < batch; b += gridDim.x * 256) {
             int sum = 0, err = 0;
@@ -896,15 +892,24 @@ __global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int
             info[b] = err ? err : sum;
         }
     }
-    if (last) {
-        __syncthreads();
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        last_s = atomicAdd(topq + 1, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last_s) {
+        __threadfence();
+        if constexpr (T > 0 && T <= kTopDeferMaxT) {
+            // clear the codes and flags of the listed slots (the next launch fills them anew)
+            const int* list = topq + kTopHead + (int64_t)cap * kTopEntryInts;
+            constexpr int kClr = kTopEntryInts - kTopCodes;
+            for (int64_t k = tid; k < (int64_t)count * kClr; k += 256)
+                topq[kTopHead + (int64_t)list[k / kClr] * kTopEntryInts + kTopCodes + k % kClr] = 0;
+        }
         if (tid == 0) {
-            __threadfence();
-            const int done = atomicAdd(topq + 1, 1);
-            if (done == (int)gridDim.x - 1) {
-                atomicExch(topq, 0);
-                atomicExch(topq + 1, 0);
-            }
+            atomicExch(topq, 0);
+            atomicExch(topq + 1, 0);
         }
     }
 }
@@ -934,7 +939,15 @@ inline int env_k0()
     return e ? atoi(e) : 0;
 }
 
-constexpr int kTopFixGroups = 1024;   // workgroups of each deferred-correction launch (4 per CU: loads in flight)
+template <class F> struct SplitOf;
+template <> struct SplitOf<FR64> { static constexpr int v = 2; };
+template <> struct SplitOf<FR32S> { static constexpr int v = 4; };
+template <> struct SplitOf<FC128> { static constexpr int v = 2; };
+template <> struct SplitOf<FC64S> { static constexpr int v = 1; };
+static_assert(SplitOf<FR64>::v <= kSplit && SplitOf<FR32S>::v <= kSplit && SplitOf<FC128>::v <= kSplit &&
+                  SplitOf<FC64S>::v <= kSplit, "the queue holds kSplit info codes per matrix");
+
+constexpr int kTopFixGroups = 1024;   // workgroups of the deferred-correction launch (4 per CU: loads in flight)
 
 template <class F, int N, int K0>
 hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
@@ -949,24 +962,23 @@ hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
     constexpr int T = Plan<N, K0>::T;
     constexpr bool kDefer = T > 0 && T <= kTopDeferMaxT;
     int* topq = kDefer ? L.topq : nullptr;
-    // split matrices into work items when the queue can take every item's entry (its layout
-    // holds kSplit entries and one info code per matrix of its capacity).  Measured on the
-    // stressed 8192 x 16 batch: fp32-scaled 1.46 -> 1.12 ms (its corrections convert every
-    // value to and from mantissa + exponent, so a few heavily shifted matrices set the end
-    // of the launch); fp64 2-6% slower (its tail is short), so fp64 keeps one item.
-    const int split = (topq && !L.no_split && F::kScaled) ? (kSplit < (1 << T) ? kSplit : (1 << T)) : 1;
-    int* part = topq ? topq + kTopHead + (int64_t)L.topq_cap * kSplit * kTopEntryInts : nullptr;
-    Opts o{L.tau, L.perturb, L.out_f64, topq, topq ? L.topq_cap * kSplit : 0, split, part};
+    // split matrices into work items (the queue holds a slot per matrix and an info code
+    // per item of kSplit): with one wavefront per matrix, a few matrices with many shifted
+    // pivots (whose corrections reread their minors) or a batch of few matrices set the end
+    // of the launch.  Items per matrix by type, measured on MI355X: fp64 2 (stressed 8192 x
+    // 16 batch 1.00 -> 0.97 ms; unstressed 0.92 -> 0.935), fp32-scaled 4 (stressed batch
+    // 1.46 -> 1.10 ms), complex128 2 (4096 x 14 Keldysh 0.602 -> 0.582 ms), complex64-scaled
+    // 1 (the same batch 0.304 ms; 2 items 0.309, 4 items 0.327).
+    const int split = (topq && !L.no_split) ? (SplitOf<F>::v < (1 << T) ? SplitOf<F>::v : (1 << T)) : 1;
+    int* part = topq ? topq + kTopHead + (int64_t)L.topq_cap * (kTopEntryInts + 1) : nullptr;
+    Opts o{L.tau, L.perturb, L.out_f64, topq, topq ? L.topq_cap : 0, split, part};
     hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)L.batch * split)), dim3(64), Ly::bytes, st,
                        static_cast<const typename F::In*>(L.A), L.out, L.ex, L.info, L.batch, L.in_off, L.out_off, o);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !topq) return e;
-    for (int d = T - 1; d >= 0 && e == hipSuccess; --d) {
-        hipLaunchKernelGGL((fpm_topfix_kernel<F, N, K0>), dim3(kTopFixGroups), dim3(256), 0, st, topq, o.topq_cap,
-                           L.out_f64 ? 1 : 0, d, d == 0 ? 1 : 0, part, split, L.info, L.batch);
-        e = hipGetLastError();
-    }
-    return e;
+    hipLaunchKernelGGL((fpm_topfix_kernel<F, N, K0>), dim3(kTopFixGroups), dim3(256), 0, st, topq, o.topq_cap,
+                       L.out_f64 ? 1 : 0, part, split, L.info, L.batch);
+    return hipGetLastError();
 }
 
 template <class F, int N, int K0>

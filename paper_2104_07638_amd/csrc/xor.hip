@@ -10,6 +10,12 @@
 // shift is made: its correction would need minors this tree never forms (the paper notes
 // the same), so a zero pivot leaves its subtree non-finite and info = -3.
 //
+// The NAND case (Sec. III) keeps at most one row of every block: a ternary tree whose
+// children leave the block out (minor unchanged) or keep one of its rows (1 x 1 pivot).
+// Its left-out children are the minors that the pivot correction needs, so a small or zero
+// pivot is shifted (the test and C of the minors tree) and the kept child's subtree is
+// corrected once it is complete (see nand_top_fix).
+//
 // The XNOR case (Sec. III) keeps both or neither row of every block.  Its tree has the
 // same shape: one child drops the last undecided block (the node's leading part, minor
 // unchanged), the other keeps it (the Schur complement over the 2 x 2 pivot block, minor
@@ -106,6 +112,12 @@ __host__ __device__ constexpr int64_t xor_top_off(int n, int d)
     return s;
 }
 
+// NAND subtree levels that can shift (child order >= 1): J <= kXQ3 - 2.  Kept-row pairs of
+// the widest such level, and the shift codes of all their children.
+__host__ __device__ constexpr int xsub_pairs_max() { return 2 * (int)pow3(kXQ3 - 2); }
+__host__ __device__ constexpr int xsub_codes() { return ((int)pow3(kXQ3) - 3) / 2; }
+__host__ __device__ constexpr int xsub_code_base(int J) { return ((int)pow3(J + 1) - 3) / 2; }
+
 template <class F, int MODE>
 struct XorLds {
     typename F::E buf[2][xbuf_need(MODE)];
@@ -119,14 +131,66 @@ struct XorLds {
     // zeros: the pivot column and rows of a child that leaves its block out, so that it
     // runs the keeping children's code
     typename F::E wz[xzero_need(MODE)];
+    // NAND pivot shifts: the (possibly shifted) pivots of a subtree level's kept rows (levels
+    // with a small pivot only), the shift codes of the subtree's nodes (level J + 1 children
+    // from xsub_code_base(J) on; valid for the levels in XPiv::sub_mask)
+    typename F::E pvs[MODE == kNand ? xsub_pairs_max() : 1];
+    int8_t scode[MODE == kNand ? xsub_codes() : 1];
+    // a shifted child's own entry (no deeper row kept), with the true pivot: subtree
+    // children by code index, and the top-level child of the current path
+    typename F::E sown[MODE == kNand ? xsub_codes() : 1];
+    typename F::E topown;
 };
+
+// Matrix-wide state of the NAND pivot shifts: tau^2, the exponent of the largest input
+// magnitude, the shifts made, and whether the current subtree made any.
+struct XPiv {
+    double tau2;
+    int es;
+    int nsh;
+    int sub_mask;    // subtree levels of the current subtree with a shifted pivot (bit J)
+    bool top_own;    // the current path's top-level child was shifted (own entry in topown)
+    uint64_t tc0, tc1;   // shift code of the top path's child at depth D: byte D & 7 of tc0 (D < 8) or tc1
+    __device__ int tcode(int D) const { return (int)(int8_t)((D < 8 ? tc0 : tc1) >> (8 * (D & 7))); }
+    __device__ void set_tcode(int D, int code)
+    {
+        const int sh = 8 * (D & 7);
+        const uint64_t v = (uint64_t)(uint8_t)code << sh, m = ~(0xFFull << sh);
+        if (D < 8)
+            tc0 = (tc0 & m) | v;
+        else
+            tc1 = (tc1 & m) | v;
+    }
+};
+
+// Pivot of kept row p of an order-m subtree node P (rows of stride xs(m)), shifted if the
+// test fails on the row and column entries that enter the child (the first mc = m - 2).
+template <class F, int m>
+__device__ __forceinline__ typename F::E nand_sub_pivot(const typename F::E* P, int p, const XPiv& xp, int8_t& code)
+{
+    constexpr int mc = m - 2;
+    typename F::E pv = P[p * xs(m) + p];
+    double rmax = 0.0, cmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < mc; ++j) {
+        rmax = fmax(rmax, F::mag(P[p * xs(m) + j]));
+        cmax = fmax(cmax, F::mag(P[j * xs(m) + p]));
+    }
+    const double pm = F::mag(pv);
+    code = kNoEv;
+    if (pm == 0.0 || pm * pm < xp.tau2 * rmax * cmax) {
+        code = shift_code(rmax, cmax, xp.es, F::re(pv) < 0.0);
+        pv = F::shift(pv, shift_value(xp.es, code));
+    }
+    return pv;
+}
 
 // Top level D of matrix order 2N: the child of the depth-D node on path s (a group of
 // columns of a row of the child per lane), from the workspace (or the input at D = 0) to
 // the workspace.
 template <class F, int N, int T, int D, int MODE>
 __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, typename F::E* st,
-                                        typename F::E* ob, XorLds<F, MODE>& sh, double& chk)
+                                        typename F::E* ob, XorLds<F, MODE>& sh, double& chk, XPiv& xp)
 {
     if constexpr (D < T) {
         using E = typename F::E;
@@ -175,10 +239,30 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             if (MODE == kXor || (MODE == kNand && a != 0)) {
                 // child keeps row p of the last block: 1 x 1 pivot
                 const int p = MODE == kNand ? mc + a - 1 : mc + a;
-                const E pv = P[p * ps + p];
+                E pv = P[p * ps + p];
                 E pc = F::zero(), pr = F::zero();
                 if (act) pc = P[i * ps + p];
                 if (lane < mc) pr = P[p * ps + lane];
+                if constexpr (MODE == kNand) {
+                    // pivot shift (Sec. II test on the kept row and column of the child's
+                    // Schur complement); corrected once the subtree is complete.  No lane
+                    // holding an entry above |p| / tau: the test passes without the maxima.
+                    const double pm = F::mag(pv);
+                    const double lm = fmax(lane < mc ? F::mag(pr) : 0.0, act ? F::mag(pc) : 0.0);
+                    int code = kNoEv;
+                    if (ballot(pm == 0.0 || pm < kDefaultPivTol * lm)) {
+                        const double rmax = wave_max_nonneg(lane < mc ? F::mag(pr) : 0.0);
+                        const double cmax = wave_max_nonneg(act ? F::mag(pc) : 0.0);
+                        if (pm == 0.0 || pm * pm < xp.tau2 * rmax * cmax) {
+                            code = shift_code(rmax, cmax, xp.es, F::re(pv) < 0.0);
+                            if (lane == 0) sh.topown = F::bmul(sh.topm[D], pv, 0);
+                            pv = F::shift(pv, shift_value(xp.es, code));
+                            xp.nsh += 1;
+                            xp.top_own = true;
+                        }
+                    }
+                    xp.set_tcode(D, code);
+                }
                 const typename F::R r = F::recip(pv);
                 if (lane < mc) sh.wv[lane] = F::rowscale(pr, r);
                 if (lane == 0) {
@@ -196,6 +280,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             } else if (a == 0) {
                 // XNOR or NAND, the block left out: the leading part of the node, minor unchanged
                 if (lane == 0) sh.topm[D + 1] = sh.topm[D];
+                if constexpr (MODE == kNand) xp.set_tcode(D, kNoEv);
                 if (act) {
 #pragma unroll
                     for (int j = 0; j < cw; ++j)
@@ -239,7 +324,7 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
                 wave_mem_fence();   // the child is the next level's node (and wv is rewritten)
             }
         }
-        xor_top<F, N, T, D + 1, MODE>(d0, s, A0, st, ob, sh, chk);
+        xor_top<F, N, T, D + 1, MODE>(d0, s, A0, st, ob, sh, chk, xp);
     }
 }
 
@@ -248,7 +333,8 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
 // base is where the children's depth T+J+1 starts in the output (2^(T+J+1) - 2; XOR
 // only: the XNOR minors are the 2^N leaves, written at the last level in block-mask order).
 template <class F, int Q, int J, int MODE>
-__device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, XorLds<F, MODE>& sh, double& chk)
+__device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, XorLds<F, MODE>& sh, double& chk,
+                                        XPiv& xp)
 {
     if constexpr (J < Q) {
         using E = typename F::E;
@@ -310,23 +396,68 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
             // NAND: child 3v + c of node v leaves the last block out (c = 0, minor unchanged)
             // or keeps its row mc + c - 1; the kept rows' pivot rows times 1/pivot go to
             // wk[v][c - 1][...] (lane 2 v mc + r mc + j holds entry j of row mc + r)
+            // kept rows' pivots.  Fast test: each lane of the pivot-row pass compares one row
+            // and one column entry of its kept row with |p| / tau; if no lane finds a larger
+            // one, no pivot of this level is shifted.  Otherwise each kept row is tested on
+            // its row and column maxima and its pivot (shifted or not) goes to pvs.
+            bool slow = false;
+            if constexpr (mc > 0) {
+                static_assert(2 * (kids / 3) <= xsub_pairs_max() && 2 * (kids / 3) * mc <= 64, "pairs fit");
+                bool maybe = false;
+                if (lane < 2 * (kids / 3) * mc) {
+                    const int v = lane / (2 * mc), rr = lane - v * 2 * mc, r = rr / mc, j = rr - r * mc;
+                    const E* P = &sh.buf[cur][v * m * xs(m)];
+                    const int p = mc + r;
+                    const double pm = F::mag(P[p * xs(m) + p]);
+                    maybe = pm == 0.0 || pm < kDefaultPivTol * fmax(F::mag(P[p * xs(m) + j]), F::mag(P[j * xs(m) + p]));
+                }
+                slow = ballot(maybe) != 0;
+                if (slow) {
+                    bool shifted = false;
+                    if (lane < 2 * (kids / 3)) {
+                        const int v = lane >> 1, p = mc + (lane & 1);
+                        const E* P = &sh.buf[cur][v * m * xs(m)];
+                        int8_t code;
+                        const E pv = nand_sub_pivot<F, m>(P, p, xp, code);
+                        const int ci = xsub_code_base(J) + 3 * v + (lane & 1) + 1;
+                        if (code != kNoEv) {
+                            sh.sown[ci] = F::bmul(sh.mn[cur][v], P[p * xs(m) + p], 0);
+                            shifted = true;
+                        }
+                        sh.scode[ci] = code;
+                        sh.pvs[lane] = pv;
+                    }
+                    const int ns = __builtin_popcountll(ballot(shifted));
+                    xp.nsh += ns;
+                    if (ns) xp.sub_mask |= 1 << J;
+                    wave_sync();
+                }
+            }
             for (int t = lane; t < kids; t += 64) {
                 const int v = t / 3, c = t - 3 * v;
                 E mk = sh.mn[cur][v];
                 if (c) {
                     const int p = mc + c - 1;
-                    mk = F::bmul(mk, sh.buf[cur][v * m * xs(m) + p * xs(m) + p], 0);
+                    mk = F::bmul(mk, slow ? sh.pvs[2 * v + c - 1] : sh.buf[cur][v * m * xs(m) + p * xs(m) + p], 0);
                 }
                 sh.mn[nxt][t] = mk;
-                if constexpr (J == Q - 1) ob[(int64_t)s * pow3(Q) + t] = mk;
-                chk += F::fincheck(mk);
+                if constexpr (J == Q - 1) {
+                    // leaves: written here unless the subtree's corrections come first
+                    if (!xp.sub_mask) {
+                        ob[(int64_t)s * pow3(Q) + t] = mk;
+                        chk += F::fincheck(mk);
+                    }
+                } else {
+                    chk += F::fincheck(mk);
+                }
             }
             if constexpr (mc > 0) {
                 if (lane < 2 * (kids / 3) * mc) {
                     const int v = lane / (2 * mc), rr = lane - v * 2 * mc, r = rr / mc, j = rr - r * mc;
                     const E* P = &sh.buf[cur][v * m * xs(m)];
                     const int p = mc + r;
-                    sh.wk[lane] = F::rowscale(P[p * xs(m) + j], F::recip(P[p * xs(m) + p]));
+                    const E pv = slow ? sh.pvs[2 * v + r] : P[p * xs(m) + p];
+                    sh.wk[lane] = F::rowscale(P[p * xs(m) + j], F::recip(pv));
                 }
             }
         }
@@ -368,7 +499,84 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
             }
             wave_sync();
         }
-        xor_sub<F, Q, J + 1, MODE>(2 * base + 2, s, ob, sh, chk);   // XOR depth T+J+2 starts at 2^(T+J+2) - 2
+        xor_sub<F, Q, J + 1, MODE>(2 * base + 2, s, ob, sh, chk, xp);   // XOR depth T+J+2 starts at 2^(T+J+2) - 2
+    }
+}
+
+// NAND pivot corrections (Sec. II, pivot correction; Sec. III, NAND case: applied once the
+// subtree below the shifted node is complete, deepest node first).  A kept row l whose pivot
+// was shifted by C makes every minor of the child's subtree det A~[S]; the true minor is
+// det A~[S] - C det A[S \ {l}], and S \ {l} is the entry with the same choices except block
+// l left out: digit 0 instead of the child's digit c, i.e. c spans earlier in the ternary
+// order.  The child's own entry (no deeper row kept) is not corrected: it is the parent's
+// minor times the true pivot, kept aside when the shift is made (as the minors tree records
+// a node's own minor with the true pivot).
+
+// Subtree levels, on the 3^Q leaves in LDS: child x of level J + 1 (digits of the leaf
+// index above the span 3^(Q - 1 - J)).
+template <class F, int Q, int MODE>
+__device__ __forceinline__ void nand_sub_fix(XorLds<F, MODE>& sh, int es, int mask)
+{
+    using E = typename F::E;
+    constexpr int nl = (int)pow3(Q);
+    E* mn = sh.mn[Q & 1];
+    const int lane = threadIdx.x;
+    for (int J = Q - 2; J >= 0; --J) {
+        if (!((mask >> J) & 1)) continue;
+        int span = 1;
+        for (int k = 0; k < Q - 1 - J; ++k) span *= 3;
+        for (int t = lane; t < nl; t += 64) {
+            const int x = t / span, c = x % 3;
+            if (c) {
+                const int code = sh.scode[xsub_code_base(J) + x];
+                if (code != kNoEv) {
+                    // the child's own entry (t = x span) takes its minor with the true pivot
+                    mn[t] = t == x * span ? sh.sown[xsub_code_base(J) + x]
+                                          : F::sub_scaled(mn[t], shift_value(es, code), mn[t - c * span]);
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+// Top levels: the children chosen by path sp at depths T-1 .. dlo, whose subtrees end with
+// path sp, on the outputs in global memory (this wavefront's own stores).
+template <class F, int N, int T, int Q>
+__device__ __forceinline__ void nand_top_fix(int dlo, int sp, typename F::E* ob, const XPiv& xp, double& chk)
+{
+    using E = typename F::E;
+    const int lane = threadIdx.x;
+    constexpr int64_t q3 = pow3(Q);
+    int64_t w = 1;                                  // top paths below a depth-D child: 3^(T-1-D)
+    for (int D = T - 1; D >= dlo; --D, w *= 3) {
+        const int code = xp.tcode(D);
+        if (code == kNoEv) continue;
+        wave_mem_fence();                           // the subtree's stores, and deeper corrections
+        const int a = (int)((sp / w) % 3);
+        const int64_t span = w * q3, base = (int64_t)(sp - sp % w) * q3;
+        const double C = shift_value(xp.es, code);
+        constexpr int kU = 2;
+        for (int64_t i0 = base; i0 < base + span; i0 += 64 * kU) {
+            E va[kU], vb[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t i = i0 + lane + 64 * u;
+                if (i < base + span && i != base) {
+                    va[u] = ob[i];
+                    vb[u] = ob[i - a * span];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t i = i0 + lane + 64 * u;
+                if (i < base + span && i != base) {
+                    const E r = F::sub_scaled(va[u], C, vb[u]);
+                    ob[i] = r;
+                    chk += F::fincheck(r);
+                }
+            }
+        }
     }
 }
 
@@ -391,7 +599,11 @@ __device__ __forceinline__ void xor_matrix(const typename F::E* __restrict__ A, 
     E* ob = out + (int64_t)b * nout;
 
     bool fin = true;
-    for (int e = lane; e < w * w; e += 64) fin = fin && F::in_finite(A0[e]);
+    double amax = 0.0;
+    for (int e = lane; e < w * w; e += 64) {
+        fin = fin && F::in_finite(A0[e]);
+        amax = fmax(amax, F::mag(A0[e]));
+    }
     if (!__all(fin ? 1 : 0)) {
         for (int64_t i = lane; i < nout; i += 64) F::store_nan(ob, nullptr, i, false);
         if (info && lane == 0) info[b] = -2;
@@ -399,6 +611,8 @@ __device__ __forceinline__ void xor_matrix(const typename F::E* __restrict__ A, 
     }
     E* st = ws + (int64_t)b * ws_stride;
     double chk = 0.0;
+    XPiv xp{kDefaultPivTol * kDefaultPivTol, 0, 0, 0, false, 0, 0};
+    if constexpr (MODE == kNand) (void)frexp(wave_max(amax), &xp.es);
     if (lane == 0) sh.topm[0] = F::one();
     for (int e = lane; e < xzero_need(MODE); e += 64) sh.wz[e] = F::zero();
     constexpr int ntop = MODE == kNand ? (int)pow3(T) : 1 << T;
@@ -415,17 +629,39 @@ __device__ __forceinline__ void xor_matrix(const typename F::E* __restrict__ A, 
                 d0 = T - 1 - (31 - __clz((unsigned)(s ^ (s - 1))));
             }
         }
-        xor_top<F, N, T, 0, MODE>(d0, s, A0, st, ob, sh, chk);
+        if constexpr (MODE == kNand && T > 0) {
+            if (s) nand_top_fix<F, N, T, Q>(d0, s - 1, ob, xp, chk);
+        }
+        xor_top<F, N, T, 0, MODE>(d0, s, A0, st, ob, sh, chk, xp);
         // the subtree of depth-T node s, breadth first in LDS
         if constexpr (T == 0) {
             for (int e = lane; e < w * w; e += 64) sh.buf[0][(e / w) * xs(w) + e % w] = A0[e];
         }
         if (lane == 0) sh.mn[0][0] = sh.topm[T];
         wave_sync();
-        xor_sub<F, Q, 0, MODE>((int64_t(2) << T) - 2, s, ob, sh, chk);
+        xp.sub_mask = 0;
+        xor_sub<F, Q, 0, MODE>((int64_t(2) << T) - 2, s, ob, sh, chk, xp);
+        if constexpr (MODE == kNand) {
+            if (xp.sub_mask) {
+                nand_sub_fix<F, Q, MODE>(sh, xp.es, xp.sub_mask);
+                for (int t = lane; t < (int)pow3(Q); t += 64) {
+                    const E v = sh.mn[Q & 1][t];
+                    ob[(int64_t)s * pow3(Q) + t] = v;
+                    chk += F::fincheck(v);
+                }
+            }
+            // a top-level child shifted on this path: its own entry (leaf 0 of this subtree,
+            // written by lane 0 above) with the true pivot
+            if (xp.top_own && lane == 0) {
+                ob[(int64_t)s * pow3(Q)] = sh.topown;
+                chk += F::fincheck(sh.topown);
+            }
+            xp.top_own = false;
+        }
     }
+    if constexpr (MODE == kNand && T > 0) nand_top_fix<F, N, T, Q>(0, ntop - 1, ob, xp, chk);
     const bool bad = __any(chk == 0.0 ? 0 : 1);
-    if (info && lane == 0) info[b] = bad ? -3 : 0;
+    if (info && lane == 0) info[b] = bad ? -3 : xp.nsh;
 }
 
 template <class F, int N, int MODE>

@@ -192,7 +192,9 @@ def test_nand_parity(apm, oracle_mod, n):
             A = A + 1j * rng.standard_normal((3, 2 * n, 2 * n))
         out, info = apm.nand_minors(torch.from_numpy(A).cuda())
         torch.cuda.synchronize()
-        assert np.all(info.cpu().numpy() == 0)
+        # a few of these pivots fall below the shift threshold (one real matrix at 7 blocks
+        # and two at 8 have a pivot under 1e-3 of its row and column scale)
+        assert np.all(info.cpu().numpy() >= 0)
         got = out.cpu().numpy()
         ref = oracle_mod.nand_minors(A)
         for b in range(3):
@@ -200,6 +202,67 @@ def test_nand_parity(apm, oracle_mod, n):
                           for r in (nand_rows(n, c) for c in range(3 ** n))])
             e = metrics.mixed_err(got[b], ref[b], H)
             assert e.max() <= 1e-10, (n, cplx, b, float(e.max()))
+
+
+def _nand_bound(A):
+    n = A.shape[0] // 2
+    return np.array([np.prod(np.linalg.norm(A[np.ix_(r, r)], axis=1)) if r else 1.0
+                     for r in (nand_rows(n, c) for c in range(3 ** n))])
+
+
+def _zero_diag(A):
+    A = A.copy()
+    i = np.arange(A.shape[-1])
+    A[..., i, i] = 0.0
+    return A
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 8])
+def test_nand_zero_pivots(apm, oracle_mod, n):
+    """Zero diagonal (every pivot of a row kept below left-out blocks is zero, at every depth:
+    the subtree levels, and the top levels from five blocks on) and a diagonal of 1e-7 times
+    the off-diagonal scale (pivots below the shift threshold but not zero): the shifted tree
+    with its back-propagated corrections against the oracle on every entry, info = the
+    number of shifts."""
+    import torch
+    rng = np.random.default_rng(1700 + n)
+    for cplx in (False, True):
+        for kind in ("zero", "tiny"):
+            A = rng.standard_normal((3, 2 * n, 2 * n))
+            if cplx:
+                A = A + 1j * rng.standard_normal((3, 2 * n, 2 * n))
+            A = _zero_diag(A)
+            if kind == "tiny":
+                i = np.arange(2 * n)
+                A[:, i, i] = 1e-7 * rng.standard_normal((3, 2 * n))
+            out, info = apm.nand_minors(torch.from_numpy(A).cuda())
+            torch.cuda.synchronize()
+            info = info.cpu().numpy()
+            assert np.all(info >= 0), (n, cplx, kind, info)
+            if n >= 2:
+                assert np.all(info > 0), (n, cplx, kind, info)
+            got = out.cpu().numpy()
+            ref = oracle_mod.nand_minors(A)
+            for b in range(3):
+                e = metrics.mixed_err(got[b], ref[b], _nand_bound(A[b]))
+                assert e.max() <= 1e-10, (n, cplx, kind, b, float(e.max()), int(np.argmax(e)))
+
+
+@pytest.mark.parametrize("n", [10, 12])
+def test_nand_zero_pivots_large(apm, oracle_mod, n):
+    """Zero-diagonal Keldysh block matrices (complex) and real random ones at 10 and 12 blocks
+    (6 and 8 top levels: corrections of whole top subtrees, up to a third of the outputs):
+    every entry against the oracle."""
+    import torch
+    rng = np.random.default_rng(1800 + n)
+    for A in (_zero_diag(W.keldysh_block(1, n, seed=1810 + n)), _zero_diag(rng.standard_normal((1, 2 * n, 2 * n)))):
+        out, info = apm.nand_minors(torch.from_numpy(A).cuda())
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() > 0)
+        got = out.cpu().numpy()[0]
+        ref = oracle_mod.nand_minors(A)[0]
+        e = metrics.mixed_err(got, ref, _bound_nand(A[0]))
+        assert e.max() <= 1e-10, (n, A.dtype, float(e.max()), int(np.argmax(e)))
 
 
 def test_nand_keldysh_sampled(apm, oracle_mod):
@@ -212,7 +275,7 @@ def test_nand_keldysh_sampled(apm, oracle_mod):
     out, info = apm.nand_minors(dA)
     xo, _ = apm.xor_minors(dA)
     torch.cuda.synchronize()
-    assert np.all(info.cpu().numpy() == 0)
+    assert np.all(info.cpu().numpy() >= 0)     # shifts of near-zero pivots are allowed
     sel = np.random.default_rng(513).choice(512, 2, replace=False)
     got = out[torch.from_numpy(sel).cuda()].cpu().numpy()
     ref = oracle_mod.nand_minors(A[sel])
@@ -275,7 +338,10 @@ def test_largest_block_counts(apm, oracle_mod, mode, n):
     for A in (W.keldysh_block(1, n, seed=910 + n), rng.standard_normal((1, 2 * n, 2 * n)) + 3.0 * np.eye(2 * n)):
         out, info = fn[0](torch.from_numpy(A).cuda())
         torch.cuda.synchronize()
-        assert np.all(info.cpu().numpy() == 0)
+        if mode == "nand":
+            assert np.all(info.cpu().numpy() >= 0)   # the number of pivot shifts
+        else:
+            assert np.all(info.cpu().numpy() == 0)
         got = out.cpu().numpy()[0]
         ref = fn[1](A)[0]
         e = metrics.mixed_err(got, ref, fn[2](A[0]))
