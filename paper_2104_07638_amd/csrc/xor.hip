@@ -142,6 +142,16 @@ struct XorLds {
     typename F::E topown;
 };
 
+// Biased binary exponent of max(|Re v|, |Im v|) (0 for zero and subnormals), from the high
+// words: the fast pivot-shift test compares exponents with integer operations.  The exact
+// test can fail only with an entry above |p| / tau >= 2^9 |p| (tau = 1e-3 <= 2^-9), whose
+// exponent is then at least kFastExp above p's; so "p normal and no entry kFastExp or more
+// above it" passes the exact test.
+__device__ __forceinline__ int xexp(double v) { return (__double2hiint(v) & 0x7FFFFFFF) >> 20; }
+__device__ __forceinline__ int xexp(cd v) { return xexp(v.x) > xexp(v.y) ? xexp(v.x) : xexp(v.y); }
+constexpr int kFastExp = 9;
+static_assert(kDefaultPivTol <= 0x1p-9, "an entry above |p| / tau has an exponent >= kFastExp above p's");
+
 // Matrix-wide state of the NAND pivot shifts: tau^2, the exponent of the largest input
 // magnitude, the shifts made, and whether the current subtree made any.
 struct XPiv {
@@ -183,6 +193,47 @@ __device__ __forceinline__ typename F::E nand_sub_pivot(const typename F::E* P, 
         pv = F::shift(pv, shift_value(xp.es, code));
     }
     return pv;
+}
+
+// NAND top level D whose fast pivot test failed (rare, out of line): the test on the row and
+// column maxima of kept row p of node P (row stride ps); if the pivot is shifted, the child C
+// (row stride cs) is formed again with the shifted pivot, the node's minor times it goes to
+// topm[D + 1] and the child's own entry (with the true pivot) to topown.  Returns the code.
+template <class F, int N, int D>
+__device__ __noinline__ int nand_top_slow(const typename F::E* P, typename F::E* C, int p, int ps, int cs,
+                                          XorLds<F, kNand>& sh, double tau2, int es)
+{
+    using E = typename F::E;
+    constexpr int m = 2 * (N - D), mc = m - 2;
+    constexpr int cw = top_cols(mc), H = (mc + cw - 1) / cw;
+    constexpr bool kEven = mc % cw == 0;
+    const int lane = threadIdx.x;
+    const int i = lane % mc, h = lane / mc, h0 = h * cw;
+    const bool act = h < H;
+    const E pv = P[p * ps + p];
+    E pc = F::zero(), pr = F::zero();
+    if (act) pc = P[i * ps + p];
+    if (lane < mc) pr = P[p * ps + lane];
+    const double rmax = wave_max_nonneg(lane < mc ? F::mag(pr) : 0.0);
+    const double cmax = wave_max_nonneg(act ? F::mag(pc) : 0.0);
+    const double pm = F::mag(pv);
+    if (!(pm == 0.0 || pm * pm < tau2 * rmax * cmax)) return kNoEv;
+    const int code = shift_code(rmax, cmax, es, F::re(pv) < 0.0);
+    const E ps2 = F::shift(pv, shift_value(es, code));
+    const typename F::R r2 = F::recip(ps2);
+    wave_sync();   // every lane has read wv
+    if (lane < mc) sh.wv[lane] = F::rowscale(pr, r2);
+    if (lane == 0) {
+        sh.topown = F::bmul(sh.topm[D], pv, 0);
+        sh.topm[D + 1] = F::bmul(sh.topm[D], ps2, 0);
+    }
+    wave_sync();
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < cw; ++j)
+            if (kEven || h0 + j < mc) C[i * cs + h0 + j] = F::upd(P[i * ps + h0 + j], pc, sh.wv[h0 + j]);
+    }
+    return code;
 }
 
 // Top level D of matrix order 2N: the child of the depth-D node on path s (a group of
@@ -239,30 +290,10 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
             if (MODE == kXor || (MODE == kNand && a != 0)) {
                 // child keeps row p of the last block: 1 x 1 pivot
                 const int p = MODE == kNand ? mc + a - 1 : mc + a;
-                E pv = P[p * ps + p];
+                const E pv = P[p * ps + p];
                 E pc = F::zero(), pr = F::zero();
                 if (act) pc = P[i * ps + p];
                 if (lane < mc) pr = P[p * ps + lane];
-                if constexpr (MODE == kNand) {
-                    // pivot shift (Sec. II test on the kept row and column of the child's
-                    // Schur complement); corrected once the subtree is complete.  No lane
-                    // holding an entry above |p| / tau: the test passes without the maxima.
-                    const double pm = F::mag(pv);
-                    const double lm = fmax(lane < mc ? F::mag(pr) : 0.0, act ? F::mag(pc) : 0.0);
-                    int code = kNoEv;
-                    if (ballot(pm == 0.0 || pm < kDefaultPivTol * lm)) {
-                        const double rmax = wave_max_nonneg(lane < mc ? F::mag(pr) : 0.0);
-                        const double cmax = wave_max_nonneg(act ? F::mag(pc) : 0.0);
-                        if (pm == 0.0 || pm * pm < xp.tau2 * rmax * cmax) {
-                            code = shift_code(rmax, cmax, xp.es, F::re(pv) < 0.0);
-                            if (lane == 0) sh.topown = F::bmul(sh.topm[D], pv, 0);
-                            pv = F::shift(pv, shift_value(xp.es, code));
-                            xp.nsh += 1;
-                            xp.top_own = true;
-                        }
-                    }
-                    xp.set_tcode(D, code);
-                }
                 const typename F::R r = F::recip(pv);
                 if (lane < mc) sh.wv[lane] = F::rowscale(pr, r);
                 if (lane == 0) {
@@ -276,6 +307,24 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
 #pragma unroll
                     for (int j = 0; j < cw; ++j)
                         if (kEven || h0 + j < mc) C[i * cs + h0 + j] = F::upd(row[j], pc, sh.wv[h0 + j]);
+                }
+                if constexpr (MODE == kNand) {
+                    // pivot shift (Sec. II test on the kept row and column of the child's Schur
+                    // complement), checked once the child is written (its inputs are at hand by
+                    // then); a shifted child is formed again and corrected once its subtree is
+                    // complete.  No lane holding an entry kFastExp binary orders above p:
+                    // the test passes without the maxima.
+                    const int ep = xexp(pv);
+                    const int le = max(lane < mc ? xexp(pr) : 0, act ? xexp(pc) : 0);
+                    int code = kNoEv;
+                    if (ballot(ep == 0 || le >= ep + kFastExp)) {
+                        code = nand_top_slow<F, N, D>(P, C, p, ps, cs, sh, xp.tau2, xp.es);
+                        if (code != kNoEv) {
+                            xp.nsh += 1;
+                            xp.top_own = true;
+                        }
+                    }
+                    xp.set_tcode(D, code);
                 }
             } else if (a == 0) {
                 // XNOR or NAND, the block left out: the leading part of the node, minor unchanged
@@ -328,6 +377,97 @@ __device__ __forceinline__ void xor_top(int d0, int s, const typename F::E* A0, 
     }
 }
 
+// Update pass of subtree level J: the children's matrices (orders 2(Q - J) - 2) from the
+// nodes in buf[J & 1] and the scaled pivot rows in wk.  Lane (h, k, i) writes columns
+// [h cw, (h + 1) cw) of row i of child k: where the rows do not fill the wavefront, each row
+// is split over H lanes.
+template <class F, int Q, int J, int MODE>
+__device__ __forceinline__ void xor_sub_update(XorLds<F, MODE>& sh)
+{
+    using E = typename F::E;
+    constexpr int cur = J & 1, nxt = cur ^ 1;
+    constexpr int m = 2 * (Q - J), mc = m - 2;
+    constexpr int kids = MODE == kNand ? (int)pow3(J + 1) : 2 << J;
+    constexpr int rows = kids * mc, H = col_groups(rows, mc), cw = mc / H;
+    const int lane = threadIdx.x;
+    if (lane < rows * H) {
+        const int r = lane % rows, h = lane / rows;
+        const int k = r / mc, i = r - k * mc, j0 = h * cw;
+        E* Cr = &sh.buf[nxt][k * mc * xs(mc) + i * xs(mc)] + j0;
+        // the node's entries from column j0 on (two children per node, three for NAND)
+        const E* P = &sh.buf[cur][(MODE == kNand ? k / 3 : k >> 1) * m * xs(m)] + j0;
+        if constexpr (MODE == kNand) {
+            const int c = k % 3;
+            // one instruction stream for all three children (a copy branch beside the
+            // update would issue both): the one that leaves the block out subtracts
+            // zero times a zero row
+            const E ci = c ? P[i * xs(m) + mc - j0 + c - 1] : F::zero();
+            const E* wr = (c ? &sh.wk[(2 * (k / 3) + c - 1) * mc] : sh.wz) + j0;
+#pragma unroll
+            for (int j = 0; j < cw; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
+        } else if constexpr (MODE == kXor) {
+            const E ci = P[i * xs(m) + mc - j0 + (k & 1)];
+            const E* wr = &sh.wk[k * mc] + j0;
+#pragma unroll
+            for (int j = 0; j < cw; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
+        } else {
+            // both children in one instruction stream: the one that drops the block
+            // subtracts zero times zero rows
+            const bool keep = k & 1;
+            const E c0 = keep ? P[i * xs(m) + mc - j0] : F::zero();
+            const E c1 = keep ? P[i * xs(m) + mc - j0 + 1] : F::zero();
+            const E* w0 = (keep ? &sh.wk[(k >> 1) * 2 * mc] : sh.wz) + j0;
+#pragma unroll
+            for (int j = 0; j < cw; ++j) Cr[j] = F::upd(F::upd(P[i * xs(m) + j], c0, w0[j]), c1, w0[mc + j]);
+        }
+    }
+    wave_sync();
+}
+
+// NAND subtree level J whose fast pivot test failed (rare, out of line): each kept row tested
+// on its row and column maxima; if any is shifted, the level's kept children are formed again
+// with the shifted pivots.  Returns the shifts made (codes and own entries in sh).
+template <class F, int Q, int J>
+__device__ __noinline__ int nand_sub_slow(XorLds<F, kNand>& sh, double tau2, int es)
+{
+    using E = typename F::E;
+    constexpr int cur = J & 1, nxt = cur ^ 1;
+    constexpr int m = 2 * (Q - J), mc = m - 2;
+    constexpr int kids = (int)pow3(J + 1);
+    const int lane = threadIdx.x;
+    XPiv xp{tau2, es, 0, 0, false, 0, 0};
+    bool shifted = false;
+    if (lane < 2 * (kids / 3)) {
+        const int v = lane >> 1, p = mc + (lane & 1);
+        const E* P = &sh.buf[cur][v * m * xs(m)];
+        int8_t code;
+        const E pv = nand_sub_pivot<F, m>(P, p, xp, code);
+        const int ci = xsub_code_base(J) + 3 * v + (lane & 1) + 1;
+        if (code != kNoEv) {
+            sh.sown[ci] = F::bmul(sh.mn[cur][v], P[p * xs(m) + p], 0);
+            shifted = true;
+        }
+        sh.scode[ci] = code;
+        sh.pvs[lane] = pv;
+    }
+    const int ns = __builtin_popcountll(ballot(shifted));
+    if (ns) {
+        wave_sync();
+        if (lane < kids) {
+            const int v = lane / 3, c = lane - 3 * v;
+            if (c) sh.mn[nxt][lane] = F::bmul(sh.mn[cur][v], sh.pvs[2 * v + c - 1], 0);
+        }
+        if (lane < 2 * (kids / 3) * mc) {
+            const int v = lane / (2 * mc), rr = lane - v * 2 * mc, r = rr / mc, j = rr - r * mc;
+            const E* P = &sh.buf[cur][v * m * xs(m)];
+            sh.wk[lane] = F::rowscale(P[(mc + r) * xs(m) + j], F::recip(sh.pvs[2 * v + r]));
+        }
+        wave_sync();
+        xor_sub_update<F, Q, J, kNand>(sh);
+    }
+    return ns;
+}
+
 // Subtree level J of a Q-level subtree: the children of the 2^J nodes in buf[J & 1]
 // (order 2(Q - J)) into buf[(J + 1) & 1], one row (or column group) of a child per lane.
 // base is where the children's depth T+J+1 starts in the output (2^(T+J+1) - 2; XOR
@@ -348,6 +488,7 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
         static_assert(2 * mc <= xzero_need(MODE), "zero pivot rows cover a level");
         static_assert(kids * sizeof(E) <= sizeof(XorLds<F, MODE>::mn[0]), "a level's minors fit");
         const int lane = threadIdx.x;
+        bool maybe = false;   // NAND: this lane's fast pivot-shift test failed
         if constexpr (MODE == kXor) {
             // child k of node k/2 keeps row mc + (k & 1) of the node's last block: its minor,
             // and the pivot row times 1/pivot (lane k mc + j holds entry j)
@@ -396,49 +537,13 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
             // NAND: child 3v + c of node v leaves the last block out (c = 0, minor unchanged)
             // or keeps its row mc + c - 1; the kept rows' pivot rows times 1/pivot go to
             // wk[v][c - 1][...] (lane 2 v mc + r mc + j holds entry j of row mc + r)
-            // kept rows' pivots.  Fast test: each lane of the pivot-row pass compares one row
-            // and one column entry of its kept row with |p| / tau; if no lane finds a larger
-            // one, no pivot of this level is shifted.  Otherwise each kept row is tested on
-            // its row and column maxima and its pivot (shifted or not) goes to pvs.
-            bool slow = false;
-            if constexpr (mc > 0) {
-                static_assert(2 * (kids / 3) <= xsub_pairs_max() && 2 * (kids / 3) * mc <= 64, "pairs fit");
-                bool maybe = false;
-                if (lane < 2 * (kids / 3) * mc) {
-                    const int v = lane / (2 * mc), rr = lane - v * 2 * mc, r = rr / mc, j = rr - r * mc;
-                    const E* P = &sh.buf[cur][v * m * xs(m)];
-                    const int p = mc + r;
-                    const double pm = F::mag(P[p * xs(m) + p]);
-                    maybe = pm == 0.0 || pm < kDefaultPivTol * fmax(F::mag(P[p * xs(m) + j]), F::mag(P[j * xs(m) + p]));
-                }
-                slow = ballot(maybe) != 0;
-                if (slow) {
-                    bool shifted = false;
-                    if (lane < 2 * (kids / 3)) {
-                        const int v = lane >> 1, p = mc + (lane & 1);
-                        const E* P = &sh.buf[cur][v * m * xs(m)];
-                        int8_t code;
-                        const E pv = nand_sub_pivot<F, m>(P, p, xp, code);
-                        const int ci = xsub_code_base(J) + 3 * v + (lane & 1) + 1;
-                        if (code != kNoEv) {
-                            sh.sown[ci] = F::bmul(sh.mn[cur][v], P[p * xs(m) + p], 0);
-                            shifted = true;
-                        }
-                        sh.scode[ci] = code;
-                        sh.pvs[lane] = pv;
-                    }
-                    const int ns = __builtin_popcountll(ballot(shifted));
-                    xp.nsh += ns;
-                    if (ns) xp.sub_mask |= 1 << J;
-                    wave_sync();
-                }
-            }
+            // (formed with the true pivots; the shift test comes after the update pass)
             for (int t = lane; t < kids; t += 64) {
                 const int v = t / 3, c = t - 3 * v;
                 E mk = sh.mn[cur][v];
                 if (c) {
                     const int p = mc + c - 1;
-                    mk = F::bmul(mk, slow ? sh.pvs[2 * v + c - 1] : sh.buf[cur][v * m * xs(m) + p * xs(m) + p], 0);
+                    mk = F::bmul(mk, sh.buf[cur][v * m * xs(m) + p * xs(m) + p], 0);
                 }
                 sh.mn[nxt][t] = mk;
                 if constexpr (J == Q - 1) {
@@ -452,52 +557,35 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
                 }
             }
             if constexpr (mc > 0) {
+                static_assert(2 * (kids / 3) <= xsub_pairs_max() && 2 * (kids / 3) * mc <= 64 && kids <= 64,
+                              "one pass per level");
                 if (lane < 2 * (kids / 3) * mc) {
                     const int v = lane / (2 * mc), rr = lane - v * 2 * mc, r = rr / mc, j = rr - r * mc;
                     const E* P = &sh.buf[cur][v * m * xs(m)];
                     const int p = mc + r;
-                    const E pv = slow ? sh.pvs[2 * v + r] : P[p * xs(m) + p];
-                    sh.wk[lane] = F::rowscale(P[p * xs(m) + j], F::recip(pv));
+                    const E pv = P[p * xs(m) + p], pj = P[p * xs(m) + j];
+                    sh.wk[lane] = F::rowscale(pj, F::recip(pv));
+                    const int ep = xexp(pv);
+                    maybe = ep == 0 || max(xexp(pj), xexp(P[j * xs(m) + p])) >= ep + kFastExp;
                 }
             }
         }
         wave_sync();
-        if constexpr (mc > 0) {
-            // lane (h, k, i) writes columns [h cw, (h + 1) cw) of row i of child k: where the
-            // rows do not fill the wavefront, each row is split over H lanes
-            constexpr int rows = kids * mc, H = col_groups(rows, mc), cw = mc / H;
-            if (lane < rows * H) {
-                const int r = lane % rows, h = lane / rows;
-                const int k = r / mc, i = r - k * mc, j0 = h * cw;
-                E* Cr = &sh.buf[nxt][k * mc * xs(mc) + i * xs(mc)] + j0;
-                // the node's entries from column j0 on (two children per node, three for NAND)
-                const E* P = &sh.buf[cur][(MODE == kNand ? k / 3 : k >> 1) * m * xs(m)] + j0;
-                if constexpr (MODE == kNand) {
-                    const int c = k % 3;
-                    // one instruction stream for all three children (a copy branch beside the
-                    // update would issue both): the one that leaves the block out subtracts
-                    // zero times a zero row
-                    const E ci = c ? P[i * xs(m) + mc - j0 + c - 1] : F::zero();
-                    const E* wr = (c ? &sh.wk[(2 * (k / 3) + c - 1) * mc] : sh.wz) + j0;
-#pragma unroll
-                    for (int j = 0; j < cw; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
-                } else if constexpr (MODE == kXor) {
-                    const E ci = P[i * xs(m) + mc - j0 + (k & 1)];
-                    const E* wr = &sh.wk[k * mc] + j0;
-#pragma unroll
-                    for (int j = 0; j < cw; ++j) Cr[j] = F::upd(P[i * xs(m) + j], ci, wr[j]);
-                } else {
-                    // both children in one instruction stream: the one that drops the block
-                    // subtracts zero times zero rows
-                    const bool keep = k & 1;
-                    const E c0 = keep ? P[i * xs(m) + mc - j0] : F::zero();
-                    const E c1 = keep ? P[i * xs(m) + mc - j0 + 1] : F::zero();
-                    const E* w0 = (keep ? &sh.wk[(k >> 1) * 2 * mc] : sh.wz) + j0;
-#pragma unroll
-                    for (int j = 0; j < cw; ++j) Cr[j] = F::upd(F::upd(P[i * xs(m) + j], c0, w0[j]), c1, w0[mc + j]);
+        if constexpr (mc > 0) xor_sub_update<F, Q, J, MODE>(sh);
+        if constexpr (MODE == kNand && mc > 0) {
+            // the NAND pivot shift test (Sec. II), consumed after the children are formed (its
+            // inputs are long loaded by then).  Fast test: each lane of the pivot-row pass
+            // compared the exponents of one row and one column entry of its kept row with
+            // p's; if no lane found one kFastExp above, no pivot of this level is shifted.  Otherwise each kept row
+            // is tested on its row and column maxima, and if any is shifted the level's kept
+            // children are formed again with the shifted pivots (pvs).
+            if (ballot(maybe)) {
+                const int ns = nand_sub_slow<F, Q, J>(sh, xp.tau2, xp.es);
+                if (ns) {
+                    xp.nsh += ns;
+                    xp.sub_mask |= 1 << J;
                 }
             }
-            wave_sync();
         }
         xor_sub<F, Q, J + 1, MODE>(2 * base + 2, s, ob, sh, chk, xp);   // XOR depth T+J+2 starts at 2^(T+J+2) - 2
     }
@@ -515,7 +603,7 @@ __device__ __forceinline__ void xor_sub(int64_t base, int s, typename F::E* ob, 
 // Subtree levels, on the 3^Q leaves in LDS: child x of level J + 1 (digits of the leaf
 // index above the span 3^(Q - 1 - J)).
 template <class F, int Q, int MODE>
-__device__ __forceinline__ void nand_sub_fix(XorLds<F, MODE>& sh, int es, int mask)
+__device__ __noinline__ void nand_sub_fix(XorLds<F, MODE>& sh, int es, int mask)
 {
     using E = typename F::E;
     constexpr int nl = (int)pow3(Q);
@@ -543,8 +631,10 @@ __device__ __forceinline__ void nand_sub_fix(XorLds<F, MODE>& sh, int es, int ma
 // Top levels: the children chosen by path sp at depths T-1 .. dlo, whose subtrees end with
 // path sp, on the outputs in global memory (this wavefront's own stores).
 template <class F, int N, int T, int Q>
-__device__ __forceinline__ void nand_top_fix(int dlo, int sp, typename F::E* ob, const XPiv& xp, double& chk)
+__device__ __noinline__ double nand_top_fix(int dlo, int sp, typename F::E* ob, uint64_t tc0, uint64_t tc1, int es)
 {
+    const XPiv xp{0.0, es, 0, 0, false, tc0, tc1};
+    double chk = 0.0;
     using E = typename F::E;
     const int lane = threadIdx.x;
     constexpr int64_t q3 = pow3(Q);
@@ -578,6 +668,7 @@ __device__ __forceinline__ void nand_top_fix(int dlo, int sp, typename F::E* ob,
             }
         }
     }
+    return chk;
 }
 
 // The block minors of matrix blockIdx.x (one wavefront).
@@ -630,7 +721,7 @@ __device__ __forceinline__ void xor_matrix(const typename F::E* __restrict__ A, 
             }
         }
         if constexpr (MODE == kNand && T > 0) {
-            if (s) nand_top_fix<F, N, T, Q>(d0, s - 1, ob, xp, chk);
+            if (s && (xp.tc0 | xp.tc1)) chk += nand_top_fix<F, N, T, Q>(d0, s - 1, ob, xp.tc0, xp.tc1, xp.es);
         }
         xor_top<F, N, T, 0, MODE>(d0, s, A0, st, ob, sh, chk, xp);
         // the subtree of depth-T node s, breadth first in LDS
@@ -659,7 +750,9 @@ __device__ __forceinline__ void xor_matrix(const typename F::E* __restrict__ A, 
             xp.top_own = false;
         }
     }
-    if constexpr (MODE == kNand && T > 0) nand_top_fix<F, N, T, Q>(0, ntop - 1, ob, xp, chk);
+    if constexpr (MODE == kNand && T > 0) {
+        if (xp.tc0 | xp.tc1) chk += nand_top_fix<F, N, T, Q>(0, ntop - 1, ob, xp.tc0, xp.tc1, xp.es);
+    }
     const bool bad = __any(chk == 0.0 ? 0 : 1);
     if (info && lane == 0) info[b] = bad ? -3 : xp.nsh;
 }
