@@ -435,12 +435,12 @@ apm_status scratch_address(char** base, int* cus)
     return APM_OK;
 }
 
-// Clears the deferred-correction queue's two counters (entries queued, workgroups done); the
-// entries themselves are written before they are read.  A kernel, not a memset, so that the
-// call can be captured into a graph.
+// Clears the deferred-correction queue's counters (matrices listed, completion counts of the
+// correction launch); a listed matrix's slot is written in full (one work item per matrix)
+// before it is read.  A kernel, not a memset, so that the call can be captured into a graph.
 __global__ void scratch_head_clear_kernel(int32_t* q)
 {
-    if (threadIdx.x < 2) q[threadIdx.x] = 0;
+    if (threadIdx.x < apm::kTopCounterInts) q[threadIdx.x] = 0;
 }
 
 }  // namespace

@@ -38,6 +38,10 @@ struct LaunchMinors {
     bool no_split;             // one work item per matrix (bit-identical results either way)
 };
 
+// Leading ints of a deferred-correction queue that hold its counters (the listed matrices and
+// the completion counts of the correction launch): zero before a launch that uses it.
+constexpr int kTopCounterInts = 10;
+
 // Bytes of a deferred-correction queue for `batch` matrices: a slot and a list entry per
 // matrix and one info code per work item of a split launch (zeroed once at allocation; each
 // use leaves it zeroed).

@@ -130,12 +130,15 @@ constexpr int kSplit = 4;
 // [1] workgroups done; from int kTopHead on, one slot of kTopEntryInts per matrix: out (2),
 // ex (2), es_true (1), the shift code of each top node by chunk (8 ints = 32 bytes), the
 // listed flag (1); then the list (cap ints); then, for split launches, the info code of each
-// work item (cap * kSplit ints).  Codes and flags are zero between uses.
+// work item (cap * kSplit ints).  Ints 2 .. 2 + kTopCounts - 1 of the head are the completion
+// counts of the correction launch.  Codes, flags and counts are zero between uses.
 constexpr int kTopDeferMaxT = 5;
 constexpr int kTopEntryInts = 14;
 constexpr int kTopCodes = 5;     // first int of the shift codes in a slot
 constexpr int kTopFlag = 13;     // the listed flag
 constexpr int kTopHead = 64;
+constexpr int kTopCounts = 8;    // partial completion counts of the correction launch (ints 2 ..)
+static_assert(2 + kTopCounts == kTopCounterInts && kTopCounterInts <= kTopHead, "the counters fit the queue head");
 
 // Matrix-wide parameters of the pivot shift.
 struct PivCtl {
@@ -817,14 +820,17 @@ __global__ __launch_bounds__(64) APM_FPM_OCC void fpm_uniform_kernel(const typen
 // the corrections of all levels act on the 2^T values at offsets j of the chunks only, so a
 // thread holds those values in registers and applies the levels deepest first, with the same
 // operations as the in-wavefront path.  Work items: (listed matrix, tile of 256 offsets).
-// The last workgroup to finish combines split info codes, clears the slots it used and resets
-// the queue head.
+// The workgroups also combine the info codes of split matrices; the last one to finish clears
+// the slots that were used and resets the queue's counters.
+constexpr int kTopFixThreads = 512;   // two work items in flight per workgroup (256 threads each)
+
 template <class F, int N, int K0MAX>
-__global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int f64, const int* part, int split,
-                                                         int32_t* info, int batch)
+__global__ __launch_bounds__(kTopFixThreads) void fpm_topfix_kernel(int* topq, int cap, int f64, const int* part,
+                                                                    int split, int32_t* info, int batch)
 {
     using P = Plan<N, K0MAX>;
     constexpr int T = P::T, K = P::K;
+    constexpr int kSub = kTopFixThreads / 256;
     const int tid = threadIdx.x;
     __shared__ int last_s;
     int count = 0;
@@ -836,9 +842,9 @@ __global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int
         const int* list = topq + kTopHead + (int64_t)cap * kTopEntryInts;
         count = __hip_atomic_load(topq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (count > cap) count = cap;
-        for (int64_t w = blockIdx.x; w < (int64_t)count * kTiles; w += gridDim.x) {
+        for (int64_t w = (int64_t)blockIdx.x * kSub + (tid >> 8); w < (int64_t)count * kTiles; w += (int64_t)gridDim.x * kSub) {
             const int* ent = topq + kTopHead + (int64_t)list[w / kTiles] * kTopEntryInts;
-            const int64_t j = (w % kTiles) * 256 + tid;
+            const int64_t j = (w % kTiles) * 256 + (tid & 255);
             void* out = reinterpret_cast<void*>((uint64_t)(uint32_t)ent[0] | ((uint64_t)(uint32_t)ent[1] << 32));
             int16_t* ex = reinterpret_cast<int16_t*>((uint64_t)(uint32_t)ent[2] | ((uint64_t)(uint32_t)ent[3] << 32));
             const int es = ent[4];
@@ -882,7 +888,7 @@ __global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int
     }
     if (split > 1 && info) {
         // info of a split matrix: the first error code of its items, else their shift counts summed
-        for (int b = blockIdx.x * 256 + tid; b < batch; b += gridDim.x * 256) {
+        for (int b = blockIdx.x * kTopFixThreads + tid; b < batch; b += gridDim.x * kTopFixThreads) {
             int sum = 0, err = 0;
             for (int k = 0; k < split; ++k) {
                 const int r = part[(int64_t)b * split + k];
@@ -892,25 +898,32 @@ __global__ __launch_bounds__(256) void fpm_topfix_kernel(int* topq, int cap, int
             info[b] = err ? err : sum;
         }
     }
+    // The group's reads of the queue are complete here (each wave used their values before
+    // the barrier), so relaxed counts suffice: the last group clears only what every other
+    // group has finished reading, and no group reads another's corrections.  (A device-scope
+    // fence in every group would write back each XCD's L2 once per group.)  Two levels of
+    // counts, kTopCounts partial ones (by group index modulo kTopCounts) and one over those,
+    // so that no single address takes one atomic per group.
     __syncthreads();
     if (tid == 0) {
-        __threadfence();
-        last_s = atomicAdd(topq + 1, 1) == (int)gridDim.x - 1;
+        const int np = (int)gridDim.x < kTopCounts ? (int)gridDim.x : kTopCounts;
+        const int r = (int)(blockIdx.x % kTopCounts);
+        const int per = ((int)gridDim.x - r + kTopCounts - 1) / kTopCounts;   // groups with index r mod kTopCounts
+        bool last = false;
+        if (__hip_atomic_fetch_add(topq + 2 + r, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == per - 1)
+            last = __hip_atomic_fetch_add(topq + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == np - 1;
+        last_s = last;
     }
     __syncthreads();
     if (last_s) {
-        __threadfence();
         if constexpr (T > 0 && T <= kTopDeferMaxT) {
             // clear the codes and flags of the listed slots (the next launch fills them anew)
             const int* list = topq + kTopHead + (int64_t)cap * kTopEntryInts;
             constexpr int kClr = kTopEntryInts - kTopCodes;
-            for (int64_t k = tid; k < (int64_t)count * kClr; k += 256)
+            for (int64_t k = tid; k < (int64_t)count * kClr; k += kTopFixThreads)
                 topq[kTopHead + (int64_t)list[k / kClr] * kTopEntryInts + kTopCodes + k % kClr] = 0;
         }
-        if (tid == 0) {
-            atomicExch(topq, 0);
-            atomicExch(topq + 1, 0);
-        }
+        if (tid < kTopCounterInts) atomicExch(topq + tid, 0);
     }
 }
 
@@ -947,7 +960,11 @@ template <> struct SplitOf<FC64S> { static constexpr int v = 1; };
 static_assert(SplitOf<FR64>::v <= kSplit && SplitOf<FR32S>::v <= kSplit && SplitOf<FC128>::v <= kSplit &&
                   SplitOf<FC64S>::v <= kSplit, "the queue holds kSplit info codes per matrix");
 
-constexpr int kTopFixGroups = 1024;   // workgroups of the deferred-correction launch (4 per CU: loads in flight)
+// Workgroups of the deferred-correction launch.  Few matrices with top-level shifts (the usual
+// case) make a launch of many workgroups cost more than their work (8192 x 16 stressed batch:
+// 1024 groups of 256 threads 19 us, 256 groups 11 us); two items per group keep the loads of
+// a batch that is shifted throughout in flight.
+constexpr int kTopFixGroups = 256;
 
 template <class F, int N, int K0>
 hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
@@ -976,7 +993,7 @@ hipError_t launch_uniform(const LaunchMinors& L, hipStream_t st)
                        static_cast<const typename F::In*>(L.A), L.out, L.ex, L.info, L.batch, L.in_off, L.out_off, o);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !topq) return e;
-    hipLaunchKernelGGL((fpm_topfix_kernel<F, N, K0>), dim3(kTopFixGroups), dim3(256), 0, st, topq, o.topq_cap,
+    hipLaunchKernelGGL((fpm_topfix_kernel<F, N, K0>), dim3(kTopFixGroups), dim3(kTopFixThreads), 0, st, topq, o.topq_cap,
                        L.out_f64 ? 1 : 0, part, split, L.info, L.batch);
     return hipGetLastError();
 }
