@@ -59,29 +59,79 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
+// Cross-lane reductions and scans by DPP: within rows of 16 lanes (row_shr:1, 2, 4, 8), then
+// across rows (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3), which leaves
+// a scan's total in lane 63; reductions read it from there.  All 64 lanes must be active.
+// dpp_d: lane i gets v of its DPP source lane, or `old` where there is none (bc: 0 instead).
+template <int CTRL, int RM = 0xF, bool BC = false>
+__device__ __forceinline__ double dpp_d(double old, double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, RM, 0xF, BC);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, RM, 0xF, BC);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ int dpp_i(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, RM, 0xF, false);
+}
+
+__device__ __forceinline__ double lane63_d(double v)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// largest value over the wavefront (any doubles; -inf allowed)
+__device__ __forceinline__ double wave_max_d(double v)
+{
+    v = fmax(v, dpp_d<0x111>(v, v));
+    v = fmax(v, dpp_d<0x112>(v, v));
+    v = fmax(v, dpp_d<0x114>(v, v));
+    v = fmax(v, dpp_d<0x118>(v, v));
+    v = fmax(v, dpp_d<0x142, 0xA>(v, v));
+    v = fmax(v, dpp_d<0x143, 0xC>(v, v));
+    return lane63_d(v);
+}
+
 __device__ __forceinline__ int wave_min_i(int v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
+    v = min(v, dpp_i<0x111>(v, v));
+    v = min(v, dpp_i<0x112>(v, v));
+    v = min(v, dpp_i<0x114>(v, v));
+    v = min(v, dpp_i<0x118>(v, v));
+    v = min(v, dpp_i<0x142, 0xA>(v, v));
+    v = min(v, dpp_i<0x143, 0xC>(v, v));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ int wave_max_i(int v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
+    v = max(v, dpp_i<0x111>(v, v));
+    v = max(v, dpp_i<0x112>(v, v));
+    v = max(v, dpp_i<0x114>(v, v));
+    v = max(v, dpp_i<0x118>(v, v));
+    v = max(v, dpp_i<0x142, 0xA>(v, v));
+    v = max(v, dpp_i<0x143, 0xC>(v, v));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // inclusive prefix sum over the 64 lanes
 __device__ __forceinline__ double wave_scan(double v)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const double u = __shfl_up(v, o);
-        if (lane >= o) v += u;
-    }
+    v += dpp_d<0x111, 0xF, true>(0.0, v);
+    v += dpp_d<0x112, 0xF, true>(0.0, v);
+    v += dpp_d<0x114, 0xF, true>(0.0, v);
+    v += dpp_d<0x118, 0xF, true>(0.0, v);
+    v += dpp_d<0x142, 0xA>(0.0, v);
+    v += dpp_d<0x143, 0xC>(0.0, v);
     return v;
 }
+
+// v of lane i - 1 (0 in lane 0): wave_shr:1
+__device__ __forceinline__ double wave_shr1(double v) { return dpp_d<0x138, 0xF, true>(0.0, v); }
 
 // Propagator matrix of walker w with vertex k replaced by vnew (k < 0: no replacement).
 // Vertices outside the grid give NaN entries (no table read).
@@ -126,7 +176,7 @@ __global__ __launch_bounds__(256) void mc_context_kernel(McArgs a, int32_t* __re
     const uint32_t v = lane < n ? a.state[(size_t)w * n + lane] : 0xFFFFFFFFu;
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-        const uint32_t vj = __shfl(v, j);
+        const uint32_t vj = (uint32_t)__builtin_amdgcn_readlane((int)v, j);
         if (j != k && j != lane && (vj < v || (vj == v && j < lane))) ++rank;
     }
     uint16_t* f = feat + (size_t)w * dp;
@@ -143,12 +193,13 @@ struct Dist {
     double mx, tot;   // max logit, sum of exp(logit - mx)
 };
 
-// log q~(v) of the mixed learned proposal given the site and bin normalisers
-__device__ __forceinline__ double log_qt(const McArgs& a, const float* lg, Dist ds, Dist db, int per_bin, int s, int t)
+// log q~(v) of the mixed learned proposal from v's site and bin terms exp(logit - max) and
+// the normalisers
+__device__ __forceinline__ double log_qt(const McArgs& a, double es, double eb, Dist ds, Dist db, int per_bin)
 {
     const int L2 = a.L * a.L;
-    const double ps = exp((double)lg[s] - ds.mx) / ds.tot;
-    const double pb = exp((double)lg[L2 + t / per_bin] - db.mx) / db.tot;
+    const double ps = es / ds.tot;
+    const double pb = eb / db.tot;
     return log((1.0 - a.eps) * ps * pb / per_bin + a.eps / ((double)L2 * a.n_tau));
 }
 
@@ -176,7 +227,7 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
         const int j0 = min(L2, lane * P), j1 = min(L2, j0 + P);
         double mx = -INFINITY;
         for (int j = j0; j < j1; ++j) mx = fmax(mx, (double)lg[j]);
-        mx = wave_max(mx);
+        mx = wave_max_d(mx);
         constexpr int kPc = 8;
         double pc[kPc];
         double part = 0.0;
@@ -187,15 +238,14 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
         }
         for (int j = j0 + kPc; j < j1; ++j) part += exp((double)lg[j] - mx);
         const double incl = wave_scan(part);
-        double excl = __shfl_up(incl, 1);
-        if (lane == 0) excl = 0.0;
-        const Dist ds{mx, __shfl(incl, 63)};
+        const double excl = wave_shr1(incl);
+        const Dist ds{mx, lane63_d(incl)};
         // bin distribution: one bin per lane
         const double bl = lane < a.n_bin ? (double)lg[L2 + lane] : -INFINITY;
-        const double mxb = wave_max(bl);
+        const double mxb = wave_max_d(bl);
         const double pbl = lane < a.n_bin ? exp(bl - mxb) : 0.0;
         const double inclb = wave_scan(pbl);
-        const Dist db{mxb, __shfl(inclb, 63)};
+        const Dist db{mxb, lane63_d(inclb)};
         if (!(unif(d0.y) < a.eps)) {
             const double tg = unif(d1.x) * ds.tot;
             int cand = 0x7FFFFFFF, lastpos = -1;
@@ -220,9 +270,25 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
             t = b * per_bin + below(d1.z, per_bin);
         }
         const uint32_t vk = a.state[(size_t)w * n + k];
-        lq = log_qt(a, lg, ds, db, per_bin, (int)(vk & 0xFFFFu) < L2 ? (int)(vk & 0xFFFFu) : 0,
-                    (int)(vk >> 16) < a.n_tau ? (int)(vk >> 16) : 0) -
-             log_qt(a, lg, ds, db, per_bin, site, t);
+        // the exp terms of the old and the new site and bin, taken from the lanes that hold
+        // them (the same values as recomputing them)
+        auto site_term = [&](int sj) {
+            double mine = 0.0;
+#pragma unroll
+            for (int u = 0; u < kPc; ++u) mine = (sj == j0 + u) ? pc[u] : mine;
+            const int owner = sj / P;   // uniform: sj is the same in every lane
+            const double r = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mine), owner),
+                                              __builtin_amdgcn_readlane(__double2loint(mine), owner));
+            return sj - owner * P < kPc ? r : exp((double)lg[sj] - ds.mx);
+        };
+        auto bin_term = [&](int bj) {
+            return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(pbl), bj),
+                                    __builtin_amdgcn_readlane(__double2loint(pbl), bj));
+        };
+        const int so = (int)(vk & 0xFFFFu) < L2 ? (int)(vk & 0xFFFFu) : 0;
+        const int to = (int)(vk >> 16) < a.n_tau ? (int)(vk >> 16) : 0;
+        lq = log_qt(a, site_term(so), bin_term(to / per_bin), ds, db, per_bin) -
+             log_qt(a, site_term(site), bin_term(t / per_bin), ds, db, per_bin);
     }
     const uint32_t vnew = (uint32_t)site | ((uint32_t)t << 16);
     if (lane == 0) {
