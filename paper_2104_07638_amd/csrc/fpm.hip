@@ -2,6 +2,7 @@
 // preparation of mixed-order batches, and the table of autotuned lane-subtree orders.
 #include <atomic>
 
+#include "apm_device.h"
 #include "apm_kernels.h"
 
 namespace apm {
@@ -57,64 +58,131 @@ hipError_t fill_tune_input(void* A, int dtype, int n, int batch, hipStream_t st)
 }
 
 // Queue preparation (one workgroup): bucket the matrices by order, largest first, so the
-// persistent waves start with the longest work; packed default offsets; queue head = 0.
+// persistent waves start with the longest work; packed default offsets; queue heads = 0.
+// Thread t owns the run [t per, (t + 1) per) of consecutive matrices, per = ceil(B / 1024);
+// its orders are loaded once (runs above kPrepCache matrices reload the rest).  Counting
+// sort without atomics: each wavefront counts its matrices per bucket with ballots, the
+// counts of all wavefronts give every (bucket, wavefront) its first queue position, and each
+// wavefront then places its matrices in the same order it counted them.  The offsets are one
+// scan over the runs.
+constexpr int kPrepCache = 16;
+constexpr int kPrepBuckets = 22;   // bucket 20 - n for orders n = 1..20, 21 for invalid ones
+
+__device__ __forceinline__ int prep_bucket(int n) { return (n >= 1 && n <= 20) ? 20 - n : 21; }
+
 __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int32_t* __restrict__ nv, int32_t* order,
                                                         int32_t* counter, int64_t* ioff, int64_t* ooff)
 {
-    __shared__ int cnt[22];
-    __shared__ int pos[22];
-    __shared__ int64_t carry[2];
-    __shared__ int64_t part[2][1024];
-    const int t = threadIdx.x;
-    if (t < 22) cnt[t] = 0;
-    if (t < 2) carry[t] = 0;
-    __syncthreads();
-    // bucket 21 - n for valid orders (so that larger n come first), 21 for invalid ones
-    for (int b = t; b < batch; b += 1024) {
-        const int n = nv[b];
-        atomicAdd(&cnt[(n >= 1 && n <= 20) ? 20 - n : 21], 1);
+    __shared__ int wcnt[16][kPrepBuckets];   // matrices per (wavefront, bucket), then first positions
+    __shared__ int btot[kPrepBuckets];       // matrices per bucket
+    __shared__ int64_t wtot[2][16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int per = (int)(((int64_t)batch + 1023) / 1024);
+    const int s0 = (int)min((int64_t)batch, (int64_t)t * per), s1 = (int)min((int64_t)batch, (int64_t)s0 + per);
+    int nc[kPrepCache];
+#pragma unroll
+    for (int i = 0; i < kPrepCache; ++i) nc[i] = s0 + i < s1 ? nv[s0 + i] : 0;
+    // round i: this lane's matrix s0 + i (bucket -1 past the run); the cached rounds unrolled
+    auto count_round = [&](int bk, int (&cw)[kPrepBuckets]) {
+#pragma unroll
+        for (int k = 0; k < kPrepBuckets; ++k) cw[k] += __builtin_popcountll(ballot(bk == k));
+    };
+    // counts of this wavefront per bucket (uniform)
+    int cw[kPrepBuckets];
+#pragma unroll
+    for (int k = 0; k < kPrepBuckets; ++k) cw[k] = 0;
+#pragma unroll
+    for (int i = 0; i < kPrepCache; ++i)
+        if (i < per) count_round(s0 + i < s1 ? prep_bucket(nc[i]) : -1, cw);
+    for (int i = kPrepCache; i < per; ++i) count_round(s0 + i < s1 ? prep_bucket(nv[s0 + i]) : -1, cw);
+    if (lane < kPrepBuckets) {
+        int v = 0;
+#pragma unroll
+        for (int k = 0; k < kPrepBuckets; ++k) v = lane == k ? cw[k] : v;
+        wcnt[wv][lane] = v;
     }
     __syncthreads();
-    if (t == 0) {
+    if (t < kPrepBuckets) {   // bucket totals
         int s = 0;
-        for (int k = 0; k < 22; ++k) {
-            pos[k] = s;
-            counter[kBucketBase + k] = s;   // where the matrices of order 20 - k start
-            s += cnt[k];
-        }
-        counter[kBucketBase + 22] = s;
-        counter[0] = 0;
-        counter[1] = 0;
+        for (int w = 0; w < 16; ++w) s += wcnt[w][t];
+        btot[t] = s;
     }
     __syncthreads();
-    for (int b = t; b < batch; b += 1024) {
-        const int n = nv[b];
-        const int k = (n >= 1 && n <= 20) ? 20 - n : 21;
-        order[atomicAdd(&pos[k], 1)] = b;
+    if (t < kPrepBuckets) {   // first queue position of each (wavefront, bucket)
+        int start = 0;
+        for (int k = 0; k < t; ++k) start += btot[k];
+        if (t == kPrepBuckets - 1) {
+            counter[kBucketBase + kPrepBuckets] = start + btot[t];
+            counter[0] = 0;
+            counter[1] = 0;
+        }
+        counter[kBucketBase + t] = start;   // where the matrices of order 20 - t start
+        for (int w = 0; w < 16; ++w) {
+            const int c = wcnt[w][t];
+            wcnt[w][t] = start;
+            start += c;
+        }
     }
-    // exclusive prefix sums of n^2 and 2^n in matrix order (chunks of 1024)
-    for (int b0 = 0; b0 < batch; b0 += 1024) {
-        const int b = b0 + t;
-        const int n = (b < batch) ? nv[b] : 0;
-        const bool ok = n >= 1 && n <= 20;
-        part[0][t] = ok ? (int64_t)n * n : 0;
-        part[1][t] = ok ? (int64_t(1) << n) : 0;
-        __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {
-            int64_t a0 = 0, a1 = 0;
-            if (t >= d) { a0 = part[0][t - d]; a1 = part[1][t - d]; }
-            __syncthreads();
-            part[0][t] += a0;
-            part[1][t] += a1;
-            __syncthreads();
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPrepBuckets; ++k) cw[k] = wcnt[wv][k];
+    auto place_round = [&](int bk, int b, int (&cw)[kPrepBuckets]) {
+#pragma unroll
+        for (int k = 0; k < kPrepBuckets; ++k) {
+            const uint64_t m = ballot(bk == k);
+            if (bk == k) order[cw[k] + __builtin_popcountll(m & ((uint64_t(1) << lane) - 1))] = b;
+            cw[k] += __builtin_popcountll(m);
         }
-        if (b < batch) {
-            ioff[b] = carry[0] + part[0][t] - (ok ? (int64_t)n * n : 0);
-            ooff[b] = carry[1] + part[1][t] - (ok ? (int64_t(1) << n) : 0);
+    };
+#pragma unroll
+    for (int i = 0; i < kPrepCache; ++i)
+        if (i < per) place_round(s0 + i < s1 ? prep_bucket(nc[i]) : -1, s0 + i, cw);
+    for (int i = kPrepCache; i < per; ++i) place_round(s0 + i < s1 ? prep_bucket(nv[s0 + i]) : -1, s0 + i, cw);
+    // exclusive prefix sums of n^2 and 2^n in matrix order
+    auto sq = [](int n) { return (n >= 1 && n <= 20) ? (int64_t)n * n : (int64_t)0; };
+    auto p2 = [](int n) { return (n >= 1 && n <= 20) ? (int64_t(1) << n) : (int64_t)0; };
+    int64_t a0 = 0, a1 = 0;
+#pragma unroll
+    for (int i = 0; i < kPrepCache; ++i) {
+        a0 += sq(nc[i]);
+        a1 += p2(nc[i]);
+    }
+    for (int b = s0 + kPrepCache; b < s1; ++b) {
+        a0 += sq(nv[b]);
+        a1 += p2(nv[b]);
+    }
+    int64_t i0 = a0, i1 = a1;   // inclusive scan over the wavefront
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u0 = __shfl_up(i0, o), u1 = __shfl_up(i1, o);
+        if (lane >= o) {
+            i0 += u0;
+            i1 += u1;
         }
-        __syncthreads();
-        if (t == 1023) { carry[0] += part[0][1023]; carry[1] += part[1][1023]; }
-        __syncthreads();
+    }
+    if (lane == 63) {
+        wtot[0][wv] = i0;
+        wtot[1][wv] = i1;
+    }
+    __syncthreads();
+    int64_t e0 = i0 - a0, e1 = i1 - a1;
+    for (int w = 0; w < wv; ++w) {
+        e0 += wtot[0][w];
+        e1 += wtot[1][w];
+    }
+#pragma unroll
+    for (int i = 0; i < kPrepCache; ++i) {
+        if (s0 + i < s1) {
+            ioff[s0 + i] = e0;
+            ooff[s0 + i] = e1;
+        }
+        e0 += sq(nc[i]);
+        e1 += p2(nc[i]);
+    }
+    for (int b = s0 + kPrepCache; b < s1; ++b) {
+        ioff[b] = e0;
+        ooff[b] = e1;
+        e0 += sq(nv[b]);
+        e1 += p2(nv[b]);
     }
 }
 
