@@ -299,7 +299,8 @@ int32_t apm_minors_k0(apm_dtype dt, int32_t n);
  * Tuning cache.  apm_autotune_minors also records its choice in a JSON file,
  *   {"version": 1, "k0": {"<gfx>/<dtype>/<n>": K0, ...}}
  * keyed by the current device's architecture name (e.g. gfx950), the dtype (r64, r32s,
- * c128, c64s) and the order; apm_plan_create with APM_PLAN_AUTOTUNE reads it before timing
+ * c128, c64s) and the order (or "mixed" / "mixed-large" for the mixed-order kernels,
+ * apm_autotune_minors_mixed); apm_plan_create with APM_PLAN_AUTOTUNE reads it before timing
  * anything, so that tuned layouts carry over between processes.  The file is the value of
  * the environment variable APM_TUNE_CACHE, else $HOME/.cache/apm_tune.json (an empty
  * APM_TUNE_CACHE disables it); missing or malformed files are ignored.
@@ -312,6 +313,27 @@ int32_t apm_minors_k0(apm_dtype dt, int32_t n);
 int32_t apm_tune_cache_load(const char *path);
 
 /*
+ * apm_autotune_minors_mixed -- the same choice for the two kernels of a mixed-order launch of
+ * apm_all_minors (orders 14..16 in one persistent kernel, the other orders in another;
+ * each instantiated at two lane-subtree orders).
+ *
+ * Times each choice of each kernel on a synthetic batch of `batch` matrices (>= 1) of orders
+ * 10..16 in turn (diagonally dominant, no pivot shifts), with the other kernel at its
+ * current choice, installs the fastest for dt (later mixed-order calls, and plans created
+ * with APM_PLAN_AUTOTUNE, use them) and records them in the tuning cache under
+ * "<gfx>/<dtype>/mixed" and "<gfx>/<dtype>/mixed-large".  *k0_small / *k0_large (either may
+ * be NULL) receive the choices.  Allocates its buffers, uses the library's mixed-order
+ * workspace and synchronizes `stream`; not for use under stream capture.
+ * Returns APM_OK, APM_EINVAL, APM_ENOMEM or APM_EDEVICE.
+ *
+ * apm_minors_k0_mixed -- the lane-subtree orders a mixed-order launch of dt uses now (the
+ * tuned ones, else the defaults); -1 for an invalid dt.  Either pointer may be NULL.
+ */
+apm_status apm_autotune_minors_mixed(apm_dtype dt, int32_t batch, int32_t *k0_small, int32_t *k0_large,
+                                     apm_stream stream);
+void apm_minors_k0_mixed(apm_dtype dt, int32_t *k0_small, int32_t *k0_large);
+
+/*
  * Plans -- one of the operations above, or the CDet pipeline, bound to fixed buffers and
  * shapes, prepared once and enqueued many times (the Monte Carlo use: the same batch
  * shapes every step, new matrix values in the same buffers).
@@ -319,9 +341,10 @@ int32_t apm_tune_cache_load(const char *path);
  * apm_plan_create validates the description as the direct call would, allocates the
  * plan's own workspace (queue head and order, packed offsets, deferred-correction queue;
  * never shared with direct calls or other plans), pins the lane-subtree order of uniform
- * minors (timing every instantiated order first with APM_PLAN_AUTOTUNE, as
- * apm_autotune_minors does, when the process has no tuned value for that dtype and order
- * yet), and records the whole launch sequence once into a HIP graph on a private stream.
+ * minors, or those of the two mixed-order kernels (timing every instantiated order first
+ * with APM_PLAN_AUTOTUNE, as apm_autotune_minors / apm_autotune_minors_mixed do, when
+ * neither the process nor the tuning cache has a value for that dtype and order yet), and
+ * records the whole launch sequence once into a HIP graph on a private stream.
  * apm_plan_launch then enqueues that graph on the caller's stream: one launch call for the
  * whole sequence, with results bit-identical to the direct calls.  With APM_PLAN_EAGER the
  * plan records nothing and each launch enqueues the kernels one by one (same results).
@@ -346,7 +369,7 @@ typedef enum {
                                      a = det A[S]^2); the three launches in one graph            */
 } apm_plan_kind;
 
-#define APM_PLAN_AUTOTUNE 1u      /* tune the lane-subtree order of uniform minors before recording */
+#define APM_PLAN_AUTOTUNE 1u      /* tune the lane-subtree orders of the minors before recording  */
 #define APM_PLAN_EAGER 2u         /* record no graph; launch enqueues the kernels directly           */
 
 typedef struct {
@@ -386,9 +409,9 @@ apm_status apm_plan_create(const apm_plan_desc *d, apm_plan **out);
  * device current) or APM_EDEVICE. */
 apm_status apm_plan_launch(apm_plan *p, apm_stream stream);
 
-/* Lane-subtree order pinned in a uniform minors or CDET plan (0 for other plans or a
- * mixed-order batch), and whether the plan holds a graph (1) or launches eagerly (0).
- * Host-only; -1 for a NULL plan. */
+/* Lane-subtree order pinned in a minors or CDET plan (for a mixed-order batch: that of the
+ * orders other than 14..16; 0 for other plans), and whether the plan holds a graph (1) or launches
+ * eagerly (0).  Host-only; -1 for a NULL plan. */
 int32_t apm_plan_k0(const apm_plan *p);
 int32_t apm_plan_graphed(const apm_plan *p);
 

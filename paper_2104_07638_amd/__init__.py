@@ -50,7 +50,8 @@ EXPORTS = ("apm_all_minors", "apm_connected_sums", "apm_all_perm_minors", "apm_s
            "apm_mc_step", "apm_mc_context", "apm_mc_propose", "apm_mc_accept", "apm_autotune_minors",
            "apm_minors_k0", "apm_plan_create", "apm_plan_launch", "apm_plan_k0", "apm_plan_graphed",
            "apm_plan_destroy", "apm_last_device_error", "apm_xor_minors", "apm_xnor_minors",
-           "apm_leading_minors", "apm_nand_minors", "apm_all_minors_noalloc", "apm_probe_fma64", "apm_probe_copy", "apm_tune_cache_load")
+           "apm_leading_minors", "apm_nand_minors", "apm_all_minors_noalloc", "apm_probe_fma64", "apm_probe_copy", "apm_tune_cache_load",
+           "apm_autotune_minors_mixed", "apm_minors_k0_mixed")
 
 APM_MLP_HIDDEN, APM_MLP_MAX_IN, APM_MLP_MAX_OUT, APM_MC_MAX_N = 128, 64, 4096, 16
 
@@ -139,6 +140,10 @@ def _load():
     lib.apm_autotune_minors.restype = ctypes.c_int
     lib.apm_minors_k0.argtypes = [ctypes.c_int, i32]
     lib.apm_minors_k0.restype = i32
+    lib.apm_autotune_minors_mixed.argtypes = [ctypes.c_int, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.apm_autotune_minors_mixed.restype = ctypes.c_int
+    lib.apm_minors_k0_mixed.argtypes = [ctypes.c_int, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.apm_minors_k0_mixed.restype = None
     lib.apm_plan_create.argtypes = [ctypes.POINTER(apm_plan_desc), ctypes.POINTER(vp)]
     lib.apm_plan_create.restype = ctypes.c_int
     lib.apm_plan_launch.argtypes = [vp, vp]
@@ -280,6 +285,31 @@ def apm_autotune_minors(dt, n, batch, k0, stream):
 
 def apm_minors_k0(dt, n):
     return _lib.apm_minors_k0(int(dt), int(n))
+
+
+def apm_autotune_minors_mixed(dt, batch, k0_small, k0_large, stream):
+    return _lib.apm_autotune_minors_mixed(int(dt), int(batch), k0_small, k0_large, stream)
+
+
+def apm_minors_k0_mixed(dt, k0_small, k0_large):
+    _lib.apm_minors_k0_mixed(int(dt), k0_small, k0_large)
+
+
+def autotune_minors_mixed(dtype, batch=4096, stream=None):
+    """Time the lane-subtree orders of the two mixed-order kernels (orders other than 14..16, and
+    14..16) on a synthetic batch of orders 10..16 and install the fastest; returns them."""
+    ks, kl = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(apm_autotune_minors_mixed(DTYPES[dtype], batch, ctypes.byref(ks), ctypes.byref(kl), _stream(stream)),
+           "apm_autotune_minors_mixed")
+    return ks.value, kl.value
+
+
+def minors_k0_mixed(dtype):
+    """The lane-subtree orders a mixed-order launch of dtype uses now: (orders other than 14..16,
+    orders 14..16)."""
+    ks, kl = ctypes.c_int32(0), ctypes.c_int32(0)
+    apm_minors_k0_mixed(DTYPES[dtype], ctypes.byref(ks), ctypes.byref(kl))
+    return ks.value, kl.value
 
 
 def autotune_minors(dtype, n, batch=4096, stream=None):

@@ -159,10 +159,13 @@ apm_status get_xor_ws(hipStream_t st, size_t bytes, void** out)
 
 // ---- persistent cache of autotuned lane-subtree orders -------------------------------------
 // A JSON file {"version": 1, "k0": {"<gfx>/<dtype>/<n>": K0, ...}} (gfx: the device's
-// architecture name up to its first ':'), written by apm_autotune_minors and read by plan
-// creation with APM_PLAN_AUTOTUNE.  Path: APM_TUNE_CACHE, else $HOME/.cache/apm_tune.json;
-// an empty APM_TUNE_CACHE disables the cache.  Unreadable or malformed files are ignored.
+// architecture name up to its first ':'; <n> an order, or "mixed" / "mixed-large" for the
+// two kernels of a mixed-order launch), written by apm_autotune_minors and
+// apm_autotune_minors_mixed and read by plan creation with APM_PLAN_AUTOTUNE.  Path:
+// APM_TUNE_CACHE, else $HOME/.cache/apm_tune.json; an empty APM_TUNE_CACHE disables the
+// cache.  Unreadable or malformed files are ignored.
 const char* kDtypeName[4] = {"r64", "r32s", "c128", "c64s"};
+const char* kMixedKey[2] = {"mixed", "mixed-large"};
 
 std::string tune_cache_path()
 {
@@ -260,11 +263,21 @@ int tune_cache_install(const std::string& path)
             apm::set_tuned_k0(dt, n, it->second);
             ++count;
         }
+        for (int w = 0; w < 2; ++w) {
+            const auto it = kv.find(arch + "/" + kDtypeName[dt] + "/" + kMixedKey[w]);
+            if (it == kv.end()) continue;
+            int lo, hi, def;
+            apm::mixed_k0_range(dt, w, &lo, &hi, &def);
+            if (it->second < lo || it->second > hi) continue;
+            apm::set_tuned_mixed_k0(dt, w, it->second);
+            ++count;
+        }
     }
     return count;
 }
 
-void tune_cache_record(int dt, int n, int k0)
+// Records (key suffix -> K0) entries of dtype dt in the cache file.
+void tune_cache_record_keys(int dt, const std::pair<std::string, int>* e, int count)
 {
     std::string arch;
     if (!device_arch(&arch)) return;
@@ -273,8 +286,14 @@ void tune_cache_record(int dt, int n, int k0)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     std::map<std::string, int> kv;
     (void)tune_cache_read(path, &kv);
-    kv[arch + "/" + kDtypeName[dt] + "/" + std::to_string(n)] = k0;
+    for (int i = 0; i < count; ++i) kv[arch + "/" + kDtypeName[dt] + "/" + e[i].first] = e[i].second;
     (void)tune_cache_write(path, kv);
+}
+
+void tune_cache_record(int dt, int n, int k0)
+{
+    const std::pair<std::string, int> e(std::to_string(n), k0);
+    tune_cache_record_keys(dt, &e, 1);
 }
 
 bool bad_batch(const apm_batch* bd, int nmax)
@@ -781,6 +800,126 @@ apm_status apm_autotune_minors(apm_dtype dt, int32_t n, int32_t batch, int32_t* 
     return APM_OK;
 }
 
+void apm_minors_k0_mixed(apm_dtype dt, int32_t* k0_small, int32_t* k0_large)
+{
+    int32_t* out[2] = {k0_small, k0_large};
+    for (int w = 0; w < 2; ++w) {
+        if (!out[w]) continue;
+        if ((int)dt < 0 || (int)dt > 3) {
+            *out[w] = -1;
+            continue;
+        }
+        int lo, hi, def;
+        apm::mixed_k0_range((int)dt, w, &lo, &hi, &def);
+        const int t = apm::tuned_mixed_k0((int)dt, w);
+        const int k = t > 0 ? t : def;
+        *out[w] = k < lo ? lo : (k > hi ? hi : k);
+    }
+}
+
+apm_status apm_autotune_minors_mixed(apm_dtype dt, int32_t batch, int32_t* k0_small, int32_t* k0_large,
+                                     apm_stream stream)
+{
+    if ((int)dt < 0 || (int)dt > 3 || batch < 1) return APM_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    const bool cplx = (dt == APM_C128 || dt == APM_C64S), scaled = (dt == APM_R32S || dt == APM_C64S);
+    // synthetic batch: orders 10..16 in turn (the large-order kernel takes 14..16)
+    std::vector<int32_t> nh((size_t)batch);
+    std::vector<int64_t> ih((size_t)batch), oh((size_t)batch);
+    int64_t in_e = 0, out_e = 0;
+    for (int32_t b = 0; b < batch; ++b) {
+        const int n = 10 + b % 7;
+        nh[b] = n;
+        ih[b] = in_e;
+        oh[b] = out_e;
+        in_e += (int64_t)n * n;
+        out_e += int64_t(1) << n;
+    }
+    const size_t in_b = (size_t)in_e * (cplx ? 16 : 8);
+    const size_t out_b = (size_t)out_e * (scaled ? (cplx ? 8 : 4) : (cplx ? 16 : 8));
+    const size_t ex_b = scaled ? (size_t)out_e * 2 : 0;
+    void *A = nullptr, *out = nullptr, *ex = nullptr, *nv = nullptr, *io = nullptr, *oo = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best[2], lo[2], hi[2];
+    for (int w = 0; w < 2; ++w) {
+        apm::mixed_k0_range((int)dt, w, &lo[w], &hi[w], &best[w]);
+        const int t = apm::tuned_mixed_k0((int)dt, w);
+        if (t > 0) best[w] = t;
+    }
+    int32_t *counter = nullptr, *order = nullptr;
+    int64_t *ioff_ws = nullptr, *ooff_ws = nullptr;
+    int cus = 0;
+    apm_status s = get_workspace(batch, &counter, &order, &ioff_ws, &ooff_ws, &cus);
+    if (s != APM_OK) return s;
+    hipError_t e = hipMalloc(&A, in_b);
+    if (e == hipSuccess) e = hipMalloc(&out, out_b);
+    if (e == hipSuccess && ex_b) e = hipMalloc(&ex, ex_b);
+    if (e == hipSuccess) e = hipMalloc(&nv, (size_t)batch * 4);
+    if (e == hipSuccess) e = hipMalloc(&io, (size_t)batch * 8);
+    if (e == hipSuccess) e = hipMalloc(&oo, (size_t)batch * 8);
+    if (e == hipSuccess) e = hipMemcpyAsync(nv, nh.data(), (size_t)batch * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(io, ih.data(), (size_t)batch * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(oo, oh.data(), (size_t)batch * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess)
+        e = apm::fill_tune_input_mixed(A, (int)dt, static_cast<const int32_t*>(nv), static_cast<const int64_t*>(io),
+                                       batch, st);
+    // each kernel's choices timed with the other kernel at its current choice (the two
+    // kernels take disjoint orders; their times add)
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) {
+        float best_ms = 3.4e38f;
+        const int keep = best[w];
+        for (int k = lo[w]; k <= hi[w] && e == hipSuccess; ++k) {
+            apm::LaunchMinors L{};
+            L.dtype = (int)dt;
+            L.A = A;
+            L.out = out;
+            L.ex = static_cast<int16_t*>(ex);
+            L.batch = batch;
+            L.n_uniform = 0;
+            L.n = static_cast<const int32_t*>(nv);
+            L.n_max = 16;
+            L.in_off = static_cast<const int64_t*>(io);
+            L.out_off = static_cast<const int64_t*>(oo);
+            L.tau = apm::kDefaultPivTol;
+            L.perturb = true;
+            L.order = order;
+            L.counter = counter;
+            L.ioff_ws = ioff_ws;
+            L.ooff_ws = ooff_ws;
+            L.n_workers = cus;
+            L.force_k0 = w == 0 ? k : best[0];
+            L.force_k0_big = w == 1 ? k : best[1];
+            e = apm::fpm_launch(L, st);                       // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = apm::fpm_launch(L, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best[w] = k;
+            }
+        }
+        if (e != hipSuccess) best[w] = keep;
+    }
+    const hipError_t es = hipStreamSynchronize(st);   // before the host arrays and buffers go
+    if (e == hipSuccess) e = es;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void* q : {ex, out, A, nv, io, oo})
+        if (q) (void)hipFree(q);
+    if (e != hipSuccess) return from_hip(e);
+    for (int w = 0; w < 2; ++w) apm::set_tuned_mixed_k0((int)dt, w, best[w]);
+    const std::pair<std::string, int> rec[2] = {{kMixedKey[0], best[0]}, {kMixedKey[1], best[1]}};
+    tune_cache_record_keys((int)dt, rec, 2);
+    if (k0_small) *k0_small = best[0];
+    if (k0_large) *k0_large = best[1];
+    return APM_OK;
+}
+
 int32_t apm_tune_cache_load(const char* path)
 {
     return tune_cache_install(path ? std::string(path) : tune_cache_path());
@@ -917,6 +1056,24 @@ apm_status apm_plan_create(const apm_plan_desc* d, apm_plan** out)
             p->k0 = apm_minors_k0(d->dtype, n);
             p->Lm.force_k0 = p->k0;
             p->Lm_dn.force_k0 = p->k0;
+        }
+    }
+    const bool mixed_minors = (d->kind == APM_PLAN_MINORS || d->kind == APM_PLAN_CDET) && d->batch.n_uniform == 0;
+    if (s == APM_OK && !p->noop && mixed_minors) {
+        if ((d->flags & APM_PLAN_AUTOTUNE) &&
+            (apm::tuned_mixed_k0((int)d->dtype, 0) <= 0 || apm::tuned_mixed_k0((int)d->dtype, 1) <= 0)) {
+            (void)tune_cache_install(tune_cache_path());
+            if (apm::tuned_mixed_k0((int)d->dtype, 0) <= 0 || apm::tuned_mixed_k0((int)d->dtype, 1) <= 0) {
+                const int32_t tb = d->batch.batch < 8192 ? d->batch.batch : 8192;
+                s = apm_autotune_minors_mixed(d->dtype, tb < 7 ? 7 : tb, nullptr, nullptr, p->ps);
+            }
+        }
+        if (s == APM_OK) {
+            int32_t ks = 0, kl = 0;
+            apm_minors_k0_mixed(d->dtype, &ks, &kl);
+            p->k0 = ks;
+            p->Lm.force_k0 = p->Lm_dn.force_k0 = ks;
+            p->Lm.force_k0_big = p->Lm_dn.force_k0_big = kl;
         }
     }
     if (s == APM_OK && !p->noop && !(d->flags & APM_PLAN_EAGER)) {

@@ -32,7 +32,9 @@ struct LaunchMinors {
     int64_t* ioff_ws;          // ragged: workspace [batch] packed input offsets (if in_off == NULL)
     int64_t* ooff_ws;          // ragged: workspace [batch] packed output offsets (if out_off == NULL)
     int n_workers;             // ragged: number of compute units (persistent grid sizing)
-    int force_k0;              // > 0: lane-subtree order to use (autotuning); 0: the table
+    int force_k0;              // > 0: lane-subtree order to use (autotuning, plans); 0: the table
+                               // (mixed orders: that of the orders other than 14..16)
+    int force_k0_big;          // mixed orders: > 0: that of the orders 14..16; 0: the table
     int32_t* topq;             // uniform batches: deferred top-level correction queue (NULL: none)
     int32_t topq_cap;          // its capacity in matrices (fpm_topq_bytes of that many)
     bool no_split;             // one work item per matrix (bit-identical results either way)
@@ -56,6 +58,14 @@ hipError_t fpm_launch(const LaunchMinors& L, hipStream_t st);
 int tuned_k0(int dtype, int n);
 void set_tuned_k0(int dtype, int n, int k0);
 void k0_range(int dtype, int* lo, int* hi);
+// The same for the two kernels of a mixed-order launch (which 0: orders other than 14..16,
+// 1: orders 14..16): tuned value (0 = none), instantiated range, default.
+int tuned_mixed_k0(int dtype, int which);
+void set_tuned_mixed_k0(int dtype, int which, int k0);
+void mixed_k0_range(int dtype, int which, int* lo, int* hi, int* def);
+// Synthetic mixed-order tuning input: orders nv (device, [batch]) at packed offsets ioff.
+hipError_t fill_tune_input_mixed(void* A, int dtype, const int32_t* nv, const int64_t* ioff, int batch,
+                                 hipStream_t st);
 hipError_t fill_tune_input(void* A, int dtype, int n, int batch, hipStream_t st);
 hipError_t fpm_prep_launch(const LaunchMinors& L, hipStream_t st);   // ragged-batch queue preparation
 

@@ -9,6 +9,33 @@ namespace apm {
 
 namespace {
 std::atomic<int> g_tuned[4][21];   // zero-initialised: nothing tuned
+std::atomic<int> g_tuned_mixed[4][2];
+}
+
+int tuned_mixed_k0(int dtype, int which)
+{
+    if (dtype < 0 || dtype > 3 || which < 0 || which > 1) return 0;
+    return g_tuned_mixed[dtype][which].load(std::memory_order_relaxed);
+}
+
+void set_tuned_mixed_k0(int dtype, int which, int k0)
+{
+    if (dtype < 0 || dtype > 3 || which < 0 || which > 1) return;
+    g_tuned_mixed[dtype][which].store(k0, std::memory_order_relaxed);
+}
+
+// the instantiated lane-subtree orders of the mixed-order kernels (RaggedK0 / BigK0) and
+// their defaults
+void mixed_k0_range(int dtype, int which, int* lo, int* hi, int* def)
+{
+    static const int r[4][2][3] = {{{3, 4, 4}, {4, 5, 5}},     // r64
+                                   {{3, 4, 4}, {4, 5, 5}},     // r32s
+                                   {{2, 2, 2}, {2, 3, 3}},     // c128
+                                   {{3, 3, 3}, {3, 4, 4}}};    // c64s
+    const int* v = r[dtype & 3][which & 1];
+    *lo = v[0];
+    *hi = v[1];
+    *def = v[2];
 }
 
 int tuned_k0(int dtype, int n)
@@ -46,6 +73,34 @@ __global__ __launch_bounds__(256) void fill_tune_kernel(double* A, int comps, in
     const int64_t ij = e % ((int64_t)n * n);
     if (ij / n == ij % n && (i % comps) == 0) v += n;
     A[i] = v;
+}
+
+// Mixed orders: one workgroup per matrix, the same entries plus n_b on the diagonal.
+__global__ __launch_bounds__(256) void fill_tune_mixed_kernel(double* A, int comps, const int32_t* nv,
+                                                              const int64_t* ioff)
+{
+    const int b = blockIdx.x;
+    const int n = nv[b];
+    const int64_t base = ioff[b] * comps;
+    for (int i = threadIdx.x; i < n * n * comps; i += 256) {
+        uint64_t h = (uint64_t)(base + i) * 0x9E3779B97F4A7C15ull;
+        h ^= h >> 31;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 29;
+        double v = (double)(h >> 11) * 0x1p-53 - 0.5;
+        const int ij = i / comps;
+        if (ij / n == ij % n && (i % comps) == 0) v += n;
+        A[base + i] = v;
+    }
+}
+
+hipError_t fill_tune_input_mixed(void* A, int dtype, const int32_t* nv, const int64_t* ioff, int batch,
+                                 hipStream_t st)
+{
+    const int comps = (dtype == 2 || dtype == 3) ? 2 : 1;
+    hipLaunchKernelGGL(fill_tune_mixed_kernel, dim3((unsigned)batch), dim3(256), 0, st, static_cast<double*>(A), comps,
+                       nv, ioff);
+    return hipGetLastError();
 }
 
 hipError_t fill_tune_input(void* A, int dtype, int n, int batch, hipStream_t st)

@@ -3,6 +3,10 @@
 
 namespace apm {
 
+// the ranges that mixed_k0_range (fpm.hip) reports for this type
+static_assert(RaggedK0<FC128>::lo == 2 && RaggedK0<FC128>::hi == 2 && BigK0<FC128>::lo == 2 && BigK0<FC128>::hi == 3,
+              "mixed-order lane-subtree ranges");
+
 template <>
 int default_k0<FC128>(int n)
 {

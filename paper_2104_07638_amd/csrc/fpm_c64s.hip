@@ -3,6 +3,10 @@
 
 namespace apm {
 
+// the ranges that mixed_k0_range (fpm.hip) reports for this type
+static_assert(RaggedK0<FC64S>::lo == 3 && RaggedK0<FC64S>::hi == 3 && BigK0<FC64S>::lo == 3 && BigK0<FC64S>::hi == 4,
+              "mixed-order lane-subtree ranges");
+
 template <>
 int default_k0<FC64S>(int n)
 {

@@ -1027,50 +1027,61 @@ hipError_t dispatch_n(const LaunchMinors& L, hipStream_t st)
 }
 
 // ----------------------------------------------------------------- ragged batches
-// Lane-subtree order used by the persistent mixed-order kernel: one below the largest,
-// which keeps the merged kernel at two wavefronts per SIMD.
+// Lane-subtree order of the persistent mixed-order kernel by default: one below the largest,
+// which keeps the merged kernel at two wavefronts per SIMD.  Instantiated range (the
+// autotuner picks within it): that order and the one below.
 template <class F>
 constexpr int ragged_k0()
 {
     return K0Set<F>::hi > K0Set<F>::lo ? K0Set<F>::hi - 1 : K0Set<F>::hi;
 }
+template <class F> struct RaggedK0 {
+    static constexpr int hi = ragged_k0<F>();
+    static constexpr int lo = hi - 1 >= K0Set<F>::lo ? hi - 1 : hi;
+};
 
-// Orders run by fpm_ragged_big_kernel (below) when a mixed batch contains them.
+// Orders run by fpm_ragged_big_kernel (below) when a mixed batch contains them; its lane-
+// subtree order is the largest by default, and the one below is instantiated too.
 constexpr int kBigLo = 14, kBigHi = 16;
+template <class F> struct BigK0 {
+    static constexpr int hi = K0Set<F>::hi;
+    static constexpr int lo = hi - 1 >= K0Set<F>::lo ? hi - 1 : hi;
+};
 
 // One order per (non-inlined) function, so that each keeps its own register allocation.
-template <class F, int N>
+template <class F, int N, int K0R>
 __device__ __noinline__ int fpm_wave_n(const typename F::In* A, void* ob, int16_t* eb, unsigned char* lds, Opts o)
 {
-    return fpm_wave<F, N, ragged_k0<F>()>(A, ob, eb, lds, o);
+    return fpm_wave<F, N, K0R>(A, ob, eb, lds, o);
 }
 
-template <class F, int N>
+template <class F, int N, int K0R>
 __device__ __forceinline__ int fpm_dispatch(int n, const typename F::In* A, void* ob, int16_t* eb, unsigned char* lds,
                                             const Opts& o)
 {
     if constexpr (N > 20) {
         return -1;
+    } else if constexpr (N >= kBigLo && N <= kBigHi) {
+        return fpm_dispatch<F, kBigHi + 1, K0R>(n, A, ob, eb, lds, o);   // fpm_ragged_big_kernel's orders
     } else {
-        if (n == N) return fpm_wave_n<F, N>(A, ob, eb, lds, o);
-        return fpm_dispatch<F, N + 1>(n, A, ob, eb, lds, o);
+        if (n == N) return fpm_wave_n<F, N, K0R>(A, ob, eb, lds, o);
+        return fpm_dispatch<F, N + 1, K0R>(n, A, ob, eb, lds, o);
     }
 }
 
-// Persistent waves over the prepared queue; each matrix is handled by the code for its order.
-template <class F>
+// Persistent waves over the prepared queue, skipping the matrices of orders kBigLo..kBigHi
+// (a contiguous range of the queue order, left to fpm_ragged_big_kernel); each matrix is
+// handled by the code for its order.
+template <class F, int K0R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fpm_ragged_kernel(const typename F::In* __restrict__ A, void* out, int16_t* ex,
                                                         int32_t* info, int32_t batch, const int32_t* __restrict__ nv,
                                                         const int64_t* __restrict__ in_off,
                                                         const int64_t* __restrict__ out_off,
-                                                        const int32_t* __restrict__ order, int32_t* counter, Opts o,
-                                                        int skip_big)
+                                                        const int32_t* __restrict__ order, int32_t* counter, Opts o)
 {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
-    // with skip_big, the matrices of orders kBigLo..kBigHi (a contiguous range of the queue
-    // order) are left to fpm_ragged_big_kernel
-    const int lo = skip_big ? counter[kBucketBase + 20 - kBigHi] : batch;
-    const int gap = skip_big ? counter[kBucketBase + 21 - kBigLo] - lo : 0;
+    const int lo = counter[kBucketBase + 20 - kBigHi];
+    const int gap = counter[kBucketBase + 21 - kBigLo] - lo;
     for (;;) {
         int i = 0;
         if (lane_id() == 0) i = atomicAdd(counter, 1);
@@ -1080,7 +1091,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
         const int b = order[i];
         const int n = nv[b];
         int r = -1;
-        if (n >= 1 && n <= 20) {
+        if (n >= 1 && n <= 20 && !(n >= kBigLo && n <= kBigHi)) {
             const int64_t io = in_off[b];
             const int64_t oo = out_off[b];
             void* ob;
@@ -1092,7 +1103,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
                                                 : (void*)(static_cast<float*>(out) + oo);
             }
             int16_t* eb = ex ? ex + oo : nullptr;
-            r = fpm_dispatch<F, 1>(n, A + io, ob, eb, lds_dyn, o);
+            r = fpm_dispatch<F, 1, K0R>(n, A + io, ob, eb, lds_dyn, o);
         }
         if (info && lane_id() == 0) info[b] = r;
         wave_sync();
@@ -1104,19 +1115,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
 // wavefronts per SIMD.  The matrices of these orders are a contiguous range of the queue
 // order (sorted by decreasing order), which this kernel walks with its own counter.
 
-template <class F, int N>
+template <class F, int N, int K0B>
 __device__ __forceinline__ int fpm_dispatch_big(int n, const typename F::In* A, void* ob, int16_t* eb,
                                                 unsigned char* lds, const Opts& o)
 {
     if constexpr (N > kBigHi) {
         return -1;
     } else {
-        if (n == N) return fpm_wave<F, N, K0Set<F>::hi>(A, ob, eb, lds, o);
-        return fpm_dispatch_big<F, N + 1>(n, A, ob, eb, lds, o);
+        if (n == N) return fpm_wave<F, N, K0B>(A, ob, eb, lds, o);
+        return fpm_dispatch_big<F, N + 1, K0B>(n, A, ob, eb, lds, o);
     }
 }
 
-template <class F>
+template <class F, int K0B>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fpm_ragged_big_kernel(
     const typename F::In* __restrict__ A, void* out, int16_t* ex, int32_t* info, const int32_t* __restrict__ nv,
     const int64_t* __restrict__ in_off, const int64_t* __restrict__ out_off, const int32_t* __restrict__ order,
@@ -1139,47 +1150,92 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
             ob = (o.out_f64 || !F::kScaled) ? (void*)(static_cast<double*>(out) + oo)
                                             : (void*)(static_cast<float*>(out) + oo);
         }
-        const int r = fpm_dispatch_big<F, kBigLo>(n, A + in_off[b], ob, ex ? ex + oo : nullptr, lds_dyn, o);
+        const int r = fpm_dispatch_big<F, kBigLo, K0B>(n, A + in_off[b], ob, ex ? ex + oo : nullptr, lds_dyn, o);
         if (info && lane_id() == 0) info[b] = r;
         wave_sync();
     }
 }
 
-template <class F, int N>
-constexpr size_t max_lay_bytes()
-{
-    if constexpr (N > 20) {
-        return 0;
-    } else {
-        constexpr size_t a = Lay<F, N, ragged_k0<F>()>::bytes;
-        constexpr size_t b = max_lay_bytes<F, N + 1>();
-        return a > b ? a : b;
-    }
-}
-
-template <class F, int N>
+// LDS of the orders up to nmax that each kernel runs
+template <class F, int N, int K0R>
 size_t lay_bytes_upto(int nmax)
 {
     if constexpr (N > 20) {
         return 0;
     } else {
-        const size_t a = N <= nmax ? Lay<F, N, ragged_k0<F>()>::bytes : 0;
-        const size_t b = lay_bytes_upto<F, N + 1>(nmax);
+        const size_t a = (N <= nmax && !(N >= kBigLo && N <= kBigHi)) ? Lay<F, N, K0R>::bytes : 0;
+        const size_t b = lay_bytes_upto<F, N + 1, K0R>(nmax);
         return a > b ? a : b;
     }
 }
 
-template <class F, int N>
-size_t big_lay_bytes(int n)
+template <class F, int N, int K0B>
+size_t big_lay_bytes_upto(int nmax)
 {
     if constexpr (N > kBigHi) {
         return 0;
     } else {
-        if (n == N) return Lay<F, N, K0Set<F>::hi>::bytes;
-        return big_lay_bytes<F, N + 1>(n);
+        const size_t a = N <= nmax ? Lay<F, N, K0B>::bytes : 0;
+        const size_t b = big_lay_bytes_upto<F, N + 1, K0B>(nmax);
+        return a > b ? a : b;
     }
 }
 
+// Persistent grid: as many workgroups as fit on the compute units at once.
+template <class Kern>
+hipError_t ragged_grid(Kern kern, size_t bytes, int cus, int64_t batch, int64_t* grid)
+{
+    if (bytes > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64, bytes);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    *grid = (int64_t)per_cu * cus;
+    if (*grid > batch) *grid = batch;
+    return hipSuccess;
+}
+
+template <class F, int K0R>
+hipError_t launch_ragged_small(int k0, const LaunchMinors& L, const int64_t* ioff, const int64_t* ooff, const Opts& o,
+                               int cus, hipStream_t st)
+{
+    if constexpr (K0R < RaggedK0<F>::hi) {
+        if (k0 > K0R) return launch_ragged_small<F, K0R + 1>(k0, L, ioff, ooff, o, cus, st);
+    }
+    const size_t bytes = lay_bytes_upto<F, 1, K0R>(L.n_max);
+    auto kern = fpm_ragged_kernel<F, K0R>;
+    int64_t grid = 0;
+    hipError_t e = ragged_grid(kern, bytes, cus, L.batch, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), bytes, st, static_cast<const typename F::In*>(L.A), L.out,
+                       L.ex, L.info, L.batch, L.n, ioff, ooff, L.order, L.counter, o);
+    return hipGetLastError();
+}
+
+template <class F, int K0B>
+hipError_t launch_ragged_big(int k0, const LaunchMinors& L, const int64_t* ioff, const int64_t* ooff, const Opts& o,
+                             int cus, hipStream_t st)
+{
+    if constexpr (K0B < BigK0<F>::hi) {
+        if (k0 > K0B) return launch_ragged_big<F, K0B + 1>(k0, L, ioff, ooff, o, cus, st);
+    }
+    const size_t bytes = big_lay_bytes_upto<F, kBigLo, K0B>(L.n_max);
+    auto kern = fpm_ragged_big_kernel<F, K0B>;
+    int64_t grid = 0;
+    hipError_t e = ragged_grid(kern, bytes, cus, L.batch, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), bytes, st, static_cast<const typename F::In*>(L.A), L.out,
+                       L.ex, L.info, L.n, ioff, ooff, L.order, L.counter, o);
+    return hipGetLastError();
+}
+
+// Mixed orders: the queue preparation, then the orders kBigLo..kBigHi (their own kernel)
+// and the rest.  Lane-subtree orders: an explicit request (force_k0 / force_k0_big,
+// autotuning and plans), else the autotuner's choice for the type, else the defaults.
 template <class F>
 hipError_t fpm_launch_ragged(const LaunchMinors& L, hipStream_t st)
 {
@@ -1187,47 +1243,19 @@ hipError_t fpm_launch_ragged(const LaunchMinors& L, hipStream_t st)
     const int64_t* ooff = L.out_off ? L.out_off : L.ooff_ws;
     hipError_t e = fpm_prep_launch(L, st);
     if (e != hipSuccess) return e;
-    const size_t bytes = lay_bytes_upto<F, 1>(L.n_max);
-    auto kern = fpm_ragged_kernel<F>;
-    if (bytes > 65536) {
-        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-    }
     const int cus = L.n_workers > 0 ? L.n_workers : 256;
     Opts o{L.tau, L.perturb, L.out_f64, nullptr, 0, 1, nullptr};   // mixed orders: corrections in the wavefront
-    // the large orders first, in their own kernel (largest lane subtrees), then the rest
-    const bool big = L.n_max >= kBigLo;
-    if (big) {
-        size_t bb = 0;
-        for (int nn = kBigLo; nn <= kBigHi && nn <= L.n_max; ++nn) {
-            const size_t x = big_lay_bytes<F, kBigLo>(nn);
-            bb = x > bb ? x : bb;
-        }
-        auto kb = fpm_ragged_big_kernel<F>;
-        if (bb > 65536) {
-            e = hipFuncSetAttribute((const void*)kb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bb);
-            if (e != hipSuccess) return e;
-        }
-        int pcb = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pcb, (const void*)kb, 64, bb);
-        if (e != hipSuccess) return e;
-        if (pcb < 1) pcb = 1;
-        int64_t gb = (int64_t)pcb * cus;
-        if (gb > L.batch) gb = L.batch;
-        hipLaunchKernelGGL(kb, dim3((unsigned)gb), dim3(64), bb, st, static_cast<const typename F::In*>(L.A), L.out,
-                           L.ex, L.info, L.n, ioff, ooff, L.order, L.counter, o);
-        e = hipGetLastError();
+    auto pick = [](int forced, int tuned, int def, int lo, int hi) {
+        int k = forced > 0 ? forced : (tuned > 0 ? tuned : def);
+        return k < lo ? lo : (k > hi ? hi : k);
+    };
+    if (L.n_max >= kBigLo) {
+        const int kb = pick(L.force_k0_big, tuned_mixed_k0(F::kId, 1), BigK0<F>::hi, BigK0<F>::lo, BigK0<F>::hi);
+        e = launch_ragged_big<F, BigK0<F>::lo>(kb, L, ioff, ooff, o, cus, st);
         if (e != hipSuccess) return e;
     }
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64, bytes);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    int64_t grid = (int64_t)per_cu * cus;
-    if (grid > L.batch) grid = L.batch;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), bytes, st, static_cast<const typename F::In*>(L.A),
-                       L.out, L.ex, L.info, L.batch, L.n, ioff, ooff, L.order, L.counter, o, big ? 1 : 0);
-    return hipGetLastError();
+    const int ks = pick(L.force_k0, tuned_mixed_k0(F::kId, 0), RaggedK0<F>::hi, RaggedK0<F>::lo, RaggedK0<F>::hi);
+    return launch_ragged_small<F, RaggedK0<F>::lo>(ks, L, ioff, ooff, o, cus, st);
 }
 
 template <class F>

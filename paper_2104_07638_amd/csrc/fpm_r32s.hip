@@ -3,6 +3,10 @@
 
 namespace apm {
 
+// the ranges that mixed_k0_range (fpm.hip) reports for this type
+static_assert(RaggedK0<FR32S>::lo == 3 && RaggedK0<FR32S>::hi == 4 && BigK0<FR32S>::lo == 4 && BigK0<FR32S>::hi == 5,
+              "mixed-order lane-subtree ranges");
+
 template <>
 int default_k0<FR32S>(int n)
 {

@@ -246,3 +246,66 @@ def test_capture_survives_workspace_growth(apm, oracle_mod):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(m, m_ref), i
+
+
+def test_mixed_kernel_variants_and_autotune(apm, oracle_mod, tmp_path, monkeypatch):
+    """Every instantiated lane-subtree order of the two mixed-order kernels (installed through
+    the tuning cache) against the oracle on a batch of orders 1..20; then the mixed-order
+    autotuner records its choices in the cache and a plan created with autotuning pins them."""
+    import json
+    import torch
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("APM_TUNE_CACHE", str(path))
+    rng = np.random.default_rng(11)
+    orders = [14, 3, 16, 9, 15, 12, 1, 13, 20, 10, 7, 16, 11, 14, 5, 18]
+    mats = [W.lattice_batch(1, k, W.Lattice(32, 1.0, -0.5, 5.0), seed=900 + i)[0] for i, k in enumerate(orders)]
+    ns, flat, ooff, tot = pack(mats)
+    n_t = torch.from_numpy(ns).cuda()
+    A_t = torch.from_numpy(flat).cuda()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    default = apm.minors_k0_mixed("r64")
+    assert default == (4, 5)
+    try:
+        for ks in (3, 4):
+            for kl in (4, 5):
+                json.dump({"version": 1, "k0": {f"{arch}/r64/mixed": ks, f"{arch}/r64/mixed-large": kl}},
+                          open(path, "w"))
+                assert apm.tune_cache_load(str(path)) == 2
+                assert apm.minors_k0_mixed("r64") == (ks, kl)
+                out = torch.full((tot,), 3.0, dtype=torch.float64, device="cuda")
+                _, _, info = apm.all_minors_ragged(A_t, n_t, 20, "r64", out=out)
+                torch.cuda.synchronize()
+                got = out.cpu().numpy()
+                assert np.all(info.cpu().numpy() >= 0)
+                for k, M in enumerate(mats):
+                    n = M.shape[0]
+                    seg = got[ooff[k]:ooff[k] + (1 << n)]
+                    if n <= 12:
+                        e = metrics.mixed_err(seg, oracle_mod.minors(M), metrics.hadamard_bounds(M))
+                    else:
+                        masks = np.unique(np.concatenate([rng.integers(0, 1 << n, 600), [0, (1 << n) - 1]]))
+                        e = metrics.mixed_err(seg[masks], oracle_mod.minors_at(M, masks), metrics.hadamard_at(M, masks))
+                    assert e.max() <= 1e-10, (ks, kl, n, float(e.max()))
+        # the autotuner: choices in range, installed, and recorded under the mixed keys
+        path.unlink()
+        ks, kl = apm.autotune_minors_mixed("r64", batch=700)
+        assert ks in (3, 4) and kl in (4, 5)
+        assert apm.minors_k0_mixed("r64") == (ks, kl)
+        doc = json.load(open(path))
+        assert doc["k0"][f"{arch}/r64/mixed"] == ks and doc["k0"][f"{arch}/r64/mixed-large"] == kl
+        # a plan with autotuning takes the installed values
+        out = torch.empty((tot,), dtype=torch.float64, device="cuda")
+        p = apm.plan_minors(A_t, out, n=n_t, n_max=20, autotune=True)
+        assert p.k0 == ks
+        p.launch()
+        torch.cuda.synchronize()
+        ref = torch.empty_like(out)
+        apm.all_minors_ragged(A_t, n_t, 20, "r64", out=ref)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        p.close()
+    finally:
+        json.dump({"version": 1, "k0": {f"{arch}/r64/mixed": default[0], f"{arch}/r64/mixed-large": default[1]}},
+                  open(path, "w"))
+        apm.tune_cache_load(str(path))
+    assert apm.minors_k0_mixed("r64") == default
