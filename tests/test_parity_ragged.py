@@ -309,3 +309,63 @@ def test_mixed_kernel_variants_and_autotune(apm, oracle_mod, tmp_path, monkeypat
                   open(path, "w"))
         apm.tune_cache_load(str(path))
     assert apm.minors_k0_mixed("r64") == default
+
+
+@pytest.mark.parametrize("dtype", ["r32s", "c128", "c64s"])
+def test_mixed_kernel_variants_other_types(apm, oracle_mod, dtype, tmp_path):
+    """The other element types' mixed-order kernel variants (every instantiated lane-subtree
+    order of both kernels, installed through a cache file) against the oracle: orders below,
+    inside and above the large-order kernel's range."""
+    import json
+    import torch
+    ranges = {"r32s": ((3, 4), (4, 5)), "c128": ((2,), (2, 3)), "c64s": ((3,), (3, 4))}[dtype]
+    cplx = dtype in ("c128", "c64s")
+    orders = [9, 14, 15, 3, 16, 12] if cplx else [9, 14, 15, 3, 16, 12, 17]
+    if cplx:
+        mats = [W.keldysh_batch(1, k, seed=70 + k)[0] for k in orders]
+    else:
+        mats = [W.lattice_batch(1, k, W.Lattice(32, 1.0, -0.5, 5.0), seed=70 + k)[0] for k in orders]
+    ns, flat, ooff, tot = pack(mats)
+    rng = np.random.default_rng(5)
+    refs = []   # (masks or None, reference values, bounds)
+    for M in mats:
+        n = M.shape[0]
+        if cplx or n <= 12:
+            full = oracle_mod.minors_complex(M) if cplx else oracle_mod.minors(M)
+            refs.append((None, full, metrics.hadamard_bounds(M)))
+        else:
+            masks = np.unique(np.concatenate([rng.integers(0, 1 << n, 400), [0, (1 << n) - 1]]))
+            refs.append((masks, oracle_mod.minors_at(M, masks), metrics.hadamard_at(M, masks)))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = tmp_path / "tune.json"
+    default = apm.minors_k0_mixed(dtype)
+    tol = 1e-10 if dtype == "c128" else 1e-4
+    A = torch.from_numpy(flat).cuda()
+    n_t = torch.from_numpy(ns).cuda()
+    try:
+        for ks in ranges[0]:
+            for kl in ranges[1]:
+                json.dump({"version": 1, "k0": {f"{arch}/{dtype}/mixed": ks, f"{arch}/{dtype}/mixed-large": kl}},
+                          open(path, "w"))
+                assert apm.tune_cache_load(str(path)) == 2 and apm.minors_k0_mixed(dtype) == (ks, kl)
+                if dtype == "c128":
+                    out = torch.empty(tot, dtype=torch.complex128, device="cuda")
+                    _, _, info = apm.all_minors_ragged(A, n_t, max(orders), dtype, out=out)
+                    got = out.cpu().numpy()
+                else:
+                    out = torch.empty(tot, dtype=torch.complex64 if cplx else torch.float32, device="cuda")
+                    ex = torch.empty(tot, dtype=torch.int16, device="cuda")
+                    _, _, info = apm.all_minors_ragged(A, n_t, max(orders), dtype, out=out, exp=ex)
+                    got = apm.decode_scaled(out, ex).cpu().numpy()
+                torch.cuda.synchronize()
+                assert np.all(info.cpu().numpy() >= 0)
+                for k, M in enumerate(mats):
+                    seg = got[ooff[k]:ooff[k] + (1 << M.shape[0])]
+                    masks, ref, H = refs[k]
+                    e = metrics.mixed_err(seg if masks is None else seg[masks], ref, H)
+                    assert e.max() <= tol, (dtype, ks, kl, M.shape[0], float(e.max()))
+    finally:
+        json.dump({"version": 1, "k0": {f"{arch}/{dtype}/mixed": default[0],
+                                        f"{arch}/{dtype}/mixed-large": default[1]}}, open(path, "w"))
+        apm.tune_cache_load(str(path))
+    assert apm.minors_k0_mixed(dtype) == default
