@@ -49,6 +49,9 @@ extern "C" {
  * parameter vector is packed W1 (128 x Dp) | W2 (128 x 128) | W3 (Op x 128) | b1 (128)
  * | b2 (128) | b3 (Op), matrices row-major [out][in]; padding rows/columns are zero and
  * stay zero under apm_mlp_adam.
+ * The BF16 copy w (read by the forward pass) holds each M x K matrix in matrix-core operand
+ * order: element (r, c) at ((r/16 (K/16) + c/16) 64 + 16 ((c % 16)/4) + r % 16) 4 + c % 4
+ * from the matrix's start (the same start as in param).  wt holds each transpose row-major.
  */
 typedef struct {
     int32_t d_in;             /* logical input size, 1..APM_MLP_MAX_IN                     */
@@ -57,7 +60,7 @@ typedef struct {
     float *grad;              /* same packing: written by apm_mlp_backward                 */
     float *adam_m;            /* same packing: Adam first moment (caller zeroes it once)   */
     float *adam_v;            /* same packing: Adam second moment (caller zeroes it once)  */
-    uint16_t *w;              /* [apm_mlp_weight_count] BF16 W1|W2|W3, row-major [out][in] */
+    uint16_t *w;              /* [apm_mlp_weight_count] BF16 W1|W2|W3, operand order above */
     uint16_t *wt;             /* [apm_mlp_weight_count] BF16 W1^T|W2^T|W3^T                */
 } apm_mlp;
 

@@ -69,6 +69,7 @@ struct McWork {
     double* logq;
     double* logc;
     double* summ;      // (c[V], d[V]) per walker, orders <= 12
+    uint64_t* draws;   // the step's Philox draws: calls 0 and 1 of every walker, 4 x uint64 each
     uint16_t* feat;
     float* logits;
     float* dout;
@@ -97,6 +98,7 @@ int64_t mc_layout(const apm_mc_model* m, int64_t W, bool with_net, char* base, M
     w.logq = reinterpret_cast<double*>(take(W * 8));
     w.logc = reinterpret_cast<double*>(take(W * 8));
     w.summ = reinterpret_cast<double*>(take(W * 16));
+    w.draws = reinterpret_cast<uint64_t*>(take(W * 64));
     if (with_net) {
         w.feat = reinterpret_cast<uint16_t*>(take(W * dp * 2));
         w.logits = reinterpret_cast<float*>(take(W * op * 4));
@@ -261,8 +263,8 @@ apm_status apm_mc_propose(const apm_mc_model* m, const apm_mc_chain* ch, uint64_
     if (logits && logit_stride < m->L * m->L + m->n_bin) return APM_EINVAL;
     if (ch->walkers == 0) return APM_OK;
     if (!moved || !proposed || !logq || !mats) return APM_EINVAL;
-    return from_hip(apm::mc_propose_launch(args_of(m, ch, seed, step), moved, logits, logit_stride, proposed, logq,
-                                           mats, (hipStream_t)stream));
+    return from_hip(apm::mc_propose_launch(args_of(m, ch, seed, step), moved, nullptr, logits, logit_stride, proposed,
+                                           logq, mats, (hipStream_t)stream));
 }
 
 apm_status apm_mc_accept(const apm_mc_model* m, const apm_mc_chain* ch, uint64_t seed, int32_t step,
@@ -305,11 +307,19 @@ apm_status apm_mc_step(const apm_mc_model* m, const apm_mc_chain* ch, const apm_
     uint32_t* prop = rec && rec->proposed ? rec->proposed : wk.prop;
     double* logq = rec && rec->logq ? rec->logq : wk.logq;
     double* logc = rec && rec->logc_prop ? rec->logc_prop : wk.logc;
-    const apm::McArgs a = args_of(m, ch, seed, step);
+    apm::McArgs a = args_of(m, ch, seed, step);
     const hipStream_t st = (hipStream_t)stream;
     const int dp = pad_in(3 * (m->n - 1)), op = pad_out(m->L * m->L + m->n_bin);
 
-    hipError_t e = apm::mc_context_launch(a, moved, net ? wk.feat : nullptr, dp, st);
+    // the first kernel that needs the step's draws (context with a network, else the
+    // proposal) computes both per walker and stores them; the later kernels read them
+    a.draws = wk.draws;
+    a.draws_ready = 0;
+    hipError_t e = hipSuccess;
+    if (net) {
+        e = apm::mc_context_launch(a, moved, wk.feat, dp, st);
+        a.draws_ready = 1;
+    }
     apm::MlpNet nt{};
     apm::MlpWork mw{};
     if (net) {
@@ -317,7 +327,11 @@ apm_status apm_mc_step(const apm_mc_model* m, const apm_mc_chain* ch, const apm_
         if (train) mw = apm::mlp_work_carve(wk.mlp, dp, op, W);
         if (e == hipSuccess) e = apm::mlp_forward_launch(nt, wk.feat, W, wk.logits, train ? &mw : nullptr, st);
     }
-    if (e == hipSuccess) e = apm::mc_propose_launch(a, moved, net ? wk.logits : nullptr, op, prop, logq, wk.mats, st);
+    // without a network the proposal kernel also draws the moved vertex
+    if (e == hipSuccess)
+        e = apm::mc_propose_launch(a, net ? moved : nullptr, net ? nullptr : moved, net ? wk.logits : nullptr, op, prop,
+                                   logq, wk.mats, st);
+    a.draws_ready = 1;
     if (e == hipSuccess) e = weights(a, wk, st);
     if (e == hipSuccess)
         e = apm::mc_accept_launch(a, moved, prop, logq, wk.csum, wk.minors, summ_of(a, wk), logc,

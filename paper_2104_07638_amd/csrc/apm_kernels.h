@@ -158,11 +158,19 @@ struct McArgs {
     int8_t* sign;
     uint64_t seed;
     int step;
+    // the step's draw table: draws 0 and 1 of walker w at entries 2 w and 2 w + 1, 4 x uint64
+    // each.  NULL: every kernel computes the draws it needs.  Otherwise the first kernel of
+    // the step that needs them computes and stores them (draws_ready = 0), the later ones
+    // read them (draws_ready = 1).
+    uint64_t* draws;
+    int draws_ready;
 };
 
 hipError_t mc_context_launch(const McArgs& a, int32_t* moved, uint16_t* feat, int dp, hipStream_t st);
-hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, const float* logits, int stride, uint32_t* prop,
-                             double* logq, double* mats, hipStream_t st);
+// moved_out != NULL: draw the moved vertex (as mc_context_launch does) into moved_out
+// instead of reading it from moved.
+hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, int32_t* moved_out, const float* logits,
+                             int stride, uint32_t* prop, double* logq, double* mats, hipStream_t st);
 hipError_t mc_gather_launch(const McArgs& a, double* mats, hipStream_t st);
 // summ (if not NULL): per-walker (c[V], d[V]) written by the connected-sum kernel; else
 // c[V] and d[V] are formed from the full c[] and minors arrays.

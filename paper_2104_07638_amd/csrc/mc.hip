@@ -48,6 +48,50 @@ __device__ __forceinline__ U4 draws(const McArgs& a, int w, int call)
     return philox((uint64_t)w, (uint64_t)(uint32_t)a.step, (uint64_t)call, 0ull, a.seed, 0ull);
 }
 
+__device__ __forceinline__ U4 load_draw(const uint64_t* p)
+{
+    const ulonglong2 lo = reinterpret_cast<const ulonglong2*>(p)[0], hi = reinterpret_cast<const ulonglong2*>(p)[1];
+    return {lo.x, lo.y, hi.x, hi.y};
+}
+
+// Walkers per workgroup of the per-walker kernels (one wavefront each).
+constexpr int kWgWalkers = 4;
+static_assert(64 * kWgWalkers == 256, "the per-walker kernels are launched with 256 threads");
+
+// Draws 0 and 1 of this wavefront's walker w = w0 + (wavefront index), in every lane.  Read
+// from the step's table when it is filled.  Otherwise lanes 0 .. 7 of wavefront 0 compute the
+// eight Philox chains of the workgroup at once (lane 2 i + c: walker w0 + i, call c), so the
+// workgroup pays for one chain instead of four; with a table they also store them there.
+// Called by every thread of the workgroup (it holds a barrier); walkers past a.W get nothing.
+__device__ __forceinline__ void wg_draws(const McArgs& a, int w0, U4& d0, U4& d1)
+{
+    const int wv = threadIdx.x >> 6;
+    if (a.draws && a.draws_ready) {
+        const int w = w0 + wv;
+        if (w < a.W) {
+            d0 = load_draw(a.draws + (size_t)w * 8);
+            d1 = load_draw(a.draws + (size_t)w * 8 + 4);
+        }
+        return;
+    }
+    __shared__ ulonglong2 sh[kWgWalkers * 2][2];
+    const int t = threadIdx.x;
+    if (t < 2 * kWgWalkers && w0 + (t >> 1) < a.W) {
+        const U4 d = draws(a, w0 + (t >> 1), t & 1);
+        sh[t][0] = make_ulonglong2(d.x, d.y);
+        sh[t][1] = make_ulonglong2(d.z, d.w);
+        if (a.draws) {
+            ulonglong2* p = reinterpret_cast<ulonglong2*>(a.draws + ((size_t)w0 * 2 + t) * 4);
+            p[0] = sh[t][0];
+            p[1] = sh[t][1];
+        }
+    }
+    __syncthreads();
+    const ulonglong2 a0 = sh[2 * wv][0], a1 = sh[2 * wv][1], b0 = sh[2 * wv + 1][0], b1 = sh[2 * wv + 1][1];
+    d0 = {a0.x, a0.y, a1.x, a1.y};
+    d1 = {b0.x, b0.y, b1.x, b1.y};
+}
+
 __device__ __forceinline__ int below(uint64_t r, int m) { return (int)__umul64hi(r, (uint64_t)m); }
 
 __device__ __forceinline__ double unif(uint64_t r) { return ((double)(r >> 12) + 0.5) * 0x1p-52; }
@@ -134,26 +178,32 @@ __device__ __forceinline__ double wave_scan(double v)
 __device__ __forceinline__ double wave_shr1(double v) { return dpp_d<0x138, 0xF, true>(0.0, v); }
 
 // Propagator matrix of walker w with vertex k replaced by vnew (k < 0: no replacement).
-// Vertices outside the grid give NaN entries (no table read).
+// Vertices outside the grid give NaN entries (no table read).  Lane i < n first unpacks
+// vertex i into (x, y, t), packed x | y << 8 | t << 16 (L <= 256, t < 2^15), or ~0 outside
+// the grid; each entry then takes the periodic differences of two such words.
 __device__ void gather(const McArgs& a, int w, int k, uint32_t vnew, double* __restrict__ mats)
 {
     const int lane = lane_id();
     const int n = a.n, L = a.L, L2 = L * L, nn = n * n;
-    uint32_t v = 0;
-    if (lane < n) v = (lane == k) ? vnew : a.state[(size_t)w * n + lane];
+    uint32_t xyt = 0xFFFFFFFFu;
+    if (lane < n) {
+        const uint32_t v = (lane == k) ? vnew : a.state[(size_t)w * n + lane];
+        const int s = (int)(v & 0xFFFFu), t = (int)(v >> 16);
+        if (s < L2 && t < a.n_tau) xyt = (uint32_t)(s % L) | ((uint32_t)(s / L) << 8) | ((uint32_t)t << 16);
+    }
     double* M = mats + (size_t)w * nn;
     for (int base = 0; base < nn; base += kWave) {
         const int e = base + lane;
-        const int i = e < nn ? e / n : 0, j = e < nn ? e % n : 0;
-        const uint32_t vi = __shfl(v, i), vj = __shfl(v, j);
+        const int i = e < nn ? e / n : 0, j = e < nn ? e - i * n : 0;
+        const uint32_t pi = (uint32_t)__shfl((int)xyt, i), pj = (uint32_t)__shfl((int)xyt, j);
         if (e < nn) {
-            const int si = (int)(vi & 0xFFFFu), ti = (int)(vi >> 16);
-            const int sj = (int)(vj & 0xFFFFu), tj = (int)(vj >> 16);
             double val = __builtin_nan("");
-            if (si < L2 && sj < L2 && ti < a.n_tau && tj < a.n_tau) {
-                const int dx = (si % L - sj % L + L) % L;
-                const int dy = (si / L - sj / L + L) % L;
-                const int d = ti - tj + a.n_tau - 1;
+            if (((pi | pj) >> 31) == 0) {
+                int dx = (int)(pi & 0xFFu) - (int)(pj & 0xFFu);
+                int dy = (int)((pi >> 8) & 0xFFu) - (int)((pj >> 8) & 0xFFu);
+                dx += dx < 0 ? L : 0;
+                dy += dy < 0 ? L : 0;
+                const int d = (int)(pi >> 16) - (int)(pj >> 16) + a.n_tau - 1;
                 val = a.g0[(size_t)d * L2 + dy * L + dx];
             }
             M[e] = val;
@@ -166,10 +216,11 @@ __global__ __launch_bounds__(256) void mc_context_kernel(McArgs a, int32_t* __re
                                                          uint16_t* __restrict__ feat, int dp)
 {
     const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int w = blockIdx.x * kWgWalkers + (threadIdx.x >> 6);
+    U4 d0, d1;
+    wg_draws(a, blockIdx.x * kWgWalkers, d0, d1);
     if (w >= a.W) return;
     const int n = a.n;
-    const U4 d0 = draws(a, w, 0);
     const int k = below(d0.x, n);
     if (lane == 0) moved[w] = k;
     if (!feat) return;
@@ -193,32 +244,44 @@ struct Dist {
     double mx, tot;   // max logit, sum of exp(logit - mx)
 };
 
-// log q~(v) of the mixed learned proposal from v's site and bin terms exp(logit - max) and
-// the normalisers
-__device__ __forceinline__ double log_qt(const McArgs& a, double es, double eb, Dist ds, Dist db, int per_bin)
+// log q~(old) - log q~(new) of the mixed learned proposal
+//   q~(v) = (1 - eps) (es / tot_s) (eb / tot_b) / per_bin + eps / (L^2 n_tau),
+// with es, eb the site and bin terms exp(logit - max) of v and tot_s, tot_b their sums.
+// Both are proportional to es eb + C with C = eps per_bin tot_s tot_b / ((1 - eps) L^2 n_tau),
+// so the ratio takes one logarithm; eps = 1 is the uniform proposal (ratio 1).
+__device__ __forceinline__ double log_q_ratio(const McArgs& a, double eso, double ebo, double esn, double ebn, Dist ds,
+                                              Dist db, int per_bin)
 {
-    const int L2 = a.L * a.L;
-    const double ps = es / ds.tot;
-    const double pb = eb / db.tot;
-    return log((1.0 - a.eps) * ps * pb / per_bin + a.eps / ((double)L2 * a.n_tau));
+    if (!(a.eps < 1.0)) return 0.0;
+    const double C = a.eps * (double)per_bin * ds.tot * db.tot / ((1.0 - a.eps) * ((double)(a.L * a.L) * a.n_tau));
+    return log((eso * ebo + C) / (esn * ebn + C));
 }
 
+// moved_out != NULL: the moved vertex is drawn here (as the context kernel draws it) and
+// written to moved_out; otherwise it is read from moved.
 __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t* __restrict__ moved,
+                                                         int32_t* __restrict__ moved_out,
                                                          const float* __restrict__ logits, int stride,
                                                          uint32_t* __restrict__ prop, double* __restrict__ logq,
                                                          double* __restrict__ mats)
 {
     const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int w = blockIdx.x * kWgWalkers + (threadIdx.x >> 6);
+    U4 d0, d1;
+    wg_draws(a, blockIdx.x * kWgWalkers, d0, d1);
     if (w >= a.W) return;
     const int n = a.n, L2 = a.L * a.L;
-    int k = moved[w];
-    if (k < 0 || k >= n) k = 0;
-    const U4 d0 = draws(a, w, 0);
+    int k;
+    if (moved_out) {
+        k = below(d0.x, n);
+        if (lane == 0) moved_out[w] = k;
+    } else {
+        k = moved[w];
+        if (k < 0 || k >= n) k = 0;
+    }
     int site = below(d0.z, L2), t = below(d0.w, a.n_tau);
     double lq = 0.0;
     if (logits) {
-        const U4 d1 = draws(a, w, 1);
         const float* lg = logits + (size_t)w * stride;
         const int per_bin = a.n_tau / a.n_bin;
         // site distribution: lane owns the contiguous block [j0, j1); up to kPc of its terms
@@ -287,8 +350,8 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
         };
         const int so = (int)(vk & 0xFFFFu) < L2 ? (int)(vk & 0xFFFFu) : 0;
         const int to = (int)(vk >> 16) < a.n_tau ? (int)(vk >> 16) : 0;
-        lq = log_qt(a, site_term(so), bin_term(to / per_bin), ds, db, per_bin) -
-             log_qt(a, site_term(site), bin_term(t / per_bin), ds, db, per_bin);
+        lq = log_q_ratio(a, site_term(so), bin_term(to / per_bin), site_term(site), bin_term(t / per_bin), ds, db,
+                         per_bin);
     }
     const uint32_t vnew = (uint32_t)site | ((uint32_t)t << 16);
     if (lane == 0) {
@@ -361,7 +424,7 @@ __global__ __launch_bounds__(256) void mc_accept_kernel(McArgs a, const int32_t*
     double lw = a.logw[w];
     int8_t sg = a.sign[w];
     const int k = moved[w];
-    const U4 d1 = draws(a, w, 1);
+    const U4 d1 = (a.draws && a.draws_ready) ? load_draw(a.draws + (size_t)w * 8 + 4) : draws(a, w, 1);
     const double logR = wt.lc - lw + logq[w];
     const bool acc = (k >= 0 && k < a.n) && wt.lc > -INFINITY && (!(lw > -INFINITY) || log(unif(d1.w)) < logR);
     if (acc) {
@@ -456,16 +519,17 @@ unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 hipError_t mc_context_launch(const McArgs& a, int32_t* moved, uint16_t* feat, int dp, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_context_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, moved, feat, dp);
+    hipLaunchKernelGGL(mc_context_kernel, dim3(blocks_for(a.W, kWgWalkers)), dim3(64 * kWgWalkers), 0, st, a, moved,
+                       feat, dp);
     return hipGetLastError();
 }
 
-hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, const float* logits, int stride, uint32_t* prop,
-                             double* logq, double* mats, hipStream_t st)
+hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, int32_t* moved_out, const float* logits,
+                             int stride, uint32_t* prop, double* logq, double* mats, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_propose_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, moved, logits, stride, prop,
-                       logq, mats);
+    hipLaunchKernelGGL(mc_propose_kernel, dim3(blocks_for(a.W, kWgWalkers)), dim3(64 * kWgWalkers), 0, st, a, moved,
+                       moved_out, logits, stride, prop, logq, mats);
     return hipGetLastError();
 }
 

@@ -11,6 +11,11 @@
 // every weight load); its wavefronts split each layer's output features and pass the
 // activations on through LDS.
 //
+// The forward pass reads its BF16 weights (net.w) in that A-operand order: for a layer of
+// M x K weights, tile (mt, ks) (rows 16 mt.., columns 16 ks..) is 64 lanes x 4 values stored
+// contiguously from ((mt (K / 16) + ks) 64 + lane) 4, so that one load instruction of a
+// wavefront reads 512 consecutive bytes (from row-major rows it would touch 16 cache lines).
+//
 // Backward: the hidden gradients are chained the same way through the transposed
 // weights (W^T kept as a second BF16 copy); the weight gradients dW = dZ^T H sum over
 // the batch, one wavefront per 16 x 16 tile of dW with the batch as the K dimension,
@@ -69,28 +74,53 @@ __device__ __forceinline__ void store_t(uint16_t* dst, int B, int f0, int r, v4s
 }
 
 // Forward pass: one workgroup of kFwdWaves wavefronts per 32 batch rows.  The wavefronts
-// split the output features of every layer (wave v computes hidden tiles 2v, 2v+1 and output
-// tiles v, v + kFwdWaves, ...) and exchange the BF16 activations through LDS between layers,
-// already in B-operand order.  Each wavefront needs only its slice of the weights and loads
-// all of it up front (straight from L2, one batch of independent loads), so the three
-// layers wait for memory once.
-constexpr int kFwdWaves = 4;
+// split the output features of every layer (wave v computes hidden tiles kMtPerWave v.. and
+// output tiles v, v + kFwdWaves, ...) and exchange the BF16 activations through LDS between
+// layers, already in B-operand order.  Each wavefront needs only its slice of the weights and
+// loads all of it up front (straight from L2, one batch of independent loads), so the three
+// layers wait for memory once.  The kernel is latency-bound (one workgroup per CU at the
+// Monte Carlo batch); eight wavefronts measured faster than four (fewer output tiles each).
+#ifndef APM_MLP_FWD_WAVES
+#define APM_MLP_FWD_WAVES 8
+#endif
+#ifndef APM_MLP_W3PRE
+#define APM_MLP_W3PRE 3
+#endif
+constexpr int kFwdWaves = APM_MLP_FWD_WAVES;   // 2, 4 or 8
 constexpr int kMtPerWave = 8 / kFwdWaves;
-constexpr int kW3Pre = 6;    // output tiles per wavefront whose weights are loaded up front
+constexpr int kW3Pre = APM_MLP_W3PRE;    // output tiles per wavefront whose weights are loaded up front
+static_assert(kFwdWaves == 2 || kFwdWaves == 4 || kFwdWaves == 8, "hidden tiles split evenly over the wavefronts");
+
+// This lane's A operands of row tile mt (k-steps 0..KS-1) of a layer, from the
+// fragment-ordered weights: one address per tile, the k-steps at constant offsets of 512 B.
+template <int KS>
+__device__ __forceinline__ void load_tile(const uint16_t* __restrict__ W, int mt, v4s (&a)[KS])
+{
+    const uint16_t* p = W + (size_t)(uint32_t)mt * (KS * 256) + (threadIdx.x & 63) * 4;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a[ks] = ld4(p + ks * 256);
+}
 
 template <int KS>
 __device__ __forceinline__ void load_slice(const uint16_t* __restrict__ W, int mt0, v4s (&a)[kMtPerWave][KS])
 {
-    const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int m = 0; m < kMtPerWave; ++m)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) a[m][ks] = ld4(W + (size_t)(16 * (mt0 + m) + r16) * (16 * KS) + 16 * ks + 4 * g);
+    for (int m = 0; m < kMtPerWave; ++m) load_tile<KS>(W, mt0 + m, a[m]);
 }
 
-// tanh(W in + b) for the hidden tiles mt0 .. mt0+kMtPerWave-1 of both row tiles
+// the biases of this lane's features 16 (mt0 + m) + 4 (lane / 16) + 0..3 of the hidden tiles
+// mt0 .. mt0+kMtPerWave-1
+__device__ __forceinline__ void load_bias(const float* __restrict__ b, int mt0, v4f (&bb)[kMtPerWave])
+{
+    const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int m = 0; m < kMtPerWave; ++m) bb[m] = *reinterpret_cast<const v4f*>(b + 16 * (mt0 + m) + 4 * g);
+}
+
+// tanh(W in + b) for the hidden tiles mt0 .. mt0+kMtPerWave-1 of both row tiles (bb: their
+// biases, from load_bias)
 template <int KS>
-__device__ __forceinline__ void hidden_slice(const v4s (&a)[kMtPerWave][KS], const float* __restrict__ b,
+__device__ __forceinline__ void hidden_slice(const v4s (&a)[kMtPerWave][KS], const v4f (&bb)[kMtPerWave],
                                              const v4s (&in)[2][KS], int mt0, v4s* act_out, int row0, int B,
                                              float* save, uint16_t* save_t)
 {
@@ -105,10 +135,9 @@ __device__ __forceinline__ void hidden_slice(const v4s (&a)[kMtPerWave][KS], con
             a1 = mfma(a[m][ks], in[1][ks], a1);
         }
         const int f0 = 16 * mt + 4 * g;
-        const v4f bb = *reinterpret_cast<const v4f*>(b + f0);
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-            const v4f z = (nt == 0 ? a0 : a1) + bb;
+            const v4f z = (nt == 0 ? a0 : a1) + bb[m];
             v4f h;
             h[0] = tanh_f(z[0]);
             h[1] = tanh_f(z[1]);
@@ -139,26 +168,38 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_fwd_kernel(const uint16_t*
     const uint16_t* W3 = W2 + H * H;
 
     const int ntile = Op / 16;
-    v4s w1[kMtPerWave][KS1], w2[kMtPerWave][8], w3[kW3Pre][8];
-    load_slice<KS1>(W1, kMtPerWave * wv, w1);
-    load_slice<8>(W2, kMtPerWave * wv, w2);
-#pragma unroll
-    for (int u = 0; u < kW3Pre; ++u) {
-        const int t = wv + u * kFwdWaves;
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks)
-            if (t < ntile) w3[u][ks] = ld4(W3 + (size_t)(16 * t + r16) * H + 16 * ks + 4 * g);
-    }
+    const float* b3 = bias + 2 * H;
+    // every input, weight and bias this wavefront uses (a slice of each layer) is requested up
+    // front, in the order the layers need them, so that each layer waits only for its own
+    // operands and the three layers wait for memory about once
     v4s xo[2][KS1];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-        for (int ks = 0; ks < KS1; ++ks) {
-            const int r = row0 + 16 * nt + r16;
-            xo[nt][ks] = ld4(x + (size_t)r * DP + 16 * ks + 4 * g);
-            if (actT && wv == 0) store_t(actT, B, 16 * ks + 4 * g, r, xo[nt][ks]);
-        }
-    hidden_slice<KS1>(w1, bias, xo, kMtPerWave * wv, act1, row0, B, h1s, actT ? actT + (size_t)DP * B : nullptr);
+        for (int ks = 0; ks < KS1; ++ks) xo[nt][ks] = ld4(x + (size_t)(row0 + 16 * nt + r16) * DP + 16 * ks + 4 * g);
+    v4s w1[kMtPerWave][KS1], w2[kMtPerWave][8], w3[kW3Pre][8];
+    v4f bb1[kMtPerWave], bb2[kMtPerWave], bb3[kW3Pre];
+    load_slice<KS1>(W1, kMtPerWave * wv, w1);
+    load_bias(bias, kMtPerWave * wv, bb1);
+    __builtin_amdgcn_sched_barrier(0);   // keep this issue order (the scheduler groups loads by size)
+    load_slice<8>(W2, kMtPerWave * wv, w2);
+    load_bias(bias + H, kMtPerWave * wv, bb2);
+    __builtin_amdgcn_sched_barrier(0);
+    // (tiles past the last one load the last tile again, unused: unconditional loads keep the
+    // compiler's count of loads in flight exact, so no wait covers more than it needs)
+#pragma unroll
+    for (int u = 0; u < kW3Pre; ++u) {
+        const int t = min(wv + u * kFwdWaves, ntile - 1);
+        load_tile<8>(W3, t, w3[u]);
+        bb3[u] = *reinterpret_cast<const v4f*>(b3 + 16 * t + 4 * g);
+    }
+    if (actT && wv == 0) {   // training: feature-major BF16 copy of the input
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int ks = 0; ks < KS1; ++ks) store_t(actT, B, 16 * ks + 4 * g, row0 + 16 * nt + r16, xo[nt][ks]);
+    }
+    hidden_slice<KS1>(w1, bb1, xo, kMtPerWave * wv, act1, row0, B, h1s, actT ? actT + (size_t)DP * B : nullptr);
     __syncthreads();
 
     v4s h1o[2][8];
@@ -166,8 +207,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_fwd_kernel(const uint16_t*
     for (int kt = 0; kt < 8; ++kt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) h1o[nt][kt] = act1[(kt * 2 + nt) * 64 + lane];
-    hidden_slice<8>(w2, bias + H, h1o, kMtPerWave * wv, act2, row0, B, h2s,
-                    actT ? actT + (size_t)(DP + H) * B : nullptr);
+    hidden_slice<8>(w2, bb2, h1o, kMtPerWave * wv, act2, row0, B, h2s, actT ? actT + (size_t)(DP + H) * B : nullptr);
     __syncthreads();
 
     v4s h2o[2][8];
@@ -175,8 +215,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_fwd_kernel(const uint16_t*
     for (int kt = 0; kt < 8; ++kt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) h2o[nt][kt] = act2[(kt * 2 + nt) * 64 + lane];
-    const float* b3 = bias + 2 * H;
-    auto out_tile = [&](int t, const v4s (&a)[8]) {
+    auto out_tile = [&](int t, const v4s (&a)[8], v4f bb) {
         v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
@@ -184,21 +223,19 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_fwd_kernel(const uint16_t*
             a1 = mfma(a[ks], h2o[1][ks], a1);
         }
         const int f0 = 16 * t + 4 * g;
-        const v4f bb = *reinterpret_cast<const v4f*>(b3 + f0);
         *reinterpret_cast<v4f*>(out + (size_t)(row0 + r16) * Op + f0) = a0 + bb;
         *reinterpret_cast<v4f*>(out + (size_t)(row0 + 16 + r16) * Op + f0) = a1 + bb;
     };
 #pragma unroll
     for (int u = 0; u < kW3Pre; ++u) {
         const int t = wv + u * kFwdWaves;
-        if (t < ntile) out_tile(t, w3[u]);
+        if (t < ntile) out_tile(t, w3[u], bb3[u]);
     }
     // tiles beyond the preloaded ones (wide output layers)
     for (int t = wv + kW3Pre * kFwdWaves; t < ntile; t += kFwdWaves) {
         v4s a[8];
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) a[ks] = ld4(W3 + (size_t)(16 * t + r16) * H + 16 * ks + 4 * g);
-        out_tile(t, a);
+        load_tile<8>(W3, t, a);
+        out_tile(t, a, *reinterpret_cast<const v4f*>(b3 + 16 * t + 4 * g));
     }
 }
 
@@ -355,19 +392,21 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ p, co
     const int64_t s2 = (int64_t)H * DP, s3 = s2 + H * H, nw = s3 + (int64_t)Op * H;
     if (i < nw) {
         const uint16_t bits = f2bf(x);
-        w[i] = bits;
-        int64_t ti;
+        // element (row, col) of the M x K layer at `base`: fragment copy at
+        // ((row/16 (K/16) + col/16) 64 + lane) 4 + col % 4, lane = 16 ((col % 16) / 4) + row % 16;
+        // transposed copy at col M + row
+        int64_t base, K, M;
         if (i < s2) {
-            const int64_t row = i / DP, col = i % DP;
-            ti = col * H + row;
+            base = 0, K = DP, M = H;
         } else if (i < s3) {
-            const int64_t l = i - s2, row = l / H, col = l % H;
-            ti = s2 + col * H + row;
+            base = s2, K = H, M = H;
         } else {
-            const int64_t l = i - s3, row = l / H, col = l % H;
-            ti = s3 + col * Op + row;
+            base = s3, K = H, M = Op;
         }
-        wt[ti] = bits;
+        const int64_t row = (i - base) / K, col = (i - base) % K;
+        const int64_t lane = 16 * ((col & 15) >> 2) + (row & 15);
+        w[base + (((row >> 4) * (K >> 4) + (col >> 4)) * 64 + lane) * 4 + (col & 3)] = bits;
+        wt[base + col * M + row] = bits;
     }
 }
 

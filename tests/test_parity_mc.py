@@ -60,6 +60,18 @@ def _relf(a, b):
 
 
 # ------------------------------------------------------------------ network
+def _operand_order(w, dp, op, H=128):
+    """The packed row-major W1 | W2 | W3 rearranged into the matrix-core operand order of
+    the BF16 forward copy: per 16 x 16 tile (row-major over tiles), lane l = 16 g + r holds
+    the 4 entries (r, 4 g .. 4 g + 3) of the tile."""
+    out, off = [], 0
+    for M, K in ((H, dp), (H, H), (op, H)):
+        m = w[off:off + M * K].reshape(M // 16, 16, K // 16, 4, 4)   # (mt, r, ks, g, j)
+        out.append(m.transpose(0, 2, 3, 1, 4).reshape(-1))             # (mt, ks, g, r, j)
+        off += M * K
+    return np.concatenate(out)
+
+
 @pytest.mark.parametrize("d_in,d_out,B", [(6, 8, 32), (27, 272, 256), (45, 1040, 64), (64, 4096, 32),
                                           (27, 272, 8192)])
 def test_mlp_forward(apm, d_in, d_out, B):
@@ -69,11 +81,12 @@ def test_mlp_forward(apm, d_in, d_out, B):
     out = net.forward(_bf(x)).cpu().numpy()
     ref, _ = omlp.forward(p.astype(np.float64), x, d_in, d_out)
     assert _relf(out, ref) <= 5e-3
-    # the BF16 weight copies are the rounded master parameters, and wt their transposes
+    # the BF16 weight copies are the rounded master parameters (in operand order), and wt
+    # their transposes
     nw = apm.apm_mlp_weight_count(d_in, d_out)
-    w = net.w.float().cpu().numpy().astype(np.float64)
-    np.testing.assert_array_equal(w, omlp.bf16(p[:nw]))
     dp, op = omlp.dims(d_in, d_out)
+    w = omlp.bf16(p[:nw])
+    np.testing.assert_array_equal(net.w.float().cpu().numpy().astype(np.float64), _operand_order(w, dp, op))
     H = 128
     wt = net.wt.float().cpu().numpy().astype(np.float64)
     np.testing.assert_array_equal(wt[:H * dp].reshape(dp, H), w[:H * dp].reshape(H, dp).T)
@@ -134,7 +147,9 @@ def test_mlp_adam(apm):
         assert np.all(err <= 1e-6 + 1e-4 * np.abs(dp_ref)), err.max()
         po = got          # continue from the GPU's parameters (fp32 state)
     nw = apm.apm_mlp_weight_count(d_in, d_out)
-    np.testing.assert_array_equal(net.w.float().cpu().numpy(), omlp.bf16(net.param.cpu().numpy()[:nw]))
+    dp, op = omlp.dims(d_in, d_out)
+    np.testing.assert_array_equal(net.w.float().cpu().numpy(),
+                                  _operand_order(omlp.bf16(net.param.cpu().numpy()[:nw]), dp, op))
 
 
 # ------------------------------------------------------------------ Monte Carlo pieces
