@@ -291,12 +291,13 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
         double mx = -INFINITY;
         for (int j = j0; j < j1; ++j) mx = fmax(mx, (double)lg[j]);
         mx = wave_max_d(mx);
-        constexpr int kPc = 8;
+        constexpr int kPc = 4;   // P at L = 16; a lane evaluates only the terms it owns
         double pc[kPc];
         double part = 0.0;
 #pragma unroll
         for (int u = 0; u < kPc; ++u) {
-            pc[u] = j0 + u < j1 ? exp((double)lg[j0 + u] - mx) : 0.0;
+            pc[u] = 0.0;
+            if (j0 + u < j1) pc[u] = exp((double)lg[j0 + u] - mx);
             part += pc[u];
         }
         for (int j = j0 + kPc; j < j1; ++j) part += exp((double)lg[j] - mx);
@@ -313,17 +314,17 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
             const double tg = unif(d1.x) * ds.tot;
             int cand = 0x7FFFFFFF, lastpos = -1;
             double run = excl;
-            for (int j = j0; j < j1; ++j) {
-                double p = 0.0;
-#pragma unroll
-                for (int u = 0; u < kPc; ++u) p = (j == j0 + u) ? pc[u] : p;
-                if (j >= j0 + kPc) p = exp((double)lg[j] - mx);
+            auto visit = [&](int j, double p) {
                 run += p;
                 if (p > 0.0) {
                     lastpos = j;
                     if (run > tg && cand == 0x7FFFFFFF) cand = j;
                 }
-            }
+            };
+#pragma unroll
+            for (int u = 0; u < kPc; ++u)
+                if (j0 + u < j1) visit(j0 + u, pc[u]);
+            for (int j = j0 + kPc; j < j1; ++j) visit(j, exp((double)lg[j] - mx));
             site = wave_min_i(cand);
             if (site == 0x7FFFFFFF) site = wave_max_i(lastpos);
             const double tgb = unif(d1.y) * db.tot;
@@ -333,17 +334,9 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
             t = b * per_bin + below(d1.z, per_bin);
         }
         const uint32_t vk = a.state[(size_t)w * n + k];
-        // the exp terms of the old and the new site and bin, taken from the lanes that hold
-        // them (the same values as recomputing them)
-        auto site_term = [&](int sj) {
-            double mine = 0.0;
-#pragma unroll
-            for (int u = 0; u < kPc; ++u) mine = (sj == j0 + u) ? pc[u] : mine;
-            const int owner = sj / P;   // uniform: sj is the same in every lane
-            const double r = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mine), owner),
-                                              __builtin_amdgcn_readlane(__double2loint(mine), owner));
-            return sj - owner * P < kPc ? r : exp((double)lg[sj] - ds.mx);
-        };
+        // the exp terms of the old and the new site (recomputed: the same values the owning
+        // lanes hold) and bin (taken from the lane that holds it)
+        auto site_term = [&](int sj) { return exp((double)lg[sj] - ds.mx); };
         auto bin_term = [&](int bj) {
             return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(pbl), bj),
                                     __builtin_amdgcn_readlane(__double2loint(pbl), bj));

@@ -227,9 +227,10 @@ def _boundary_ok(model, logits_row, u_site, u_bin):
     return out
 
 
-@pytest.mark.parametrize("gain", [1.0, 6.0])
-def test_mc_propose_learned(apm, gain):
-    s = _Setup(apm, CFG5, 2048, seed=8)
+@pytest.mark.parametrize("gain,W", [(1.0, 2048), (6.0, 2048), (6.0, 1000)])
+def test_mc_propose_learned(apm, gain, W):
+    # W = 1000: the sampler's last workgroup holds 8 walkers and its last wavefront none
+    s = _Setup(apm, CFG5, W, seed=8)
     p = _params(s.model.d_in, s.model.d_out, seed=31, gain=gain)
     moved, _ = _context(apm, s, 17, 2, with_feat=False)
     d0, d1 = omc.draws(17, s.W, 2)
@@ -248,6 +249,34 @@ def test_mc_propose_learned(apm, gain):
     new = s.states.copy()
     new[np.arange(s.W), k] = got
     np.testing.assert_array_equal(mats.cpu().numpy(), omc.matrices(s.model, s.g0, new))
+
+
+@pytest.mark.parametrize("gain", [1.0, 6.0])
+def test_mc_step_learned_proposals(apm, gain):
+    """The proposals of one learned apm_mc_step (the draws shared through the step's table,
+    the sampler on four walkers per wavefront) against the oracle's sampler on the same
+    logits (the network's forward pass on the context features, which are bit-exact)."""
+    model = wl.McModel(n=10, L=16, mu=0.0, beta=4.0, n_tau=128, n_bin=16, eps=0.1)
+    s = _Setup(apm, model, 1056, seed=9)
+    p = _params(model.d_in, model.d_out, seed=51, gain=gain)
+    net = apm.Mlp(model.d_in, model.d_out, p)
+    work = apm.mc_work(s.m, s.W, True)
+    apm.mc_evaluate(s.m, s.chain, work)
+    rec = apm.McRecord(s.W)
+    apm.mc_step(s.m, s.chain, work, seed=13, step=5, net=net, record=rec)
+    d0, d1 = omc.draws(13, s.W, 5)
+    k = omc.moved_vertex(model, d0)
+    np.testing.assert_array_equal(rec.moved.cpu().numpy(), k)
+    feat = omc.features(model, omc.context(model, s.states, k))
+    logits = net.forward(_bf(feat)).cpu().numpy()
+    pr, lq = omc.propose(model, s.states, k, d0, d1, logits.astype(np.float64))
+    got = rec.proposed.cpu().numpy().view(np.uint32)
+    for w in np.nonzero(got != pr)[0]:
+        assert _boundary_ok(model, logits[w].astype(np.float64), philox.uniform(d1[w, 0]),
+                            philox.uniform(d1[w, 1])), w
+    same = got == pr
+    assert same.sum() >= s.W - 2
+    np.testing.assert_allclose(rec.logq.cpu().numpy()[same], lq[same], rtol=1e-12, atol=1e-12)
 
 
 def _accept_check(s, seed, step, k, prop_u32, logq, logw, logw_tol, acc_gpu, lc_gpu):
