@@ -361,24 +361,29 @@ __global__ __launch_bounds__(256) void mc_gather_kernel(McArgs a, double* __rest
     gather(a, w, -1, 0u, mats);
 }
 
-// log|c[V]| and the sign of c[V] for walker w, or (-inf, 0) when c[V] is zero, not
-// finite, or (resolve > 0) below resolve * d[V] with
-//     d[V] = |a[V]| + sum_{T containing vertex 0, T != V} |c[T]| |a[V \ T]|,  a = m^2,
-// the rounding scale of the recursion at V.  Called by a whole wavefront.
 struct Wt {
     double lc;
     int8_t sg;
 };
 
+// full_weight (below) from the (c[V], d[V]) pair of walker w that the connected-sum kernel
+// wrote; one lane.
+__device__ __forceinline__ Wt summ_weight(const McArgs& a, int w, const double* __restrict__ summ)
+{
+    const double cv = summ[2 * w], dv = summ[2 * w + 1];
+    const bool ok = isfinite(cv) && cv != 0.0 && !(a.resolve > 0.0 && !(fabs(cv) >= a.resolve * dv));
+    return ok ? Wt{log(fabs(cv)), cv > 0.0 ? (int8_t)1 : (int8_t)-1} : Wt{-INFINITY, (int8_t)0};
+}
+
+// log|c[V]| and the sign of c[V] for walker w, or (-inf, 0) when c[V] is zero, not
+// finite, or (resolve > 0) below resolve * d[V] with
+//     d[V] = |a[V]| + sum_{T containing vertex 0, T != V} |c[T]| |a[V \ T]|,  a = m^2,
+// the rounding scale of the recursion at V.  Called by a whole wavefront.
 __device__ Wt full_weight(const McArgs& a, int w, const double* __restrict__ c, const double* __restrict__ m,
                          const double* __restrict__ summ)
 {
     const int lane = lane_id();
-    if (summ) {
-        const double cv = summ[2 * w], dv = summ[2 * w + 1];
-        const bool ok = isfinite(cv) && cv != 0.0 && !(a.resolve > 0.0 && !(fabs(cv) >= a.resolve * dv));
-        return ok ? Wt{log(fabs(cv)), cv > 0.0 ? (int8_t)1 : (int8_t)-1} : Wt{-INFINITY, (int8_t)0};
-    }
+    if (summ) return summ_weight(a, w, summ);
     const uint32_t nm = 1u << a.n, V = nm - 1u;
     const double* cw = c + (size_t)w * nm;
     const double* mw = m + (size_t)w * nm;
@@ -401,19 +406,11 @@ __device__ Wt full_weight(const McArgs& a, int w, const double* __restrict__ c, 
     return ok ? Wt{log(fabs(cv)), cv > 0.0 ? (int8_t)1 : (int8_t)-1} : Wt{-INFINITY, (int8_t)0};
 }
 
-// acceptance test and state update; one wavefront per walker
-__global__ __launch_bounds__(256) void mc_accept_kernel(McArgs a, const int32_t* __restrict__ moved,
-                                                        const uint32_t* __restrict__ prop,
-                                                        const double* __restrict__ logq,
-                                                        const double* __restrict__ c,
-                                                        const double* __restrict__ minors,
-                                                        const double* __restrict__ summ, double* logc_out,
-                                                        uint8_t* acc_out, float* obs_logw, int8_t* obs_sign)
+// Acceptance test and state update of walker w, given the weight of its proposal.
+__device__ __forceinline__ void accept_one(const McArgs& a, int w, Wt wt, const int32_t* __restrict__ moved,
+                                           const uint32_t* __restrict__ prop, const double* __restrict__ logq,
+                                           double* logc_out, uint8_t* acc_out, float* obs_logw, int8_t* obs_sign)
 {
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= a.W) return;
-    const Wt wt = full_weight(a, w, c, minors, summ);
-    if (lane_id() != 0) return;
     double lw = a.logw[w];
     int8_t sg = a.sign[w];
     const int k = moved[w];
@@ -431,6 +428,33 @@ __global__ __launch_bounds__(256) void mc_accept_kernel(McArgs a, const int32_t*
     if (acc_out) acc_out[w] = acc ? 1 : 0;
     if (obs_logw) obs_logw[w] = (float)lw;
     if (obs_sign) obs_sign[w] = sg;
+}
+
+// one wavefront per walker (the weight reduced over c[] and the minors)
+__global__ __launch_bounds__(256) void mc_accept_kernel(McArgs a, const int32_t* __restrict__ moved,
+                                                        const uint32_t* __restrict__ prop,
+                                                        const double* __restrict__ logq,
+                                                        const double* __restrict__ c,
+                                                        const double* __restrict__ minors, double* logc_out,
+                                                        uint8_t* acc_out, float* obs_logw, int8_t* obs_sign)
+{
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.W) return;
+    const Wt wt = full_weight(a, w, c, minors, nullptr);
+    if (lane_id() != 0) return;
+    accept_one(a, w, wt, moved, prop, logq, logc_out, acc_out, obs_logw, obs_sign);
+}
+
+// one lane per walker, with (c[V], d[V]) per walker from the connected-sum kernel
+__global__ __launch_bounds__(256) void mc_accept_summ_kernel(McArgs a, const int32_t* __restrict__ moved,
+                                                             const uint32_t* __restrict__ prop,
+                                                             const double* __restrict__ logq,
+                                                             const double* __restrict__ summ, double* logc_out,
+                                                             uint8_t* acc_out, float* obs_logw, int8_t* obs_sign)
+{
+    const int w = blockIdx.x * 256 + threadIdx.x;
+    if (w >= a.W) return;
+    accept_one(a, w, summ_weight(a, w, summ), moved, prop, logq, logc_out, acc_out, obs_logw, obs_sign);
 }
 
 __global__ __launch_bounds__(256) void mc_set_kernel(McArgs a, const double* __restrict__ c,
@@ -538,8 +562,12 @@ hipError_t mc_accept_launch(const McArgs& a, const int32_t* moved, const uint32_
                             uint8_t* acc_out, float* obs_logw, int8_t* obs_sign, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_accept_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, moved, prop, logq, c, minors,
-                       summ, logc_out, acc_out, obs_logw, obs_sign);
+    if (summ)
+        hipLaunchKernelGGL(mc_accept_summ_kernel, dim3(blocks_for(a.W, 256)), dim3(256), 0, st, a, moved, prop, logq,
+                           summ, logc_out, acc_out, obs_logw, obs_sign);
+    else
+        hipLaunchKernelGGL(mc_accept_kernel, dim3(blocks_for(a.W, 4)), dim3(256), 0, st, a, moved, prop, logq, c,
+                           minors, logc_out, acc_out, obs_logw, obs_sign);
     return hipGetLastError();
 }
 
