@@ -473,23 +473,41 @@ __device__ void cs_problem(const CsArgs& g, int64_t base, int j, bool zero_even,
     // one 16-byte load per x stages both (the block's own b is staged later otherwise)
     constexpr bool kOneBlock = CP::TB == 0;
     const bool pair_stage = kOneBlock && j == 0 && !(base & 1);
-    if (pair_stage) {
-        for (int x1 = act ? tid : (1 << P); x1 < (1 << P); x1 += NT) {
-            const double2 u = *reinterpret_cast<const double2*>(g.up + base + 2 * x1);
-            double w0, w1;
-            if (g.weights) {
-                w0 = u.x;
-                w1 = u.y;
-            } else if (g.dn) {
-                const double2 d = *reinterpret_cast<const double2*>(g.dn + base + 2 * x1);
-                w0 = u.x * d.x;
-                w1 = u.y * d.y;
-            } else {
-                w0 = u.x * u.x;
-                w1 = u.y * u.y;
+    if (pair_stage && act) {
+        // the loads of CH entries are issued before their stores (one memory round trip per
+        // CH entries instead of per entry)
+        constexpr int N = 1 << P, IT = (N + NT - 1) / NT, CH = IT < 4 ? IT : 4;
+        const bool two = !g.weights && g.dn;
+#pragma unroll
+        for (int i0 = 0; i0 < IT; i0 += CH) {
+            double2 u[CH], d[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int x1 = tid + (i0 + i) * NT;
+                if (x1 < N) {
+                    u[i] = *reinterpret_cast<const double2*>(g.up + base + 2 * x1);
+                    if (two) d[i] = *reinterpret_cast<const double2*>(g.dn + base + 2 * x1);
+                }
             }
-            lds_b[sw<LB, kPad>(x1)] = x1 ? w0 : 0.0;
-            rhs[sw<LB, kRPad>(x1)] = w1;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int x1 = tid + (i0 + i) * NT;
+                if (x1 < N) {
+                    double w0, w1;
+                    if (g.weights) {
+                        w0 = u[i].x;
+                        w1 = u[i].y;
+                    } else if (two) {
+                        w0 = u[i].x * d[i].x;
+                        w1 = u[i].y * d[i].y;
+                    } else {
+                        w0 = u[i].x * u[i].x;
+                        w1 = u[i].y * u[i].y;
+                    }
+                    lds_b[sw<LB, kPad>(x1)] = x1 ? w0 : 0.0;
+                    rhs[sw<LB, kRPad>(x1)] = w1;
+                }
+            }
         }
     }
     for (int x2 = 0; x2 < (1 << CP::TB); ++x2) {
