@@ -443,6 +443,26 @@ def test_mc_uniform_chain(apm, resolve):
     assert live.sum() >= s.W - 4
 
 
+def test_mc_step_ragged_workgroup(apm):
+    """A walker count that leaves the last workgroup of the per-walker kernels partly empty
+    (1001 = 4 x 250 + 1): the moved vertices, proposals and their draws (shared within a
+    workgroup and passed on through the step's table) against the oracle over two steps."""
+    model = wl.McModel(n=10, L=16, t=1.0, mu=0.0, beta=4.0, n_tau=128, n_bin=16, eps=0.1)
+    s = _Setup(apm, model, 1001, seed=12)
+    work = apm.mc_work(s.m, s.W, False)
+    apm.mc_evaluate(s.m, s.chain, work)
+    rec = apm.McRecord(s.W, loss=False)
+    for step in range(2):
+        states = s.state_np().copy()
+        apm.mc_step(s.m, s.chain, work, seed=77, step=step, record=rec)
+        d0, d1 = omc.draws(77, s.W, step)
+        k = omc.moved_vertex(model, d0)
+        np.testing.assert_array_equal(rec.moved.cpu().numpy(), k)
+        pr, _ = omc.propose(model, states, k, d0, d1, None)
+        np.testing.assert_array_equal(rec.proposed.cpu().numpy().view(np.uint32), pr)
+        assert np.all(rec.logq.cpu().numpy() == 0.0)
+
+
 def test_mc_training_step_gradient(apm):
     """One training step with eps = 1 (the proposals are the uniform ones, so the GPU and
     the oracle train on identical data): the GPU gradient against the oracle's."""
