@@ -54,29 +54,35 @@ __device__ __forceinline__ U4 load_draw(const uint64_t* p)
     return {lo.x, lo.y, hi.x, hi.y};
 }
 
-// Walkers per workgroup of the per-walker kernels (one wavefront each).
+// Walkers per workgroup (256 threads) of the per-walker kernels: one wavefront per walker
+// (kWgWalkers), or a group of 16 lanes per walker (kGrpWalkers) where a walker's work is
+// small.
 constexpr int kWgWalkers = 4;
+constexpr int kGrpWalkers = 16;
 static_assert(64 * kWgWalkers == 256, "the per-walker kernels are launched with 256 threads");
 
-// Draws 0 and 1 of this wavefront's walker w = w0 + (wavefront index), in every lane.  Read
-// from the step's table when it is filled.  Otherwise lanes 0 .. 7 of wavefront 0 compute the
-// eight Philox chains of the workgroup at once (lane 2 i + c: walker w0 + i, call c), so the
-// workgroup pays for one chain instead of four; with a table they also store them there.
-// Called by every thread of the workgroup (it holds a barrier); walkers past a.W get nothing.
+// Draws 0 and 1 of the calling thread's walker w = w0 + threadIdx.x / (256 / WPG) (WPG walkers
+// per workgroup), in every lane.  Read from the step's table when it is filled.  Otherwise
+// lanes 0 .. 2 WPG - 1 of wavefront 0 compute the workgroup's 2 WPG Philox chains at once
+// (lane 2 i + c: walker w0 + i, call c), so the workgroup pays for one chain instead of WPG;
+// with a table they also store them there.  Called by every thread of the workgroup (it holds
+// a barrier); walkers past a.W get nothing.
+template <int WPG>
 __device__ __forceinline__ void wg_draws(const McArgs& a, int w0, U4& d0, U4& d1)
 {
-    const int wv = threadIdx.x >> 6;
+    static_assert(2 * WPG <= 64, "the chains fit one wavefront");
+    const int wi = threadIdx.x / (256 / WPG);
     if (a.draws && a.draws_ready) {
-        const int w = w0 + wv;
+        const int w = w0 + wi;
         if (w < a.W) {
             d0 = load_draw(a.draws + (size_t)w * 8);
             d1 = load_draw(a.draws + (size_t)w * 8 + 4);
         }
         return;
     }
-    __shared__ ulonglong2 sh[kWgWalkers * 2][2];
+    __shared__ ulonglong2 sh[WPG * 2][2];
     const int t = threadIdx.x;
-    if (t < 2 * kWgWalkers && w0 + (t >> 1) < a.W) {
+    if (t < 2 * WPG && w0 + (t >> 1) < a.W) {
         const U4 d = draws(a, w0 + (t >> 1), t & 1);
         sh[t][0] = make_ulonglong2(d.x, d.y);
         sh[t][1] = make_ulonglong2(d.z, d.w);
@@ -87,7 +93,7 @@ __device__ __forceinline__ void wg_draws(const McArgs& a, int w0, U4& d0, U4& d1
         }
     }
     __syncthreads();
-    const ulonglong2 a0 = sh[2 * wv][0], a1 = sh[2 * wv][1], b0 = sh[2 * wv + 1][0], b1 = sh[2 * wv + 1][1];
+    const ulonglong2 a0 = sh[2 * wi][0], a1 = sh[2 * wi][1], b0 = sh[2 * wi + 1][0], b1 = sh[2 * wi + 1][1];
     d0 = {a0.x, a0.y, a1.x, a1.y};
     d1 = {b0.x, b0.y, b1.x, b1.y};
 }
@@ -177,25 +183,27 @@ __device__ __forceinline__ double wave_scan(double v)
 // v of lane i - 1 (0 in lane 0): wave_shr:1
 __device__ __forceinline__ double wave_shr1(double v) { return dpp_d<0x138, 0xF, true>(0.0, v); }
 
-// Propagator matrix of walker w with vertex k replaced by vnew (k < 0: no replacement).
-// Vertices outside the grid give NaN entries (no table read).  Lane i < n first unpacks
-// vertex i into (x, y, t), packed x | y << 8 | t << 16 (L <= 256, t < 2^15), or ~0 outside
-// the grid; each entry then takes the periodic differences of two such words.
-__device__ void gather(const McArgs& a, int w, int k, uint32_t vnew, double* __restrict__ mats)
+// Propagator matrix of walker w with vertex k replaced by vnew (k < 0: no replacement),
+// by a group of G lanes (G divides 64, all of them active).  Vertices outside the grid give
+// NaN entries (no table read).  Lane i < n of the group first unpacks vertex i into
+// (x, y, t), packed x | y << 8 | t << 16 (L <= 256, t < 2^15), or ~0 outside the grid; each
+// entry then takes the periodic differences of two such words.
+template <int G>
+__device__ void gather_grp(const McArgs& a, int w, int k, uint32_t vnew, double* __restrict__ mats)
 {
-    const int lane = lane_id();
+    const int r = threadIdx.x & (G - 1), gbase = (int)(threadIdx.x & 63) & ~(G - 1);
     const int n = a.n, L = a.L, L2 = L * L, nn = n * n;
     uint32_t xyt = 0xFFFFFFFFu;
-    if (lane < n) {
-        const uint32_t v = (lane == k) ? vnew : a.state[(size_t)w * n + lane];
+    if (r < n) {
+        const uint32_t v = (r == k) ? vnew : a.state[(size_t)w * n + r];
         const int s = (int)(v & 0xFFFFu), t = (int)(v >> 16);
         if (s < L2 && t < a.n_tau) xyt = (uint32_t)(s % L) | ((uint32_t)(s / L) << 8) | ((uint32_t)t << 16);
     }
     double* M = mats + (size_t)w * nn;
-    for (int base = 0; base < nn; base += kWave) {
-        const int e = base + lane;
+    for (int base = 0; base < nn; base += G) {
+        const int e = base + r;
         const int i = e < nn ? e / n : 0, j = e < nn ? e - i * n : 0;
-        const uint32_t pi = (uint32_t)__shfl((int)xyt, i), pj = (uint32_t)__shfl((int)xyt, j);
+        const uint32_t pi = (uint32_t)__shfl((int)xyt, gbase + i, 64), pj = (uint32_t)__shfl((int)xyt, gbase + j, 64);
         if (e < nn) {
             double val = __builtin_nan("");
             if (((pi | pj) >> 31) == 0) {
@@ -211,33 +219,34 @@ __device__ void gather(const McArgs& a, int w, int k, uint32_t vnew, double* __r
     }
 }
 
-// moved vertex and (optionally) BF16 context features; one wavefront per walker
+// moved vertex and (optionally) BF16 context features; 16 lanes per walker (n <= 16)
 __global__ __launch_bounds__(256) void mc_context_kernel(McArgs a, int32_t* __restrict__ moved,
                                                          uint16_t* __restrict__ feat, int dp)
 {
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * kWgWalkers + (threadIdx.x >> 6);
+    constexpr int G = 256 / kGrpWalkers;
+    const int r = threadIdx.x & (G - 1), gbase = (int)(threadIdx.x & 63) & ~(G - 1);
+    const int w = blockIdx.x * kGrpWalkers + threadIdx.x / G;
     U4 d0, d1;
-    wg_draws(a, blockIdx.x * kWgWalkers, d0, d1);
-    if (w >= a.W) return;
+    wg_draws<kGrpWalkers>(a, blockIdx.x * kGrpWalkers, d0, d1);
+    if (w >= a.W) return;   // whole groups
     const int n = a.n;
     const int k = below(d0.x, n);
-    if (lane == 0) moved[w] = k;
+    if (r == 0) moved[w] = k;
     if (!feat) return;
-    const uint32_t v = lane < n ? a.state[(size_t)w * n + lane] : 0xFFFFFFFFu;
+    const uint32_t v = r < n ? a.state[(size_t)w * n + r] : 0xFFFFFFFFu;
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-        const uint32_t vj = (uint32_t)__builtin_amdgcn_readlane((int)v, j);
-        if (j != k && j != lane && (vj < v || (vj == v && j < lane))) ++rank;
+        const uint32_t vj = (uint32_t)__shfl((int)v, gbase + j, 64);
+        if (j != k && j != r && (vj < v || (vj == v && j < r))) ++rank;
     }
     uint16_t* f = feat + (size_t)w * dp;
-    if (lane < n && lane != k) {
+    if (r < n && r != k) {
         const int s = (int)(v & 0xFFFFu), t = (int)(v >> 16);
         f[3 * rank + 0] = f2bf((float)(s % a.L) / (float)a.L);
         f[3 * rank + 1] = f2bf((float)(s / a.L) / (float)a.L);
         f[3 * rank + 2] = f2bf(((float)t + 0.5f) / (float)a.n_tau);
     }
-    for (int q = 3 * (n - 1) + lane; q < dp; q += kWave) f[q] = 0;
+    for (int q = 3 * (n - 1) + r; q < dp; q += G) f[q] = 0;
 }
 
 struct Dist {
@@ -257,10 +266,41 @@ __device__ __forceinline__ double log_q_ratio(const McArgs& a, double eso, doubl
     return log((eso * ebo + C) / (esn * ebn + C));
 }
 
+// The uniform proposal (site and time point uniform, log q ratio 0) and its matrices, one
+// wavefront per walker (groups of 16 lanes measured no faster: the gather dominates).
 // moved_out != NULL: the moved vertex is drawn here (as the context kernel draws it) and
 // written to moved_out; otherwise it is read from moved.
-__global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t* __restrict__ moved,
-                                                         int32_t* __restrict__ moved_out,
+__global__ __launch_bounds__(256) void mc_propose_uniform_kernel(McArgs a, const int32_t* __restrict__ moved,
+                                                                 int32_t* __restrict__ moved_out,
+                                                                 uint32_t* __restrict__ prop,
+                                                                 double* __restrict__ logq, double* __restrict__ mats)
+{
+    constexpr int G = 256 / kWgWalkers;
+    const int r = threadIdx.x & (G - 1);
+    const int w = blockIdx.x * kWgWalkers + threadIdx.x / G;
+    U4 d0, d1;
+    wg_draws<kWgWalkers>(a, blockIdx.x * kWgWalkers, d0, d1);
+    if (w >= a.W) return;   // whole groups
+    const int n = a.n;
+    int k;
+    if (moved_out) {
+        k = below(d0.x, n);
+        if (r == 0) moved_out[w] = k;
+    } else {
+        k = moved[w];
+        if (k < 0 || k >= n) k = 0;
+    }
+    const uint32_t vnew = (uint32_t)below(d0.z, a.L * a.L) | ((uint32_t)below(d0.w, a.n_tau) << 16);
+    if (r == 0) {
+        prop[w] = vnew;
+        logq[w] = 0.0;
+    }
+    gather_grp<G>(a, w, k, vnew, mats);
+}
+
+// The learned proposal (site and time bin from the network's logits, mixed with the uniform
+// proposal at weight eps) with its log q ratio, and its matrices; one wavefront per walker.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void mc_propose_kernel(McArgs a, const int32_t* __restrict__ moved,
                                                          const float* __restrict__ logits, int stride,
                                                          uint32_t* __restrict__ prop, double* __restrict__ logq,
                                                          double* __restrict__ mats)
@@ -268,20 +308,14 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
     const int lane = threadIdx.x & 63;
     const int w = blockIdx.x * kWgWalkers + (threadIdx.x >> 6);
     U4 d0, d1;
-    wg_draws(a, blockIdx.x * kWgWalkers, d0, d1);
+    wg_draws<kWgWalkers>(a, blockIdx.x * kWgWalkers, d0, d1);
     if (w >= a.W) return;
     const int n = a.n, L2 = a.L * a.L;
-    int k;
-    if (moved_out) {
-        k = below(d0.x, n);
-        if (lane == 0) moved_out[w] = k;
-    } else {
-        k = moved[w];
-        if (k < 0 || k >= n) k = 0;
-    }
+    int k = moved[w];
+    if (k < 0 || k >= n) k = 0;
     int site = below(d0.z, L2), t = below(d0.w, a.n_tau);
     double lq = 0.0;
-    if (logits) {
+    {
         const float* lg = logits + (size_t)w * stride;
         const int per_bin = a.n_tau / a.n_bin;
         // site distribution: lane owns the contiguous block [j0, j1); up to kPc of its terms
@@ -351,14 +385,14 @@ __global__ __launch_bounds__(256) void mc_propose_kernel(McArgs a, const int32_t
         prop[w] = vnew;
         logq[w] = lq;
     }
-    gather(a, w, k, vnew, mats);
+    gather_grp<64>(a, w, k, vnew, mats);
 }
 
 __global__ __launch_bounds__(256) void mc_gather_kernel(McArgs a, double* __restrict__ mats)
 {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= a.W) return;
-    gather(a, w, -1, 0u, mats);
+    gather_grp<64>(a, w, -1, 0u, mats);
 }
 
 struct Wt {
@@ -536,8 +570,7 @@ unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 hipError_t mc_context_launch(const McArgs& a, int32_t* moved, uint16_t* feat, int dp, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_context_kernel, dim3(blocks_for(a.W, kWgWalkers)), dim3(64 * kWgWalkers), 0, st, a, moved,
-                       feat, dp);
+    hipLaunchKernelGGL(mc_context_kernel, dim3(blocks_for(a.W, kGrpWalkers)), dim3(256), 0, st, a, moved, feat, dp);
     return hipGetLastError();
 }
 
@@ -545,8 +578,14 @@ hipError_t mc_propose_launch(const McArgs& a, const int32_t* moved, int32_t* mov
                              int stride, uint32_t* prop, double* logq, double* mats, hipStream_t st)
 {
     if (a.W == 0) return hipSuccess;
-    hipLaunchKernelGGL(mc_propose_kernel, dim3(blocks_for(a.W, kWgWalkers)), dim3(64 * kWgWalkers), 0, st, a, moved,
-                       moved_out, logits, stride, prop, logq, mats);
+    if (logits) {
+        if (moved_out) return hipErrorInvalidValue;   // the learned proposal takes the context's moved vertex
+        hipLaunchKernelGGL(mc_propose_kernel, dim3(blocks_for(a.W, kWgWalkers)), dim3(64 * kWgWalkers), 0, st, a,
+                           moved, logits, stride, prop, logq, mats);
+    } else {
+        hipLaunchKernelGGL(mc_propose_uniform_kernel, dim3(blocks_for(a.W, kWgWalkers)), dim3(256), 0, st, a, moved,
+                           moved_out, prop, logq, mats);
+    }
     return hipGetLastError();
 }
 
