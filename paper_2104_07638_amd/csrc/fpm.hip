@@ -137,10 +137,20 @@ __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int
     int nc[kPrepCache];
 #pragma unroll
     for (int i = 0; i < kPrepCache; ++i) nc[i] = s0 + i < s1 ? nv[s0 + i] : 0;
+    // the buckets that occur in this wavefront (uniform): only those are counted and placed
+    uint32_t seen = 0;
+#pragma unroll
+    for (int i = 0; i < kPrepCache; ++i)
+        if (s0 + i < s1) seen |= 1u << prep_bucket(nc[i]);
+    for (int i = kPrepCache; i < per; ++i)
+        if (s0 + i < s1) seen |= 1u << prep_bucket(nv[s0 + i]);
+    for (int o = 1; o < 64; o <<= 1) seen |= (uint32_t)__shfl_xor((int)seen, o);
+    const uint32_t present = (uint32_t)__builtin_amdgcn_readfirstlane((int)seen);
     // round i: this lane's matrix s0 + i (bucket -1 past the run); the cached rounds unrolled
     auto count_round = [&](int bk, int (&cw)[kPrepBuckets]) {
 #pragma unroll
-        for (int k = 0; k < kPrepBuckets; ++k) cw[k] += __builtin_popcountll(ballot(bk == k));
+        for (int k = 0; k < kPrepBuckets; ++k)
+            if ((present >> k) & 1u) cw[k] += __builtin_popcountll(ballot(bk == k));
     };
     // counts of this wavefront per bucket (uniform)
     int cw[kPrepBuckets];
@@ -184,6 +194,7 @@ __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int
     auto place_round = [&](int bk, int b, int (&cw)[kPrepBuckets]) {
 #pragma unroll
         for (int k = 0; k < kPrepBuckets; ++k) {
+            if (!((present >> k) & 1u)) continue;
             const uint64_t m = ballot(bk == k);
             if (bk == k) order[cw[k] + __builtin_popcountll(m & ((uint64_t(1) << lane) - 1))] = b;
             cw[k] += __builtin_popcountll(m);
