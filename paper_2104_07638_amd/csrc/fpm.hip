@@ -125,6 +125,28 @@ constexpr int kPrepBuckets = 22;   // bucket 20 - n for orders n = 1..20, 21 for
 
 __device__ __forceinline__ int prep_bucket(int n) { return (n >= 1 && n <= 20) ? 20 - n : 21; }
 
+// x plus the int64 of its DPP source lane (0 where there is none or the row is masked off)
+template <int CTRL, int RM, bool BC>
+__device__ __forceinline__ int64_t dpp_add64(int64_t x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, RM, 0xF, BC);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)x >> 32), CTRL, RM, 0xF, BC);
+    return x + (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// inclusive prefix sum over the 64 lanes by DPP: row_shr:1, 2, 4, 8 within rows of 16, then
+// row_bcast:15 into rows 1 and 3 and row_bcast:31 into rows 2 and 3
+__device__ __forceinline__ int64_t wave_scan64(int64_t v)
+{
+    v = dpp_add64<0x111, 0xF, true>(v);
+    v = dpp_add64<0x112, 0xF, true>(v);
+    v = dpp_add64<0x114, 0xF, true>(v);
+    v = dpp_add64<0x118, 0xF, true>(v);
+    v = dpp_add64<0x142, 0xA, false>(v);
+    v = dpp_add64<0x143, 0xC, false>(v);
+    return v;
+}
+
 __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int32_t* __restrict__ nv, int32_t* order,
                                                         int32_t* counter, int64_t* ioff, int64_t* ooff)
 {
@@ -217,14 +239,7 @@ __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int
         a0 += sq(nv[b]);
         a1 += p2(nv[b]);
     }
-    int64_t i0 = a0, i1 = a1;   // inclusive scan over the wavefront
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t u0 = __shfl_up(i0, o), u1 = __shfl_up(i1, o);
-        if (lane >= o) {
-            i0 += u0;
-            i1 += u1;
-        }
-    }
+    const int64_t i0 = wave_scan64(a0), i1 = wave_scan64(a1);   // inclusive scans over the wavefront
     if (lane == 63) {
         wtot[0][wv] = i0;
         wtot[1][wv] = i1;
