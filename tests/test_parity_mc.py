@@ -344,10 +344,10 @@ def test_mc_evaluate_resolve(apm):
     assert np.all(ch.sign.cpu().numpy()[both] == sg_ref[both])
 
 
-@pytest.mark.parametrize("n", [12, 13])
+@pytest.mark.parametrize("n", [6, 11, 12, 13])
 def test_mc_evaluate_orders(apm, n):
     """Up to n = 12 the connected-sum kernel hands the acceptance step only (c[V], d[V]);
-    above, c[V] and d[V] come from the full c[] and minors arrays.  Both against the oracle,
+    above, c[V] and d[V] come from the full c[] and minors arrays.  All against the oracle,
     with the resolution cutoff on."""
     model = wl.McModel(n=n, L=16, mu=0.0, beta=4.0, n_tau=128, n_bin=16, resolve=1e-10)
     s = _Setup(apm, model, 128, seed=11)
