@@ -114,12 +114,14 @@ hipError_t fill_tune_input(void* A, int dtype, int n, int batch, hipStream_t st)
 
 // Queue preparation (one workgroup): bucket the matrices by order, largest first, so the
 // persistent waves start with the longest work; packed default offsets; queue heads = 0.
-// Thread t owns the run [t per, (t + 1) per) of consecutive matrices, per = ceil(B / 1024);
-// its orders are loaded once (runs above kPrepCache matrices reload the rest).  Counting
-// sort without atomics: each wavefront counts its matrices per bucket with ballots, the
-// counts of all wavefronts give every (bucket, wavefront) its first queue position, and each
-// wavefront then places its matrices in the same order it counted them.  The offsets are one
-// scan over the runs.
+// Wavefront w owns the segment [w S, (w + 1) S) of consecutive matrices, S = 64 per with
+// per = ceil(B / 1024) rounds; in round i lane l takes matrix w S + 64 i + l, so every
+// access of a round is one contiguous run.  The orders of the first kPrepCache rounds are
+// kept in registers.  Counting sort without atomics: each wavefront counts its matrices per
+// bucket with ballots, the counts of all wavefronts give every (bucket, wavefront) its first
+// queue position, and each wavefront then places its matrices in the order it counted them
+// (within a bucket: by matrix index).  The offsets are one scan per round over the lanes,
+// carried from round to round, on top of the totals of the wavefronts before.
 constexpr int kPrepCache = 16;
 constexpr int kPrepBuckets = 22;   // bucket 20 - n for orders n = 1..20, 21 for invalid ones
 
@@ -147,6 +149,14 @@ __device__ __forceinline__ int64_t wave_scan64(int64_t v)
     return v;
 }
 
+// the int64 of lane 63 (uniform)
+__device__ __forceinline__ int64_t lane63(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), 63);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int32_t* __restrict__ nv, int32_t* order,
                                                         int32_t* counter, int64_t* ioff, int64_t* ooff)
 {
@@ -155,38 +165,56 @@ __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int
     __shared__ int64_t wtot[2][16];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int per = (int)(((int64_t)batch + 1023) / 1024);
-    const int s0 = (int)min((int64_t)batch, (int64_t)t * per), s1 = (int)min((int64_t)batch, (int64_t)s0 + per);
+    const int64_t seg = (int64_t)wv * 64 * per + lane;   // this lane's matrix of round 0
+    auto mat = [&](int i) { return seg + (int64_t)i * 64; };
+    auto order_of = [&](int i) { return mat(i) < batch ? nv[mat(i)] : 0; };
     int nc[kPrepCache];
 #pragma unroll
-    for (int i = 0; i < kPrepCache; ++i) nc[i] = s0 + i < s1 ? nv[s0 + i] : 0;
+    for (int i = 0; i < kPrepCache; ++i) nc[i] = i < per ? order_of(i) : 0;
     // the buckets that occur in this wavefront (uniform): only those are counted and placed
     uint32_t seen = 0;
 #pragma unroll
     for (int i = 0; i < kPrepCache; ++i)
-        if (s0 + i < s1) seen |= 1u << prep_bucket(nc[i]);
+        if (i < per && mat(i) < batch) seen |= 1u << prep_bucket(nc[i]);
     for (int i = kPrepCache; i < per; ++i)
-        if (s0 + i < s1) seen |= 1u << prep_bucket(nv[s0 + i]);
+        if (mat(i) < batch) seen |= 1u << prep_bucket(nv[mat(i)]);
     for (int o = 1; o < 64; o <<= 1) seen |= (uint32_t)__shfl_xor((int)seen, o);
     const uint32_t present = (uint32_t)__builtin_amdgcn_readfirstlane((int)seen);
-    // round i: this lane's matrix s0 + i (bucket -1 past the run); the cached rounds unrolled
-    auto count_round = [&](int bk, int (&cw)[kPrepBuckets]) {
-#pragma unroll
-        for (int k = 0; k < kPrepBuckets; ++k)
-            if ((present >> k) & 1u) cw[k] += __builtin_popcountll(ballot(bk == k));
+    // round i: this lane's matrix (bucket -1 past the batch); the cached rounds unrolled.
+    // Lane k of cw holds this wavefront's count of bucket k; the loops run over the present
+    // buckets only (a scalar loop: present is uniform).
+    int cw = 0;
+    auto count_round = [&](int bk) {
+        for (uint32_t pb = present; pb; pb &= pb - 1u) {
+            const int k = __builtin_ctz(pb);
+            const int c = __builtin_popcountll(ballot(bk == k));
+            cw += lane == k ? c : 0;
+        }
     };
-    // counts of this wavefront per bucket (uniform)
-    int cw[kPrepBuckets];
-#pragma unroll
-    for (int k = 0; k < kPrepBuckets; ++k) cw[k] = 0;
 #pragma unroll
     for (int i = 0; i < kPrepCache; ++i)
-        if (i < per) count_round(s0 + i < s1 ? prep_bucket(nc[i]) : -1, cw);
-    for (int i = kPrepCache; i < per; ++i) count_round(s0 + i < s1 ? prep_bucket(nv[s0 + i]) : -1, cw);
-    if (lane < kPrepBuckets) {
-        int v = 0;
+        if (i < per) count_round(mat(i) < batch ? prep_bucket(nc[i]) : -1);
+    for (int i = kPrepCache; i < per; ++i) count_round(mat(i) < batch ? prep_bucket(nv[mat(i)]) : -1);
+    if (lane < kPrepBuckets) wcnt[wv][lane] = cw;
+    // this lane's sums of n^2 and 2^n over its rounds, for the wavefront totals
+    auto sq = [](int n) { return (n >= 1 && n <= 20) ? (int64_t)n * n : (int64_t)0; };
+    auto p2 = [](int n) { return (n >= 1 && n <= 20) ? (int64_t(1) << n) : (int64_t)0; };
+    int64_t a0 = 0, a1 = 0;
 #pragma unroll
-        for (int k = 0; k < kPrepBuckets; ++k) v = lane == k ? cw[k] : v;
-        wcnt[wv][lane] = v;
+    for (int i = 0; i < kPrepCache; ++i) {
+        a0 += sq(nc[i]);
+        a1 += p2(nc[i]);
+    }
+    for (int i = kPrepCache; i < per; ++i) {
+        const int n = order_of(i);
+        a0 += sq(n);
+        a1 += p2(n);
+    }
+    a0 = wave_scan64(a0);
+    a1 = wave_scan64(a1);
+    if (lane == 63) {
+        wtot[0][wv] = a0;
+        wtot[1][wv] = a1;
     }
     __syncthreads();
     if (t < kPrepBuckets) {   // bucket totals
@@ -211,60 +239,42 @@ __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kPrepBuckets; ++k) cw[k] = wcnt[wv][k];
-    auto place_round = [&](int bk, int b, int (&cw)[kPrepBuckets]) {
-#pragma unroll
-        for (int k = 0; k < kPrepBuckets; ++k) {
-            if (!((present >> k) & 1u)) continue;
+    cw = lane < kPrepBuckets ? wcnt[wv][lane] : 0;   // first positions
+    const uint64_t below = (uint64_t(1) << lane) - 1;
+    auto place_round = [&](int bk, int64_t b) {
+        for (uint32_t pb = present; pb; pb &= pb - 1u) {
+            const int k = __builtin_ctz(pb);
             const uint64_t m = ballot(bk == k);
-            if (bk == k) order[cw[k] + __builtin_popcountll(m & ((uint64_t(1) << lane) - 1))] = b;
-            cw[k] += __builtin_popcountll(m);
+            const int first = __builtin_amdgcn_readlane(cw, k);
+            if (bk == k) order[first + __builtin_popcountll(m & below)] = (int32_t)b;
+            cw += lane == k ? __builtin_popcountll(m) : 0;
         }
     };
 #pragma unroll
     for (int i = 0; i < kPrepCache; ++i)
-        if (i < per) place_round(s0 + i < s1 ? prep_bucket(nc[i]) : -1, s0 + i, cw);
-    for (int i = kPrepCache; i < per; ++i) place_round(s0 + i < s1 ? prep_bucket(nv[s0 + i]) : -1, s0 + i, cw);
-    // exclusive prefix sums of n^2 and 2^n in matrix order
-    auto sq = [](int n) { return (n >= 1 && n <= 20) ? (int64_t)n * n : (int64_t)0; };
-    auto p2 = [](int n) { return (n >= 1 && n <= 20) ? (int64_t(1) << n) : (int64_t)0; };
-    int64_t a0 = 0, a1 = 0;
-#pragma unroll
-    for (int i = 0; i < kPrepCache; ++i) {
-        a0 += sq(nc[i]);
-        a1 += p2(nc[i]);
-    }
-    for (int b = s0 + kPrepCache; b < s1; ++b) {
-        a0 += sq(nv[b]);
-        a1 += p2(nv[b]);
-    }
-    const int64_t i0 = wave_scan64(a0), i1 = wave_scan64(a1);   // inclusive scans over the wavefront
-    if (lane == 63) {
-        wtot[0][wv] = i0;
-        wtot[1][wv] = i1;
-    }
-    __syncthreads();
-    int64_t e0 = i0 - a0, e1 = i1 - a1;
+        if (i < per) place_round(mat(i) < batch ? prep_bucket(nc[i]) : -1, mat(i));
+    for (int i = kPrepCache; i < per; ++i) place_round(mat(i) < batch ? prep_bucket(nv[mat(i)]) : -1, mat(i));
+    // exclusive prefix sums of n^2 and 2^n in matrix order: the wavefronts before, then the
+    // rounds before, then the lanes before
+    int64_t e0 = 0, e1 = 0;
     for (int w = 0; w < wv; ++w) {
         e0 += wtot[0][w];
         e1 += wtot[1][w];
     }
-#pragma unroll
-    for (int i = 0; i < kPrepCache; ++i) {
-        if (s0 + i < s1) {
-            ioff[s0 + i] = e0;
-            ooff[s0 + i] = e1;
+    auto offsets_round = [&](int i, int n) {
+        const int64_t v0 = sq(n), v1 = p2(n);
+        const int64_t i0 = wave_scan64(v0), i1 = wave_scan64(v1);
+        if (mat(i) < batch) {
+            ioff[mat(i)] = e0 + i0 - v0;
+            ooff[mat(i)] = e1 + i1 - v1;
         }
-        e0 += sq(nc[i]);
-        e1 += p2(nc[i]);
-    }
-    for (int b = s0 + kPrepCache; b < s1; ++b) {
-        ioff[b] = e0;
-        ooff[b] = e1;
-        e0 += sq(nv[b]);
-        e1 += p2(nv[b]);
-    }
+        e0 += lane63(i0);
+        e1 += lane63(i1);
+    };
+#pragma unroll
+    for (int i = 0; i < kPrepCache; ++i)
+        if (i < per) offsets_round(i, nc[i]);
+    for (int i = kPrepCache; i < per; ++i) offsets_round(i, order_of(i));
 }
 
 hipError_t fpm_prep_launch(const LaunchMinors& L, hipStream_t st)
