@@ -45,17 +45,6 @@ constexpr int kPmax = APM_CS_PMAX;
 template <int M>
 constexpr int cs_threads() { return M <= 10 ? 64 : APM_CS_NT_LARGE; }
 
-__device__ __forceinline__ uint32_t pdep_u32(uint32_t k, uint32_t mask)
-{
-    uint32_t r = 0;
-    for (uint32_t bit = 1; mask; bit <<= 1) {
-        const uint32_t low = mask & (0u - mask);
-        if (k & bit) r |= low;
-        mask ^= low;
-    }
-    return r;
-}
-
 // LDS block layouts.  The c' and b blocks, read row by row by many lanes at once, have rows
 // padded to 2^LB + 2 values: row r starts 16 bytes further round the banks than row r-1, and
 // each 16-byte pair of a row sits at a fixed offset from the row start (an immediate of the
@@ -316,10 +305,14 @@ __device__ __forceinline__ void row_group(bool valid, uint32_t xh, int items, in
     for (int i = 0; i < W; ++i) acc[i] = 0.0;
     if (valid) {
         // pair k = s + G t has Yh = pdep(s) | pdep(t) over the bits of Xh above its lowest
-        // log2(G) ones: the second part steps through the subsets of those bits in order
-        const uint32_t ys = pdep_u32((uint32_t)s, xh);
-        uint32_t xhi = xh;
-        for (int gg = 1; gg < G; gg <<= 1) xhi &= xhi - 1u;
+        // log2(G) ones: the second part steps through the subsets of those bits in order.
+        // s < G: its bits go to the lowest log2(G) bits of Xh, and xhi keeps the rest.
+        uint32_t ys = 0, xhi = xh;
+        for (int gg = 1; gg < G; gg <<= 1) {
+            const uint32_t low = xhi & (0u - xhi);
+            if (s & gg) ys |= low;
+            xhi ^= low;
+        }
         uint32_t z = 0;
         for (int k = s; k < items; k += G, z = (z - xhi) & xhi) {
             const uint32_t yh = ys | z;
