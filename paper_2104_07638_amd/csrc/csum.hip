@@ -84,7 +84,9 @@ __device__ __forceinline__ uint32_t row_addr(int row)
 {
     constexpr int W = 1 << LB;
     constexpr int pm = (W >> 1) - 1;
-    if constexpr (PAD) return __umul24((uint32_t)row, 8u * (W + 2));
+    // rows have at most 7 bits: with the mask the product is a full-rate 24-bit multiply
+    // (an unbounded row index becomes a quarter-rate 32-bit one)
+    if constexpr (PAD) return ((uint32_t)row & 0x7Fu) * (8u * (W + 2));
     return (uint32_t)row * (8u * W) + ((uint32_t)(row & pm) << 4);
 }
 
@@ -358,11 +360,12 @@ __device__ __forceinline__ void rank_pass(int tid, int r, const uint16_t* rk_tab
     constexpr int GMUL = NT < kWave ? 1 : (NT == kWave ? APM_CS_GMUL_SMALL : (TRI ? APM_CS_GMUL_TRI : APM_CS_GMUL));
     constexpr int GMAX = NT < kWave ? NT : kWave;
     while (G * 2 <= GMAX && nout * G * GMUL <= NT && G * 2 <= (items > 0 ? items : 1)) G *= 2;
-    const int per_pass = NT / G;
+    const int lg = __builtin_ctz((unsigned)G);   // G is a power of two: shifts, not divisions
+    const int per_pass = NT >> lg;
     for (int ob = 0; ob < nout; ob += per_pass) {
-        const int o = ob + tid / G;
+        const int o = ob + (tid >> lg);
         const bool valid = o < nout;
-        row_group<M, TRI, 0, RPAD>(valid, valid ? rk_tab[rk_off[r] + o] : 0u, items, G, tid % G, cb, bb, rb,
+        row_group<M, TRI, 0, RPAD>(valid, valid ? rk_tab[rk_off[r] + o] : 0u, items, G, tid & (G - 1), cb, bb, rb,
                                    cb_out);
     }
 }
