@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-mc", action="store_true")
-    ap.add_argument("--mc-train-steps", type=int, default=20000)
+    ap.add_argument("--mc-train-steps", type=int, default=60000)
     ap.add_argument("--mc-steps", type=int, default=5000)
     args = ap.parse_args()
     if args.gpus != 1:
