@@ -1082,10 +1082,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int lo = counter[kBucketBase + 20 - kBigHi];
     const int gap = counter[kBucketBase + 21 - kBigLo] - lo;
-    for (;;) {
-        int i = 0;
-        if (lane_id() == 0) i = atomicAdd(counter, 1);
-        i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
+    // the first item of each workgroup is its own index; the queue head counts the rest
+    for (int first = (int)blockIdx.x;; first = -1) {
+        int i = first;
+        if (first < 0) {
+            if (lane_id() == 0) i = atomicAdd(counter, 1);
+            i = __builtin_amdgcn_readfirstlane(__shfl(i, 0)) + (int)gridDim.x;
+        }
         if (i >= lo) i += gap;
         if (i >= batch) break;
         const int b = order[i];
@@ -1135,10 +1138,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
 {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int lo = counter[kBucketBase + 20 - kBigHi], hi = counter[kBucketBase + 21 - kBigLo];
-    for (;;) {
-        int i = 0;
-        if (lane_id() == 0) i = atomicAdd(counter + 1, 1);
-        i = __builtin_amdgcn_readfirstlane(__shfl(i, 0)) + lo;
+    // the first item of each workgroup is its own index; the queue head counts the rest
+    for (int first = (int)blockIdx.x;; first = -1) {
+        int i = first;
+        if (first < 0) {
+            if (lane_id() == 0) i = atomicAdd(counter + 1, 1);
+            i = __builtin_amdgcn_readfirstlane(__shfl(i, 0)) + (int)gridDim.x;
+        }
+        i += lo;
         if (i >= hi) break;
         const int b = order[i];
         const int n = nv[b];
