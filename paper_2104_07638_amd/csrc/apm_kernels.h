@@ -10,7 +10,8 @@ constexpr double kDefaultPivTol = 1e-3;
 
 // Queue-preparation workspace: int32 counter[0] is the mixed-order queue head, counter[1] the
 // head of the large-order queue, counter[kBucketBase + k] (k = 0..22) the start in the queue
-// order of the matrices of order 20 - k (k = 21: invalid orders; k = 22: the end).
+// order of the matrices of order 20 - k (k = 21: invalid orders; k = 22: the end); ints 32..63
+// hold the persistent kernels' per-stream queue heads (256 bytes in all).
 constexpr int kBucketBase = 8;
 
 struct LaunchMinors {

@@ -230,6 +230,7 @@ __global__ __launch_bounds__(1024) void fpm_prep_kernel(int32_t batch, const int
             counter[kBucketBase + kPrepBuckets] = start + btot[t];
             counter[0] = 0;
             counter[1] = 0;
+            for (int h = 32; h < 64; ++h) counter[h] = 0;   // the persistent kernels' stream heads
         }
         counter[kBucketBase + t] = start;   // where the matrices of order 20 - t start
         for (int w = 0; w < 16; ++w) {

@@ -1069,6 +1069,27 @@ __device__ __forceinline__ int fpm_dispatch(int n, const typename F::In* A, void
     }
 }
 
+// A persistent kernel's positions in the queue are split into kStreams interleaved streams
+// (position p in stream p mod kStreams); workgroup g serves stream g mod kStreams, which takes
+// consecutive workgroups to different XCDs.  Its first position is g itself; later ones come
+// from the stream's own head (an atomic counter), so that the heads' atomics are spread over
+// kStreams addresses instead of one.  Each stream keeps the queue order (largest first).
+constexpr int kStreams = 8;
+constexpr int kSmallHeads = 32, kBigHeads = 48;   // heads (every second int) in the counter block
+// queue position of a workgroup's first item (its own index) and of the later ones (from the
+// head of its stream)
+__device__ __forceinline__ int stream_first() { return (int)blockIdx.x; }
+
+__device__ __forceinline__ int stream_pop(int32_t* heads)
+{
+    const int x = (int)(blockIdx.x % kStreams);
+    int j = 0;
+    if (lane_id() == 0) j = atomicAdd(heads + 2 * x, 1);
+    // the stream's first positions are the first items of the workgroups that serve it
+    j = __builtin_amdgcn_readfirstlane(__shfl(j, 0)) + ((int)gridDim.x - x + kStreams - 1) / kStreams;
+    return x + kStreams * j;
+}
+
 // Persistent waves over the prepared queue, skipping the matrices of orders kBigLo..kBigHi
 // (a contiguous range of the queue order, left to fpm_ragged_big_kernel); each matrix is
 // handled by the code for its order.
@@ -1082,14 +1103,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int lo = counter[kBucketBase + 20 - kBigHi];
     const int gap = counter[kBucketBase + 21 - kBigLo] - lo;
-    // the first item of each workgroup is its own index; the queue head counts the rest
-    for (int first = (int)blockIdx.x;; first = -1) {
-        int i = first;
-        if (first < 0) {
-            if (lane_id() == 0) i = atomicAdd(counter, 1);
-            i = __builtin_amdgcn_readfirstlane(__shfl(i, 0)) + (int)gridDim.x;
-        }
-        if (i >= lo) i += gap;
+    for (int p = stream_first();; p = stream_pop(counter + kSmallHeads)) {
+        const int i = p >= lo ? p + gap : p;
         if (i >= batch) break;
         const int b = order[i];
         const int n = nv[b];
@@ -1138,14 +1153,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fp
 {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int lo = counter[kBucketBase + 20 - kBigHi], hi = counter[kBucketBase + 21 - kBigLo];
-    // the first item of each workgroup is its own index; the queue head counts the rest
-    for (int first = (int)blockIdx.x;; first = -1) {
-        int i = first;
-        if (first < 0) {
-            if (lane_id() == 0) i = atomicAdd(counter + 1, 1);
-            i = __builtin_amdgcn_readfirstlane(__shfl(i, 0)) + (int)gridDim.x;
-        }
-        i += lo;
+    for (int p = stream_first();; p = stream_pop(counter + kBigHeads)) {
+        const int i = p + lo;
         if (i >= hi) break;
         const int b = order[i];
         const int n = nv[b];
